@@ -1,0 +1,195 @@
+"""Throughput of the Subsampling SMC hot path on one MI355X.
+
+One step = one stage of Algorithm 2 on a live run: tempering exponent by ESS
+bisection + reweighting, mass matrix (weighted covariance + Cholesky),
+systematic resampling, and one fused Markov move (block pseudo-marginal
+refresh of u + HMC with L leapfrog steps). The control-variate summaries and
+packed rows are built once in setup (the centre is fixed at the posterior
+mode). Inputs are resident in HBM before timing starts.
+
+Metric: particle x subsample-slot log-likelihood + gradient evaluations per
+second; a move does M * m * (L + 1) of them (one estimator pass for the
+u-refresh and one per leapfrog step). `value` is the mixed-precision path
+(FP32 data and per-observation terms, FP64 control variates, reductions and
+accept ratios); the plain FP64 path on the same data is reported beside it.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison path")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-particles", type=int, default=64)
+    ap.add_argument("--only", choices=["mixed", "fp64"], default=None, help="time one path only (profiling)")
+    return ap.parse_args()
+
+
+def algorithmic_bytes_per_eval(d, fp32):
+    """x_k (d values) + y_k + the 4-byte subsample index."""
+    s = 4 if fp32 else 8
+    return d * s + s + 4
+
+
+def run_path(w, precision, Xy_dev, args, eps):
+    import torch
+    from paper_1805_03317_amd.binding import SubsampledSMC
+
+    smc = SubsampledSMC(Xy_dev, w.d, w.family, precision, w.M, w.m, w.G, w.prior_mean, w.prior_prec, w.seed)
+    stream = torch.cuda.current_stream()
+    evals_per_move = w.M * w.m * (w.L + 1)
+    state = {"tempered": 0}
+
+    def step(events=None):
+        if smc.info()["a"] < 1.0:
+            smc.temper()
+            state["tempered"] += 1
+        smc.mass()
+        smc.resample()
+        if events is not None:
+            events[0].record(stream)
+        smc.move(eps, w.L, 1)
+        if events is not None:
+            events[1].record(stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step(evs[k])
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    move_ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+    info = smc.info()
+    acc = smc.accept.float().mean(0).cpu().numpy()
+    res = {
+        "evals_per_s": args.steps * evals_per_move / elapsed,
+        "ms_per_step": 1e3 * elapsed / args.steps,
+        "move_ms": move_ms,
+        "move_evals_per_s": evals_per_move / (move_ms * 1e-3),
+        "a": info["a"],
+        "stage": info["stage"],
+        "stages_tempered": state["tempered"],
+        "accept_u": float(acc[0]),
+        "accept_theta": float(acc[1]),
+        "newton_iters": info["newton_iters"],
+    }
+    return smc, res
+
+
+def roofline(w, fp32, move_ms):
+    bpe = algorithmic_bytes_per_eval(w.d, fp32)
+    evals = w.M * w.m * (w.L + 1)
+    achieved = bpe * evals / (move_ms * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
+            "kernel": "move_kernel", "bytes_per_eval": bpe, "evals_per_launch": evals}
+
+
+def cpu_baseline(w, count, eps):
+    """The oracle's move on `count` particles of the same workload, at a = 1."""
+    import oracle
+
+    P = oracle.Problem(w.Xy(np.float64), w.d, w.family, w.prior_mean, w.prior_prec)
+    tb, _ = P.newton_mode()
+    P.set_cv_centre(tb)
+    thp, u0, _ = oracle.init_particles(count, w.d, w.m, w.n, w.seed, w.prior_mean, w.prior_prec)
+    _, B, Cm = P.cv_build(tb)
+    cov = np.linalg.inv(-Cm + w.prior_prec)
+    Lc = np.linalg.cholesky(cov)
+    z = (thp - w.prior_mean) @ np.linalg.cholesky(w.prior_prec)  # standard normals
+    th0 = tb + z @ Lc.T                                             # Laplace approximation draws
+    t0 = time.perf_counter()
+    oracle.move(P, th0, u0, 1.0, eps, w.L, w.seed, 1, 0, w.G, cov, Lc)
+    dt = time.perf_counter() - t0
+    evals = count * w.m * (w.L + 1)
+    return {"value": evals / dt, "unit": "evals/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"one Markov move of {count} of the {w.M} particles (same data, Laplace-approximation "
+                      f"state at a=1), {evals} algorithmic evals in {dt:.2f} s wall"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU design is described "
+              "in DESIGN.md and is not built", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_1805_03317_amd import workloads as W
+
+    w = W.config2()
+    eps = 1.0 / w.L
+    Xy = torch.tensor(w.Xy(np.float32), device="cuda:0")
+    torch.cuda.synchronize()
+
+    paths = ["mixed", "fp64"] if args.only is None else [args.only]
+    if args.no_fp64 and "fp64" in paths and args.only is None:
+        paths.remove("fp64")
+    results = {}
+    ctxs = {}
+    for p in paths:
+        prec = W.MIXED if p == "mixed" else W.FP64
+        ctxs[p], results[p] = run_path(w, prec, Xy, args, eps)
+        print(f"# {p}: {results[p]}", file=sys.stderr, flush=True)
+
+    head = "mixed" if "mixed" in results else "fp64"
+    r = results[head]
+    out = {
+        "metric": "particle-obs loglik+grad evals/s (mixed vs FP64 plain, <=1e-5 rel err)",
+        "value": r["evals_per_s"],
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64" if head == "mixed" else "f64",
+        "data": "synthetic",
+        "config": {"workload": w.name, "n": w.n, "d": w.d, "M": w.M, "m": w.m, "G": w.G, "L": w.L,
+                   "R": 1, "eps": eps, "precision": head, "step": "temper+mass+resample+move"},
+        "roofline": roofline(w, head == "mixed", r["move_ms"]),
+        "move_ms": r["move_ms"],
+        "move_evals_per_s": r["move_evals_per_s"],
+        "run": {k: r[k] for k in ("a", "stage", "stages_tempered", "accept_u", "accept_theta", "newton_iters")},
+    }
+    if "fp64" in results and head == "mixed":
+        f = results["fp64"]
+        out["fp64"] = {"value": f["evals_per_s"], "ms_per_step": f["ms_per_step"], "move_ms": f["move_ms"],
+                       "roofline": roofline(w, False, f["move_ms"]),
+                       "mixed_over_fp64": r["evals_per_s"] / f["evals_per_s"]}
+        # error of the mixed path against the FP64 path on the same particles
+        sm, sf = ctxs["mixed"], ctxs["fp64"]
+        th = sm.theta[:256].clone()
+        u = sm.u[:256].clone()
+        lm, s2m, _ = sm.loglik_est(th, u)
+        lf, s2f, _ = sf.loglik_est(th, u)
+        out["mixed_rel_err"] = {
+            "lhat_max": float(((lm - lf).abs() / lf.abs()).max()),
+            "sig2_max": float(((s2m - s2f).abs() / s2f.abs().clamp_min(1e-300)).max()),
+        }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_particles, eps)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,198 @@
+/*
+ * subsmc.h - C ABI of the MI355X Subsampling SMC hot path.
+ *
+ * Method: Subsampling Sequential Monte Carlo for static Bayesian models
+ * (Gunawan, Dang, Quiroz, Kohn, Tran, arXiv:1805.03317). The library runs,
+ * on one GPU, the stages of Algorithm 2: the adaptive tempering exponent and
+ * reweighting with the annealed likelihood estimator (sections 2.2, 3.3, 3.5),
+ * the mass matrix from the particle covariance (Algorithm 2 step d),
+ * resampling, and the Markov move of Algorithm 1 (a block pseudo-marginal
+ * refresh of the subsample indices u, then HMC on theta given u), with the
+ * difference estimator of the log-likelihood, its variance estimate and the
+ * second-order Taylor control variates of section 3.2.
+ *
+ * Conventions
+ *  - All functions return an smc_status; SMC_OK is 0. On failure the context
+ *    keeps a message readable with smc_last_error().
+ *  - "device" pointers are HIP device allocations owned by the caller; the
+ *    library never frees them and never allocates device memory: its scratch
+ *    comes from the caller's workspace (size from smc_workspace_size).
+ *  - "host" pointers are read (or written) before the call returns.
+ *  - All device work is enqueued on the stream given to smc_init, in call
+ *    order. Functions that return host values (smc_temper, smc_get_*,
+ *    smc_init) synchronise that stream; the others only enqueue.
+ *  - Matrices are row-major FP64. Subsample indices are 0-based int32.
+ *  - A context is used by one host thread at a time.
+ *  - Random numbers: Philox4x64-10 keyed by (seed, 0); every draw is a pure
+ *    function of (seed, purpose, stage, move index, particle, draw number),
+ *    so runs are reproducible and resumable.
+ */
+#ifndef SUBSMC_H
+#define SUBSMC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SMC_OK = 0,
+  SMC_ERR_INVALID_ARG = 1, /* bad size, null pointer, or unsupported combination */
+  SMC_ERR_STATE = 2,       /* call out of order (e.g. smc_move before a mass matrix exists) */
+  SMC_ERR_DEVICE = 3,      /* a HIP call failed; see smc_last_error */
+  SMC_ERR_NOT_PD = 4,      /* covariance not positive definite even after jitter */
+  SMC_ERR_NONFINITE = 5,   /* every incremental weight is non-finite */
+  SMC_ERR_UNSUPPORTED = 6  /* valid request this build does not implement (e.g. d > 32) */
+} smc_status;
+
+typedef enum {
+  SMC_LOGISTIC = 0, /* y in {0,1}, l = y eta - log(1 + e^eta)        (Exp. 1)        */
+  SMC_POISSON = 1,  /* y in N,     l = y eta - e^eta - log y!        (Exp. 2)        */
+  SMC_GAUSSIAN = 2  /* known noise variance gauss_s2; quadratic test family           */
+} smc_family;
+
+typedef enum {
+  SMC_FP64 = 0,  /* data and arithmetic in FP64                                        */
+  SMC_MIXED = 1  /* data stored FP32; x'delta and the per-observation terms in FP32;  */
+                 /* control variates, reductions, weights and MH ratios in FP64       */
+} smc_precision;
+
+typedef struct smc_ctx_s* smc_ctx;
+
+/*
+ * Problem description (copied by smc_init; pointers must stay valid for the
+ * context's lifetime where marked "kept").
+ */
+typedef struct smc_problem {
+  int32_t family;      /* smc_family */
+  int32_t precision;   /* smc_precision */
+  int32_t cv_order;    /* 2: second-order Taylor control variate (section 3.2); 1: first order */
+  int32_t d;           /* number of parameters, 1 <= d <= 32 in this build */
+  int64_t n;           /* number of observations, 1 <= n < 2^31 */
+  int32_t ld;          /* pitch of Xy in elements, ld >= d + 1 */
+  int32_t xy_fp32;     /* 1: Xy holds float, 0: double */
+  const void* Xy;      /* device: n rows [x_k (d) | y_k | ...]; read by smc_init (and smc_set_cv) only */
+  double gauss_s2;     /* noise variance for SMC_GAUSSIAN, else ignored */
+  int32_t M;           /* particles, 1 <= M <= 8192 */
+  int32_t m;           /* subsample size (with replacement), 1 <= m */
+  int32_t G;           /* blocks of u for the pseudo-marginal refresh, 1 <= G <= m */
+  int32_t n_bisect;    /* bisection steps for the tempering exponent (e.g. 60) */
+  uint64_t seed;       /* Philox key */
+  double ess_frac;     /* target ESS = ess_frac * M, 0 < ess_frac <= 1 */
+  const double* prior_mean; /* host d: Gaussian prior mean */
+  const double* prior_prec; /* host d*d: Gaussian prior precision (SPD) */
+  const double* theta_bar;  /* host d: control-variate centre, or NULL: the posterior
+                               mode found by Newton's method on the full data */
+  /* particle state, device, caller-owned, kept: */
+  double* theta;       /* M*d */
+  int32_t* u;          /* M*m */
+  double* logw;        /* M, normalised log weights */
+  double* lhat;        /* M, l_hat at the particle's (theta, u) */
+  double* sig2;        /* M, sigma2_hat at the particle's (theta, u) */
+  int32_t* accept;     /* M*2, last move's decisions: [u accepted, theta accepted] */
+  void* workspace;     /* device, kept: smc_workspace_size bytes, 256-byte aligned */
+  size_t workspace_bytes;
+} smc_problem;
+
+/* Bytes of device workspace smc_init needs for this problem (0 if invalid). */
+size_t smc_workspace_size(const smc_problem* pb);
+
+/*
+ * Algorithm 2 step 1. Validates the problem, finds the control-variate centre
+ * (Newton's method on the full-data log posterior unless pb->theta_bar is
+ * given), builds A, B, C (section 3.2) and the packed per-observation rows in
+ * the workspace, draws theta_i ~ prior and u_i ~ uniform (stage 0), sets
+ * logw = -log M, and evaluates lhat, sig2 (and the cached gradients) at every
+ * particle. Temperature a = 0, log Z = 0, stage 0. `stream` is a hipStream_t
+ * (NULL: the default stream). Synchronises.
+ */
+smc_status smc_init(const smc_problem* pb, void* stream, smc_ctx* out);
+
+/*
+ * Algorithm 2 steps a-c. Increments the stage, chooses the next exponent
+ * a in (a_prev, 1] by bisection on ESS(a) = ess_frac * M (a = 1 when ESS(1)
+ * already meets it), reweights logw with the annealed estimator
+ * (a - a_prev) l_hat - (a^2 - a_prev^2) sigma2_hat / 2 (normalised), and adds
+ * the log evidence increment log sum_i W_i exp(...) (section 3.5).
+ * Host outputs (any may be NULL). Synchronises.
+ */
+smc_status smc_temper(smc_ctx ctx, double* a_out, double* dlogz_out, double* ess_out);
+
+/* Algorithm 2 step d: weighted particle covariance Sigma (inverse mass matrix),
+ * its Cholesky factor and inverse factor. SMC_ERR_NOT_PD is reported by the
+ * next synchronising call or smc_get_mass. */
+smc_status smc_mass(smc_ctx ctx);
+
+/* Algorithm 2 step e: systematic resampling with exact integer arithmetic
+ * (one Philox offset per stage); copies theta, u and the caches from the
+ * ancestors and sets logw = -log M. */
+smc_status smc_resample(smc_ctx ctx);
+
+/* Algorithm 2 step f: R Markov moves (Algorithm 1) of every particle at the
+ * current exponent: block refresh of u (one of G blocks, uniform), then HMC
+ * with step eps, L leapfrog steps, momentum ~ N(0, Sigma^{-1}). Requires a
+ * mass matrix (smc_mass or smc_set_mass). */
+smc_status smc_move(smc_ctx ctx, double eps, int32_t L, int32_t R);
+
+/*
+ * Difference estimator (eq. difference_estimator_logl) and its variance
+ * estimate (section 3.2) for `count` particles at exponent-free level:
+ * device theta (count*d), u (count*m) -> device lhat, sig2, dhat (count each;
+ * dhat = (n/m) sum_j d_{u_j}); any output may be NULL.
+ */
+smc_status loglik_est(smc_ctx ctx, int32_t count, const double* theta, const int32_t* u,
+                      double* lhat, double* sig2, double* dhat);
+
+/*
+ * Gradients of the same quantities: device grad (count*d) receives
+ * g_lhat[i] * grad l_hat + g_sig2[i] * grad sigma2_hat (g_* device, count,
+ * NULL meaning 0). grad_l / grad_s (count*d, nullable) receive the two
+ * gradients separately.
+ */
+smc_status loglik_grad(smc_ctx ctx, int32_t count, const double* theta, const int32_t* u,
+                       const double* g_lhat, const double* g_sig2, double* grad,
+                       double* grad_l, double* grad_s);
+
+/* Recompute lhat, sig2 and the cached gradients at the current (theta, u),
+ * after the caller has written the particle buffers directly. */
+smc_status smc_refresh(smc_ctx ctx);
+
+/* Host scalars of the run. */
+typedef struct smc_info {
+  double a;        /* current tempering exponent */
+  double logz;     /* accumulated log evidence estimate */
+  int32_t stage;   /* current stage p */
+  int32_t move;    /* moves done in this stage */
+  int32_t have_mass;
+  int32_t newton_iters;
+} smc_info;
+smc_status smc_get_info(smc_ctx ctx, smc_info* out);
+
+/* Overwrite the stage counters (checkpoint resume, tests). */
+smc_status smc_set_stage(smc_ctx ctx, int32_t stage, int32_t move, double a, double logz);
+
+/* Host d*d covariance -> device Sigma, factor and inverse factor. */
+smc_status smc_set_mass(smc_ctx ctx, const double* sigma_host);
+
+/* Host copies of Sigma, its lower Cholesky factor and its inverse (nullable). */
+smc_status smc_get_mass(smc_ctx ctx, double* sigma, double* chol, double* chol_inv);
+
+/* Host copies of theta_bar (d), A (1), B (d), C (d*d) (nullable). */
+smc_status smc_get_cv(smc_ctx ctx, double* theta_bar, double* A, double* B, double* C);
+
+/* Full-data log-likelihood, gradient and Hessian at a host theta (FP64,
+ * host outputs, nullable). Synchronises. */
+smc_status smc_full_loglik(smc_ctx ctx, const double* theta, double* A, double* B, double* C);
+
+/* Release the context (device buffers stay with the caller). */
+void smc_destroy(smc_ctx ctx);
+
+const char* smc_status_string(smc_status s);
+const char* smc_last_error(smc_ctx ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SUBSMC_H */

@@ -89,7 +89,7 @@ def lib():
         L.orc_move_range.argtypes = [C.POINTER(_Data), C.POINTER(_CV), C.POINTER(_MoveCfg), C.c_double,
                                      C.c_double, C.c_int32, C.c_uint32, C.c_int32, C.c_int32,
                                      C.POINTER(C.c_double), C.POINTER(C.c_int32), C.POINTER(C.c_int32),
-                                     C.POINTER(C.c_double), C.POINTER(C.c_double)]
+                                     C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_double)]
         L.orc_num_threads.restype = C.c_int
         _lib = L
     return _lib
@@ -244,8 +244,12 @@ def init_particles(M, d, m, n, seed, mu0, Q0):
     return theta, u, logw
 
 
-def move(prob, theta, u, a, eps, L, seed, stage, mv, G, Sigma, Lchol, i0=0):
-    """One Markov move (Algorithm 1) of particles i0, i0+1, ... held in theta/u (rows)."""
+def move(prob, theta, u, a, eps, L, seed, stage, mv, G, Sigma, Lchol, i0=0, diag=False):
+    """One Markov move (Algorithm 1) of particles i0, i0+1, ... held in theta/u (rows).
+
+    With diag=True also returns (count, 4): log r and log U of the u-refresh
+    and of the HMC accept step.
+    """
     theta = np.array(theta, dtype=np.float64, order="C")
     u = np.array(u, dtype=np.int32, order="C")
     cnt, m = u.shape
@@ -255,10 +259,14 @@ def move(prob, theta, u, a, eps, L, seed, stage, mv, G, Sigma, Lchol, i0=0):
     Sigma = np.ascontiguousarray(Sigma, dtype=np.float64)
     Lchol = np.ascontiguousarray(Lchol, dtype=np.float64)
     cfg = _MoveCfg(cnt, m, int(G), int(seed), int(stage), _dp(prob.mu0), _dp(prob.Q0), _dp(Sigma), _dp(Lchol))
+    dg = np.zeros((cnt, 4)) if diag else None
     st = lib().orc_move_range(C.byref(prob._data), C.byref(prob._cv), C.byref(cfg), float(a), float(eps),
-                              int(L), int(mv), int(i0), cnt, _dp(theta), _ip(u), _ip(acc), _dp(lhat), _dp(sig2))
+                              int(L), int(mv), int(i0), cnt, _dp(theta), _ip(u), _ip(acc), _dp(lhat), _dp(sig2),
+                              _dp(dg) if diag else C.POINTER(C.c_double)())
     if st != 0:
         raise RuntimeError(f"oracle move failed: {st}")
+    if diag:
+        return theta, u, acc, lhat, sig2, dg
     return theta, u, acc, lhat, sig2
 
 

@@ -703,7 +703,7 @@ static double kinetic(int d, const double *Sigma, const double *p)
 
 static void move_one(const orc_data *D, const orc_cv *cv, const orc_move_cfg *K, double a,
                      double eps, int32_t L, uint32_t mv, int32_t i, double *theta, int32_t *u,
-                     int32_t *acc_u, int32_t *acc_th, double *lhat_out, double *sig2_out)
+                     int32_t *acc_u, int32_t *acc_th, double *lhat_out, double *sig2_out, double *diag)
 {
     const int d = D->d;
     const int32_t m = K->m, G = K->G;
@@ -723,6 +723,7 @@ static void move_one(const orc_data *D, const orc_cv *cv, const orc_move_cfg *K,
     double logr_u = lambda_of(a, &e_new) - lambda_of(a, &e_cur);
     double logU = log(rng_uniform_open0(orc_rng_word(seed, 5, st, mv, 0, (uint64_t)i, 0)));
     *acc_u = (isfinite(logr_u) && logU < logr_u) ? 1 : 0;
+    if (diag) { diag[0] = logr_u; diag[1] = logU; }
     if (*acc_u) memcpy(u, ustar, sizeof(int32_t) * (size_t)m);
     free(ustar);
 
@@ -751,6 +752,7 @@ static void move_one(const orc_data *D, const orc_cv *cv, const orc_move_cfg *K,
     double logr = H0 - H1;
     double logU2 = log(rng_uniform_open0(orc_rng_word(seed, 7, st, mv, 0, (uint64_t)i, 0)));
     *acc_th = (isfinite(logr) && logU2 < logr) ? 1 : 0;
+    if (diag) { diag[2] = logr; diag[3] = logU2; }
     if (*acc_th) {
         for (int r = 0; r < d; ++r) theta[r] = th1[r];
         *lhat_out = e1.lhat;
@@ -774,22 +776,25 @@ int orc_move(const orc_data *D, const orc_cv *cv, const orc_move_cfg *K, double 
 #pragma omp parallel for schedule(dynamic, 1)
     for (int32_t i = 0; i < K->M; ++i) {
         move_one(D, cv, K, a, eps, L, mv, i, theta + (size_t)i * D->d, u + (size_t)i * K->m,
-                 &acc[2 * i], &acc[2 * i + 1], &lhat[i], &sig2[i]);
+                 &acc[2 * i], &acc[2 * i + 1], &lhat[i], &sig2[i], NULL);
     }
     return ORC_OK;
 }
 
-/* Move a subset of particles [i0, i0+count), for bounded CPU timing. */
+/*
+ * Move a subset of particles [i0, i0+count) (bounded CPU timing, tests).
+ * diag (count*4, nullable): log r and log U of the u-refresh and of the HMC step.
+ */
 int orc_move_range(const orc_data *D, const orc_cv *cv, const orc_move_cfg *K, double a,
                    double eps, int32_t L, uint32_t mv, int32_t i0, int32_t count, double *theta,
-                   int32_t *u, int32_t *acc, double *lhat, double *sig2)
+                   int32_t *u, int32_t *acc, double *lhat, double *sig2, double *diag)
 {
     if (D->d > 512) return ORC_ERR_ARG;
 #pragma omp parallel for schedule(dynamic, 1)
     for (int32_t t = 0; t < count; ++t) {
         int32_t i = i0 + t;
         move_one(D, cv, K, a, eps, L, mv, i, theta + (size_t)t * D->d, u + (size_t)t * K->m,
-                 &acc[2 * t], &acc[2 * t + 1], &lhat[t], &sig2[t]);
+                 &acc[2 * t], &acc[2 * t + 1], &lhat[t], &sig2[t], diag ? diag + 4 * (size_t)t : NULL);
     }
     return ORC_OK;
 }

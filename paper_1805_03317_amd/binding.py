@@ -1,0 +1,288 @@
+"""ctypes binding of libsubsmc.so (include/subsmc.h): argument marshalling only.
+
+PyTorch provides device memory and the stream; every step of the method runs
+in the HIP library. Loading fails loudly when the library has not been built.
+"""
+import ctypes as C
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsubsmc.so")
+
+LOGISTIC, POISSON, GAUSSIAN = 0, 1, 2
+FP64, MIXED = 0, 1
+STATUS = {0: "ok", 1: "invalid argument", 2: "call out of order", 3: "device error",
+          4: "matrix not positive definite", 5: "non-finite weights", 6: "unsupported"}
+
+
+class _Problem(C.Structure):
+    _fields_ = [
+        ("family", C.c_int32), ("precision", C.c_int32), ("cv_order", C.c_int32), ("d", C.c_int32),
+        ("n", C.c_int64), ("ld", C.c_int32), ("xy_fp32", C.c_int32), ("Xy", C.c_void_p),
+        ("gauss_s2", C.c_double), ("M", C.c_int32), ("m", C.c_int32), ("G", C.c_int32),
+        ("n_bisect", C.c_int32), ("seed", C.c_uint64), ("ess_frac", C.c_double),
+        ("prior_mean", C.c_void_p), ("prior_prec", C.c_void_p), ("theta_bar", C.c_void_p),
+        ("theta", C.c_void_p), ("u", C.c_void_p), ("logw", C.c_void_p), ("lhat", C.c_void_p),
+        ("sig2", C.c_void_p), ("accept", C.c_void_p), ("workspace", C.c_void_p),
+        ("workspace_bytes", C.c_size_t),
+    ]
+
+
+class _Info(C.Structure):
+    _fields_ = [("a", C.c_double), ("logz", C.c_double), ("stage", C.c_int32), ("move", C.c_int32),
+                ("have_mass", C.c_int32), ("newton_iters", C.c_int32)]
+
+
+EXPORTS = [
+    "smc_workspace_size", "smc_init", "smc_temper", "smc_mass", "smc_resample", "smc_move",
+    "loglik_est", "loglik_grad", "smc_refresh", "smc_get_info", "smc_set_stage", "smc_set_mass",
+    "smc_get_mass", "smc_get_cv", "smc_full_loglik", "smc_destroy", "smc_status_string",
+    "smc_last_error",
+]
+
+_lib = None
+
+
+def lib():
+    """Load libsubsmc.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_1805_03317_amd.build` "
+                           "(or __graft_entry__.build()); there is no fallback path")
+    L = C.CDLL(LIB_PATH)
+    vp, i32, dbl = C.c_void_p, C.c_int32, C.c_double
+    L.smc_workspace_size.restype = C.c_size_t
+    L.smc_workspace_size.argtypes = [C.POINTER(_Problem)]
+    L.smc_init.argtypes = [C.POINTER(_Problem), vp, C.POINTER(vp)]
+    L.smc_temper.argtypes = [vp, C.POINTER(dbl), C.POINTER(dbl), C.POINTER(dbl)]
+    L.smc_mass.argtypes = [vp]
+    L.smc_resample.argtypes = [vp]
+    L.smc_move.argtypes = [vp, dbl, i32, i32]
+    L.loglik_est.argtypes = [vp, i32, vp, vp, vp, vp, vp]
+    L.loglik_grad.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp]
+    L.smc_refresh.argtypes = [vp]
+    L.smc_get_info.argtypes = [vp, C.POINTER(_Info)]
+    L.smc_set_stage.argtypes = [vp, i32, i32, dbl, dbl]
+    L.smc_set_mass.argtypes = [vp, vp]
+    L.smc_get_mass.argtypes = [vp, vp, vp, vp]
+    L.smc_get_cv.argtypes = [vp, vp, vp, vp, vp]
+    L.smc_full_loglik.argtypes = [vp, vp, vp, vp, vp]
+    L.smc_destroy.argtypes = [vp]
+    L.smc_destroy.restype = None
+    L.smc_status_string.restype = C.c_char_p
+    L.smc_status_string.argtypes = [C.c_int]
+    L.smc_last_error.restype = C.c_char_p
+    L.smc_last_error.argtypes = [vp]
+    for name in EXPORTS:
+        if name not in ("smc_workspace_size", "smc_destroy", "smc_status_string", "smc_last_error"):
+            getattr(L, name).restype = C.c_int
+    _lib = L
+    return L
+
+
+class SMCError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _host_ptr(a):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+class SubsampledSMC:
+    """One Subsampling SMC run (Algorithm 2) on one GPU.
+
+    Xy: device tensor (n, ld) float64 or float32 with rows [x_k | y_k | ...].
+    Particle buffers are torch tensors owned here and filled by the library.
+    """
+
+    def __init__(self, Xy, d, family, precision, M, m, G, prior_mean, prior_prec, seed,
+                 ess_frac=0.5, cv_order=2, theta_bar=None, gauss_s2=1.0, n_bisect=60):
+        import numpy as np
+
+        L = lib()
+        assert Xy.is_cuda and Xy.dim() == 2 and Xy.is_contiguous()
+        self.device = Xy.device
+        self.Xy = Xy
+        self.d, self.M, self.m, self.G = int(d), int(M), int(m), int(G)
+        self.n = int(Xy.shape[0])
+        dev = self.device
+        self.theta = torch.zeros((M, d), dtype=torch.float64, device=dev)
+        self.u = torch.zeros((M, m), dtype=torch.int32, device=dev)
+        self.logw = torch.zeros(M, dtype=torch.float64, device=dev)
+        self.lhat = torch.zeros(M, dtype=torch.float64, device=dev)
+        self.sig2 = torch.zeros(M, dtype=torch.float64, device=dev)
+        self.accept = torch.zeros((M, 2), dtype=torch.int32, device=dev)
+        self._mu0 = np.ascontiguousarray(prior_mean, dtype=np.float64)
+        self._Q0 = np.ascontiguousarray(prior_prec, dtype=np.float64)
+        self._tb = None if theta_bar is None else np.ascontiguousarray(theta_bar, dtype=np.float64)
+        pb = _Problem()
+        pb.family, pb.precision, pb.cv_order, pb.d = int(family), int(precision), int(cv_order), self.d
+        pb.n, pb.ld = self.n, int(Xy.shape[1])
+        pb.xy_fp32 = 1 if Xy.dtype == torch.float32 else 0
+        pb.Xy = Xy.data_ptr()
+        pb.gauss_s2 = float(gauss_s2)
+        pb.M, pb.m, pb.G, pb.n_bisect = self.M, self.m, self.G, int(n_bisect)
+        pb.seed, pb.ess_frac = int(seed), float(ess_frac)
+        pb.prior_mean = self._mu0.ctypes.data
+        pb.prior_prec = self._Q0.ctypes.data
+        pb.theta_bar = None if self._tb is None else self._tb.ctypes.data
+        pb.theta, pb.u, pb.logw = self.theta.data_ptr(), self.u.data_ptr(), self.logw.data_ptr()
+        pb.lhat, pb.sig2, pb.accept = self.lhat.data_ptr(), self.sig2.data_ptr(), self.accept.data_ptr()
+        pb.workspace = 1
+        nbytes = L.smc_workspace_size(C.byref(pb))
+        if nbytes == 0:
+            raise SMCError(1, "invalid problem (smc_workspace_size returned 0)")
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
+        base = self.workspace.data_ptr()
+        pb.workspace = (base + 255) & ~255
+        pb.workspace_bytes = nbytes
+        self._pb = pb
+        self.stream = torch.cuda.current_stream(dev)
+        h = C.c_void_p()
+        st = L.smc_init(C.byref(pb), C.c_void_p(self.stream.cuda_stream), C.byref(h))
+        self._h = h
+        if st != 0:
+            msg = L.smc_last_error(h).decode() if h.value else ""
+            raise SMCError(st, msg)
+
+    # -- lifecycle ----------------------------------------------------------
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().smc_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st):
+        if st != 0:
+            raise SMCError(st, lib().smc_last_error(self._h).decode())
+
+    # -- the stage of Algorithm 2 ---------------------------------------------
+    def temper(self):
+        a, dz, ess = C.c_double(), C.c_double(), C.c_double()
+        self._check(lib().smc_temper(self._h, C.byref(a), C.byref(dz), C.byref(ess)))
+        return a.value, dz.value, ess.value
+
+    def mass(self):
+        self._check(lib().smc_mass(self._h))
+
+    def resample(self):
+        self._check(lib().smc_resample(self._h))
+
+    def move(self, eps, L, R=1):
+        self._check(lib().smc_move(self._h, float(eps), int(L), int(R)))
+
+    def refresh(self):
+        self._check(lib().smc_refresh(self._h))
+
+    # -- estimator entry points -------------------------------------------------
+    def loglik_est(self, theta, u):
+        theta = theta.contiguous()
+        u = u.contiguous()
+        cnt = theta.shape[0]
+        lh = torch.empty(cnt, dtype=torch.float64, device=self.device)
+        s2 = torch.empty_like(lh)
+        dh = torch.empty_like(lh)
+        self._check(lib().loglik_est(self._h, cnt, _ptr(theta), _ptr(u), _ptr(lh), _ptr(s2), _ptr(dh)))
+        return lh, s2, dh
+
+    def loglik_grad(self, theta, u, g_lhat=None, g_sig2=None, separate=False):
+        theta = theta.contiguous()
+        u = u.contiguous()
+        cnt = theta.shape[0]
+        grad = torch.empty((cnt, self.d), dtype=torch.float64, device=self.device)
+        gl = torch.empty_like(grad) if separate else None
+        gs = torch.empty_like(grad) if separate else None
+        gl_in = None if g_lhat is None else g_lhat.to(torch.float64).contiguous()
+        gs_in = None if g_sig2 is None else g_sig2.to(torch.float64).contiguous()
+        self._check(lib().loglik_grad(self._h, cnt, _ptr(theta), _ptr(u), _ptr(gl_in), _ptr(gs_in),
+                                      _ptr(grad), _ptr(gl), _ptr(gs)))
+        return (grad, gl, gs) if separate else grad
+
+    # -- state access -----------------------------------------------------------
+    def info(self):
+        o = _Info()
+        self._check(lib().smc_get_info(self._h, C.byref(o)))
+        return {"a": o.a, "logz": o.logz, "stage": o.stage, "move": o.move, "have_mass": o.have_mass,
+                "newton_iters": o.newton_iters}
+
+    def set_stage(self, stage, move, a, logz=0.0):
+        self._check(lib().smc_set_stage(self._h, int(stage), int(move), float(a), float(logz)))
+
+    def set_mass(self, Sigma):
+        import numpy as np
+        S = np.ascontiguousarray(Sigma, dtype=np.float64)
+        self._check(lib().smc_set_mass(self._h, _host_ptr(S)))
+
+    def get_mass(self):
+        import numpy as np
+        d = self.d
+        S, Lc, Li = np.zeros((d, d)), np.zeros((d, d)), np.zeros((d, d))
+        self._check(lib().smc_get_mass(self._h, _host_ptr(S), _host_ptr(Lc), _host_ptr(Li)))
+        return S, Lc, Li
+
+    def get_cv(self):
+        import numpy as np
+        d = self.d
+        tb, A, B, Cm = np.zeros(d), np.zeros(1), np.zeros(d), np.zeros((d, d))
+        self._check(lib().smc_get_cv(self._h, _host_ptr(tb), _host_ptr(A), _host_ptr(B), _host_ptr(Cm)))
+        return tb, float(A[0]), B, Cm
+
+    def full_loglik(self, theta):
+        import numpy as np
+        d = self.d
+        th = np.ascontiguousarray(theta, dtype=np.float64)
+        A, B, Cm = np.zeros(1), np.zeros(d), np.zeros((d, d))
+        self._check(lib().smc_full_loglik(self._h, _host_ptr(th), _host_ptr(A), _host_ptr(B), _host_ptr(Cm)))
+        return float(A[0]), B, Cm
+
+    # -- a full run ---------------------------------------------------------------
+    def run(self, eps_fn, L, R, max_stages=100000, callback=None):
+        """Algorithm 2 until a = 1; returns log Z and the per-stage record."""
+        rec = []
+        a = self.info()["a"]
+        while a < 1.0 and len(rec) < max_stages:
+            a, dz, ess = self.temper()
+            self.mass()
+            self.resample()
+            eps = eps_fn(len(rec) + 1, a, self.d)
+            self.move(eps, L, R)
+            rec.append({"a": a, "dlogz": dz, "ess": ess, "eps": eps})
+            if callback:
+                callback(self, rec[-1])
+        return self.info()["logz"], rec
+
+
+class LogLikEstimate(torch.autograd.Function):
+    """(l_hat, sigma2_hat) per particle with the hand-written HIP backward."""
+
+    @staticmethod
+    def forward(ctx, theta, u, smc):
+        lh, s2, _ = smc.loglik_est(theta.detach(), u)
+        ctx.save_for_backward(theta.detach(), u)
+        ctx.smc = smc
+        return lh, s2
+
+    @staticmethod
+    def backward(ctx, g_lhat, g_sig2):
+        theta, u = ctx.saved_tensors
+        grad = ctx.smc.loglik_grad(theta, u, g_lhat, g_sig2)
+        return grad, None, None
+
+
+def loglik(theta, u, smc):
+    return LogLikEstimate.apply(theta, u, smc)

@@ -1,0 +1,232 @@
+// Per-observation control-variate remainder d = l_k - q_k and its derivative
+// d' with respect to the linear predictor (section 3.2: q_k is the Taylor
+// expansion of l_k around theta_bar; gradient of d_k is d' x_k).
+//
+// Everything is evaluated from the per-row constants stored next to x_k:
+//   eta_bar = x_k' theta_bar and aux = sigmoid(-|eta_bar|) (logistic) or
+//   exp(eta_bar) (Poisson), plus Delta = x_k' (theta - theta_bar).
+// The remainder is O(Delta^3) while l_k is O(1), so it is never formed as a
+// difference of the two: each family uses an expansion whose terms are of the
+// size of the result.
+//
+// Logistic, l(eta) = y eta - softplus(eta): the y terms cancel exactly and
+//   d = -R, d' = -R' with R the second-order Taylor remainder of softplus.
+//   softplus(x) = x + softplus(-x), so R(eta_bar, Delta) = R(-eta_bar, -Delta)
+//   and the evaluation always runs with s = sigmoid(eta_bar) <= 1/2.
+//   softplus(eta_bar + t) - softplus(eta_bar) = log(1 - s + s e^t) is the
+//   cumulant generating function of a Bernoulli(s) variable, so for small
+//   |Delta| R = sum_{k>=3} kappa_k Delta^k / k! with the Bernoulli cumulants
+//   kappa_k = v P_k(v) (k even) or v (1-2s) P_k(v) (k odd), v = s(1-s), from
+//   the recursion kappa_{k+1} = v d(kappa_k)/ds.
+//   Medium |Delta| uses R = L3(z) + s E3 - s^2 Delta E2 - s^2 E2^2 / 2 with
+//   z = s expm1(Delta), E2 = e^D - 1 - D, E3 = E2 - D^2/2, L3(z) = log1p(z) - z + z^2/2;
+//   large |Delta| uses the softplus difference directly.
+// Poisson, l = y eta - e^eta - log y!: d = -e^{eta_bar} E3(Delta),
+//   d' = -e^{eta_bar} E2(Delta).
+// Gaussian (known variance, test family): d = d' = 0 exactly.
+// First-order control variate (cv_order 1): the dropped f'' Delta^2 / 2 term
+// is added back: d1 = d2 + f''(eta_bar) Delta^2 / 2, d1' = d2' + f''(eta_bar) Delta.
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace subsmc {
+
+enum Family : int { kLogistic = 0, kPoisson = 1, kGaussian = 2 };
+
+template <typename T> struct Tol;
+template <> struct Tol<double> {
+  static constexpr double series_logistic = 0.25;  // |Delta| below: cumulant series
+  static constexpr double direct_logistic = 2.0;   // |Delta| above: softplus difference
+  static constexpr double series_exp = 0.5;         // |Delta| below: exp series for E2/E3
+  static constexpr int n_cumulant = 14;
+  static constexpr int n_exp = 16;
+};
+template <> struct Tol<float> {
+  static constexpr float series_logistic = 0.25f;
+  static constexpr float direct_logistic = 2.0f;
+  static constexpr float series_exp = 0.5f;
+  static constexpr int n_cumulant = 10;
+  static constexpr int n_exp = 10;
+};
+
+__device__ __forceinline__ double dev_expm1(double x) { return expm1(x); }
+__device__ __forceinline__ float dev_expm1(float x) { return expm1f(x); }
+__device__ __forceinline__ double dev_log1p(double x) { return log1p(x); }
+__device__ __forceinline__ float dev_log1p(float x) { return log1pf(x); }
+__device__ __forceinline__ double dev_exp(double x) { return exp(x); }
+__device__ __forceinline__ float dev_exp(float x) { return expf(x); }
+
+template <typename T>
+__device__ __forceinline__ T softplus(T x) {
+  const T ax = x < T(0) ? -x : x;
+  return (x > T(0) ? x : T(0)) + dev_log1p(dev_exp(-ax));
+}
+
+template <typename T>
+__device__ __forceinline__ T sigmoid(T x) {
+  if (x >= T(0)) return T(1) / (T(1) + dev_exp(-x));
+  const T e = dev_exp(x);
+  return e / (T(1) + e);
+}
+
+// Bernoulli cumulant kappa_k(s) divided by k! and by (k-1)!, k = 3..14.
+// Coefficients of P_k(v) (ascending powers of v).
+template <typename T>
+__device__ __forceinline__ T cumulant(int k, T v, T w) {
+  T p;
+  switch (k) {
+    case 3: p = T(1); break;
+    case 4: p = T(1) + v * T(-6); break;
+    case 5: p = T(1) + v * T(-12); break;
+    case 6: p = T(1) + v * (T(-30) + v * T(120)); break;
+    case 7: p = T(1) + v * (T(-60) + v * T(360)); break;
+    case 8: p = T(1) + v * (T(-126) + v * (T(1680) + v * T(-5040))); break;
+    case 9: p = T(1) + v * (T(-252) + v * (T(5040) + v * T(-20160))); break;
+    case 10: p = T(1) + v * (T(-510) + v * (T(17640) + v * (T(-151200) + v * T(362880)))); break;
+    case 11: p = T(1) + v * (T(-1020) + v * (T(52920) + v * (T(-604800) + v * T(1814400)))); break;
+    case 12:
+      p = T(1) + v * (T(-2046) + v * (T(168960) + v * (T(-3160080) + v * (T(19958400) + v * T(-39916800)))));
+      break;
+    case 13:
+      p = T(1) + v * (T(-4092) + v * (T(506880) + v * (T(-12640320) + v * (T(99792000) + v * T(-239500800)))));
+      break;
+    default:
+      p = T(1) + v * (T(-8190) + v * (T(1561560) + v * (T(-57657600) +
+              v * (T(726485760) + v * (T(-3632428800.0) + v * T(6227020800.0))))));
+      break;
+  }
+  return (k & 1) ? v * w * p : v * p;
+}
+
+// 1/k! for k = 0..16
+template <typename T>
+__device__ __forceinline__ T inv_fact(int k) {
+  switch (k) {
+    case 0: case 1: return T(1);
+    case 2: return T(0.5);
+    case 3: return T(1.0 / 6.0);
+    case 4: return T(1.0 / 24.0);
+    case 5: return T(1.0 / 120.0);
+    case 6: return T(1.0 / 720.0);
+    case 7: return T(1.0 / 5040.0);
+    case 8: return T(1.0 / 40320.0);
+    case 9: return T(1.0 / 362880.0);
+    case 10: return T(1.0 / 3628800.0);
+    case 11: return T(1.0 / 39916800.0);
+    case 12: return T(1.0 / 479001600.0);
+    case 13: return T(1.0 / 6227020800.0);
+    case 14: return T(1.0 / 87178291200.0);
+    case 15: return T(1.0 / 1307674368000.0);
+    default: return T(1.0 / 20922789888000.0);
+  }
+}
+
+// E2 = e^D - 1 - D and E3 = e^D - 1 - D - D^2/2
+template <typename T>
+__device__ __forceinline__ void exp_remainders(T D, T& E2, T& E3) {
+  const T aD = D < T(0) ? -D : D;
+  if (aD < Tol<T>::series_exp) {
+    T acc = T(0);
+#pragma unroll
+    for (int k = Tol<T>::n_exp; k >= 3; --k) acc = acc * D + inv_fact<T>(k);
+    E3 = acc * D * D * D;
+    E2 = E3 + T(0.5) * D * D;
+  } else {
+    const T em1 = dev_expm1(D);
+    E2 = em1 - D;
+    E3 = E2 - T(0.5) * D * D;
+  }
+}
+
+// Second-order Taylor remainder of softplus at eta_bar <= 0 (s = sigmoid(eta_bar)).
+template <typename T>
+__device__ __forceinline__ void softplus_remainder(T eb, T s, T D, T& R, T& Rp) {
+  const T sc = T(1) - s;
+  const T v = s * sc;
+  const T w = sc - s;
+  const T aD = D < T(0) ? -D : D;
+  if (aD < Tol<T>::series_logistic) {
+    T r = T(0), rp = T(0);
+#pragma unroll
+    for (int k = Tol<T>::n_cumulant; k >= 3; --k) {
+      const T c = cumulant<T>(k, v, w);
+      r = r * D + c * inv_fact<T>(k);
+      rp = rp * D + c * inv_fact<T>(k - 1);
+    }
+    R = r * D * D * D;
+    Rp = rp * D * D;
+  } else if (aD <= Tol<T>::direct_logistic) {
+    const T em1 = dev_expm1(D);
+    const T E2 = em1 - D;
+    const T E3 = E2 - T(0.5) * D * D;
+    const T z = s * em1;
+    const T L3 = dev_log1p(z) - z + T(0.5) * z * z;
+    R = L3 + s * E3 - s * s * D * E2 - T(0.5) * s * s * E2 * E2;
+    Rp = v * (T(0.5) * w * D * D + E3 - s * D * E2) / (T(1) + z);
+  } else {
+    const T sp0 = -dev_log1p(-s);  // softplus(eb) for eb <= 0
+    R = (softplus<T>(eb + D) - sp0) - s * D - T(0.5) * v * D * D;
+    Rp = (sigmoid<T>(eb + D) - s) - v * D;
+  }
+}
+
+// Returns d (remainder) and dp (its eta-derivative).
+template <typename T>
+__device__ __forceinline__ void cv_remainder(int family, int cv_order, T eb, T aux, T D, T inv_s2,
+                                             T& d, T& dp) {
+  if (family == kLogistic) {
+    const bool flip = eb > T(0);
+    const T e = flip ? -eb : eb;
+    const T Dm = flip ? -D : D;
+    T R, Rp;
+    softplus_remainder<T>(e, aux, Dm, R, Rp);
+    d = -R;
+    dp = flip ? Rp : -Rp;
+    if (cv_order == 1) {
+      const T v = aux * (T(1) - aux);
+      d -= T(0.5) * v * D * D;
+      dp -= v * D;
+    }
+  } else if (family == kPoisson) {
+    T E2, E3;
+    exp_remainders<T>(D, E2, E3);
+    d = -aux * E3;
+    dp = -aux * E2;
+    if (cv_order == 1) {
+      d -= T(0.5) * aux * D * D;
+      dp -= aux * D;
+    }
+  } else {
+    d = T(0);
+    dp = T(0);
+    if (cv_order == 1) {
+      d = -T(0.5) * inv_s2 * D * D;
+      dp = -inv_s2 * D;
+    }
+  }
+}
+
+// Full-data log-density and its first two eta-derivatives (FP64), for the
+// control-variate summaries A, B, C.
+__device__ __forceinline__ void loglik_derivs(int family, double y, double eta, double inv_s2,
+                                              double log2pis2, double& f0, double& f1, double& f2) {
+  if (family == kLogistic) {
+    const double s = sigmoid<double>(eta);
+    const double sn = sigmoid<double>(-eta);
+    f0 = y * eta - softplus<double>(eta);
+    f1 = y - s;
+    f2 = -s * sn;
+  } else if (family == kPoisson) {
+    const double mu = exp(eta);
+    f0 = y * eta - mu - lgamma(y + 1.0);
+    f1 = y - mu;
+    f2 = -mu;
+  } else {
+    const double r = y - eta;
+    f0 = -0.5 * log2pis2 - 0.5 * r * r * inv_s2;
+    f1 = r * inv_s2;
+    f2 = -inv_s2;
+  }
+}
+
+}  // namespace subsmc

@@ -1,0 +1,982 @@
+// Device kernels of the Subsampling SMC hot path (gfx950, wave64).
+//
+// Particle work maps one wavefront to one particle: the wave owns the
+// particle's theta, momentum and caches (component c in lane c, d <= 64) and
+// streams its m subsample rows, 64 rows at a time, one row per lane. Every
+// reduction is a fixed-order butterfly across the 64 lanes (all lanes end
+// with bitwise-identical sums), so decisions are wave-uniform and runs are
+// bitwise reproducible.
+//
+// Packed data row (Real = double for the FP64 path, float for mixed):
+//   [eta_bar, aux, y, 0, x_0 .. x_{d-1}, 0 ...], pitch ld (a multiple of 64 B)
+// with eta_bar = x' theta_bar and aux = sigmoid(-|eta_bar|) (logistic) or
+// exp(eta_bar) (Poisson), both computed in FP64 once per run.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "glm.hpp"
+#include "rng.hpp"
+
+namespace subsmc {
+
+constexpr int kWave = 64;
+constexpr int kHeader = 4;  // eta_bar, aux, y, pad
+
+// --------------------------------------------------------------------------
+// wave-level helpers
+// --------------------------------------------------------------------------
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, kWave);
+  return v;
+}
+
+__device__ __forceinline__ double readlane_d(double v, int l) {
+  const unsigned long long b = __double_as_longlong(v);
+  const unsigned lo = __builtin_amdgcn_readlane((unsigned)(b & 0xffffffffu), l);
+  const unsigned hi = __builtin_amdgcn_readlane((unsigned)(b >> 32), l);
+  return __longlong_as_double(((unsigned long long)hi << 32) | lo);
+}
+
+template <int DC>
+__device__ __forceinline__ double pick_lane(const double (&a)[DC], int lane) {
+  double r = 0.0;
+#pragma unroll
+  for (int c = 0; c < DC; ++c) r = (lane == c) ? a[c] : r;
+  return r;
+}
+
+// --------------------------------------------------------------------------
+// problem description handed to kernels
+// --------------------------------------------------------------------------
+
+struct Prob {
+  int family, cv_order, d, ld;
+  int64_t n;
+  int M, m, G;
+  uint64_t seed;
+  double inv_s2, log2pis2;
+  double n_over_m;
+  const void* X;            // packed rows
+  const double* theta_bar;  // d
+  const double* cvA;        // 1
+  const double* cvB;        // d
+  const double* cvC;        // d*d
+  const double* mu0;        // d
+  const double* Q0;         // d*d
+  const double* Sigma;      // d*d
+  const double* Linv;       // d*d, inverse of the lower Cholesky factor of Sigma
+};
+
+template <typename Real, int DC>
+struct RowLoad {
+  Real eb, aux;
+  Real x[DC];
+};
+
+template <typename Real, int DC>
+__device__ __forceinline__ void load_row(const Real* __restrict__ row, RowLoad<Real, DC>& r) {
+  if constexpr (sizeof(Real) == 4) {
+    const float2 h = *reinterpret_cast<const float2*>(row);
+    r.eb = h.x;
+    r.aux = h.y;
+    const float4* xv = reinterpret_cast<const float4*>(row + kHeader);
+#pragma unroll
+    for (int q = 0; q < DC / 4; ++q) {
+      const float4 t = xv[q];
+      r.x[4 * q + 0] = t.x; r.x[4 * q + 1] = t.y; r.x[4 * q + 2] = t.z; r.x[4 * q + 3] = t.w;
+    }
+  } else {
+    const double2 h = *reinterpret_cast<const double2*>(row);
+    r.eb = h.x;
+    r.aux = h.y;
+    const double2* xv = reinterpret_cast<const double2*>(row + kHeader);
+#pragma unroll
+    for (int q = 0; q < DC / 2; ++q) {
+      const double2 t = xv[q];
+      r.x[2 * q + 0] = t.x; r.x[2 * q + 1] = t.y;
+    }
+  }
+}
+
+// Result of one estimator pass for one particle (wave-uniform scalars; the
+// gradient components live in lane c).
+struct PassResult {
+  double lhat, sig2, dhat;
+  double gl, gs;  // lane c: component c of grad l_hat and grad sigma2_hat
+};
+
+// Index of slot j: the stored subsample, or a fresh draw inside [b0, b1).
+__device__ __forceinline__ int32_t slot_index(const int32_t* __restrict__ urow, int j, int b0, int b1,
+                                              uint64_t seed, uint64_t ctr0, uint64_t particle, int64_t n) {
+  if (j >= b0 && j < b1) return (int32_t)word_to_index(stream_word(seed, ctr0, particle, (uint64_t)(j - b0)), (uint64_t)n);
+  return urow[j];
+}
+
+// One pass of the difference estimator (eq. difference_estimator_logl), its
+// variance estimate (section 3.2) and both gradients at theta = theta_bar + delta,
+// for the subsample urow (with block [b0,b1) replaced by fresh draws when b1 > b0).
+//   l_hat   = A + B'delta + delta'C delta/2 + (n/m) sum_j d_j
+//   s2_hat  = (n/m)^2 sum_j (d_j - dbar)^2
+//   grad l  = B + C delta + (n/m) sum_j d'_j x_j
+//   grad s2 = 2 (n/m)^2 sum_j (d_j - dbar) d'_j x_j
+// The d_j sums are taken about the shift d_{u_0} (evaluated first by every
+// lane) to keep the single-pass variance accurate.
+template <typename Real, int DC>
+__device__ __forceinline__ PassResult estimator_pass(const Prob& P, const int32_t* __restrict__ urow,
+                                                     int b0, int b1, uint64_t ctr0, uint64_t particle,
+                                                     double delta64, int lane) {
+  const Real* __restrict__ X = static_cast<const Real*>(P.X);
+  const int m = P.m;
+  const int ld = P.ld;
+  const Real inv_s2 = (Real)P.inv_s2;
+
+  Real dl[DC];
+#pragma unroll
+  for (int c = 0; c < DC; ++c) dl[c] = (Real)readlane_d(delta64, c);
+
+  // shift: the remainder at slot 0, evaluated redundantly by every lane
+  double shift;
+  {
+    const int32_t k0 = slot_index(urow, 0, b0, b1, P.seed, ctr0, particle, P.n);
+    const bool bad = (uint32_t)k0 >= (uint32_t)P.n;  // caller index out of range: poison, never read
+    RowLoad<Real, DC> r;
+    load_row<Real, DC>(X + (int64_t)(bad ? 0 : k0) * ld, r);
+    Real D = Real(0);
+#pragma unroll
+    for (int c = 0; c < DC; ++c) D += r.x[c] * dl[c];
+    Real dd, dp;
+    cv_remainder<Real>(P.family, P.cv_order, r.eb, r.aux, D, inv_s2, dd, dp);
+    shift = bad ? __builtin_nan("") : (double)dd;
+  }
+
+  double se = 0.0, se2 = 0.0;
+  Real S1[DC], T1[DC];
+#pragma unroll
+  for (int c = 0; c < DC; ++c) { S1[c] = Real(0); T1[c] = Real(0); }
+
+  for (int j = lane; j < m; j += kWave) {
+    const int32_t k = slot_index(urow, j, b0, b1, P.seed, ctr0, particle, P.n);
+    const bool bad = (uint32_t)k >= (uint32_t)P.n;
+    RowLoad<Real, DC> r;
+    load_row<Real, DC>(X + (int64_t)(bad ? 0 : k) * ld, r);
+    Real D = Real(0);
+#pragma unroll
+    for (int c = 0; c < DC; ++c) D += r.x[c] * dl[c];
+    Real dd, dp;
+    cv_remainder<Real>(P.family, P.cv_order, r.eb, r.aux, D, inv_s2, dd, dp);
+    if (bad) dd = dp = Real(__builtin_nan(""));
+    const double e = (double)dd - shift;
+    se += e;
+    se2 += e * e;
+    const Real edp = (Real)e * dp;
+#pragma unroll
+    for (int c = 0; c < DC; ++c) {
+      S1[c] += dp * r.x[c];
+      T1[c] += edp * r.x[c];
+    }
+  }
+
+  // fixed-order butterfly reductions
+  se = wave_sum(se);
+  se2 = wave_sum(se2);
+  double s1[DC], t1[DC];
+#pragma unroll
+  for (int c = 0; c < DC; ++c) {
+    s1[c] = wave_sum((double)S1[c]);
+    t1[c] = wave_sum((double)T1[c]);
+  }
+
+  const double md = (double)m;
+  const double nm = P.n_over_m;
+  const double dsum = se + md * shift;
+  const double dbar_minus_shift = se / md;
+  const double m2 = se2 - se * dbar_minus_shift;  // sum (d - dbar)^2
+  PassResult out;
+  out.dhat = nm * dsum;
+  out.sig2 = nm * nm * (m2 < 0.0 ? 0.0 : m2);  // NaN propagates
+
+  // control-variate quadratic and its gradient, FP64
+  const int d = P.d;
+  double cdel = 0.0;
+  for (int e = 0; e < d; ++e) {
+    const double de = readlane_d(delta64, e);
+    cdel += (lane < d ? P.cvC[lane * d + e] : 0.0) * de;
+  }
+  const double bl = lane < d ? P.cvB[lane] : 0.0;
+  const double qpart = (P.cv_order == 2) ? (bl * delta64 + 0.5 * delta64 * cdel) : bl * delta64;
+  const double qsum = wave_sum(qpart);
+  out.lhat = P.cvA[0] + qsum + out.dhat;
+  const double s1c = pick_lane<DC>(s1, lane);
+  const double t1c = pick_lane<DC>(t1, lane);
+  out.gl = lane < d ? bl + (P.cv_order == 2 ? cdel : 0.0) + nm * s1c : 0.0;
+  out.gs = lane < d ? 2.0 * nm * nm * (t1c - dbar_minus_shift * s1c) : 0.0;
+  return out;
+}
+
+// --------------------------------------------------------------------------
+// estimator kernels (loglik_est / loglik_grad / cache refresh)
+// --------------------------------------------------------------------------
+
+struct EstArgs {
+  Prob P;
+  int count;
+  const double* theta;   // count*d
+  const int32_t* u;      // count*m
+  double* lhat;          // count (nullable)
+  double* sig2;          // count (nullable)
+  double* dhat;          // count (nullable)
+  double* grad_l;        // count*d (nullable)
+  double* grad_s;        // count*d (nullable)
+  const double* g_lhat;  // count (nullable): combined gradient g_l * grad l + g_s * grad s2
+  const double* g_sig2;  // count (nullable)
+  double* grad;          // count*d (nullable)
+};
+
+template <typename Real, int DC>
+__global__ void __launch_bounds__(kWave) estimator_kernel(EstArgs A) {
+  const int i = blockIdx.x;
+  const int lane = threadIdx.x;
+  if (i >= A.count) return;
+  const Prob& P = A.P;
+  const int d = P.d;
+  const double th = lane < d ? A.theta[(int64_t)i * d + lane] : 0.0;
+  const double tb = lane < d ? P.theta_bar[lane] : 0.0;
+  const PassResult r = estimator_pass<Real, DC>(P, A.u + (int64_t)i * P.m, 0, 0, 0, 0, th - tb, lane);
+  if (lane == 0) {
+    if (A.lhat) A.lhat[i] = r.lhat;
+    if (A.sig2) A.sig2[i] = r.sig2;
+    if (A.dhat) A.dhat[i] = r.dhat;
+  }
+  if (lane < d) {
+    if (A.grad_l) A.grad_l[(int64_t)i * d + lane] = r.gl;
+    if (A.grad_s) A.grad_s[(int64_t)i * d + lane] = r.gs;
+    if (A.grad) {
+      const double gl = A.g_lhat ? A.g_lhat[i] : 0.0;
+      const double gs = A.g_sig2 ? A.g_sig2[i] : 0.0;
+      A.grad[(int64_t)i * d + lane] = gl * r.gl + gs * r.gs;
+    }
+  }
+}
+
+// --------------------------------------------------------------------------
+// fused Markov move (Algorithm 1): block pseudo-marginal refresh of u, then
+// HMC on theta given u with inverse mass matrix Sigma; R = 1 per launch.
+// --------------------------------------------------------------------------
+
+struct MoveArgs {
+  Prob P;
+  double a, eps;
+  int L;
+  uint32_t stage, move;
+  double* theta;   // M*d
+  int32_t* u;      // M*m
+  double* lhat;    // M   cache at the current state
+  double* sig2;    // M
+  double* grad_l;  // M*d
+  double* grad_s;  // M*d
+  int32_t* accept; // M*2
+};
+
+template <int DC>
+__device__ __forceinline__ void prior_terms(const Prob& P, double th, int lane, double& r, double& lp) {
+  // r = (Q0 (theta - mu0))_lane, lp = -(theta-mu0)' Q0 (theta-mu0) / 2
+  const int d = P.d;
+  const double dm = lane < d ? th - P.mu0[lane] : 0.0;
+  double acc = 0.0;
+  for (int e = 0; e < d; ++e) {
+    const double x = readlane_d(dm, e);
+    acc += (lane < d ? P.Q0[lane * d + e] : 0.0) * x;
+  }
+  r = acc;
+  lp = wave_sum(-0.5 * dm * acc);
+}
+
+__device__ __forceinline__ double sigma_times(const Prob& P, double p, int lane) {
+  const int d = P.d;
+  double acc = 0.0;
+  for (int e = 0; e < d; ++e) {
+    const double x = readlane_d(p, e);
+    acc += (lane < d ? P.Sigma[lane * d + e] : 0.0) * x;
+  }
+  return acc;
+}
+
+template <typename Real, int DC>
+__global__ void __launch_bounds__(kWave) move_kernel(MoveArgs A) {
+  const int i = blockIdx.x;
+  const int lane = threadIdx.x;
+  const Prob& P = A.P;
+  if (i >= P.M) return;
+  const int d = P.d;
+  const int m = P.m;
+  const double a = A.a;
+  const double eps = A.eps;
+  int32_t* urow = A.u + (int64_t)i * m;
+
+  const double tb = lane < d ? P.theta_bar[lane] : 0.0;
+  double th = lane < d ? A.theta[(int64_t)i * d + lane] : 0.0;
+  double lh0 = A.lhat[i], sg0 = A.sig2[i];
+  double gl0 = lane < d ? A.grad_l[(int64_t)i * d + lane] : 0.0;
+  double gs0 = lane < d ? A.grad_s[(int64_t)i * d + lane] : 0.0;
+
+  // ---- 1. u | theta: one block, chosen uniformly, replaced by fresh indices
+  const uint64_t cg = stream_ctr0(kBlockChoice, A.stage, A.move, 0);
+  const int g = (int)word_to_index(stream_word(P.seed, cg, (uint64_t)i, 0), (uint64_t)P.G);
+  const int b0 = (int)((int64_t)g * m / P.G);
+  const int b1 = (int)((int64_t)(g + 1) * m / P.G);
+  const uint64_t cb = stream_ctr0(kBlockIndex, A.stage, A.move, 0);
+  int ob0 = 0, ob1 = 0;
+  {
+    const PassResult r = estimator_pass<Real, DC>(P, urow, b0, b1, cb, (uint64_t)i, th - tb, lane);
+    const double lam0 = a * lh0 - 0.5 * a * a * sg0;
+    const double lam1 = a * r.lhat - 0.5 * a * a * r.sig2;
+    const double logr = lam1 - lam0;
+    const double logU = log(word_to_uniform(stream_word(P.seed, stream_ctr0(kUAccept, A.stage, A.move, 0), (uint64_t)i, 0)));
+    const bool acc = isfinite(logr) && (logU < logr);
+    if (acc) {
+      for (int j = b0 + lane; j < b1; j += kWave)
+        urow[j] = (int32_t)word_to_index(stream_word(P.seed, cb, (uint64_t)i, (uint64_t)(j - b0)), (uint64_t)P.n);
+      lh0 = r.lhat; sg0 = r.sig2; gl0 = r.gl; gs0 = r.gs;
+      // later passes of this launch regenerate the new block instead of
+      // reading back the indices just stored
+      ob0 = b0; ob1 = b1;
+    }
+    if (lane == 0) A.accept[2 * i] = acc ? 1 : 0;
+  }
+
+  // ---- 2. theta | u: HMC
+  const uint64_t cm = stream_ctr0(kMomentum, A.stage, A.move, 0);
+  const double z = lane < d ? stream_normal(P.seed, cm, (uint64_t)i, (uint32_t)lane) : 0.0;
+  double p = 0.0;  // p = Linv' z, so p ~ N(0, Sigma^{-1})
+  for (int e = 0; e < d; ++e) {
+    const double ze = readlane_d(z, e);
+    p += (lane < d && e >= lane ? P.Linv[e * d + lane] : 0.0) * ze;
+  }
+  double v = sigma_times(P, p, lane);
+  const double K0 = 0.5 * wave_sum(p * v);
+  double rq, lp;
+  prior_terms<DC>(P, th, lane, rq, lp);
+  const double logpi0 = (a * lh0 - 0.5 * a * a * sg0) + lp;
+  const double H0 = -logpi0 + K0;
+  double grad = a * gl0 - 0.5 * a * a * gs0 - rq;
+  p += 0.5 * eps * grad;
+  double th1 = th;
+  PassResult r1;
+  r1.lhat = lh0; r1.sig2 = sg0; r1.gl = gl0; r1.gs = gs0; r1.dhat = 0.0;
+  double lp1 = lp;
+  for (int l = 1; l <= A.L; ++l) {
+    v = sigma_times(P, p, lane);
+    th1 += eps * v;
+    r1 = estimator_pass<Real, DC>(P, urow, ob0, ob1, cb, (uint64_t)i, th1 - tb, lane);
+    prior_terms<DC>(P, th1, lane, rq, lp1);
+    grad = a * r1.gl - 0.5 * a * a * r1.gs - rq;
+    p += ((l < A.L) ? eps : 0.5 * eps) * grad;
+  }
+  v = sigma_times(P, p, lane);
+  const double K1 = 0.5 * wave_sum(p * v);
+  const double logpi1 = (a * r1.lhat - 0.5 * a * a * r1.sig2) + lp1;
+  const double H1 = -logpi1 + K1;
+  const double logr = H0 - H1;
+  const double logU = log(word_to_uniform(stream_word(P.seed, stream_ctr0(kThetaAccept, A.stage, A.move, 0), (uint64_t)i, 0)));
+  const bool acc = isfinite(logr) && (logU < logr);
+  if (acc) {
+    th = th1; lh0 = r1.lhat; sg0 = r1.sig2; gl0 = r1.gl; gs0 = r1.gs;
+  }
+  if (lane < d) {
+    A.theta[(int64_t)i * d + lane] = th;
+    A.grad_l[(int64_t)i * d + lane] = gl0;
+    A.grad_s[(int64_t)i * d + lane] = gs0;
+  }
+  if (lane == 0) {
+    A.lhat[i] = lh0;
+    A.sig2[i] = sg0;
+    A.accept[2 * i + 1] = acc ? 1 : 0;
+  }
+}
+
+// --------------------------------------------------------------------------
+// initial particles (Algorithm 2 step 1)
+// --------------------------------------------------------------------------
+
+struct InitArgs {
+  Prob P;
+  const double* L0inv;  // inverse of the lower Cholesky factor of the prior precision
+  double* theta;
+  int32_t* u;
+  double* logw;
+};
+
+__global__ void __launch_bounds__(kWave) init_kernel(InitArgs A) {
+  const int i = blockIdx.x;
+  const int lane = threadIdx.x;
+  const Prob& P = A.P;
+  if (i >= P.M) return;
+  const int d = P.d;
+  const uint64_t c0 = stream_ctr0(kPriorNormal, 0, 0, 0);
+  const double z = lane < d ? stream_normal(P.seed, c0, (uint64_t)i, (uint32_t)lane) : 0.0;
+  double x = 0.0;  // theta - mu0 = L0^{-T} z
+  for (int e = 0; e < d; ++e) {
+    const double ze = readlane_d(z, e);
+    x += (lane < d && e >= lane ? A.L0inv[e * d + lane] : 0.0) * ze;
+  }
+  if (lane < d) A.theta[(int64_t)i * d + lane] = P.mu0[lane] + x;
+  const uint64_t c1 = stream_ctr0(kInitIndex, 0, 0, 0);
+  int32_t* urow = A.u + (int64_t)i * P.m;
+  for (int j = lane; j < P.m; j += kWave)
+    urow[j] = (int32_t)word_to_index(stream_word(P.seed, c1, (uint64_t)i, (uint64_t)j), (uint64_t)P.n);
+  if (lane == 0) A.logw[i] = -log((double)P.M);
+}
+
+// --------------------------------------------------------------------------
+// block-level helpers (multi-wave kernels)
+// --------------------------------------------------------------------------
+
+template <int NT>
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  v = wave_sum(v);
+  const int w = threadIdx.x / kWave, l = threadIdx.x % kWave;
+  __syncthreads();
+  if (l == 0) sh[w] = v;
+  __syncthreads();
+  double t = 0.0;
+#pragma unroll
+  for (int k = 0; k < NT / kWave; ++k) t += sh[k];
+  return t;
+}
+
+template <int NT>
+__device__ __forceinline__ double block_max(double v, double* sh) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o, kWave));
+  const int w = threadIdx.x / kWave, l = threadIdx.x % kWave;
+  __syncthreads();
+  if (l == 0) sh[w] = v;
+  __syncthreads();
+  double t = -INFINITY;
+#pragma unroll
+  for (int k = 0; k < NT / kWave; ++k) t = fmax(t, sh[k]);
+  return t;
+}
+
+// --------------------------------------------------------------------------
+// tempering: ESS bisection, reweighting and evidence increment
+// (sections 2.2, 3.3 and 3.5; Algorithm 2 steps b-c)
+// --------------------------------------------------------------------------
+
+constexpr int kTemperThreads = 1024;
+constexpr int kTemperPer = 8;  // particles per thread: M <= 8192
+
+struct TemperArgs {
+  int M;
+  double a_prev, ess_frac;
+  int n_bisect;
+  const double* lhat;
+  const double* sig2;
+  double* logw;     // in/out
+  double* out;      // [a, dlogz, ess, status]
+};
+
+__device__ __forceinline__ double incr_weight(double a, double a_prev, double lh, double s2) {
+  const double v = (a - a_prev) * (lh - 0.5 * (a + a_prev) * s2);
+  return isfinite(v) ? v : -INFINITY;
+}
+
+__global__ void __launch_bounds__(kTemperThreads) temper_kernel(TemperArgs A) {
+  __shared__ double sh[kTemperThreads / kWave];
+  const int t = threadIdx.x;
+  double lw[kTemperPer], lh[kTemperPer], s2[kTemperPer];
+#pragma unroll
+  for (int q = 0; q < kTemperPer; ++q) {
+    const int i = t + q * kTemperThreads;
+    const bool ok = i < A.M;
+    lw[q] = ok ? A.logw[i] : -INFINITY;
+    lh[q] = ok ? A.lhat[i] : 0.0;
+    s2[q] = ok ? A.sig2[i] : 0.0;
+  }
+  auto ess_at = [&](double a) -> double {
+    double mx = -INFINITY;
+#pragma unroll
+    for (int q = 0; q < kTemperPer; ++q) mx = fmax(mx, lw[q] + incr_weight(a, A.a_prev, lh[q], s2[q]));
+    mx = block_max<kTemperThreads>(mx, sh);
+    if (!isfinite(mx)) return 0.0;
+    double w1 = 0.0, w2 = 0.0;
+#pragma unroll
+    for (int q = 0; q < kTemperPer; ++q) {
+      const double w = exp(lw[q] + incr_weight(a, A.a_prev, lh[q], s2[q]) - mx);
+      w1 += w;
+      w2 += w * w;
+    }
+    w1 = block_sum<kTemperThreads>(w1, sh);
+    w2 = block_sum<kTemperThreads>(w2, sh);
+    return w1 * w1 / w2;
+  };
+  const double target = A.ess_frac * (double)A.M;
+  double a;
+  if (ess_at(1.0) >= target) {
+    a = 1.0;
+  } else {
+    double lo = A.a_prev, hi = 1.0;
+    for (int it = 0; it < A.n_bisect; ++it) {
+      const double mid = 0.5 * (lo + hi);
+      if (ess_at(mid) >= target) lo = mid;
+      else hi = mid;
+    }
+    a = (lo > A.a_prev) ? lo : hi;
+  }
+  const double ess = ess_at(a);
+  // log-sum-exp of old and new log weights
+  double mo = -INFINITY, mn = -INFINITY;
+  double nw[kTemperPer];
+#pragma unroll
+  for (int q = 0; q < kTemperPer; ++q) {
+    nw[q] = lw[q] + incr_weight(a, A.a_prev, lh[q], s2[q]);
+    mo = fmax(mo, lw[q]);
+    mn = fmax(mn, nw[q]);
+  }
+  mo = block_max<kTemperThreads>(mo, sh);
+  mn = block_max<kTemperThreads>(mn, sh);
+  double so = 0.0, sn = 0.0;
+#pragma unroll
+  for (int q = 0; q < kTemperPer; ++q) {
+    so += exp(lw[q] - mo);
+    sn += exp(nw[q] - mn);
+  }
+  so = block_sum<kTemperThreads>(so, sh);
+  sn = block_sum<kTemperThreads>(sn, sh);
+  const double lse_old = mo + log(so);
+  const double lse_new = mn + log(sn);
+  const bool ok = isfinite(lse_new);
+#pragma unroll
+  for (int q = 0; q < kTemperPer; ++q) {
+    const int i = t + q * kTemperThreads;
+    if (i < A.M && ok) A.logw[i] = nw[q] - lse_new;
+  }
+  if (t == 0) {
+    A.out[0] = a;
+    A.out[1] = lse_new - lse_old;
+    A.out[2] = ess;
+    A.out[3] = ok ? 0.0 : 1.0;
+  }
+}
+
+// --------------------------------------------------------------------------
+// mass matrix: weighted particle covariance, Cholesky factor and its inverse
+// (Algorithm 2 step d). One workgroup; the matrix lives in global scratch.
+// --------------------------------------------------------------------------
+
+constexpr int kMomThreads = 256;
+
+struct FactorArgs {
+  int d;
+  double* S;      // d*d in: symmetric positive definite (jitter may be added in place)
+  double* L;      // d*d out: lower Cholesky factor
+  double* Linv;   // d*d out: inverse of L (lower)
+  double* status; // 1: 0 ok, 1 not positive definite
+};
+
+// Cholesky with a jitter ladder (1e-10 * mean diagonal * 10^t, t = 0..9) and
+// the inverse factor by column-wise forward substitution.
+__device__ void factor_spd(const FactorArgs& F, double* sh) {
+  const int d = F.d;
+  const int t = threadIdx.x;
+  double tr = 0.0;
+  for (int r = 0; r < d; ++r) tr += F.S[r * d + r];
+  bool ok = false;
+  for (int att = 0; att <= 10 && !ok; ++att) {
+    if (att > 0) {
+      const double jit = 1e-10 * (tr / d) * pow(10.0, (double)(att - 1));
+      // restart from S + jit*I: S is kept pristine, jitter accumulates only in L's input copy
+      for (int e = t; e < d * d; e += kMomThreads) {
+        const int r = e / d, c = e % d;
+        F.L[e] = F.S[e] + (r == c ? jit : 0.0);
+      }
+    } else {
+      for (int e = t; e < d * d; e += kMomThreads) F.L[e] = F.S[e];
+    }
+    __syncthreads();
+    // right-looking Cholesky in place on F.L (lower part)
+    bool good = true;
+    for (int j = 0; j < d; ++j) {
+      const double ljj2 = F.L[j * d + j];
+      good = good && (ljj2 > 0.0);
+      if (!good) break;
+      const double ljj = sqrt(ljj2);
+      __syncthreads();
+      for (int i2 = j + 1 + t; i2 < d; i2 += kMomThreads) F.L[i2 * d + j] /= ljj;
+      __syncthreads();
+      for (int e = t; e < (d - j - 1) * (d - j - 1); e += kMomThreads) {
+        const int r = j + 1 + e / (d - j - 1), c = j + 1 + e % (d - j - 1);
+        if (c <= r) F.L[r * d + c] -= F.L[r * d + j] * F.L[c * d + j];
+      }
+      __syncthreads();
+      if (t == 0) F.L[j * d + j] = ljj;
+      __syncthreads();
+    }
+    ok = good;
+    __syncthreads();
+    if (ok && att > 0) {
+      const double jit = 1e-10 * (tr / d) * pow(10.0, (double)(att - 1));
+      for (int r = t; r < d; r += kMomThreads) F.S[r * d + r] += jit;
+    }
+    __syncthreads();
+  }
+  // zero the strict upper triangle
+  for (int e = t; e < d * d; e += kMomThreads) {
+    const int r = e / d, c = e % d;
+    if (c > r) F.L[e] = 0.0;
+  }
+  __syncthreads();
+  // inverse: column c of L^{-1} solves L x = e_c
+  for (int c = t; c < d; c += kMomThreads) {
+    for (int r = 0; r < d; ++r) {
+      double s = (r == c) ? 1.0 : 0.0;
+      if (r < c) { F.Linv[r * d + c] = 0.0; continue; }
+      for (int k = c; k < r; ++k) s -= F.L[r * d + k] * F.Linv[k * d + c];
+      F.Linv[r * d + c] = s / F.L[r * d + r];
+    }
+  }
+  if (t == 0) F.status[0] = ok ? 0.0 : 1.0;
+  (void)sh;
+}
+
+__global__ void __launch_bounds__(kMomThreads) factor_kernel(FactorArgs F) {
+  __shared__ double sh[kMomThreads / kWave];
+  factor_spd(F, sh);
+}
+
+struct MomentArgs {
+  int M, d;
+  const double* theta;
+  const double* logw;
+  double* mean;   // d
+  FactorArgs F;   // F.S receives the covariance
+};
+
+__global__ void __launch_bounds__(kMomThreads) moments_kernel(MomentArgs A) {
+  __shared__ double sh[kMomThreads / kWave];
+  const int t = threadIdx.x;
+  const int M = A.M, d = A.d;
+  double mx = -INFINITY;
+  for (int i = t; i < M; i += kMomThreads) mx = fmax(mx, A.logw[i]);
+  mx = block_max<kMomThreads>(mx, sh);
+  double s = 0.0;
+  for (int i = t; i < M; i += kMomThreads) s += exp(A.logw[i] - mx);
+  s = block_sum<kMomThreads>(s, sh);
+  const double lse = mx + log(s);
+  for (int r = t; r < d; r += kMomThreads) {
+    double acc = 0.0;
+    for (int i = 0; i < M; ++i) acc += exp(A.logw[i] - lse) * A.theta[(int64_t)i * d + r];
+    A.mean[r] = acc;
+  }
+  __syncthreads();
+  const int ne = d * (d + 1) / 2;
+  for (int e = t; e < ne; e += kMomThreads) {
+    // e -> (r, c) with c <= r
+    int r = (int)((sqrt(8.0 * e + 1.0) - 1.0) * 0.5);
+    while ((r + 1) * (r + 2) / 2 <= e) ++r;
+    while (r * (r + 1) / 2 > e) --r;
+    const int c = e - r * (r + 1) / 2;
+    const double mr = A.mean[r], mc = A.mean[c];
+    double acc = 0.0;
+    for (int i = 0; i < M; ++i)
+      acc += exp(A.logw[i] - lse) * (A.theta[(int64_t)i * d + r] - mr) * (A.theta[(int64_t)i * d + c] - mc);
+    A.F.S[r * d + c] = acc;
+    A.F.S[c * d + r] = acc;
+  }
+  __syncthreads();
+  factor_spd(A.F, sh);
+}
+
+// --------------------------------------------------------------------------
+// systematic resampling in exact integer arithmetic
+// --------------------------------------------------------------------------
+
+constexpr int kResThreads = 1024;
+constexpr int kResPer = 8;  // M <= 8192
+
+struct ResampleArgs {
+  int M;
+  uint64_t seed;
+  uint32_t stage;
+  const double* logw;
+  int32_t* anc;
+};
+
+// floor(X / M) for X = hi:lo (X < 2^72 after the 2^32 split), M < 2^31
+__device__ __forceinline__ uint64_t div_u96_by_u32(uint64_t hi32, uint64_t lo64, uint32_t M) {
+  // X = hi32 * 2^64 + lo64 with hi32 < 2^32
+  uint64_t r = 0, q2, q1, q0;
+  uint64_t cur = hi32;
+  q2 = cur / M; r = cur % M;
+  cur = (r << 32) | (lo64 >> 32);
+  q1 = cur / M; r = cur % M;
+  cur = (r << 32) | (lo64 & 0xffffffffull);
+  q0 = cur / M;
+  (void)q2;  // zero by construction (quotient < 2^64)
+  return (q1 << 32) + q0;
+}
+
+__global__ void __launch_bounds__(kResThreads) resample_kernel(ResampleArgs A) {
+  __shared__ double sh[kResThreads / kWave];
+  __shared__ unsigned long long cum[kResThreads * kResPer];
+  __shared__ unsigned long long wsum[kResThreads / kWave];
+  const int t = threadIdx.x;
+  const int M = A.M;
+  double mx = -INFINITY;
+  for (int i = t; i < M; i += kResThreads) mx = fmax(mx, A.logw[i]);
+  mx = block_max<kResThreads>(mx, sh);
+  // each thread owns a contiguous run of kResPer particles
+  unsigned long long c[kResPer];
+  unsigned long long run = 0;
+#pragma unroll
+  for (int q = 0; q < kResPer; ++q) {
+    const int i = t * kResPer + q;
+    unsigned long long ci = 0;
+    if (i < M) {
+      const double w = exp(A.logw[i] - mx);
+      ci = (unsigned long long)floor(ldexp(w, 48));
+    }
+    run += ci;
+    c[q] = run;
+  }
+  // exclusive scan of per-thread totals: wave scan then across waves
+  const int l = t % kWave, w = t / kWave;
+  unsigned long long incl = run;
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    const unsigned long long y = __shfl_up(incl, o, kWave);
+    if (l >= o) incl += y;
+  }
+  if (l == kWave - 1) wsum[w] = incl;
+  __syncthreads();
+  unsigned long long base = 0;
+  for (int k = 0; k < w; ++k) base += wsum[k];
+  const unsigned long long excl = base + incl - run;
+#pragma unroll
+  for (int q = 0; q < kResPer; ++q) cum[t * kResPer + q] = excl + c[q];
+  __syncthreads();
+  const unsigned long long S = cum[M - 1];
+  const uint32_t U32 = (uint32_t)(stream_word(A.seed, stream_ctr0(kResampleOffset, A.stage, 0, 0), 0, 0) >> 32);
+  for (int k = t; k < M; k += kResThreads) {
+    // t_k = floor((k 2^32 + U32) S / (M 2^32)) = floor(floor(P / 2^32) / M)
+    const uint64_t a = ((uint64_t)k << 32) + U32;
+    const uint64_t plo = a * (uint64_t)S, phi = __umul64hi(a, (uint64_t)S);
+    const uint64_t shi = phi >> 32;
+    const uint64_t slo = (phi << 32) | (plo >> 32);
+    const uint64_t tk = div_u96_by_u32(shi, slo, (uint32_t)M);
+    // smallest j with cum[j] > tk
+    int lo = 0, hi = M - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (cum[mid] > tk) hi = mid;
+      else lo = mid + 1;
+    }
+    A.anc[k] = lo;
+  }
+}
+
+struct GatherArgs {
+  int M, d, m;
+  const int32_t* anc;
+  const double* theta; const int32_t* u; const double* lhat; const double* sig2;
+  const double* gl; const double* gs;
+  double* theta2; int32_t* u2; double* lhat2; double* sig22; double* gl2; double* gs2;
+};
+
+// dst row k <- src row anc[k]; blockIdx.x = k, the u row copied with 16-byte moves
+__global__ void __launch_bounds__(256) gather_kernel(GatherArgs A) {
+  const int k = blockIdx.x;
+  const int t = threadIdx.x;
+  const int s = A.anc[k];
+  const int d = A.d, m = A.m;
+  for (int c = t; c < d; c += 256) {
+    A.theta2[(int64_t)k * d + c] = A.theta[(int64_t)s * d + c];
+    A.gl2[(int64_t)k * d + c] = A.gl[(int64_t)s * d + c];
+    A.gs2[(int64_t)k * d + c] = A.gs[(int64_t)s * d + c];
+  }
+  if (t == 0) {
+    A.lhat2[k] = A.lhat[s];
+    A.sig22[k] = A.sig2[s];
+  }
+  const int32_t* src = A.u + (int64_t)s * m;
+  int32_t* dst = A.u2 + (int64_t)k * m;
+  if ((m & 3) == 0) {
+    const int4* s4 = reinterpret_cast<const int4*>(src);
+    int4* d4 = reinterpret_cast<int4*>(dst);
+    for (int j = t; j < m / 4; j += 256) d4[j] = s4[j];
+  } else {
+    for (int j = t; j < m; j += 256) dst[j] = src[j];
+  }
+}
+
+struct CopyBackArgs {
+  int M, d, m;
+  const double* theta2; const int32_t* u2; const double* lhat2; const double* sig22;
+  const double* gl2; const double* gs2;
+  double* theta; int32_t* u; double* lhat; double* sig2; double* gl; double* gs; double* logw;
+};
+
+__global__ void __launch_bounds__(256) copyback_kernel(CopyBackArgs A) {
+  const int k = blockIdx.x;
+  const int t = threadIdx.x;
+  const int d = A.d, m = A.m;
+  for (int c = t; c < d; c += 256) {
+    A.theta[(int64_t)k * d + c] = A.theta2[(int64_t)k * d + c];
+    A.gl[(int64_t)k * d + c] = A.gl2[(int64_t)k * d + c];
+    A.gs[(int64_t)k * d + c] = A.gs2[(int64_t)k * d + c];
+  }
+  if (t == 0) {
+    A.lhat[k] = A.lhat2[k];
+    A.sig2[k] = A.sig22[k];
+    A.logw[k] = -log((double)A.M);
+  }
+  const int32_t* src = A.u2 + (int64_t)k * m;
+  int32_t* dst = A.u + (int64_t)k * m;
+  if ((m & 3) == 0) {
+    const int4* s4 = reinterpret_cast<const int4*>(src);
+    int4* d4 = reinterpret_cast<int4*>(dst);
+    for (int j = t; j < m / 4; j += 256) d4[j] = s4[j];
+  } else {
+    for (int j = t; j < m; j += 256) dst[j] = src[j];
+  }
+}
+
+// --------------------------------------------------------------------------
+// full-data control-variate summaries A, B, C at theta (section 3.2) and the
+// packed rows; FP64 throughout. Each block reduces its tiles of rows into one
+// partial vector [A, B (d), C upper triangle]; a second kernel sums the
+// partials in block order.
+// --------------------------------------------------------------------------
+
+constexpr int kCvThreads = 256;
+constexpr int kCvTile = 64;   // rows per tile
+constexpr int kCvMaxD = 128;
+
+struct CvArgs {
+  int family, d, ld_in, ld_out, in_fp32, out_fp32;
+  int64_t n;
+  double inv_s2, log2pis2;
+  const void* Xin;      // caller rows [x (d) | y | ...], pitch ld_in
+  const double* theta;  // d
+  void* Xout;           // packed rows or nullptr
+  double* partials;     // gridDim.x * (1 + d + d(d+1)/2)
+};
+
+__global__ void __launch_bounds__(kCvThreads) cv_kernel(CvArgs A) {
+  extern __shared__ double tile[];  // kCvTile * (d + 3)
+  const int t = threadIdx.x;
+  const int d = A.d;
+  const int stride = d + 3;
+  const int ne = 1 + d + d * (d + 1) / 2;
+  constexpr int kMaxPer = (1 + kCvMaxD + kCvMaxD * (kCvMaxD + 1) / 2 + kCvThreads - 1) / kCvThreads;
+  double acc[kMaxPer];
+#pragma unroll
+  for (int q = 0; q < kMaxPer; ++q) acc[q] = 0.0;
+  const int64_t ntiles = (A.n + kCvTile - 1) / kCvTile;
+  for (int64_t tl = blockIdx.x; tl < ntiles; tl += gridDim.x) {
+    const int64_t r0 = tl * kCvTile;
+    // phase 1: one thread per row computes eta, f0, f1, f2 and the packed row
+    if (t < kCvTile) {
+      const int64_t k = r0 + t;
+      double* trow = tile + t * stride;
+      if (k < A.n) {
+        double eta = 0.0, y;
+        if (A.in_fp32) {
+          const float* row = static_cast<const float*>(A.Xin) + k * A.ld_in;
+          for (int c = 0; c < d; ++c) { trow[3 + c] = row[c]; eta += (double)row[c] * A.theta[c]; }
+          y = row[d];
+        } else {
+          const double* row = static_cast<const double*>(A.Xin) + k * A.ld_in;
+          for (int c = 0; c < d; ++c) { trow[3 + c] = row[c]; eta += row[c] * A.theta[c]; }
+          y = row[d];
+        }
+        double f0, f1, f2;
+        loglik_derivs(A.family, y, eta, A.inv_s2, A.log2pis2, f0, f1, f2);
+        trow[0] = f0; trow[1] = f1; trow[2] = f2;
+        if (A.Xout) {
+          double aux = 0.0;
+          if (A.family == kLogistic) aux = sigmoid<double>(-fabs(eta));
+          else if (A.family == kPoisson) aux = exp(eta);
+          if (A.out_fp32) {
+            float* o = static_cast<float*>(A.Xout) + k * A.ld_out;
+            o[0] = (float)eta; o[1] = (float)aux; o[2] = (float)y; o[3] = 0.f;
+            for (int c = 0; c < d; ++c) o[kHeader + c] = (float)trow[3 + c];
+            for (int c = kHeader + d; c < A.ld_out; ++c) o[c] = 0.f;
+          } else {
+            double* o = static_cast<double*>(A.Xout) + k * A.ld_out;
+            o[0] = eta; o[1] = aux; o[2] = y; o[3] = 0.0;
+            for (int c = 0; c < d; ++c) o[kHeader + c] = trow[3 + c];
+            for (int c = kHeader + d; c < A.ld_out; ++c) o[c] = 0.0;
+          }
+        }
+      } else {
+        for (int c = 0; c < stride; ++c) trow[c] = 0.0;
+      }
+    }
+    __syncthreads();
+    // phase 2: thread owns entries e = t, t + 256, ...
+    const int rows = (int)((A.n - r0) < kCvTile ? (A.n - r0) : kCvTile);
+#pragma unroll
+    for (int q = 0; q < kMaxPer; ++q) {
+      const int e = t + q * kCvThreads;
+      if (e >= ne) break;
+      double s = 0.0;
+      if (e == 0) {
+        for (int rr = 0; rr < rows; ++rr) s += tile[rr * stride + 0];
+      } else if (e <= d) {
+        const int c = e - 1;
+        for (int rr = 0; rr < rows; ++rr) s += tile[rr * stride + 1] * tile[rr * stride + 3 + c];
+      } else {
+        const int f = e - 1 - d;  // f -> (r, c), c <= r
+        int r = (int)((sqrt(8.0 * f + 1.0) - 1.0) * 0.5);
+        while ((r + 1) * (r + 2) / 2 <= f) ++r;
+        while (r * (r + 1) / 2 > f) --r;
+        const int c = f - r * (r + 1) / 2;
+        for (int rr = 0; rr < rows; ++rr)
+          s += tile[rr * stride + 2] * tile[rr * stride + 3 + r] * tile[rr * stride + 3 + c];
+      }
+      acc[q] += s;
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int q = 0; q < kMaxPer; ++q) {
+    const int e = t + q * kCvThreads;
+    if (e < ne) A.partials[(int64_t)blockIdx.x * ne + e] = acc[q];
+  }
+}
+
+struct CvReduceArgs {
+  int nblocks, d;
+  const double* partials;
+  double* A;  // 1
+  double* B;  // d
+  double* C;  // d*d
+};
+
+__global__ void __launch_bounds__(256) cv_reduce_kernel(CvReduceArgs R) {
+  const int d = R.d;
+  const int ne = 1 + d + d * (d + 1) / 2;
+  for (int e = blockIdx.x * 256 + threadIdx.x; e < ne; e += gridDim.x * 256) {
+    double s = 0.0;
+    for (int b = 0; b < R.nblocks; ++b) s += R.partials[(int64_t)b * ne + e];
+    if (e == 0) {
+      R.A[0] = s;
+    } else if (e <= d) {
+      R.B[e - 1] = s;
+    } else {
+      const int f = e - 1 - d;
+      int r = (int)((sqrt(8.0 * f + 1.0) - 1.0) * 0.5);
+      while ((r + 1) * (r + 2) / 2 <= f) ++r;
+      while (r * (r + 1) / 2 > f) --r;
+      const int c = f - r * (r + 1) / 2;
+      R.C[r * d + c] = s;
+      R.C[c * d + r] = s;
+    }
+  }
+}
+
+}  // namespace subsmc

@@ -1,0 +1,682 @@
+// Host side of the C ABI declared in include/subsmc.h: workspace layout,
+// argument checks, kernel dispatch and the Newton iteration for the
+// control-variate centre.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/subsmc.h"
+#include "kernels.hpp"
+
+using namespace subsmc;
+
+namespace {
+
+constexpr int kMaxD = 32;
+constexpr int kMaxM = kTemperThreads * kTemperPer;
+constexpr int kCvMaxBlocks = 1024;
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+int pad_dc(int d) { return (d + 3) & ~3; }
+
+int packed_ld(int d, bool fp32) {
+  const int per64 = fp32 ? 16 : 8;
+  const int need = kHeader + pad_dc(d);
+  return (need + per64 - 1) / per64 * per64;
+}
+
+// Workspace regions, in carve order.
+struct Layout {
+  size_t Xp, theta_bar, cvA, cvB, cvC, mu0, Q0, Qw, L0, L0inv, Sigma, Lchol, Linv, mean, status,
+      tout, scratch_theta, grad_l, grad_s, anc, th2, u2, lh2, sg2, gl2, gs2, partials, total;
+  int ld;
+  int cv_blocks;
+};
+
+bool compute_layout(const smc_problem* pb, Layout& L) {
+  const bool fp32 = pb->precision == SMC_MIXED;
+  const size_t es = fp32 ? 4 : 8;
+  const int d = pb->d;
+  const size_t M = pb->M, m = pb->m, n = (size_t)pb->n;
+  L.ld = packed_ld(d, fp32);
+  const int64_t ntiles = (pb->n + kCvTile - 1) / kCvTile;
+  L.cv_blocks = (int)(ntiles < kCvMaxBlocks ? ntiles : kCvMaxBlocks);
+  const size_t ne = 1 + d + (size_t)d * (d + 1) / 2;
+  size_t off = 0;
+  auto take = [&](size_t bytes) { const size_t o = off; off = align256(off + bytes); return o; };
+  const size_t dd = (size_t)d * d * 8;
+  L.Xp = take(n * L.ld * es);
+  L.theta_bar = take(d * 8);
+  L.cvA = take(8);
+  L.cvB = take(d * 8);
+  L.cvC = take(dd);
+  L.mu0 = take(d * 8);
+  L.Q0 = take(dd);
+  L.Qw = take(dd);
+  L.L0 = take(dd);
+  L.L0inv = take(dd);
+  L.Sigma = take(dd);
+  L.Lchol = take(dd);
+  L.Linv = take(dd);
+  L.mean = take(d * 8);
+  L.status = take(4 * 8);
+  L.tout = take(4 * 8);
+  L.scratch_theta = take(d * 8);
+  L.grad_l = take(M * d * 8);
+  L.grad_s = take(M * d * 8);
+  L.anc = take(M * 4);
+  L.th2 = take(M * d * 8);
+  L.u2 = take(M * m * 4);
+  L.lh2 = take(M * 8);
+  L.sg2 = take(M * 8);
+  L.gl2 = take(M * d * 8);
+  L.gs2 = take(M * d * 8);
+  L.partials = take((size_t)L.cv_blocks * ne * 8);
+  L.total = off;
+  return true;
+}
+
+}  // namespace
+
+struct smc_ctx_s {
+  smc_problem pb;
+  hipStream_t stream = nullptr;
+  Layout lay;
+  char* ws = nullptr;
+  Prob prob;
+  double a = 0.0, logz = 0.0;
+  int stage = 0, move = 0, have_mass = 0, newton_iters = 0;
+  std::vector<double> mu0, Q0;
+  char err[512] = {0};
+
+  template <typename T> T* at(size_t off) { return reinterpret_cast<T*>(ws + off); }
+};
+
+namespace {
+
+smc_status fail(smc_ctx c, smc_status s, const char* fmt, ...) {
+  if (c) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(c->err, sizeof(c->err), fmt, ap);
+    va_end(ap);
+  }
+  return s;
+}
+
+#define HIP_TRY(ctx, expr)                                                                      \
+  do {                                                                                          \
+    hipError_t e_ = (expr);                                                                     \
+    if (e_ != hipSuccess)                                                                       \
+      return fail(ctx, SMC_ERR_DEVICE, "%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_),   \
+                  __FILE__, __LINE__);                                                          \
+  } while (0)
+
+#define LAUNCH_CHECK(ctx) HIP_TRY(ctx, hipGetLastError())
+
+smc_status validate(const smc_problem* pb) {
+  if (!pb) return SMC_ERR_INVALID_ARG;
+  if (pb->family < 0 || pb->family > 2) return SMC_ERR_INVALID_ARG;
+  if (pb->precision != SMC_FP64 && pb->precision != SMC_MIXED) return SMC_ERR_INVALID_ARG;
+  if (pb->cv_order != 1 && pb->cv_order != 2) return SMC_ERR_INVALID_ARG;
+  if (pb->d < 1 || pb->n < 1 || pb->n >= (int64_t(1) << 31)) return SMC_ERR_INVALID_ARG;
+  if (pb->ld < pb->d + 1 || !pb->Xy) return SMC_ERR_INVALID_ARG;
+  if (pb->M < 1 || pb->M > kMaxM || pb->m < 1 || pb->G < 1 || pb->G > pb->m) return SMC_ERR_INVALID_ARG;
+  if (!(pb->ess_frac > 0.0 && pb->ess_frac <= 1.0) || pb->n_bisect < 1 || pb->n_bisect > 200)
+    return SMC_ERR_INVALID_ARG;
+  if (!pb->prior_mean || !pb->prior_prec) return SMC_ERR_INVALID_ARG;
+  if (!pb->theta || !pb->u || !pb->logw || !pb->lhat || !pb->sig2 || !pb->accept || !pb->workspace)
+    return SMC_ERR_INVALID_ARG;
+  if (pb->family == SMC_GAUSSIAN && !(pb->gauss_s2 > 0.0)) return SMC_ERR_INVALID_ARG;
+  if (pb->d > kMaxD) return SMC_ERR_UNSUPPORTED;
+  return SMC_OK;
+}
+
+// ------------------------------------------------------------------------
+// kernel dispatch on (precision, padded d)
+// ------------------------------------------------------------------------
+
+template <typename Real>
+hipError_t launch_estimator_t(int dc, int count, const EstArgs& a, hipStream_t s) {
+  switch (dc) {
+#define CASE(DC) case DC: hipLaunchKernelGGL((estimator_kernel<Real, DC>), dim3(count), dim3(kWave), 0, s, a); break;
+    CASE(4) CASE(8) CASE(12) CASE(16) CASE(20) CASE(24) CASE(28) CASE(32)
+#undef CASE
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <typename Real>
+hipError_t launch_move_t(int dc, int M, const MoveArgs& a, hipStream_t s) {
+  switch (dc) {
+#define CASE(DC) case DC: hipLaunchKernelGGL((move_kernel<Real, DC>), dim3(M), dim3(kWave), 0, s, a); break;
+    CASE(4) CASE(8) CASE(12) CASE(16) CASE(20) CASE(24) CASE(28) CASE(32)
+#undef CASE
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_estimator(smc_ctx c, int count, const EstArgs& a) {
+  if (count <= 0) return hipSuccess;
+  const int dc = pad_dc(c->pb.d);
+  return c->pb.precision == SMC_MIXED ? launch_estimator_t<float>(dc, count, a, c->stream)
+                                      : launch_estimator_t<double>(dc, count, a, c->stream);
+}
+
+hipError_t launch_move(smc_ctx c, const MoveArgs& a) {
+  const int dc = pad_dc(c->pb.d);
+  return c->pb.precision == SMC_MIXED ? launch_move_t<float>(dc, c->pb.M, a, c->stream)
+                                      : launch_move_t<double>(dc, c->pb.M, a, c->stream);
+}
+
+// Full-data A, B, C at device theta; packs rows when pack != 0.
+smc_status run_cv(smc_ctx c, const double* dtheta, bool pack, double* dA, double* dB, double* dC) {
+  const smc_problem& pb = c->pb;
+  CvArgs a;
+  a.family = pb.family;
+  a.d = pb.d;
+  a.ld_in = pb.ld;
+  a.ld_out = c->lay.ld;
+  a.in_fp32 = pb.xy_fp32;
+  a.out_fp32 = pb.precision == SMC_MIXED;
+  a.n = pb.n;
+  a.inv_s2 = c->prob.inv_s2;
+  a.log2pis2 = c->prob.log2pis2;
+  a.Xin = pb.Xy;
+  a.theta = dtheta;
+  a.Xout = pack ? c->ws + c->lay.Xp : nullptr;
+  a.partials = c->at<double>(c->lay.partials);
+  const size_t shmem = (size_t)kCvTile * (pb.d + 3) * sizeof(double);
+  hipLaunchKernelGGL(cv_kernel, dim3(c->lay.cv_blocks), dim3(kCvThreads), shmem, c->stream, a);
+  LAUNCH_CHECK(c);
+  CvReduceArgs r;
+  r.nblocks = c->lay.cv_blocks;
+  r.d = pb.d;
+  r.partials = a.partials;
+  r.A = dA;
+  r.B = dB;
+  r.C = dC;
+  const int ne = 1 + pb.d + pb.d * (pb.d + 1) / 2;
+  hipLaunchKernelGGL(cv_reduce_kernel, dim3((ne + 255) / 256), dim3(256), 0, c->stream, r);
+  LAUNCH_CHECK(c);
+  return SMC_OK;
+}
+
+// host FP64 Cholesky solve of H s = g (H SPD), false if not PD
+bool host_spd_solve(int d, const std::vector<double>& H, const std::vector<double>& g, std::vector<double>& s) {
+  std::vector<double> L(d * d, 0.0);
+  for (int j = 0; j < d; ++j) {
+    double t = H[j * d + j];
+    for (int k = 0; k < j; ++k) t -= L[j * d + k] * L[j * d + k];
+    if (!(t > 0.0)) return false;
+    L[j * d + j] = std::sqrt(t);
+    for (int i = j + 1; i < d; ++i) {
+      double u = H[i * d + j];
+      for (int k = 0; k < j; ++k) u -= L[i * d + k] * L[j * d + k];
+      L[i * d + j] = u / L[j * d + j];
+    }
+  }
+  std::vector<double> y(d);
+  for (int k = 0; k < d; ++k) {
+    double t = g[k];
+    for (int j = 0; j < k; ++j) t -= L[k * d + j] * y[j];
+    y[k] = t / L[k * d + k];
+  }
+  s.assign(d, 0.0);
+  for (int k = d - 1; k >= 0; --k) {
+    double t = y[k];
+    for (int j = k + 1; j < d; ++j) t -= L[j * d + k] * s[j];
+    s[k] = t / L[k * d + k];
+  }
+  return true;
+}
+
+double host_log_prior(const smc_ctx c, const std::vector<double>& th) {
+  const int d = c->pb.d;
+  double s = 0.0;
+  for (int r = 0; r < d; ++r)
+    for (int q = 0; q < d; ++q) s += (th[r] - c->mu0[r]) * c->Q0[r * d + q] * (th[q] - c->mu0[q]);
+  return -0.5 * s;
+}
+
+smc_status full_eval(smc_ctx c, const std::vector<double>& th, double& A, std::vector<double>& B,
+                     std::vector<double>& C) {
+  const int d = c->pb.d;
+  double* dth = c->at<double>(c->lay.scratch_theta);
+  HIP_TRY(c, hipMemcpyAsync(dth, th.data(), d * 8, hipMemcpyHostToDevice, c->stream));
+  double* dA = c->at<double>(c->lay.tout);
+  double* dB = c->at<double>(c->lay.mean);
+  double* dC = c->at<double>(c->lay.Qw);
+  smc_status st = run_cv(c, dth, false, dA, dB, dC);
+  if (st != SMC_OK) return st;
+  B.resize(d);
+  C.resize(d * d);
+  HIP_TRY(c, hipMemcpyAsync(&A, dA, 8, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(B.data(), dB, d * 8, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(C.data(), dC, d * d * 8, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return SMC_OK;
+}
+
+// Posterior mode by Newton's method with step halving (same stopping rule as
+// a plain textbook Newton: step below 1e-12 in max norm, or no ascent).
+smc_status newton_mode(smc_ctx c, std::vector<double>& th) {
+  const int d = c->pb.d;
+  th = c->mu0;
+  double A;
+  std::vector<double> B, C, H(d * d), g(d), s, tn(d);
+  smc_status st = full_eval(c, th, A, B, C);
+  if (st != SMC_OK) return st;
+  double obj = A + host_log_prior(c, th);
+  int it;
+  for (it = 0; it < 100; ++it) {
+    for (int r = 0; r < d; ++r) {
+      double q = 0.0;
+      for (int k = 0; k < d; ++k) q += c->Q0[r * d + k] * (th[k] - c->mu0[k]);
+      g[r] = B[r] - q;
+      for (int k = 0; k < d; ++k) H[r * d + k] = -C[r * d + k] + c->Q0[r * d + k];
+    }
+    if (!host_spd_solve(d, H, g, s)) return fail(c, SMC_ERR_NOT_PD, "Newton: negative Hessian not PD");
+    double t = 1.0, newobj = 0.0;
+    bool ok = false;
+    std::vector<double> Bn, Cn;
+    double An = 0.0;
+    for (int h = 0; h < 60; ++h) {
+      for (int r = 0; r < d; ++r) tn[r] = th[r] + t * s[r];
+      st = full_eval(c, tn, An, Bn, Cn);
+      if (st != SMC_OK) return st;
+      newobj = An + host_log_prior(c, tn);
+      if (newobj >= obj || std::isnan(obj)) { ok = true; break; }
+      t *= 0.5;
+    }
+    if (!ok) { ++it; break; }
+    double stepmax = 0.0;
+    for (int r = 0; r < d; ++r) stepmax = std::fmax(stepmax, std::fabs(tn[r] - th[r]));
+    th = tn;
+    obj = newobj;
+    B = Bn;
+    C = Cn;
+    if (stepmax < 1e-12) { ++it; break; }
+  }
+  c->newton_iters = it;
+  return SMC_OK;
+}
+
+smc_status factor_device(smc_ctx c, double* S, double* L, double* Linv) {
+  FactorArgs f;
+  f.d = c->pb.d;
+  f.S = S;
+  f.L = L;
+  f.Linv = Linv;
+  f.status = c->at<double>(c->lay.status);
+  hipLaunchKernelGGL(factor_kernel, dim3(1), dim3(kMomThreads), 0, c->stream, f);
+  LAUNCH_CHECK(c);
+  double stv = 0.0;
+  HIP_TRY(c, hipMemcpyAsync(&stv, f.status, 8, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  if (stv != 0.0) return fail(c, SMC_ERR_NOT_PD, "matrix not positive definite");
+  return SMC_OK;
+}
+
+smc_status refresh(smc_ctx c) {
+  EstArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.P = c->prob;
+  a.count = c->pb.M;
+  a.theta = c->pb.theta;
+  a.u = c->pb.u;
+  a.lhat = c->pb.lhat;
+  a.sig2 = c->pb.sig2;
+  a.grad_l = c->at<double>(c->lay.grad_l);
+  a.grad_s = c->at<double>(c->lay.grad_s);
+  HIP_TRY(c, launch_estimator(c, c->pb.M, a));
+  return SMC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t smc_workspace_size(const smc_problem* pb) {
+  smc_problem tmp;
+  if (!pb) return 0;
+  tmp = *pb;
+  // workspace itself is what is being sized
+  if (!tmp.workspace) tmp.workspace = reinterpret_cast<void*>(1);
+  if (validate(&tmp) != SMC_OK) return 0;
+  Layout L;
+  compute_layout(pb, L);
+  return L.total;
+}
+
+smc_status smc_init(const smc_problem* pb, void* stream, smc_ctx* out) {
+  if (!out) return SMC_ERR_INVALID_ARG;
+  *out = nullptr;
+  smc_status st = validate(pb);
+  if (st != SMC_OK) return st;
+  Layout lay;
+  compute_layout(pb, lay);
+  if (pb->workspace_bytes < lay.total || (reinterpret_cast<uintptr_t>(pb->workspace) & 255))
+    return SMC_ERR_INVALID_ARG;
+  smc_ctx c = new (std::nothrow) smc_ctx_s;
+  if (!c) return SMC_ERR_DEVICE;
+  c->pb = *pb;
+  c->stream = reinterpret_cast<hipStream_t>(stream);
+  c->lay = lay;
+  c->ws = static_cast<char*>(pb->workspace);
+  const int d = pb->d;
+  c->mu0.assign(pb->prior_mean, pb->prior_mean + d);
+  c->Q0.assign(pb->prior_prec, pb->prior_prec + (size_t)d * d);
+  c->pb.theta_bar = nullptr;  // host pointer not kept
+
+  Prob& P = c->prob;
+  P.family = pb->family;
+  P.cv_order = pb->cv_order;
+  P.d = d;
+  P.ld = lay.ld;
+  P.n = pb->n;
+  P.M = pb->M;
+  P.m = pb->m;
+  P.G = pb->G;
+  P.seed = pb->seed;
+  P.inv_s2 = pb->family == SMC_GAUSSIAN ? 1.0 / pb->gauss_s2 : 0.0;
+  P.log2pis2 = pb->family == SMC_GAUSSIAN ? std::log(2.0 * M_PI * pb->gauss_s2) : 0.0;
+  P.n_over_m = (double)pb->n / (double)pb->m;
+  P.X = c->ws + lay.Xp;
+  P.theta_bar = c->at<double>(lay.theta_bar);
+  P.cvA = c->at<double>(lay.cvA);
+  P.cvB = c->at<double>(lay.cvB);
+  P.cvC = c->at<double>(lay.cvC);
+  P.mu0 = c->at<double>(lay.mu0);
+  P.Q0 = c->at<double>(lay.Q0);
+  P.Sigma = c->at<double>(lay.Sigma);
+  P.Linv = c->at<double>(lay.Linv);
+
+#define TRY(expr)                                 \
+  do {                                            \
+    smc_status s_ = (expr);                       \
+    if (s_ != SMC_OK) { *out = c; return s_; }    \
+  } while (0)
+#define HTRY(expr)                                                                                 \
+  do {                                                                                             \
+    hipError_t e_ = (expr);                                                                        \
+    if (e_ != hipSuccess) {                                                                        \
+      *out = c;                                                                                    \
+      return fail(c, SMC_ERR_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));              \
+    }                                                                                              \
+  } while (0)
+
+  HTRY(hipMemcpyAsync((void*)P.mu0, pb->prior_mean, d * 8, hipMemcpyHostToDevice, c->stream));
+  HTRY(hipMemcpyAsync((void*)P.Q0, pb->prior_prec, (size_t)d * d * 8, hipMemcpyHostToDevice, c->stream));
+  HTRY(hipMemcpyAsync(c->at<double>(lay.Qw), pb->prior_prec, (size_t)d * d * 8, hipMemcpyHostToDevice, c->stream));
+  TRY(factor_device(c, c->at<double>(lay.Qw), c->at<double>(lay.L0), c->at<double>(lay.L0inv)));
+
+  std::vector<double> tb(d);
+  if (pb->theta_bar) {
+    tb.assign(pb->theta_bar, pb->theta_bar + d);
+  } else {
+    TRY(newton_mode(c, tb));
+  }
+  HTRY(hipMemcpyAsync((void*)P.theta_bar, tb.data(), d * 8, hipMemcpyHostToDevice, c->stream));
+  TRY(run_cv(c, P.theta_bar, true, (double*)P.cvA, (double*)P.cvB, (double*)P.cvC));
+
+  InitArgs ia;
+  ia.P = P;
+  ia.L0inv = c->at<double>(lay.L0inv);
+  ia.theta = pb->theta;
+  ia.u = pb->u;
+  ia.logw = pb->logw;
+  hipLaunchKernelGGL(init_kernel, dim3(pb->M), dim3(kWave), 0, c->stream, ia);
+  HTRY(hipGetLastError());
+  TRY(refresh(c));
+  HTRY(hipStreamSynchronize(c->stream));
+  c->a = 0.0;
+  c->logz = 0.0;
+  c->stage = 0;
+  c->move = 0;
+  *out = c;
+  return SMC_OK;
+#undef TRY
+#undef HTRY
+}
+
+smc_status smc_temper(smc_ctx c, double* a_out, double* dlogz_out, double* ess_out) {
+  if (!c) return SMC_ERR_INVALID_ARG;
+  if (c->a >= 1.0) return fail(c, SMC_ERR_STATE, "tempering already reached a = 1");
+  TemperArgs t;
+  t.M = c->pb.M;
+  t.a_prev = c->a;
+  t.ess_frac = c->pb.ess_frac;
+  t.n_bisect = c->pb.n_bisect;
+  t.lhat = c->pb.lhat;
+  t.sig2 = c->pb.sig2;
+  t.logw = c->pb.logw;
+  t.out = c->at<double>(c->lay.tout);
+  hipLaunchKernelGGL(temper_kernel, dim3(1), dim3(kTemperThreads), 0, c->stream, t);
+  LAUNCH_CHECK(c);
+  double o[4];
+  HIP_TRY(c, hipMemcpyAsync(o, t.out, sizeof(o), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  if (o[3] != 0.0) return fail(c, SMC_ERR_NONFINITE, "all incremental weights non-finite");
+  c->stage += 1;
+  c->move = 0;
+  c->a = o[0];
+  c->logz += o[1];
+  c->have_mass = 0;
+  if (a_out) *a_out = o[0];
+  if (dlogz_out) *dlogz_out = o[1];
+  if (ess_out) *ess_out = o[2];
+  return SMC_OK;
+}
+
+smc_status smc_mass(smc_ctx c) {
+  if (!c) return SMC_ERR_INVALID_ARG;
+  MomentArgs a;
+  a.M = c->pb.M;
+  a.d = c->pb.d;
+  a.theta = c->pb.theta;
+  a.logw = c->pb.logw;
+  a.mean = c->at<double>(c->lay.mean);
+  a.F.d = c->pb.d;
+  a.F.S = c->at<double>(c->lay.Sigma);
+  a.F.L = c->at<double>(c->lay.Lchol);
+  a.F.Linv = c->at<double>(c->lay.Linv);
+  a.F.status = c->at<double>(c->lay.status);
+  hipLaunchKernelGGL(moments_kernel, dim3(1), dim3(kMomThreads), 0, c->stream, a);
+  LAUNCH_CHECK(c);
+  double stv = 0.0;
+  HIP_TRY(c, hipMemcpyAsync(&stv, a.F.status, 8, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  if (stv != 0.0) return fail(c, SMC_ERR_NOT_PD, "particle covariance not positive definite");
+  c->have_mass = 1;
+  return SMC_OK;
+}
+
+smc_status smc_resample(smc_ctx c) {
+  if (!c) return SMC_ERR_INVALID_ARG;
+  const smc_problem& pb = c->pb;
+  ResampleArgs r;
+  r.M = pb.M;
+  r.seed = pb.seed;
+  r.stage = (uint32_t)c->stage;
+  r.logw = pb.logw;
+  r.anc = c->at<int32_t>(c->lay.anc);
+  hipLaunchKernelGGL(resample_kernel, dim3(1), dim3(kResThreads), 0, c->stream, r);
+  LAUNCH_CHECK(c);
+  GatherArgs g;
+  g.M = pb.M; g.d = pb.d; g.m = pb.m;
+  g.anc = r.anc;
+  g.theta = pb.theta; g.u = pb.u; g.lhat = pb.lhat; g.sig2 = pb.sig2;
+  g.gl = c->at<double>(c->lay.grad_l); g.gs = c->at<double>(c->lay.grad_s);
+  g.theta2 = c->at<double>(c->lay.th2); g.u2 = c->at<int32_t>(c->lay.u2);
+  g.lhat2 = c->at<double>(c->lay.lh2); g.sig22 = c->at<double>(c->lay.sg2);
+  g.gl2 = c->at<double>(c->lay.gl2); g.gs2 = c->at<double>(c->lay.gs2);
+  hipLaunchKernelGGL(gather_kernel, dim3(pb.M), dim3(256), 0, c->stream, g);
+  LAUNCH_CHECK(c);
+  CopyBackArgs b;
+  b.M = pb.M; b.d = pb.d; b.m = pb.m;
+  b.theta2 = g.theta2; b.u2 = g.u2; b.lhat2 = g.lhat2; b.sig22 = g.sig22; b.gl2 = g.gl2; b.gs2 = g.gs2;
+  b.theta = pb.theta; b.u = pb.u; b.lhat = pb.lhat; b.sig2 = pb.sig2;
+  b.gl = const_cast<double*>(g.gl); b.gs = const_cast<double*>(g.gs); b.logw = pb.logw;
+  hipLaunchKernelGGL(copyback_kernel, dim3(pb.M), dim3(256), 0, c->stream, b);
+  LAUNCH_CHECK(c);
+  return SMC_OK;
+}
+
+smc_status smc_move(smc_ctx c, double eps, int32_t L, int32_t R) {
+  if (!c) return SMC_ERR_INVALID_ARG;
+  if (!(eps > 0.0) || L < 1 || R < 0) return fail(c, SMC_ERR_INVALID_ARG, "bad eps/L/R");
+  if (!c->have_mass) return fail(c, SMC_ERR_STATE, "no mass matrix for this stage");
+  if (c->move + R > 0xFFFF) return fail(c, SMC_ERR_INVALID_ARG, "too many moves in one stage");
+  for (int r = 0; r < R; ++r) {
+    MoveArgs a;
+    a.P = c->prob;
+    a.a = c->a;
+    a.eps = eps;
+    a.L = L;
+    a.stage = (uint32_t)c->stage;
+    a.move = (uint32_t)c->move;
+    a.theta = c->pb.theta;
+    a.u = c->pb.u;
+    a.lhat = c->pb.lhat;
+    a.sig2 = c->pb.sig2;
+    a.grad_l = c->at<double>(c->lay.grad_l);
+    a.grad_s = c->at<double>(c->lay.grad_s);
+    a.accept = c->pb.accept;
+    HIP_TRY(c, launch_move(c, a));
+    c->move += 1;
+  }
+  return SMC_OK;
+}
+
+smc_status loglik_est(smc_ctx c, int32_t count, const double* theta, const int32_t* u, double* lhat,
+                      double* sig2, double* dhat) {
+  if (!c || count < 0 || (count > 0 && (!theta || !u))) return SMC_ERR_INVALID_ARG;
+  EstArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.P = c->prob;
+  a.count = count;
+  a.theta = theta;
+  a.u = u;
+  a.lhat = lhat;
+  a.sig2 = sig2;
+  a.dhat = dhat;
+  HIP_TRY(c, launch_estimator(c, count, a));
+  return SMC_OK;
+}
+
+smc_status loglik_grad(smc_ctx c, int32_t count, const double* theta, const int32_t* u, const double* g_lhat,
+                       const double* g_sig2, double* grad, double* grad_l, double* grad_s) {
+  if (!c || count < 0 || (count > 0 && (!theta || !u))) return SMC_ERR_INVALID_ARG;
+  EstArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.P = c->prob;
+  a.count = count;
+  a.theta = theta;
+  a.u = u;
+  a.g_lhat = g_lhat;
+  a.g_sig2 = g_sig2;
+  a.grad = grad;
+  a.grad_l = grad_l;
+  a.grad_s = grad_s;
+  HIP_TRY(c, launch_estimator(c, count, a));
+  return SMC_OK;
+}
+
+smc_status smc_refresh(smc_ctx c) {
+  if (!c) return SMC_ERR_INVALID_ARG;
+  return refresh(c);
+}
+
+smc_status smc_get_info(smc_ctx c, smc_info* o) {
+  if (!c || !o) return SMC_ERR_INVALID_ARG;
+  o->a = c->a;
+  o->logz = c->logz;
+  o->stage = c->stage;
+  o->move = c->move;
+  o->have_mass = c->have_mass;
+  o->newton_iters = c->newton_iters;
+  return SMC_OK;
+}
+
+smc_status smc_set_stage(smc_ctx c, int32_t stage, int32_t move, double a, double logz) {
+  if (!c || stage < 0 || stage > 0xFFFFFF || move < 0 || move > 0xFFFF || !(a >= 0.0 && a <= 1.0))
+    return SMC_ERR_INVALID_ARG;
+  c->stage = stage;
+  c->move = move;
+  c->a = a;
+  c->logz = logz;
+  return SMC_OK;
+}
+
+smc_status smc_set_mass(smc_ctx c, const double* sigma_host) {
+  if (!c || !sigma_host) return SMC_ERR_INVALID_ARG;
+  const int d = c->pb.d;
+  double* S = c->at<double>(c->lay.Sigma);
+  HIP_TRY(c, hipMemcpyAsync(S, sigma_host, (size_t)d * d * 8, hipMemcpyHostToDevice, c->stream));
+  smc_status st = factor_device(c, S, c->at<double>(c->lay.Lchol), c->at<double>(c->lay.Linv));
+  if (st != SMC_OK) return st;
+  c->have_mass = 1;
+  return SMC_OK;
+}
+
+smc_status smc_get_mass(smc_ctx c, double* sigma, double* chol, double* chol_inv) {
+  if (!c) return SMC_ERR_INVALID_ARG;
+  const size_t b = (size_t)c->pb.d * c->pb.d * 8;
+  if (sigma) HIP_TRY(c, hipMemcpyAsync(sigma, c->at<double>(c->lay.Sigma), b, hipMemcpyDeviceToHost, c->stream));
+  if (chol) HIP_TRY(c, hipMemcpyAsync(chol, c->at<double>(c->lay.Lchol), b, hipMemcpyDeviceToHost, c->stream));
+  if (chol_inv) HIP_TRY(c, hipMemcpyAsync(chol_inv, c->at<double>(c->lay.Linv), b, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return SMC_OK;
+}
+
+smc_status smc_get_cv(smc_ctx c, double* theta_bar, double* A, double* B, double* C) {
+  if (!c) return SMC_ERR_INVALID_ARG;
+  const int d = c->pb.d;
+  if (theta_bar) HIP_TRY(c, hipMemcpyAsync(theta_bar, c->prob.theta_bar, d * 8, hipMemcpyDeviceToHost, c->stream));
+  if (A) HIP_TRY(c, hipMemcpyAsync(A, c->prob.cvA, 8, hipMemcpyDeviceToHost, c->stream));
+  if (B) HIP_TRY(c, hipMemcpyAsync(B, c->prob.cvB, d * 8, hipMemcpyDeviceToHost, c->stream));
+  if (C) HIP_TRY(c, hipMemcpyAsync(C, c->prob.cvC, (size_t)d * d * 8, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return SMC_OK;
+}
+
+smc_status smc_full_loglik(smc_ctx c, const double* theta, double* A, double* B, double* C) {
+  if (!c || !theta) return SMC_ERR_INVALID_ARG;
+  const int d = c->pb.d;
+  std::vector<double> th(theta, theta + d), Bv, Cv;
+  double Av = 0.0;
+  smc_status st = full_eval(c, th, Av, Bv, Cv);
+  if (st != SMC_OK) return st;
+  if (A) *A = Av;
+  if (B) std::memcpy(B, Bv.data(), d * 8);
+  if (C) std::memcpy(C, Cv.data(), (size_t)d * d * 8);
+  return SMC_OK;
+}
+
+void smc_destroy(smc_ctx c) { delete c; }
+
+const char* smc_status_string(smc_status s) {
+  switch (s) {
+    case SMC_OK: return "ok";
+    case SMC_ERR_INVALID_ARG: return "invalid argument";
+    case SMC_ERR_STATE: return "call out of order";
+    case SMC_ERR_DEVICE: return "device error";
+    case SMC_ERR_NOT_PD: return "matrix not positive definite";
+    case SMC_ERR_NONFINITE: return "non-finite weights";
+    case SMC_ERR_UNSUPPORTED: return "unsupported";
+  }
+  return "unknown status";
+}
+
+const char* smc_last_error(smc_ctx c) { return c ? c->err : "no context"; }
+
+}  // extern "C"

@@ -1,0 +1,336 @@
+"""GPU parity: every C-ABI entry point against the CPU oracle on the same
+seeded inputs (FP64 path within 1e-9 relative, mixed path within the stated
+bounds, indices and ancestors bit for bit, accept decisions equal outside a
+1e-9 near-tie band)."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1805_03317_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def _binding():
+    from paper_1805_03317_amd import binding
+    return binding
+
+
+def make_pair(w, precision=None, theta_bar=None, M=None, m=None, G=None, cv_order=2):
+    B = _binding()
+    prec = w.precision if precision is None else precision
+    P = oracle.Problem(w.Xy(np.float64), w.d, w.family, w.prior_mean, w.prior_prec,
+                       cv_order=cv_order, gauss_s2=w.gauss_s2)
+    if theta_bar is None:
+        theta_bar, _ = P.newton_mode()
+    P.set_cv_centre(theta_bar)
+    data_dt = np.float32 if w.precision == W.MIXED else np.float64
+    Xy = torch.tensor(w.Xy(data_dt), device=DEV)
+    smc = B.SubsampledSMC(Xy, w.d, w.family, prec, M or w.M, m or w.m, G or w.G, w.prior_mean, w.prior_prec,
+                          w.seed, theta_bar=theta_bar, gauss_s2=w.gauss_s2, cv_order=cv_order)
+    return P, smc
+
+
+def grad_scale(P, theta, gl_ref):
+    """Absolute-sum scale of grad l_hat: |B| + |C||delta| + |(n/m) S1| per component."""
+    delta = theta - P.theta_bar[None, :]
+    cd = delta @ P.C.T
+    return np.abs(P.B)[None, :] + np.abs(delta) @ np.abs(P.C).T + np.abs(gl_ref - P.B[None, :] - cd)
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+CASES = [
+    ("logistic", lambda: W.logistic_small(4000, 5, seed=1, M=64, m=500, G=4), 0.15),
+    ("logistic_ragged", lambda: W.logistic_small(3000, 3, seed=2, M=33, m=101, G=3), 0.3),
+    ("logistic_d7", lambda: W.logistic_small(2000, 7, seed=3, M=40, m=77, G=7), 0.2),
+    ("poisson", lambda: W.poisson_small(5000, 6, seed=4, M=48, m=300, G=10), 0.1),
+    ("poisson_d20", lambda: W.poisson_small(20000, 20, seed=5, M=32, m=1000, G=100), 0.05),
+    ("gaussian", lambda: W.gaussian_small(500, 4, seed=6, M=32, m=64, G=4), 0.3),
+    ("logistic_m1", lambda: W.logistic_small(100, 2, seed=7, M=8, m=1, G=1), 0.5),
+]
+
+
+@pytest.mark.parametrize("name,mk,scale", CASES, ids=[c[0] for c in CASES])
+@pytest.mark.parametrize("far", [False, True], ids=["near", "far"])
+def test_estimator_fp64(name, mk, scale, far):
+    w = mk()
+    say("case", name, "far" if far else "near", "n", w.n, "d", w.d, "m", w.m)
+    P, smc = make_pair(w)
+    th, u = W.random_state(w, 24, scale * (8 if far else 1), P.theta_bar, seed=11)
+    tht, ut = torch.tensor(th, device=DEV), torch.tensor(u, device=DEV)
+    lh, s2, dh = smc.loglik_est(tht, ut)
+    grad, gl, gs = smc.loglik_grad(tht, ut, separate=True)
+    torch.cuda.synchronize()
+    ref = P.estimate(th, u, grad=True)
+    lh, s2, dh, gl, gs = (x.cpu().numpy() for x in (lh, s2, dh, gl, gs))
+    np.testing.assert_allclose(lh, ref["lhat"], rtol=1e-9)
+    dscale = np.abs(ref["dhat"]) + 1e-30 * abs(P.A)
+    assert np.all(np.abs(dh - ref["dhat"]) <= 1e-9 * dscale + 1e-13 * np.abs(ref["lhat"])), (dh, ref["dhat"])
+    if w.family == W.GAUSSIAN:
+        assert np.all(np.abs(s2) < 1e-20)
+    else:
+        np.testing.assert_allclose(s2, ref["sig2"], rtol=1e-9, atol=1e-300)
+    sc = grad_scale(P, th, ref["grad_l"])
+    assert np.all(np.abs(gl - ref["grad_l"]) <= 1e-9 * sc), np.max(np.abs(gl - ref["grad_l"]) / sc)
+    gsc = np.abs(ref["grad_s"]).max(axis=1, keepdims=True) + 1e-300
+    if w.family == W.GAUSSIAN:
+        # d_k = 0 exactly: the oracle's binary128 residue is ~1e-60, the GPU's zero is exact
+        assert np.all(np.abs(gs) < 1e-20) and np.all(np.abs(ref["grad_s"]) < 1e-20)
+        gsc = np.zeros_like(gsc)
+    else:
+        assert np.all(np.abs(gs - ref["grad_s"]) <= 1e-9 * gsc), np.max(np.abs(gs - ref["grad_s"]) / gsc)
+    # combined gradient for autograd backward
+    g1 = torch.linspace(0.5, 1.5, len(th), dtype=torch.float64, device=DEV)
+    g2 = torch.linspace(-1.0, 2.0, len(th), dtype=torch.float64, device=DEV)
+    comb = smc.loglik_grad(tht, ut, g1, g2).cpu().numpy()
+    want = g1.cpu().numpy()[:, None] * ref["grad_l"] + g2.cpu().numpy()[:, None] * ref["grad_s"]
+    assert np.all(np.abs(comb - want) <= 1e-9 * (sc + 2 * gsc) + 1e-20)
+    smc.close()
+
+
+MIXED_CASES = [
+    ("logistic_mixed", lambda: W.logistic_small(4000, 5, seed=1, precision=W.MIXED, M=64, m=500, G=4), 0.15),
+    ("poisson_mixed_d20", lambda: W.poisson_small(20000, 20, seed=5, precision=W.MIXED, M=32, m=1000, G=100), 0.05),
+    ("logistic_mixed_d12", lambda: W.logistic_small(3000, 12, seed=8, precision=W.MIXED, M=32, m=257, G=8), 0.1),
+]
+
+
+@pytest.mark.parametrize("name,mk,scale", MIXED_CASES, ids=[c[0] for c in MIXED_CASES])
+def test_estimator_mixed(name, mk, scale):
+    w = mk()
+    say("case", name, "n", w.n, "d", w.d, "m", w.m)
+    P, smc = make_pair(w)
+    th, u = W.random_state(w, 24, scale, P.theta_bar, seed=12)
+    tht, ut = torch.tensor(th, device=DEV), torch.tensor(u, device=DEV)
+    lh, s2, dh = smc.loglik_est(tht, ut)
+    grad, gl, gs = smc.loglik_grad(tht, ut, separate=True)
+    torch.cuda.synchronize()
+    ref = P.estimate(th, u, grad=True)
+    lh, s2, gl, gs = (x.cpu().numpy() for x in (lh, s2, gl, gs))
+    # metric bound: relative log-likelihood error <= 1e-5
+    assert np.max(np.abs(lh - ref["lhat"]) / np.abs(ref["lhat"])) <= 1e-5
+    assert np.max(np.abs(s2 - ref["sig2"]) / ref["sig2"]) <= 1e-4
+    sc = grad_scale(P, th, ref["grad_l"])
+    assert np.max(np.abs(gl - ref["grad_l"]) / sc) <= 1e-5
+    gsc = np.abs(ref["grad_s"]).max(axis=1, keepdims=True)
+    assert np.max(np.abs(gs - ref["grad_s"]) / gsc) <= 1e-4
+    smc.close()
+
+
+def test_cv_and_newton_parity():
+    for w in (W.logistic_small(5000, 6, seed=21), W.poisson_small(8000, 10, seed=22),
+              W.gaussian_small(700, 3, seed=23)):
+        say("cv case", w.name)
+        P = oracle.Problem(w.Xy(np.float64), w.d, w.family, w.prior_mean, w.prior_prec, gauss_s2=w.gauss_s2)
+        mode, _ = P.newton_mode()
+        B = _binding()
+        Xy = torch.tensor(w.Xy(np.float64), device=DEV)
+        smc = B.SubsampledSMC(Xy, w.d, w.family, W.FP64, 16, 32, 4, w.prior_mean, w.prior_prec, w.seed,
+                              gauss_s2=w.gauss_s2)
+        tb, A, Bv, Cm = smc.get_cv()
+        np.testing.assert_allclose(tb, mode, rtol=0, atol=1e-9 * (1 + np.abs(mode).max()))
+        A0, B0, C0 = P.cv_build(tb)
+        assert abs(A - A0) <= 1e-11 * abs(A0)
+        np.testing.assert_allclose(Bv, B0, rtol=0, atol=1e-10 * (np.abs(B0).max() + np.abs(C0).max()))
+        np.testing.assert_allclose(Cm, C0, rtol=0, atol=1e-11 * np.abs(C0).max())
+        smc.close()
+
+
+def test_init_parity():
+    w = W.logistic_small(3000, 5, seed=31, M=100, m=130, G=4)
+    say("init", w.name)
+    P, smc = make_pair(w)
+    th0, u0, lw0 = oracle.init_particles(w.M, w.d, w.m, w.n, w.seed, w.prior_mean, w.prior_prec)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(smc.u.cpu().numpy(), u0)
+    np.testing.assert_allclose(smc.theta.cpu().numpy(), th0, rtol=1e-13, atol=1e-13)
+    np.testing.assert_allclose(smc.logw.cpu().numpy(), lw0, rtol=0, atol=1e-15)
+    ref = P.estimate(th0, u0)
+    np.testing.assert_allclose(smc.lhat.cpu().numpy(), ref["lhat"], rtol=1e-9)
+    np.testing.assert_allclose(smc.sig2.cpu().numpy(), ref["sig2"], rtol=1e-9)
+    smc.close()
+
+
+@pytest.mark.parametrize("M", [1, 7, 256, 1000, 4096])
+def test_temper_parity(M):
+    w = W.logistic_small(500, 2, seed=41, M=M, m=16, G=2)
+    say("temper M", M)
+    P, smc = make_pair(w)
+    g = np.random.default_rng(M)
+    lhat = -3000 + 30 * g.standard_normal(M)
+    sig2 = np.abs(g.standard_normal(M)) * 3
+    logw = np.full(M, -math.log(M))
+    a_prev = 0.05
+    smc.lhat.copy_(torch.tensor(lhat))
+    smc.sig2.copy_(torch.tensor(sig2))
+    smc.logw.copy_(torch.tensor(logw))
+    smc.set_stage(4, 0, a_prev, 0.0)
+    a, dz, ess = smc.temper()
+    a0, dz0, ess0, lw0 = oracle.temper(lhat, sig2, logw, a_prev, 0.5)
+    assert abs(a - a0) <= 1e-12
+    assert abs(dz - dz0) <= 1e-9 * max(1.0, abs(dz0))
+    assert abs(ess - ess0) <= 1e-9 * M
+    np.testing.assert_allclose(smc.logw.cpu().numpy(), lw0, rtol=1e-9, atol=1e-9)
+    info = smc.info()
+    assert info["stage"] == 5 and info["a"] == a
+    smc.close()
+
+
+def test_mass_parity():
+    w = W.logistic_small(500, 6, seed=42, M=700, m=16, G=2)
+    P, smc = make_pair(w)
+    g = np.random.default_rng(3)
+    th = g.standard_normal((w.M, w.d)) @ g.standard_normal((w.d, w.d)) * 0.3 + 1
+    lw = g.standard_normal(w.M)
+    lw -= np.log(np.exp(lw).sum())
+    smc.theta.copy_(torch.tensor(th))
+    smc.logw.copy_(torch.tensor(lw))
+    smc.mass()
+    S, Lc, Li = smc.get_mass()
+    mean0, S0, L0 = oracle.moments(th, lw)
+    np.testing.assert_allclose(S, S0, rtol=1e-11, atol=1e-13)
+    np.testing.assert_allclose(Lc, L0, rtol=1e-10, atol=1e-13)
+    np.testing.assert_allclose(Li @ L0, np.eye(w.d), atol=1e-10)
+    smc.close()
+
+
+@pytest.mark.parametrize("M", [5, 64, 1000, 4096])
+def test_resample_parity(M):
+    w = W.logistic_small(800, 3, seed=43, M=M, m=24, G=2)
+    say("resample M", M)
+    P, smc = make_pair(w)
+    g = np.random.default_rng(M + 1)
+    lw = 2.5 * g.standard_normal(M)
+    lw -= np.log(np.exp(lw - lw.max()).sum()) + lw.max()
+    th, u = W.random_state(w, M, 0.5, P.theta_bar, seed=M)
+    lh = g.standard_normal(M)
+    smc.theta.copy_(torch.tensor(th))
+    smc.u.copy_(torch.tensor(u))
+    smc.lhat.copy_(torch.tensor(lh))
+    smc.logw.copy_(torch.tensor(lw))
+    smc.set_stage(9, 0, 0.4)
+    smc.resample()
+    anc = oracle.resample_ancestors(lw, oracle.resample_offset(w.seed, 9))
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(smc.u.cpu().numpy(), u[anc])
+    np.testing.assert_array_equal(smc.theta.cpu().numpy(), th[anc])
+    np.testing.assert_array_equal(smc.lhat.cpu().numpy(), lh[anc])
+    np.testing.assert_allclose(smc.logw.cpu().numpy(), -math.log(M), rtol=0, atol=1e-15)
+    smc.close()
+
+
+MOVE_CASES = [
+    ("logistic", lambda: W.logistic_small(4000, 5, seed=51, M=96, m=300, G=4, L=8), 0.6, 0.12),
+    ("poisson", lambda: W.poisson_small(6000, 8, seed=52, M=64, m=400, G=10, L=10), 0.9, 0.1),
+    ("gaussian", lambda: W.gaussian_small(600, 3, seed=53, M=64, m=50, G=5, L=6), 1.0, 0.2),
+    ("logistic_mixed", lambda: W.logistic_small(4000, 5, seed=54, precision=W.MIXED, M=96, m=300, G=4, L=8), 0.6, 0.12),
+    ("poisson_mixed_d20", lambda: W.poisson_small(20000, 20, seed=55, precision=W.MIXED, M=64, m=1000, G=100, L=20), 1.0, 0.05),
+]
+
+
+@pytest.mark.parametrize("name,mk,a,eps", MOVE_CASES, ids=[c[0] for c in MOVE_CASES])
+def test_move_parity(name, mk, a, eps):
+    """One Markov move from the same state on both sides (teacher forced)."""
+    w = mk()
+    say("move case", name)
+    P, smc = make_pair(w)
+    mixed = w.precision == W.MIXED
+    # a particle cloud near the tempered posterior: the oracle's prior draws shrunk around theta_bar
+    thp, u0, _ = oracle.init_particles(w.M, w.d, w.m, w.n, w.seed, w.prior_mean, w.prior_prec)
+    th0 = P.theta_bar + 0.02 * (thp - w.prior_mean)
+    _, Sig, Lc = oracle.moments(th0, np.full(w.M, -math.log(w.M)))
+    smc.theta.copy_(torch.tensor(th0))
+    smc.u.copy_(torch.tensor(u0))
+    smc.refresh()
+    smc.set_mass(Sig)
+    stage, mv = 3, 1
+    smc.set_stage(stage, mv, a)
+    smc.move(eps, w.L, 1)
+    torch.cuda.synchronize()
+    th1, u1, acc, lh1, sg1, dg = oracle.move(P, th0, u0, a, eps, w.L, w.seed, stage, mv, w.G, Sig, Lc, diag=True)
+    gacc = smc.accept.cpu().numpy()
+    tau = 1e-5 if mixed else 1e-9
+    near_u = np.abs(dg[:, 1] - dg[:, 0]) <= tau * (1 + np.abs(dg[:, 0]))
+    near_t = np.abs(dg[:, 3] - dg[:, 2]) <= tau * (1 + np.abs(dg[:, 2]))
+    ok_u = (gacc[:, 0] == acc[:, 0]) | near_u
+    ok_t = (gacc[:, 1] == acc[:, 1]) | near_t
+    say("accept rates", acc.mean(0), "near ties", near_u.sum(), near_t.sum())
+    assert ok_u.all() and ok_t.all(), (np.where(~ok_u), np.where(~ok_t))
+    same = (gacc == acc).all(axis=1)
+    gu = smc.u.cpu().numpy()
+    np.testing.assert_array_equal(gu[same], u1[same])
+    rt = 1e-5 if mixed else 1e-9
+    gth = smc.theta.cpu().numpy()
+    np.testing.assert_allclose(gth[same], th1[same], rtol=rt, atol=rt * np.abs(th1).max())
+    np.testing.assert_allclose(smc.lhat.cpu().numpy()[same], lh1[same], rtol=rt)
+    if w.family != W.GAUSSIAN:
+        np.testing.assert_allclose(smc.sig2.cpu().numpy()[same], sg1[same], rtol=1e-4 if mixed else 1e-8)
+    assert 0 < acc[:, 1].mean()
+    smc.close()
+
+
+def test_full_run_matches_oracle_fp64():
+    """Whole Algorithm 2 on a small logistic problem: same stages, temperatures and evidence."""
+    w = W.logistic_small(3000, 3, seed=61, M=128, m=150, G=4, L=6)
+    say("full run", w.name)
+    P, smc = make_pair(w)
+    eps_fn = lambda st, a, d: 1.0 / 6
+    logz, rec = smc.run(eps_fn, L=6, R=2)
+    ref = oracle.run_smc(P, M=w.M, m=w.m, G=w.G, seed=w.seed, eps_fn=eps_fn, L=6, R=2)
+    temps = np.array([r["a"] for r in rec])
+    assert len(temps) == len(ref["temps"])
+    np.testing.assert_allclose(temps, ref["temps"], rtol=1e-8, atol=1e-10)
+    assert abs(logz - ref["logz"]) <= 1e-7 * abs(ref["logz"])
+    np.testing.assert_allclose(smc.theta.cpu().numpy(), ref["theta"], rtol=1e-6, atol=1e-8)
+    np.testing.assert_array_equal(smc.u.cpu().numpy(), ref["u"])
+    smc.close()
+
+
+def test_autograd_backward_matches_fd_and_oracle():
+    B = _binding()
+    w = W.poisson_small(5000, 4, seed=71, M=16, m=200, G=4)
+    P, smc = make_pair(w)
+    th, u = W.random_state(w, 6, 0.1, P.theta_bar, seed=5)
+    t = torch.tensor(th, device=DEV, requires_grad=True)
+    ut = torch.tensor(u, device=DEV)
+    lh, s2 = B.loglik(t, ut, smc)
+    (lh.sum() + 0.5 * s2.sum()).backward()
+    ref = P.estimate(th, u, grad=True)
+    want = ref["grad_l"] + 0.5 * ref["grad_s"]
+    got = t.grad.cpu().numpy()
+    sc = grad_scale(P, th, ref["grad_l"])
+    assert np.all(np.abs(got - want) <= 1e-9 * (sc + np.abs(ref["grad_s"])))
+    # central differences of the GPU forward (d-part only, FP64, h = 1e-6)
+    h = 1e-6
+    for c in range(w.d):
+        e = torch.zeros_like(t)
+        e[:, c] = h
+        lp, sp, dp = smc.loglik_est((t + e).detach(), ut)
+        lm, sm, dm = smc.loglik_est((t - e).detach(), ut)
+        fd = ((lp - P.A) - (lm - P.A) + 0.5 * (sp - sm)) / (2 * h)
+        err = np.abs(fd.cpu().numpy() - got[:, c])
+        tol = 1e-6 * (sc[:, c] + 1)
+        assert np.all(err <= tol), (c, err, tol, fd.cpu().numpy(), got[:, c])
+    smc.close()
+
+
+def test_errors_are_reported():
+    B = _binding()
+    w = W.logistic_small(300, 3, seed=81, M=8, m=10, G=2)
+    P, smc = make_pair(w)
+    with pytest.raises(B.SMCError):
+        smc.move(0.1, 5, 1)          # no mass matrix yet in this stage
+    with pytest.raises(B.SMCError):
+        smc.set_mass(-np.eye(3))     # not positive definite
+    smc.close()
+    Xy = torch.tensor(w.Xy(np.float64), device=DEV)
+    with pytest.raises(B.SMCError):
+        B.SubsampledSMC(Xy, 40, w.family, W.FP64, 8, 10, 2, np.zeros(40), np.eye(40), 1)  # ld < d+1
