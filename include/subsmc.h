@@ -77,8 +77,8 @@ typedef struct smc_problem {
   double gauss_s2;     /* noise variance for SMC_GAUSSIAN, else ignored */
   int32_t M;           /* particles, 1 <= M <= 8192 */
   int32_t m;           /* subsample size (with replacement), 1 <= m */
-  int32_t G;           /* blocks of u for the pseudo-marginal refresh, 1 <= G <= m */
-  int32_t n_bisect;    /* bisection steps for the tempering exponent (e.g. 60) */
+  int32_t G;           /* blocks of u for the pseudo-marginal refresh, 1 <= G <= m,
+                          ceil(m/G) <= 16384 */
   uint64_t seed;       /* Philox key */
   double ess_frac;     /* target ESS = ess_frac * M, 0 < ess_frac <= 1 */
   const double* prior_mean; /* host d: Gaussian prior mean */
@@ -112,8 +112,9 @@ smc_status smc_init(const smc_problem* pb, void* stream, smc_ctx* out);
 
 /*
  * Algorithm 2 steps a-c. Increments the stage, chooses the next exponent
- * a in (a_prev, 1] by bisection on ESS(a) = ess_frac * M (a = 1 when ESS(1)
- * already meets it), reweights logw with the annealed estimator
+ * a in (a_prev, 1] with ESS(a) = ess_frac * M by multisection (bisection
+ * with 16 probes per step, 15 steps: resolution below 1e-16 of 1 - a_prev;
+ * a = 1 when ESS(1) already meets it), reweights logw with the annealed estimator
  * (a - a_prev) l_hat - (a^2 - a_prev^2) sigma2_hat / 2 (normalised), and adds
  * the log evidence increment log sum_i W_i exp(...) (section 3.5).
  * Host outputs (any may be NULL). Synchronises.
@@ -121,8 +122,8 @@ smc_status smc_init(const smc_problem* pb, void* stream, smc_ctx* out);
 smc_status smc_temper(smc_ctx ctx, double* a_out, double* dlogz_out, double* ess_out);
 
 /* Algorithm 2 step d: weighted particle covariance Sigma (inverse mass matrix),
- * its Cholesky factor and inverse factor. SMC_ERR_NOT_PD is reported by the
- * next synchronising call or smc_get_mass. */
+ * its Cholesky factor and inverse factor (a jitter ladder 1e-10..1e-1 times
+ * the mean variance is tried before SMC_ERR_NOT_PD). Synchronises. */
 smc_status smc_mass(smc_ctx ctx);
 
 /* Algorithm 2 step e: systematic resampling with exact integer arithmetic

@@ -22,7 +22,7 @@ class _Problem(C.Structure):
         ("family", C.c_int32), ("precision", C.c_int32), ("cv_order", C.c_int32), ("d", C.c_int32),
         ("n", C.c_int64), ("ld", C.c_int32), ("xy_fp32", C.c_int32), ("Xy", C.c_void_p),
         ("gauss_s2", C.c_double), ("M", C.c_int32), ("m", C.c_int32), ("G", C.c_int32),
-        ("n_bisect", C.c_int32), ("seed", C.c_uint64), ("ess_frac", C.c_double),
+        ("seed", C.c_uint64), ("ess_frac", C.c_double),
         ("prior_mean", C.c_void_p), ("prior_prec", C.c_void_p), ("theta_bar", C.c_void_p),
         ("theta", C.c_void_p), ("u", C.c_void_p), ("logw", C.c_void_p), ("lhat", C.c_void_p),
         ("sig2", C.c_void_p), ("accept", C.c_void_p), ("workspace", C.c_void_p),
@@ -106,7 +106,7 @@ class SubsampledSMC:
     """
 
     def __init__(self, Xy, d, family, precision, M, m, G, prior_mean, prior_prec, seed,
-                 ess_frac=0.5, cv_order=2, theta_bar=None, gauss_s2=1.0, n_bisect=60):
+                 ess_frac=0.5, cv_order=2, theta_bar=None, gauss_s2=1.0):
         import numpy as np
 
         L = lib()
@@ -131,7 +131,7 @@ class SubsampledSMC:
         pb.xy_fp32 = 1 if Xy.dtype == torch.float32 else 0
         pb.Xy = Xy.data_ptr()
         pb.gauss_s2 = float(gauss_s2)
-        pb.M, pb.m, pb.G, pb.n_bisect = self.M, self.m, self.G, int(n_bisect)
+        pb.M, pb.m, pb.G = self.M, self.m, self.G
         pb.seed, pb.ess_frac = int(seed), float(ess_frac)
         pb.prior_mean = self._mu0.ctypes.data
         pb.prior_prec = self._Q0.ctypes.data

@@ -170,11 +170,10 @@ __device__ __forceinline__ void softplus_remainder(T eb, T s, T D, T& R, T& Rp) 
   }
 }
 
-// Returns d (remainder) and dp (its eta-derivative).
-template <typename T>
-__device__ __forceinline__ void cv_remainder(int family, int cv_order, T eb, T aux, T D, T inv_s2,
-                                             T& d, T& dp) {
-  if (family == kLogistic) {
+// Returns d (remainder) and dp (its eta-derivative); FAM is the family.
+template <typename T, int FAM>
+__device__ __forceinline__ void cv_remainder(int cv_order, T eb, T aux, T D, T inv_s2, T& d, T& dp) {
+  if constexpr (FAM == kLogistic) {
     const bool flip = eb > T(0);
     const T e = flip ? -eb : eb;
     const T Dm = flip ? -D : D;
@@ -187,7 +186,7 @@ __device__ __forceinline__ void cv_remainder(int family, int cv_order, T eb, T a
       d -= T(0.5) * v * D * D;
       dp -= v * D;
     }
-  } else if (family == kPoisson) {
+  } else if constexpr (FAM == kPoisson) {
     T E2, E3;
     exp_remainders<T>(D, E2, E3);
     d = -aux * E3;

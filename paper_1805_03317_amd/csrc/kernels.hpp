@@ -108,30 +108,56 @@ struct PassResult {
   double gl, gs;  // lane c: component c of grad l_hat and grad sigma2_hat
 };
 
-// Index of slot j: the stored subsample, or a fresh draw inside [b0, b1).
-__device__ __forceinline__ int32_t slot_index(const int32_t* __restrict__ urow, int j, int b0, int b1,
-                                              uint64_t seed, uint64_t ctr0, uint64_t particle, int64_t n) {
-  if (j >= b0 && j < b1) return (int32_t)word_to_index(stream_word(seed, ctr0, particle, (uint64_t)(j - b0)), (uint64_t)n);
-  return urow[j];
+// Sum over the 64 lanes of v[c], returned in lane c (0 elsewhere), through
+// 64*DC elements of LDS; the adds run in FP64 in lane order.
+template <typename Real, int DC>
+__device__ __forceinline__ double lds_column_sum(const Real (&v)[DC], Real* red, int lane) {
+  __syncthreads();
+#pragma unroll
+  for (int c = 0; c < DC; ++c) red[lane * DC + c] = v[c];
+  __syncthreads();
+  double s = 0.0;
+  if (lane < DC) {
+    for (int r = 0; r < kWave; ++r) s += (double)red[r * DC + lane];
+  }
+  return s;
 }
 
 // One pass of the difference estimator (eq. difference_estimator_logl), its
 // variance estimate (section 3.2) and both gradients at theta = theta_bar + delta,
-// for the subsample urow (with block [b0,b1) replaced by fresh draws when b1 > b0).
+// for the subsample urow; slots [b0, b1) take their indices from `blk` (the
+// freshly drawn block of a pseudo-marginal refresh, staged in LDS).
 //   l_hat   = A + B'delta + delta'C delta/2 + (n/m) sum_j d_j
 //   s2_hat  = (n/m)^2 sum_j (d_j - dbar)^2
 //   grad l  = B + C delta + (n/m) sum_j d'_j x_j
 //   grad s2 = 2 (n/m)^2 sum_j (d_j - dbar) d'_j x_j
 // The d_j sums are taken about the shift d_{u_0} (evaluated first by every
-// lane) to keep the single-pass variance accurate.
-template <typename Real, int DC>
+// lane) to keep the single-pass variance accurate. Each lane streams slots
+// lane, lane+64, ...; the next row and the index after it are loaded before
+// the current row is used, so two gathers per lane are in flight.
+// A caller index outside [0, n) is never dereferenced: it poisons the pass
+// with NaN.
+template <typename Real, int DC, int FAM, bool BLK>
 __device__ __forceinline__ PassResult estimator_pass(const Prob& P, const int32_t* __restrict__ urow,
-                                                     int b0, int b1, uint64_t ctr0, uint64_t particle,
+                                                     int b0, int b1, const int32_t* blk, Real* red,
                                                      double delta64, int lane) {
   const Real* __restrict__ X = static_cast<const Real*>(P.X);
   const int m = P.m;
   const int ld = P.ld;
+  const uint32_t n = (uint32_t)P.n;
   const Real inv_s2 = (Real)P.inv_s2;
+  // both sources are read unconditionally and the value selected, so the
+  // LDS and global accesses keep their own address spaces
+  auto index_of = [&](int j) -> int32_t {
+    const int32_t g = urow[j];
+    if constexpr (BLK) {
+      const bool in = (unsigned)(j - b0) < (unsigned)(b1 - b0);
+      const int32_t l = blk[in ? j - b0 : 0];
+      return in ? l : g;
+    } else {
+      return g;
+    }
+  };
 
   Real dl[DC];
 #pragma unroll
@@ -140,15 +166,15 @@ __device__ __forceinline__ PassResult estimator_pass(const Prob& P, const int32_
   // shift: the remainder at slot 0, evaluated redundantly by every lane
   double shift;
   {
-    const int32_t k0 = slot_index(urow, 0, b0, b1, P.seed, ctr0, particle, P.n);
-    const bool bad = (uint32_t)k0 >= (uint32_t)P.n;  // caller index out of range: poison, never read
+    const int32_t k0 = index_of(0);
+    const bool bad = (uint32_t)k0 >= n;
     RowLoad<Real, DC> r;
     load_row<Real, DC>(X + (int64_t)(bad ? 0 : k0) * ld, r);
     Real D = Real(0);
 #pragma unroll
     for (int c = 0; c < DC; ++c) D += r.x[c] * dl[c];
     Real dd, dp;
-    cv_remainder<Real>(P.family, P.cv_order, r.eb, r.aux, D, inv_s2, dd, dp);
+    cv_remainder<Real, FAM>(P.cv_order, r.eb, r.aux, D, inv_s2, dd, dp);
     shift = bad ? __builtin_nan("") : (double)dd;
   }
 
@@ -157,16 +183,23 @@ __device__ __forceinline__ PassResult estimator_pass(const Prob& P, const int32_
 #pragma unroll
   for (int c = 0; c < DC; ++c) { S1[c] = Real(0); T1[c] = Real(0); }
 
-  for (int j = lane; j < m; j += kWave) {
-    const int32_t k = slot_index(urow, j, b0, b1, P.seed, ctr0, particle, P.n);
-    const bool bad = (uint32_t)k >= (uint32_t)P.n;
-    RowLoad<Real, DC> r;
-    load_row<Real, DC>(X + (int64_t)(bad ? 0 : k) * ld, r);
+  int j = lane;
+  int32_t k_cur = j < m ? index_of(j) : 0;
+  int32_t k_nxt = j + kWave < m ? index_of(j + kWave) : 0;
+  RowLoad<Real, DC> r_nxt;
+  if (j < m) load_row<Real, DC>(X + (int64_t)((uint32_t)k_cur < n ? k_cur : 0) * ld, r_nxt);
+  for (; j < m; j += kWave) {
+    const RowLoad<Real, DC> r = r_nxt;
+    const bool bad = (uint32_t)k_cur >= n;
+    if (j + kWave < m) load_row<Real, DC>(X + (int64_t)((uint32_t)k_nxt < n ? k_nxt : 0) * ld, r_nxt);
+    k_cur = k_nxt;
+    k_nxt = j + 2 * kWave < m ? index_of(j + 2 * kWave) : 0;
+
     Real D = Real(0);
 #pragma unroll
     for (int c = 0; c < DC; ++c) D += r.x[c] * dl[c];
     Real dd, dp;
-    cv_remainder<Real>(P.family, P.cv_order, r.eb, r.aux, D, inv_s2, dd, dp);
+    cv_remainder<Real, FAM>(P.cv_order, r.eb, r.aux, D, inv_s2, dd, dp);
     if (bad) dd = dp = Real(__builtin_nan(""));
     const double e = (double)dd - shift;
     se += e;
@@ -179,15 +212,12 @@ __device__ __forceinline__ PassResult estimator_pass(const Prob& P, const int32_
     }
   }
 
-  // fixed-order butterfly reductions
+  // fixed-order reductions: scalars by butterfly; the vectors S1, T1 by an LDS
+  // transpose (lane c adds column c over lanes 0..63 in FP64)
   se = wave_sum(se);
   se2 = wave_sum(se2);
-  double s1[DC], t1[DC];
-#pragma unroll
-  for (int c = 0; c < DC; ++c) {
-    s1[c] = wave_sum((double)S1[c]);
-    t1[c] = wave_sum((double)T1[c]);
-  }
+  const double s1c = lds_column_sum<Real, DC>(S1, red, lane);
+  const double t1c = lds_column_sum<Real, DC>(T1, red, lane);
 
   const double md = (double)m;
   const double nm = P.n_over_m;
@@ -209,8 +239,6 @@ __device__ __forceinline__ PassResult estimator_pass(const Prob& P, const int32_
   const double qpart = (P.cv_order == 2) ? (bl * delta64 + 0.5 * delta64 * cdel) : bl * delta64;
   const double qsum = wave_sum(qpart);
   out.lhat = P.cvA[0] + qsum + out.dhat;
-  const double s1c = pick_lane<DC>(s1, lane);
-  const double t1c = pick_lane<DC>(t1, lane);
   out.gl = lane < d ? bl + (P.cv_order == 2 ? cdel : 0.0) + nm * s1c : 0.0;
   out.gs = lane < d ? 2.0 * nm * nm * (t1c - dbar_minus_shift * s1c) : 0.0;
   return out;
@@ -235,8 +263,9 @@ struct EstArgs {
   double* grad;          // count*d (nullable)
 };
 
-template <typename Real, int DC>
+template <typename Real, int DC, int FAM>
 __global__ void __launch_bounds__(kWave) estimator_kernel(EstArgs A) {
+  __shared__ Real red[kWave * DC];
   const int i = blockIdx.x;
   const int lane = threadIdx.x;
   if (i >= A.count) return;
@@ -244,7 +273,7 @@ __global__ void __launch_bounds__(kWave) estimator_kernel(EstArgs A) {
   const int d = P.d;
   const double th = lane < d ? A.theta[(int64_t)i * d + lane] : 0.0;
   const double tb = lane < d ? P.theta_bar[lane] : 0.0;
-  const PassResult r = estimator_pass<Real, DC>(P, A.u + (int64_t)i * P.m, 0, 0, 0, 0, th - tb, lane);
+  const PassResult r = estimator_pass<Real, DC, FAM, false>(P, A.u + (int64_t)i * P.m, 0, 0, nullptr, red, th - tb, lane);
   if (lane == 0) {
     if (A.lhat) A.lhat[i] = r.lhat;
     if (A.sig2) A.sig2[i] = r.sig2;
@@ -264,6 +293,7 @@ __global__ void __launch_bounds__(kWave) estimator_kernel(EstArgs A) {
 // --------------------------------------------------------------------------
 // fused Markov move (Algorithm 1): block pseudo-marginal refresh of u, then
 // HMC on theta given u with inverse mass matrix Sigma; R = 1 per launch.
+// Dynamic LDS: ceil(m/G) int32 for the refreshed block's indices.
 // --------------------------------------------------------------------------
 
 struct MoveArgs {
@@ -304,8 +334,10 @@ __device__ __forceinline__ double sigma_times(const Prob& P, double p, int lane)
   return acc;
 }
 
-template <typename Real, int DC>
+template <typename Real, int DC, int FAM>
 __global__ void __launch_bounds__(kWave) move_kernel(MoveArgs A) {
+  __shared__ Real red[kWave * DC];
+  extern __shared__ int32_t blk[];
   const int i = blockIdx.x;
   const int lane = threadIdx.x;
   const Prob& P = A.P;
@@ -328,20 +360,20 @@ __global__ void __launch_bounds__(kWave) move_kernel(MoveArgs A) {
   const int b0 = (int)((int64_t)g * m / P.G);
   const int b1 = (int)((int64_t)(g + 1) * m / P.G);
   const uint64_t cb = stream_ctr0(kBlockIndex, A.stage, A.move, 0);
-  int ob0 = 0, ob1 = 0;
+  for (int t = lane; t < b1 - b0; t += kWave)
+    blk[t] = (int32_t)word_to_index(stream_word(P.seed, cb, (uint64_t)i, (uint64_t)t), (uint64_t)P.n);
+  __syncthreads();
+  int ob0 = 0, ob1 = 0;  // block override seen by the leapfrog passes
   {
-    const PassResult r = estimator_pass<Real, DC>(P, urow, b0, b1, cb, (uint64_t)i, th - tb, lane);
+    const PassResult r = estimator_pass<Real, DC, FAM, true>(P, urow, b0, b1, blk, red, th - tb, lane);
     const double lam0 = a * lh0 - 0.5 * a * a * sg0;
     const double lam1 = a * r.lhat - 0.5 * a * a * r.sig2;
     const double logr = lam1 - lam0;
     const double logU = log(word_to_uniform(stream_word(P.seed, stream_ctr0(kUAccept, A.stage, A.move, 0), (uint64_t)i, 0)));
     const bool acc = isfinite(logr) && (logU < logr);
     if (acc) {
-      for (int j = b0 + lane; j < b1; j += kWave)
-        urow[j] = (int32_t)word_to_index(stream_word(P.seed, cb, (uint64_t)i, (uint64_t)(j - b0)), (uint64_t)P.n);
+      for (int t = lane; t < b1 - b0; t += kWave) urow[b0 + t] = blk[t];
       lh0 = r.lhat; sg0 = r.sig2; gl0 = r.gl; gs0 = r.gs;
-      // later passes of this launch regenerate the new block instead of
-      // reading back the indices just stored
       ob0 = b0; ob1 = b1;
     }
     if (lane == 0) A.accept[2 * i] = acc ? 1 : 0;
@@ -370,7 +402,7 @@ __global__ void __launch_bounds__(kWave) move_kernel(MoveArgs A) {
   for (int l = 1; l <= A.L; ++l) {
     v = sigma_times(P, p, lane);
     th1 += eps * v;
-    r1 = estimator_pass<Real, DC>(P, urow, ob0, ob1, cb, (uint64_t)i, th1 - tb, lane);
+    r1 = estimator_pass<Real, DC, FAM, true>(P, urow, ob0, ob1, blk, red, th1 - tb, lane);
     prior_terms<DC>(P, th1, lane, rq, lp1);
     grad = a * r1.gl - 0.5 * a * a * r1.gs - rq;
     p += ((l < A.L) ? eps : 0.5 * eps) * grad;
@@ -467,12 +499,13 @@ __device__ __forceinline__ double block_max(double v, double* sh) {
 // --------------------------------------------------------------------------
 
 constexpr int kTemperThreads = 1024;
-constexpr int kTemperPer = 8;  // particles per thread: M <= 8192
+constexpr int kTemperWaves = kTemperThreads / kWave;  // candidates per round
+constexpr int kTemperPer = 8;                          // M <= 8192
+constexpr int kTemperRounds = 15;                      // 17^15 > 2^61 subdivisions
 
 struct TemperArgs {
   int M;
   double a_prev, ess_frac;
-  int n_bisect;
   const double* lhat;
   const double* sig2;
   double* logw;     // in/out
@@ -484,68 +517,84 @@ __device__ __forceinline__ double incr_weight(double a, double a_prev, double lh
   return isfinite(v) ? v : -INFINITY;
 }
 
-__global__ void __launch_bounds__(kTemperThreads) temper_kernel(TemperArgs A) {
-  __shared__ double sh[kTemperThreads / kWave];
-  const int t = threadIdx.x;
-  double lw[kTemperPer], lh[kTemperPer], s2[kTemperPer];
+// ESS((W_i exp(nu_i(a)))) over all M particles, evaluated by one wavefront.
+__device__ double wave_ess(const TemperArgs& A, double a, int lane) {
+  double mx = -INFINITY;
+  for (int i = lane; i < A.M; i += kWave) mx = fmax(mx, A.logw[i] + incr_weight(a, A.a_prev, A.lhat[i], A.sig2[i]));
 #pragma unroll
-  for (int q = 0; q < kTemperPer; ++q) {
-    const int i = t + q * kTemperThreads;
-    const bool ok = i < A.M;
-    lw[q] = ok ? A.logw[i] : -INFINITY;
-    lh[q] = ok ? A.lhat[i] : 0.0;
-    s2[q] = ok ? A.sig2[i] : 0.0;
+  for (int o = 32; o >= 1; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, kWave));
+  if (!isfinite(mx)) return 0.0;
+  double w1 = 0.0, w2 = 0.0;
+  for (int i = lane; i < A.M; i += kWave) {
+    const double w = exp(A.logw[i] + incr_weight(a, A.a_prev, A.lhat[i], A.sig2[i]) - mx);
+    w1 += w;
+    w2 += w * w;
   }
-  auto ess_at = [&](double a) -> double {
-    double mx = -INFINITY;
-#pragma unroll
-    for (int q = 0; q < kTemperPer; ++q) mx = fmax(mx, lw[q] + incr_weight(a, A.a_prev, lh[q], s2[q]));
-    mx = block_max<kTemperThreads>(mx, sh);
-    if (!isfinite(mx)) return 0.0;
-    double w1 = 0.0, w2 = 0.0;
-#pragma unroll
-    for (int q = 0; q < kTemperPer; ++q) {
-      const double w = exp(lw[q] + incr_weight(a, A.a_prev, lh[q], s2[q]) - mx);
-      w1 += w;
-      w2 += w * w;
-    }
-    w1 = block_sum<kTemperThreads>(w1, sh);
-    w2 = block_sum<kTemperThreads>(w2, sh);
-    return w1 * w1 / w2;
-  };
+  w1 = wave_sum(w1);
+  w2 = wave_sum(w2);
+  return w1 * w1 / w2;
+}
+
+// Tempering exponent: the ESS target is bracketed by multisection, each
+// wavefront testing one of 16 equispaced interior points per round and the
+// bracket shrinking to the gap before the first point whose ESS falls below
+// the target (bisection with 16 probes per step). a = 1 when ESS(1) meets the
+// target. Then the reweighting and the evidence increment
+// log sum_i W_i exp(nu_i) (sections 2.2, 3.3, 3.5; Algorithm 2 steps b-c).
+__global__ void __launch_bounds__(kTemperThreads) temper_kernel(TemperArgs A) {
+  __shared__ double sh[kTemperWaves];
+  __shared__ int flag[kTemperWaves];
+  const int t = threadIdx.x, w = t / kWave, lane = t % kWave;
   const double target = A.ess_frac * (double)A.M;
-  double a;
-  if (ess_at(1.0) >= target) {
-    a = 1.0;
-  } else {
+  __shared__ double ess1;
+  if (w == 0) {
+    const double e = wave_ess(A, 1.0, lane);
+    if (lane == 0) ess1 = e;
+  }
+  __syncthreads();
+  double a = 1.0;
+  if (!(ess1 >= target)) {
     double lo = A.a_prev, hi = 1.0;
-    for (int it = 0; it < A.n_bisect; ++it) {
-      const double mid = 0.5 * (lo + hi);
-      if (ess_at(mid) >= target) lo = mid;
-      else hi = mid;
+    for (int round = 0; round < kTemperRounds; ++round) {
+      const double cand = lo + (hi - lo) * (double)(w + 1) / (double)(kTemperWaves + 1);
+      const double e = wave_ess(A, cand, lane);
+      if (lane == 0) flag[w] = (e >= target) ? 1 : 0;
+      __syncthreads();
+      int first_fail = kTemperWaves;
+      for (int k = kTemperWaves - 1; k >= 0; --k) first_fail = flag[k] ? first_fail : k;
+      const double nlo = first_fail == 0 ? lo : lo + (hi - lo) * (double)first_fail / (double)(kTemperWaves + 1);
+      const double nhi = first_fail == kTemperWaves ? hi
+                                                    : lo + (hi - lo) * (double)(first_fail + 1) / (double)(kTemperWaves + 1);
+      lo = nlo;
+      hi = nhi;
+      __syncthreads();
     }
     a = (lo > A.a_prev) ? lo : hi;
   }
-  const double ess = ess_at(a);
-  // log-sum-exp of old and new log weights
+  // reweight, normalise and the evidence increment
+  double lw[kTemperPer], nw[kTemperPer];
   double mo = -INFINITY, mn = -INFINITY;
-  double nw[kTemperPer];
 #pragma unroll
   for (int q = 0; q < kTemperPer; ++q) {
-    nw[q] = lw[q] + incr_weight(a, A.a_prev, lh[q], s2[q]);
+    const int i = t + q * kTemperThreads;
+    lw[q] = i < A.M ? A.logw[i] : -INFINITY;
+    nw[q] = i < A.M ? lw[q] + incr_weight(a, A.a_prev, A.lhat[i], A.sig2[i]) : -INFINITY;
     mo = fmax(mo, lw[q]);
     mn = fmax(mn, nw[q]);
   }
   mo = block_max<kTemperThreads>(mo, sh);
   mn = block_max<kTemperThreads>(mn, sh);
-  double so = 0.0, sn = 0.0;
+  double so = 0.0, sn = 0.0, sn2 = 0.0;
 #pragma unroll
   for (int q = 0; q < kTemperPer; ++q) {
     so += exp(lw[q] - mo);
-    sn += exp(nw[q] - mn);
+    const double e = exp(nw[q] - mn);
+    sn += e;
+    sn2 += e * e;
   }
   so = block_sum<kTemperThreads>(so, sh);
   sn = block_sum<kTemperThreads>(sn, sh);
+  sn2 = block_sum<kTemperThreads>(sn2, sh);
   const double lse_old = mo + log(so);
   const double lse_new = mn + log(sn);
   const bool ok = isfinite(lse_new);
@@ -557,7 +606,7 @@ __global__ void __launch_bounds__(kTemperThreads) temper_kernel(TemperArgs A) {
   if (t == 0) {
     A.out[0] = a;
     A.out[1] = lse_new - lse_old;
-    A.out[2] = ess;
+    A.out[2] = sn * sn / sn2;
     A.out[3] = ok ? 0.0 : 1.0;
   }
 }
@@ -647,18 +696,38 @@ __global__ void __launch_bounds__(kMomThreads) factor_kernel(FactorArgs F) {
   factor_spd(F, sh);
 }
 
+// Weighted mean and covariance, accumulated about theta_bar (close to the
+// particle mean, so the one-pass second moment does not cancel): block b sums
+// W_i (theta_i - theta_bar) and W_i (theta_i - theta_bar)(theta_i - theta_bar)'
+// over its particles into partials; the final kernel adds the partials in block
+// order, forms mean and covariance and factors the covariance.
+constexpr int kMomTile = 128;  // particles per block
+
 struct MomentArgs {
   int M, d;
   const double* theta;
   const double* logw;
-  double* mean;   // d
-  FactorArgs F;   // F.S receives the covariance
+  const double* centre;   // d
+  double* partials;       // nblocks * (d + d(d+1)/2)
+  int nblocks;
+  double* mean;           // d
+  FactorArgs F;           // F.S receives the covariance
 };
 
-__global__ void __launch_bounds__(kMomThreads) moments_kernel(MomentArgs A) {
+__device__ __forceinline__ void tri_index(int f, int& r, int& c) {
+  r = (int)((sqrt(8.0 * f + 1.0) - 1.0) * 0.5);
+  while ((r + 1) * (r + 2) / 2 <= f) ++r;
+  while (r * (r + 1) / 2 > f) --r;
+  c = f - r * (r + 1) / 2;
+}
+
+__global__ void __launch_bounds__(kMomThreads) moments_partial_kernel(MomentArgs A) {
   __shared__ double sh[kMomThreads / kWave];
+  __shared__ double wt[kMomTile];
+  extern __shared__ double xs[];  // kMomTile * d
   const int t = threadIdx.x;
   const int M = A.M, d = A.d;
+  // log-sum-exp of all weights (each block redundantly)
   double mx = -INFINITY;
   for (int i = t; i < M; i += kMomThreads) mx = fmax(mx, A.logw[i]);
   mx = block_max<kMomThreads>(mx, sh);
@@ -666,25 +735,47 @@ __global__ void __launch_bounds__(kMomThreads) moments_kernel(MomentArgs A) {
   for (int i = t; i < M; i += kMomThreads) s += exp(A.logw[i] - mx);
   s = block_sum<kMomThreads>(s, sh);
   const double lse = mx + log(s);
-  for (int r = t; r < d; r += kMomThreads) {
-    double acc = 0.0;
-    for (int i = 0; i < M; ++i) acc += exp(A.logw[i] - lse) * A.theta[(int64_t)i * d + r];
-    A.mean[r] = acc;
+  const int i0 = blockIdx.x * kMomTile;
+  const int cnt = min(kMomTile, M - i0);
+  for (int q = t; q < kMomTile; q += kMomThreads) wt[q] = q < cnt ? exp(A.logw[i0 + q] - lse) : 0.0;
+  for (int e = t; e < kMomTile * d; e += kMomThreads) {
+    const int q = e / d, c = e % d;
+    xs[e] = q < cnt ? A.theta[(int64_t)(i0 + q) * d + c] - A.centre[c] : 0.0;
   }
   __syncthreads();
-  const int ne = d * (d + 1) / 2;
+  const int ne = d + d * (d + 1) / 2;
   for (int e = t; e < ne; e += kMomThreads) {
-    // e -> (r, c) with c <= r
-    int r = (int)((sqrt(8.0 * e + 1.0) - 1.0) * 0.5);
-    while ((r + 1) * (r + 2) / 2 <= e) ++r;
-    while (r * (r + 1) / 2 > e) --r;
-    const int c = e - r * (r + 1) / 2;
-    const double mr = A.mean[r], mc = A.mean[c];
     double acc = 0.0;
-    for (int i = 0; i < M; ++i)
-      acc += exp(A.logw[i] - lse) * (A.theta[(int64_t)i * d + r] - mr) * (A.theta[(int64_t)i * d + c] - mc);
-    A.F.S[r * d + c] = acc;
-    A.F.S[c * d + r] = acc;
+    if (e < d) {
+      for (int q = 0; q < cnt; ++q) acc += wt[q] * xs[q * d + e];
+    } else {
+      int r, c;
+      tri_index(e - d, r, c);
+      for (int q = 0; q < cnt; ++q) acc += wt[q] * xs[q * d + r] * xs[q * d + c];
+    }
+    A.partials[(int64_t)blockIdx.x * ne + e] = acc;
+  }
+}
+
+__global__ void __launch_bounds__(kMomThreads) moments_final_kernel(MomentArgs A) {
+  __shared__ double sh[kMomThreads / kWave];
+  extern __shared__ double tot[];  // d + d(d+1)/2
+  const int t = threadIdx.x;
+  const int d = A.d;
+  const int ne = d + d * (d + 1) / 2;
+  for (int e = t; e < ne; e += kMomThreads) {
+    double acc = 0.0;
+    for (int b = 0; b < A.nblocks; ++b) acc += A.partials[(int64_t)b * ne + e];
+    tot[e] = acc;
+  }
+  __syncthreads();
+  for (int r = t; r < d; r += kMomThreads) A.mean[r] = A.centre[r] + tot[r];
+  for (int f = t; f < d * (d + 1) / 2; f += kMomThreads) {
+    int r, c;
+    tri_index(f, r, c);
+    const double v = tot[d + f] - tot[r] * tot[c];
+    A.F.S[r * d + c] = v;
+    A.F.S[c * d + r] = v;
   }
   __syncthreads();
   factor_spd(A.F, sh);

@@ -20,6 +20,7 @@ namespace {
 constexpr int kMaxD = 32;
 constexpr int kMaxM = kTemperThreads * kTemperPer;
 constexpr int kCvMaxBlocks = 1024;
+constexpr int kMaxBlock = 16384;  // slots per refreshed block (LDS)
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
@@ -34,9 +35,10 @@ int packed_ld(int d, bool fp32) {
 // Workspace regions, in carve order.
 struct Layout {
   size_t Xp, theta_bar, cvA, cvB, cvC, mu0, Q0, Qw, L0, L0inv, Sigma, Lchol, Linv, mean, status,
-      tout, scratch_theta, grad_l, grad_s, anc, th2, u2, lh2, sg2, gl2, gs2, partials, total;
+      tout, scratch_theta, grad_l, grad_s, anc, th2, u2, lh2, sg2, gl2, gs2, partials, mpartials, total;
   int ld;
   int cv_blocks;
+  int mom_blocks;
 };
 
 bool compute_layout(const smc_problem* pb, Layout& L) {
@@ -78,6 +80,8 @@ bool compute_layout(const smc_problem* pb, Layout& L) {
   L.gl2 = take(M * d * 8);
   L.gs2 = take(M * d * 8);
   L.partials = take((size_t)L.cv_blocks * ne * 8);
+  L.mom_blocks = (pb->M + kMomTile - 1) / kMomTile;
+  L.mpartials = take((size_t)L.mom_blocks * (d + (size_t)d * (d + 1) / 2) * 8);
   L.total = off;
   return true;
 }
@@ -128,8 +132,8 @@ smc_status validate(const smc_problem* pb) {
   if (pb->d < 1 || pb->n < 1 || pb->n >= (int64_t(1) << 31)) return SMC_ERR_INVALID_ARG;
   if (pb->ld < pb->d + 1 || !pb->Xy) return SMC_ERR_INVALID_ARG;
   if (pb->M < 1 || pb->M > kMaxM || pb->m < 1 || pb->G < 1 || pb->G > pb->m) return SMC_ERR_INVALID_ARG;
-  if (!(pb->ess_frac > 0.0 && pb->ess_frac <= 1.0) || pb->n_bisect < 1 || pb->n_bisect > 200)
-    return SMC_ERR_INVALID_ARG;
+  if (!(pb->ess_frac > 0.0 && pb->ess_frac <= 1.0)) return SMC_ERR_INVALID_ARG;
+  if ((pb->m + pb->G - 1) / pb->G > kMaxBlock) return SMC_ERR_UNSUPPORTED;
   if (!pb->prior_mean || !pb->prior_prec) return SMC_ERR_INVALID_ARG;
   if (!pb->theta || !pb->u || !pb->logw || !pb->lhat || !pb->sig2 || !pb->accept || !pb->workspace)
     return SMC_ERR_INVALID_ARG;
@@ -142,10 +146,21 @@ smc_status validate(const smc_problem* pb) {
 // kernel dispatch on (precision, padded d)
 // ------------------------------------------------------------------------
 
-template <typename Real>
+template <typename Real, int FAM>
 hipError_t launch_estimator_t(int dc, int count, const EstArgs& a, hipStream_t s) {
   switch (dc) {
-#define CASE(DC) case DC: hipLaunchKernelGGL((estimator_kernel<Real, DC>), dim3(count), dim3(kWave), 0, s, a); break;
+#define CASE(DC) case DC: hipLaunchKernelGGL((estimator_kernel<Real, DC, FAM>), dim3(count), dim3(kWave), 0, s, a); break;
+    CASE(4) CASE(8) CASE(12) CASE(16) CASE(20) CASE(24) CASE(28) CASE(32)
+#undef CASE
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <typename Real, int FAM>
+hipError_t launch_move_t(int dc, int M, size_t lds, const MoveArgs& a, hipStream_t s) {
+  switch (dc) {
+#define CASE(DC) case DC: hipLaunchKernelGGL((move_kernel<Real, DC, FAM>), dim3(M), dim3(kWave), lds, s, a); break;
     CASE(4) CASE(8) CASE(12) CASE(16) CASE(20) CASE(24) CASE(28) CASE(32)
 #undef CASE
     default: return hipErrorInvalidValue;
@@ -154,27 +169,39 @@ hipError_t launch_estimator_t(int dc, int count, const EstArgs& a, hipStream_t s
 }
 
 template <typename Real>
-hipError_t launch_move_t(int dc, int M, const MoveArgs& a, hipStream_t s) {
-  switch (dc) {
-#define CASE(DC) case DC: hipLaunchKernelGGL((move_kernel<Real, DC>), dim3(M), dim3(kWave), 0, s, a); break;
-    CASE(4) CASE(8) CASE(12) CASE(16) CASE(20) CASE(24) CASE(28) CASE(32)
-#undef CASE
-    default: return hipErrorInvalidValue;
+hipError_t launch_estimator_p(int fam, int dc, int count, const EstArgs& a, hipStream_t s) {
+  switch (fam) {
+    case kLogistic: return launch_estimator_t<Real, kLogistic>(dc, count, a, s);
+    case kPoisson: return launch_estimator_t<Real, kPoisson>(dc, count, a, s);
+    default: return launch_estimator_t<Real, kGaussian>(dc, count, a, s);
   }
-  return hipGetLastError();
+}
+
+template <typename Real>
+hipError_t launch_move_p(int fam, int dc, int M, size_t lds, const MoveArgs& a, hipStream_t s) {
+  switch (fam) {
+    case kLogistic: return launch_move_t<Real, kLogistic>(dc, M, lds, a, s);
+    case kPoisson: return launch_move_t<Real, kPoisson>(dc, M, lds, a, s);
+    default: return launch_move_t<Real, kGaussian>(dc, M, lds, a, s);
+  }
 }
 
 hipError_t launch_estimator(smc_ctx c, int count, const EstArgs& a) {
   if (count <= 0) return hipSuccess;
   const int dc = pad_dc(c->pb.d);
-  return c->pb.precision == SMC_MIXED ? launch_estimator_t<float>(dc, count, a, c->stream)
-                                      : launch_estimator_t<double>(dc, count, a, c->stream);
+  return c->pb.precision == SMC_MIXED ? launch_estimator_p<float>(c->pb.family, dc, count, a, c->stream)
+                                      : launch_estimator_p<double>(c->pb.family, dc, count, a, c->stream);
+}
+
+size_t block_lds_bytes(const smc_problem& pb) {
+  return (size_t)((pb.m + pb.G - 1) / pb.G) * sizeof(int32_t);
 }
 
 hipError_t launch_move(smc_ctx c, const MoveArgs& a) {
   const int dc = pad_dc(c->pb.d);
-  return c->pb.precision == SMC_MIXED ? launch_move_t<float>(dc, c->pb.M, a, c->stream)
-                                      : launch_move_t<double>(dc, c->pb.M, a, c->stream);
+  const size_t lds = block_lds_bytes(c->pb);
+  return c->pb.precision == SMC_MIXED ? launch_move_p<float>(c->pb.family, dc, c->pb.M, lds, a, c->stream)
+                                      : launch_move_p<double>(c->pb.family, dc, c->pb.M, lds, a, c->stream);
 }
 
 // Full-data A, B, C at device theta; packs rows when pack != 0.
@@ -455,7 +482,6 @@ smc_status smc_temper(smc_ctx c, double* a_out, double* dlogz_out, double* ess_o
   t.M = c->pb.M;
   t.a_prev = c->a;
   t.ess_frac = c->pb.ess_frac;
-  t.n_bisect = c->pb.n_bisect;
   t.lhat = c->pb.lhat;
   t.sig2 = c->pb.sig2;
   t.logw = c->pb.logw;
@@ -479,18 +505,26 @@ smc_status smc_temper(smc_ctx c, double* a_out, double* dlogz_out, double* ess_o
 
 smc_status smc_mass(smc_ctx c) {
   if (!c) return SMC_ERR_INVALID_ARG;
+  const int d = c->pb.d;
   MomentArgs a;
   a.M = c->pb.M;
-  a.d = c->pb.d;
+  a.d = d;
   a.theta = c->pb.theta;
   a.logw = c->pb.logw;
+  a.centre = c->prob.theta_bar;
+  a.partials = c->at<double>(c->lay.mpartials);
+  a.nblocks = c->lay.mom_blocks;
   a.mean = c->at<double>(c->lay.mean);
-  a.F.d = c->pb.d;
+  a.F.d = d;
   a.F.S = c->at<double>(c->lay.Sigma);
   a.F.L = c->at<double>(c->lay.Lchol);
   a.F.Linv = c->at<double>(c->lay.Linv);
   a.F.status = c->at<double>(c->lay.status);
-  hipLaunchKernelGGL(moments_kernel, dim3(1), dim3(kMomThreads), 0, c->stream, a);
+  hipLaunchKernelGGL(moments_partial_kernel, dim3(a.nblocks), dim3(kMomThreads), (size_t)kMomTile * d * 8,
+                     c->stream, a);
+  LAUNCH_CHECK(c);
+  hipLaunchKernelGGL(moments_final_kernel, dim3(1), dim3(kMomThreads), (size_t)(d + d * (d + 1) / 2) * 8,
+                     c->stream, a);
   LAUNCH_CHECK(c);
   double stv = 0.0;
   HIP_TRY(c, hipMemcpyAsync(&stv, a.F.status, 8, hipMemcpyDeviceToHost, c->stream));

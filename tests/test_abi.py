@@ -52,7 +52,7 @@ def _problem(d=5, n=1000, M=64, m=100, G=4, ld=8, family=0, precision=0):
     pb = B._Problem()
     pb.family, pb.precision, pb.cv_order, pb.d = family, precision, 2, d
     pb.n, pb.ld, pb.xy_fp32, pb.Xy = n, ld, 0, 0x1000
-    pb.gauss_s2, pb.M, pb.m, pb.G, pb.n_bisect = 1.0, M, m, G, 60
+    pb.gauss_s2, pb.M, pb.m, pb.G = 1.0, M, m, G
     pb.seed, pb.ess_frac = 1, 0.5
     pb.prior_mean = pb.prior_prec = 0x2000
     for f in ("theta", "u", "logw", "lhat", "sig2", "accept", "workspace"):
