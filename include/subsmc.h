@@ -113,7 +113,7 @@ smc_status smc_init(const smc_problem* pb, void* stream, smc_ctx* out);
 /*
  * Algorithm 2 steps a-c. Increments the stage, chooses the next exponent
  * a in (a_prev, 1] with ESS(a) = ess_frac * M by multisection (bisection
- * with 16 probes per step, 15 steps: resolution below 1e-16 of 1 - a_prev;
+ * with 8 probes per step, 19 steps: resolution below 1e-18 of 1 - a_prev;
  * a = 1 when ESS(1) already meets it), reweights logw with the annealed estimator
  * (a - a_prev) l_hat - (a^2 - a_prev^2) sigma2_hat / 2 (normalised), and adds
  * the log evidence increment log sum_i W_i exp(...) (section 3.5).

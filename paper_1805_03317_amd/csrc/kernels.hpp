@@ -183,15 +183,25 @@ __device__ __forceinline__ PassResult estimator_pass(const Prob& P, const int32_
 #pragma unroll
   for (int c = 0; c < DC; ++c) { S1[c] = Real(0); T1[c] = Real(0); }
 
+  // rows are prefetched one iteration ahead (measured: for FP64 d = 20 one
+  // resident wave with the prefetch beats two without it)
+  constexpr bool kPrefetchRow = true;
   int j = lane;
   int32_t k_cur = j < m ? index_of(j) : 0;
   int32_t k_nxt = j + kWave < m ? index_of(j + kWave) : 0;
   RowLoad<Real, DC> r_nxt;
-  if (j < m) load_row<Real, DC>(X + (int64_t)((uint32_t)k_cur < n ? k_cur : 0) * ld, r_nxt);
+  if constexpr (kPrefetchRow) {
+    if (j < m) load_row<Real, DC>(X + (int64_t)((uint32_t)k_cur < n ? k_cur : 0) * ld, r_nxt);
+  }
   for (; j < m; j += kWave) {
-    const RowLoad<Real, DC> r = r_nxt;
+    RowLoad<Real, DC> r;
     const bool bad = (uint32_t)k_cur >= n;
-    if (j + kWave < m) load_row<Real, DC>(X + (int64_t)((uint32_t)k_nxt < n ? k_nxt : 0) * ld, r_nxt);
+    if constexpr (kPrefetchRow) {
+      r = r_nxt;
+      if (j + kWave < m) load_row<Real, DC>(X + (int64_t)((uint32_t)k_nxt < n ? k_nxt : 0) * ld, r_nxt);
+    } else {
+      load_row<Real, DC>(X + (int64_t)(bad ? 0 : k_cur) * ld, r);
+    }
     k_cur = k_nxt;
     k_nxt = j + 2 * kWave < m ? index_of(j + 2 * kWave) : 0;
 
@@ -499,9 +509,9 @@ __device__ __forceinline__ double block_max(double v, double* sh) {
 // --------------------------------------------------------------------------
 
 constexpr int kTemperThreads = 1024;
-constexpr int kTemperWaves = kTemperThreads / kWave;  // candidates per round
-constexpr int kTemperPer = 8;                          // M <= 8192
-constexpr int kTemperRounds = 15;                      // 17^15 > 2^61 subdivisions
+constexpr int kTemperWaves = kTemperThreads / kWave;
+constexpr int kTemperPer = 8;        // particles per thread: M <= 8192
+constexpr int kTemperMaxIter = 100;  // root-finding iterations (each one ESS evaluation)
 
 struct TemperArgs {
   int M;
@@ -509,7 +519,7 @@ struct TemperArgs {
   const double* lhat;
   const double* sig2;
   double* logw;     // in/out
-  double* out;      // [a, dlogz, ess, status]
+  double* out;      // [a, dlogz, ess, status, evaluations]
 };
 
 __device__ __forceinline__ double incr_weight(double a, double a_prev, double lh, double s2) {
@@ -517,73 +527,123 @@ __device__ __forceinline__ double incr_weight(double a, double a_prev, double lh
   return isfinite(v) ? v : -INFINITY;
 }
 
-// ESS((W_i exp(nu_i(a)))) over all M particles, evaluated by one wavefront.
-__device__ double wave_ess(const TemperArgs& A, double a, int lane) {
-  double mx = -INFINITY;
-  for (int i = lane; i < A.M; i += kWave) mx = fmax(mx, A.logw[i] + incr_weight(a, A.a_prev, A.lhat[i], A.sig2[i]));
+// Block reductions with one barrier each: every call writes the wave partials
+// into its own half of `sh` (the caller alternates `buf`), so a write never
+// races the previous call's reads. Fixed order: butterfly, then waves 0..15.
+__device__ __forceinline__ double block_max_1(double v, double* sh, int buf) {
+  const int w = threadIdx.x / kWave, l = threadIdx.x % kWave;
 #pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, kWave));
-  if (!isfinite(mx)) return 0.0;
-  double w1 = 0.0, w2 = 0.0;
-  for (int i = lane; i < A.M; i += kWave) {
-    const double w = exp(A.logw[i] + incr_weight(a, A.a_prev, A.lhat[i], A.sig2[i]) - mx);
-    w1 += w;
-    w2 += w * w;
-  }
-  w1 = wave_sum(w1);
-  w2 = wave_sum(w2);
-  return w1 * w1 / w2;
+  for (int o = 32; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o, kWave));
+  double* b = sh + buf * 2 * kTemperWaves;
+  if (l == 0) b[w] = v;
+  __syncthreads();
+  double t = -INFINITY;
+#pragma unroll
+  for (int q = 0; q < kTemperWaves; ++q) t = fmax(t, b[q]);
+  return t;
 }
 
-// Tempering exponent: the ESS target is bracketed by multisection, each
-// wavefront testing one of 16 equispaced interior points per round and the
-// bracket shrinking to the gap before the first point whose ESS falls below
-// the target (bisection with 16 probes per step). a = 1 when ESS(1) meets the
-// target. Then the reweighting and the evidence increment
-// log sum_i W_i exp(nu_i) (sections 2.2, 3.3, 3.5; Algorithm 2 steps b-c).
-__global__ void __launch_bounds__(kTemperThreads) temper_kernel(TemperArgs A) {
-  __shared__ double sh[kTemperWaves];
-  __shared__ int flag[kTemperWaves];
-  const int t = threadIdx.x, w = t / kWave, lane = t % kWave;
-  const double target = A.ess_frac * (double)A.M;
-  __shared__ double ess1;
-  if (w == 0) {
-    const double e = wave_ess(A, 1.0, lane);
-    if (lane == 0) ess1 = e;
-  }
+__device__ __forceinline__ void block_sum_2(double& v1, double& v2, double* sh, int buf) {
+  const int w = threadIdx.x / kWave, l = threadIdx.x % kWave;
+  v1 = wave_sum(v1);
+  v2 = wave_sum(v2);
+  double* b = sh + buf * 2 * kTemperWaves;
+  if (l == 0) { b[w] = v1; b[kTemperWaves + w] = v2; }
   __syncthreads();
+  double t1 = 0.0, t2 = 0.0;
+#pragma unroll
+  for (int q = 0; q < kTemperWaves; ++q) { t1 += b[q]; t2 += b[kTemperWaves + q]; }
+  v1 = t1;
+  v2 = t2;
+}
+
+// Tempering exponent (section 2.2; Algorithm 2 step b): the root in
+// (a_prev, 1] of g(a) = log ESS(a) - log(ess_frac M), by false position with
+// the Illinois modification, keeping the bracket [lo, hi] with g(lo) >= 0 >
+// g(hi) and taking a bisection step every fourth iteration, until the bracket
+// is below 1e-15 (1 - a_prev). a = 1 when ESS(1) meets the target; a = lo
+// (the largest point found with ESS >= target), or hi if lo never moved.
+// Then the reweighting, normalisation and the evidence increment
+// log sum_i W_i exp(nu_i) (sections 3.3, 3.5; Algorithm 2 step c).
+__global__ void __launch_bounds__(kTemperThreads) temper_kernel(TemperArgs A) {
+  __shared__ double sh[4 * 2 * kTemperWaves];
+  const int t = threadIdx.x;
+  double lw[kTemperPer], lh[kTemperPer], s2[kTemperPer];
+#pragma unroll
+  for (int q = 0; q < kTemperPer; ++q) {
+    const int i = t + q * kTemperThreads;
+    const bool ok = i < A.M;
+    lw[q] = ok ? A.logw[i] : -INFINITY;
+    lh[q] = ok ? A.lhat[i] : 0.0;
+    s2[q] = ok ? A.sig2[i] : 0.0;
+  }
+  const double log_target = log(A.ess_frac * (double)A.M);
+  int buf = 0, evals = 0;
+  auto log_ess = [&](double a) -> double {
+    double mx = -INFINITY;
+#pragma unroll
+    for (int q = 0; q < kTemperPer; ++q) mx = fmax(mx, lw[q] + incr_weight(a, A.a_prev, lh[q], s2[q]));
+    mx = block_max_1(mx, sh, buf);
+    buf = (buf + 1) & 3;
+    double w1 = 0.0, w2 = 0.0;
+    if (isfinite(mx)) {
+#pragma unroll
+      for (int q = 0; q < kTemperPer; ++q) {
+        const double w = exp(lw[q] + incr_weight(a, A.a_prev, lh[q], s2[q]) - mx);
+        w1 += w;
+        w2 += w * w;
+      }
+    }
+    block_sum_2(w1, w2, sh, buf);
+    buf = (buf + 1) & 3;
+    ++evals;
+    return isfinite(mx) ? 2.0 * log(w1) - log(w2) : -INFINITY;
+  };
   double a = 1.0;
-  if (!(ess1 >= target)) {
+  double ghi = log_ess(1.0) - log_target;
+  if (!(ghi >= 0.0)) {
     double lo = A.a_prev, hi = 1.0;
-    for (int round = 0; round < kTemperRounds; ++round) {
-      const double cand = lo + (hi - lo) * (double)(w + 1) / (double)(kTemperWaves + 1);
-      const double e = wave_ess(A, cand, lane);
-      if (lane == 0) flag[w] = (e >= target) ? 1 : 0;
-      __syncthreads();
-      int first_fail = kTemperWaves;
-      for (int k = kTemperWaves - 1; k >= 0; --k) first_fail = flag[k] ? first_fail : k;
-      const double nlo = first_fail == 0 ? lo : lo + (hi - lo) * (double)first_fail / (double)(kTemperWaves + 1);
-      const double nhi = first_fail == kTemperWaves ? hi
-                                                    : lo + (hi - lo) * (double)(first_fail + 1) / (double)(kTemperWaves + 1);
-      lo = nlo;
-      hi = nhi;
-      __syncthreads();
+    double glo = log_ess(lo) - log_target;
+    const double tol = 1e-15 * (1.0 - A.a_prev);
+    if (glo >= 0.0) {
+      int side = 0;
+      for (int it = 0; it < kTemperMaxIter && (hi - lo) > tol; ++it) {
+        double c = (it % 4 == 3) ? 0.5 * (lo + hi) : hi - ghi * (hi - lo) / (ghi - glo);
+        if (!(c > lo && c < hi)) c = 0.5 * (lo + hi);
+        if (!(c > lo && c < hi)) break;  // no representable point inside the bracket
+        const double gc = log_ess(c) - log_target;
+        if (gc >= 0.0) {
+          lo = c;
+          glo = gc;
+          if (side == 1) ghi *= 0.5;
+          side = 1;
+        } else {
+          hi = c;
+          ghi = (gc > -INFINITY) ? gc : -1e300;
+          if (side == -1) glo *= 0.5;
+          side = -1;
+        }
+      }
+    } else {
+      // ESS already below the target at a_prev: the smallest step a 60-step
+      // bisection of (a_prev, 1] can take
+      hi = A.a_prev + (1.0 - A.a_prev) * 0x1.0p-60;
     }
     a = (lo > A.a_prev) ? lo : hi;
   }
+  __syncthreads();
   // reweight, normalise and the evidence increment
-  double lw[kTemperPer], nw[kTemperPer];
+  double nw[kTemperPer];
   double mo = -INFINITY, mn = -INFINITY;
 #pragma unroll
   for (int q = 0; q < kTemperPer; ++q) {
     const int i = t + q * kTemperThreads;
-    lw[q] = i < A.M ? A.logw[i] : -INFINITY;
-    nw[q] = i < A.M ? lw[q] + incr_weight(a, A.a_prev, A.lhat[i], A.sig2[i]) : -INFINITY;
+    nw[q] = i < A.M ? lw[q] + incr_weight(a, A.a_prev, lh[q], s2[q]) : -INFINITY;
     mo = fmax(mo, lw[q]);
     mn = fmax(mn, nw[q]);
   }
-  mo = block_max<kTemperThreads>(mo, sh);
-  mn = block_max<kTemperThreads>(mn, sh);
+  mo = block_max_1(mo, sh, 0);
+  mn = block_max_1(mn, sh, 1);
   double so = 0.0, sn = 0.0, sn2 = 0.0;
 #pragma unroll
   for (int q = 0; q < kTemperPer; ++q) {
@@ -592,9 +652,9 @@ __global__ void __launch_bounds__(kTemperThreads) temper_kernel(TemperArgs A) {
     sn += e;
     sn2 += e * e;
   }
-  so = block_sum<kTemperThreads>(so, sh);
-  sn = block_sum<kTemperThreads>(sn, sh);
-  sn2 = block_sum<kTemperThreads>(sn2, sh);
+  block_sum_2(sn, sn2, sh, 2);
+  double dummy = 0.0;
+  block_sum_2(so, dummy, sh, 3);
   const double lse_old = mo + log(so);
   const double lse_new = mn + log(sn);
   const bool ok = isfinite(lse_new);
@@ -608,6 +668,7 @@ __global__ void __launch_bounds__(kTemperThreads) temper_kernel(TemperArgs A) {
     A.out[1] = lse_new - lse_old;
     A.out[2] = sn * sn / sn2;
     A.out[3] = ok ? 0.0 : 1.0;
+    A.out[4] = (double)evals;
   }
 }
 

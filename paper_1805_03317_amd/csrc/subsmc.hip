@@ -68,7 +68,7 @@ bool compute_layout(const smc_problem* pb, Layout& L) {
   L.Linv = take(dd);
   L.mean = take(d * 8);
   L.status = take(4 * 8);
-  L.tout = take(4 * 8);
+  L.tout = take(8 * 8);
   L.scratch_theta = take(d * 8);
   L.grad_l = take(M * d * 8);
   L.grad_s = take(M * d * 8);
@@ -488,7 +488,7 @@ smc_status smc_temper(smc_ctx c, double* a_out, double* dlogz_out, double* ess_o
   t.out = c->at<double>(c->lay.tout);
   hipLaunchKernelGGL(temper_kernel, dim3(1), dim3(kTemperThreads), 0, c->stream, t);
   LAUNCH_CHECK(c);
-  double o[4];
+  double o[5];
   HIP_TRY(c, hipMemcpyAsync(o, t.out, sizeof(o), hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   if (o[3] != 0.0) return fail(c, SMC_ERR_NONFINITE, "all incremental weights non-finite");
