@@ -1,0 +1,409 @@
+// Wide-row variants of the estimator pass and the fused move for
+// 32 < d <= 128. A group of G lanes (G = 4 or 8) shares one packed row, each
+// lane holding a contiguous chunk of CH elements of it, so a wavefront streams
+// 64/G rows per iteration with 16-byte loads. Parameter component c lives in
+// lane c % 64, slot c / 64 (NC = 2 slots per lane). Vectors that every lane
+// needs at arbitrary positions (delta, momentum, theta) are broadcast through
+// LDS. Everything else (remainders, fixed-order reductions, RNG streams, the
+// structure of Algorithm 1) is as in the narrow kernels.
+#pragma once
+#include "kernels.hpp"
+
+namespace subsmc {
+
+constexpr int kWideNC = 2;  // parameter components per lane (d <= 128)
+
+struct PassResultW {
+  double lhat, sig2, dhat;
+  double gl[kWideNC], gs[kWideNC];
+};
+
+template <typename Real, int CH>
+__device__ __forceinline__ void load_chunk(const Real* __restrict__ p, Real (&x)[CH]) {
+  if constexpr (sizeof(Real) == 4) {
+    static_assert(CH % 4 == 0, "float chunk must be a multiple of 4");
+    const float4* v = reinterpret_cast<const float4*>(p);
+#pragma unroll
+    for (int q = 0; q < CH / 4; ++q) {
+      const float4 t = v[q];
+      x[4 * q] = t.x; x[4 * q + 1] = t.y; x[4 * q + 2] = t.z; x[4 * q + 3] = t.w;
+    }
+  } else {
+    static_assert(CH % 2 == 0, "double chunk must be even");
+    const double2* v = reinterpret_cast<const double2*>(p);
+#pragma unroll
+    for (int q = 0; q < CH / 2; ++q) {
+      const double2 t = v[q];
+      x[2 * q] = t.x; x[2 * q + 1] = t.y;
+    }
+  }
+}
+
+// Pass of the difference estimator for one particle (see estimator_pass);
+// `vec` (LDS) holds delta = theta - theta_bar. Each lane gathers the CH
+// elements of delta aligned with its chunk of the row (zero at the header and
+// padding positions).
+template <typename Real, int G, int CH, int FAM, bool BLK>
+__device__ __forceinline__ PassResultW estimator_pass_wide(const Prob& P, const int32_t* __restrict__ urow,
+                                                           int b0, int b1, const int32_t* blk, Real* red,
+                                                           const double* vec /* LDS: delta, d values */,
+                                                           int lane) {
+  const Real* __restrict__ X = static_cast<const Real*>(P.X);
+  const int m = P.m;
+  const int ld = P.ld;
+  const int d = P.d;
+  const uint32_t n = (uint32_t)P.n;
+  const Real inv_s2 = (Real)P.inv_s2;
+  constexpr int kRows = kWave / G;  // rows per wave iteration
+  const int q = lane % G;           // chunk index within the row
+  const int grp = lane / G;         // row group
+  const int src0 = lane - q;        // lane holding the row header
+
+  Real dl[CH];
+#pragma unroll
+  for (int k = 0; k < CH; ++k) {
+    const int c = q * CH + k - kHeader;
+    dl[k] = (c >= 0 && c < d) ? (Real)vec[c] : Real(0);
+  }
+  auto index_of = [&](int j) -> int32_t {
+    const int32_t g = urow[j];
+    if constexpr (BLK) {
+      const bool in = (unsigned)(j - b0) < (unsigned)(b1 - b0);
+      const int32_t l = blk[in ? j - b0 : 0];
+      return in ? l : g;
+    } else {
+      return g;
+    }
+  };
+  auto eval_row = [&](const Real (&x)[CH], Real& dd, Real& dp) {
+    Real part = Real(0);
+#pragma unroll
+    for (int k = 0; k < CH; ++k) part += x[k] * dl[k];
+#pragma unroll
+    for (int o = 1; o < G; o <<= 1) part += __shfl_xor(part, o, kWave);
+    const Real eb = __shfl(x[0], src0, kWave);
+    const Real aux = __shfl(x[1], src0, kWave);
+    cv_remainder<Real, FAM>(P.cv_order, eb, aux, part, inv_s2, dd, dp);
+  };
+
+  double shift;
+  {
+    const int32_t k0 = index_of(0);
+    const bool bad = (uint32_t)k0 >= n;
+    Real x[CH];
+    load_chunk<Real, CH>(X + (int64_t)(bad ? 0 : k0) * ld + q * CH, x);
+    Real dd, dp;
+    eval_row(x, dd, dp);
+    shift = bad ? __builtin_nan("") : (double)dd;
+  }
+
+  double se = 0.0, se2 = 0.0;
+  Real S1[CH], T1[CH];
+#pragma unroll
+  for (int k = 0; k < CH; ++k) { S1[k] = Real(0); T1[k] = Real(0); }
+
+  int j = grp;
+  int32_t k_cur = j < m ? index_of(j) : 0;
+  int32_t k_nxt = j + kRows < m ? index_of(j + kRows) : 0;
+  Real x_nxt[CH];
+  if (j < m) load_chunk<Real, CH>(X + (int64_t)((uint32_t)k_cur < n ? k_cur : 0) * ld + q * CH, x_nxt);
+  // all lanes of a group share j, so groups exit together; the shuffles in
+  // eval_row only read lanes of the same group
+  for (; j < m; j += kRows) {
+    Real x[CH];
+#pragma unroll
+    for (int k = 0; k < CH; ++k) x[k] = x_nxt[k];
+    const bool bad = (uint32_t)k_cur >= n;
+    if (j + kRows < m) load_chunk<Real, CH>(X + (int64_t)((uint32_t)k_nxt < n ? k_nxt : 0) * ld + q * CH, x_nxt);
+    k_cur = k_nxt;
+    k_nxt = j + 2 * kRows < m ? index_of(j + 2 * kRows) : 0;
+    Real dd, dp;
+    eval_row(x, dd, dp);
+    if (bad) dd = dp = Real(__builtin_nan(""));
+    const double e = (double)dd - shift;
+    if (q == 0) {
+      se += e;
+      se2 += e * e;
+    }
+    const Real edp = (Real)e * dp;
+#pragma unroll
+    for (int k = 0; k < CH; ++k) {
+      S1[k] += dp * x[k];
+      T1[k] += edp * x[k];
+    }
+  }
+
+  se = wave_sum(se);
+  se2 = wave_sum(se2);
+  // column sums: position p = c + header lives in chunk p / CH, element p % CH
+  auto column = [&](const Real (&v)[CH], double (&out)[kWideNC]) {
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < CH; ++k) red[lane * CH + k] = v[k];
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < kWideNC; ++s) {
+      const int c = lane + kWave * s;
+      double acc = 0.0;
+      if (c < d) {
+        const int p = c + kHeader;
+        const int qq = p / CH, kk = p % CH;
+        for (int g = 0; g < kRows; ++g) acc += (double)red[(g * G + qq) * CH + kk];
+      }
+      out[s] = acc;
+    }
+  };
+  double s1[kWideNC], t1[kWideNC];
+  column(S1, s1);
+  column(T1, t1);
+
+  const double md = (double)m;
+  const double nm = P.n_over_m;
+  const double dsum = se + md * shift;
+  const double dbar_minus_shift = se / md;
+  const double m2 = se2 - se * dbar_minus_shift;
+  PassResultW out;
+  out.dhat = nm * dsum;
+  out.sig2 = nm * nm * (m2 < 0.0 ? 0.0 : m2);
+  double qpart = 0.0;
+#pragma unroll
+  for (int s = 0; s < kWideNC; ++s) {
+    const int c = lane + kWave * s;
+    double cdel = 0.0, bl = 0.0, dc = 0.0;
+    if (c < d) {
+      for (int e = 0; e < d; ++e) cdel += P.cvC[c * d + e] * vec[e];
+      bl = P.cvB[c];
+      dc = vec[c];
+    }
+    qpart += (P.cv_order == 2) ? (bl * dc + 0.5 * dc * cdel) : bl * dc;
+    out.gl[s] = c < d ? bl + (P.cv_order == 2 ? cdel : 0.0) + nm * s1[s] : 0.0;
+    out.gs[s] = c < d ? 2.0 * nm * nm * (t1[s] - dbar_minus_shift * s1[s]) : 0.0;
+  }
+  out.lhat = P.cvA[0] + wave_sum(qpart) + out.dhat;
+  return out;
+}
+
+// vec <- x (component slots of every lane), with the fences around it
+__device__ __forceinline__ void to_lds(double* vec, const double (&x)[kWideNC], int lane, int d) {
+  __syncthreads();
+#pragma unroll
+  for (int s = 0; s < kWideNC; ++s) {
+    const int c = lane + kWave * s;
+    if (c < d) vec[c] = x[s];
+  }
+  __syncthreads();
+}
+
+template <typename Real, int G, int CH, int FAM>
+__global__ void __launch_bounds__(kWave) estimator_kernel_wide(EstArgs A) {
+  __shared__ Real red[kWave * CH];
+  __shared__ double vec[128];
+  const int i = blockIdx.x;
+  const int lane = threadIdx.x;
+  if (i >= A.count) return;
+  const Prob& P = A.P;
+  const int d = P.d;
+  double dl[kWideNC];
+#pragma unroll
+  for (int s = 0; s < kWideNC; ++s) {
+    const int c = lane + kWave * s;
+    dl[s] = c < d ? A.theta[(int64_t)i * d + c] - P.theta_bar[c] : 0.0;
+  }
+  to_lds(vec, dl, lane, d);
+  const PassResultW r = estimator_pass_wide<Real, G, CH, FAM, false>(P, A.u + (int64_t)i * P.m, 0, 0, nullptr,
+                                                                     red, vec, lane);
+  if (lane == 0) {
+    if (A.lhat) A.lhat[i] = r.lhat;
+    if (A.sig2) A.sig2[i] = r.sig2;
+    if (A.dhat) A.dhat[i] = r.dhat;
+  }
+#pragma unroll
+  for (int s = 0; s < kWideNC; ++s) {
+    const int c = lane + kWave * s;
+    if (c < d) {
+      if (A.grad_l) A.grad_l[(int64_t)i * d + c] = r.gl[s];
+      if (A.grad_s) A.grad_s[(int64_t)i * d + c] = r.gs[s];
+      if (A.grad) {
+        const double gl = A.g_lhat ? A.g_lhat[i] : 0.0;
+        const double gs = A.g_sig2 ? A.g_sig2[i] : 0.0;
+        A.grad[(int64_t)i * d + c] = gl * r.gl[s] + gs * r.gs[s];
+      }
+    }
+  }
+}
+
+// y = M x for a d x d row-major matrix; x broadcast through LDS
+__device__ __forceinline__ void matvec_wide(const double* __restrict__ Mx, const double* vec, int d, int lane,
+                                            double (&y)[kWideNC]) {
+#pragma unroll
+  for (int s = 0; s < kWideNC; ++s) {
+    const int c = lane + kWave * s;
+    double acc = 0.0;
+    if (c < d)
+      for (int e = 0; e < d; ++e) acc += Mx[c * d + e] * vec[e];
+    y[s] = acc;
+  }
+}
+
+// Fused Markov move (Algorithm 1) for wide rows; same steps, draws and
+// decisions as move_kernel.
+template <typename Real, int G, int CH, int FAM>
+__global__ void __launch_bounds__(kWave) move_kernel_wide(MoveArgs A) {
+  __shared__ Real red[kWave * CH];
+  __shared__ double vec[128];
+  extern __shared__ int32_t blk[];
+  const int i = blockIdx.x;
+  const int lane = threadIdx.x;
+  const Prob& P = A.P;
+  if (i >= P.M) return;
+  const int d = P.d;
+  const int m = P.m;
+  const double a = A.a;
+  const double eps = A.eps;
+  int32_t* urow = A.u + (int64_t)i * m;
+
+  double tb[kWideNC], th[kWideNC], gl0[kWideNC], gs0[kWideNC];
+#pragma unroll
+  for (int s = 0; s < kWideNC; ++s) {
+    const int c = lane + kWave * s;
+    tb[s] = c < d ? P.theta_bar[c] : 0.0;
+    th[s] = c < d ? A.theta[(int64_t)i * d + c] : 0.0;
+    gl0[s] = c < d ? A.grad_l[(int64_t)i * d + c] : 0.0;
+    gs0[s] = c < d ? A.grad_s[(int64_t)i * d + c] : 0.0;
+  }
+  double lh0 = A.lhat[i], sg0 = A.sig2[i];
+
+  // ---- 1. u | theta
+  const uint64_t cg = stream_ctr0(kBlockChoice, A.stage, A.move, 0);
+  const int g = (int)word_to_index(stream_word(P.seed, cg, (uint64_t)i, 0), (uint64_t)P.G);
+  const int b0 = (int)((int64_t)g * m / P.G);
+  const int b1 = (int)((int64_t)(g + 1) * m / P.G);
+  const uint64_t cb = stream_ctr0(kBlockIndex, A.stage, A.move, 0);
+  for (int t = lane; t < b1 - b0; t += kWave)
+    blk[t] = (int32_t)word_to_index(stream_word(P.seed, cb, (uint64_t)i, (uint64_t)t), (uint64_t)P.n);
+  int ob0 = 0, ob1 = 0;
+  {
+    double dl[kWideNC];
+#pragma unroll
+    for (int s = 0; s < kWideNC; ++s) dl[s] = th[s] - tb[s];
+    to_lds(vec, dl, lane, d);  // also fences the block indices
+    const PassResultW r = estimator_pass_wide<Real, G, CH, FAM, true>(P, urow, b0, b1, blk, red, vec, lane);
+    const double lam0 = a * lh0 - 0.5 * a * a * sg0;
+    const double lam1 = a * r.lhat - 0.5 * a * a * r.sig2;
+    const double logr = lam1 - lam0;
+    const double logU = log(word_to_uniform(stream_word(P.seed, stream_ctr0(kUAccept, A.stage, A.move, 0), (uint64_t)i, 0)));
+    const bool acc = isfinite(logr) && (logU < logr);
+    if (acc) {
+      for (int t = lane; t < b1 - b0; t += kWave) urow[b0 + t] = blk[t];
+      lh0 = r.lhat; sg0 = r.sig2;
+#pragma unroll
+      for (int s = 0; s < kWideNC; ++s) { gl0[s] = r.gl[s]; gs0[s] = r.gs[s]; }
+      ob0 = b0; ob1 = b1;
+    }
+    if (lane == 0) A.accept[2 * i] = acc ? 1 : 0;
+  }
+
+  // ---- 2. theta | u: HMC
+  const uint64_t cm = stream_ctr0(kMomentum, A.stage, A.move, 0);
+  double z[kWideNC];
+#pragma unroll
+  for (int s = 0; s < kWideNC; ++s) {
+    const int c = lane + kWave * s;
+    z[s] = c < d ? stream_normal(P.seed, cm, (uint64_t)i, (uint32_t)c) : 0.0;
+  }
+  to_lds(vec, z, lane, d);
+  double p[kWideNC];  // p = Linv' z
+#pragma unroll
+  for (int s = 0; s < kWideNC; ++s) {
+    const int c = lane + kWave * s;
+    double acc = 0.0;
+    if (c < d)
+      for (int e = c; e < d; ++e) acc += P.Linv[e * d + c] * vec[e];
+    p[s] = acc;
+  }
+  auto kinetic_and_velocity = [&](double (&v)[kWideNC]) -> double {
+    to_lds(vec, p, lane, d);
+    matvec_wide(P.Sigma, vec, d, lane, v);
+    double k = 0.0;
+#pragma unroll
+    for (int s = 0; s < kWideNC; ++s) k += p[s] * v[s];
+    return 0.5 * wave_sum(k);
+  };
+  auto prior = [&](const double (&t)[kWideNC], double (&r)[kWideNC]) -> double {
+    double dm[kWideNC];
+#pragma unroll
+    for (int s = 0; s < kWideNC; ++s) {
+      const int c = lane + kWave * s;
+      dm[s] = c < d ? t[s] - P.mu0[c] : 0.0;
+    }
+    to_lds(vec, dm, lane, d);
+    matvec_wide(P.Q0, vec, d, lane, r);
+    double lp = 0.0;
+#pragma unroll
+    for (int s = 0; s < kWideNC; ++s) lp += -0.5 * dm[s] * r[s];
+    return wave_sum(lp);
+  };
+  double v[kWideNC], rq[kWideNC];
+  const double K0 = kinetic_and_velocity(v);
+  const double lp0 = prior(th, rq);
+  const double logpi0 = (a * lh0 - 0.5 * a * a * sg0) + lp0;
+  const double H0 = -logpi0 + K0;
+  double th1[kWideNC];
+#pragma unroll
+  for (int s = 0; s < kWideNC; ++s) {
+    p[s] += 0.5 * eps * (a * gl0[s] - 0.5 * a * a * gs0[s] - rq[s]);
+    th1[s] = th[s];
+  }
+  double lh1 = lh0, sg1 = sg0, gl1[kWideNC], gs1[kWideNC], lp1 = lp0;
+#pragma unroll
+  for (int s = 0; s < kWideNC; ++s) { gl1[s] = gl0[s]; gs1[s] = gs0[s]; }
+  for (int l = 1; l <= A.L; ++l) {
+    to_lds(vec, p, lane, d);
+    matvec_wide(P.Sigma, vec, d, lane, v);
+    double dl[kWideNC];
+#pragma unroll
+    for (int s = 0; s < kWideNC; ++s) {
+      th1[s] += eps * v[s];
+      dl[s] = th1[s] - tb[s];
+    }
+    to_lds(vec, dl, lane, d);
+    const PassResultW r = estimator_pass_wide<Real, G, CH, FAM, true>(P, urow, ob0, ob1, blk, red, vec, lane);
+    lh1 = r.lhat;
+    sg1 = r.sig2;
+    lp1 = prior(th1, rq);
+    const double h = (l < A.L) ? eps : 0.5 * eps;
+#pragma unroll
+    for (int s = 0; s < kWideNC; ++s) {
+      gl1[s] = r.gl[s];
+      gs1[s] = r.gs[s];
+      p[s] += h * (a * gl1[s] - 0.5 * a * a * gs1[s] - rq[s]);
+    }
+  }
+  const double K1 = kinetic_and_velocity(v);
+  const double logpi1 = (a * lh1 - 0.5 * a * a * sg1) + lp1;
+  const double H1 = -logpi1 + K1;
+  const double logr = H0 - H1;
+  const double logU = log(word_to_uniform(stream_word(P.seed, stream_ctr0(kThetaAccept, A.stage, A.move, 0), (uint64_t)i, 0)));
+  const bool acc = isfinite(logr) && (logU < logr);
+  if (acc) {
+    lh0 = lh1; sg0 = sg1;
+#pragma unroll
+    for (int s = 0; s < kWideNC; ++s) { th[s] = th1[s]; gl0[s] = gl1[s]; gs0[s] = gs1[s]; }
+  }
+#pragma unroll
+  for (int s = 0; s < kWideNC; ++s) {
+    const int c = lane + kWave * s;
+    if (c < d) {
+      A.theta[(int64_t)i * d + c] = th[s];
+      A.grad_l[(int64_t)i * d + c] = gl0[s];
+      A.grad_s[(int64_t)i * d + c] = gs0[s];
+    }
+  }
+  if (lane == 0) {
+    A.lhat[i] = lh0;
+    A.sig2[i] = sg0;
+    A.accept[2 * i + 1] = acc ? 1 : 0;
+  }
+}
+
+}  // namespace subsmc

@@ -12,12 +12,14 @@
 
 #include "../../include/subsmc.h"
 #include "kernels.hpp"
+#include "kernels_wide.hpp"
 
 using namespace subsmc;
 
 namespace {
 
-constexpr int kMaxD = 32;
+constexpr int kMaxNarrowD = 32;   // one lane per row up to here
+constexpr int kMaxD = 128;        // lane groups per row beyond
 constexpr int kMaxM = kTemperThreads * kTemperPer;
 constexpr int kCvMaxBlocks = 1024;
 constexpr int kMaxBlock = 16384;  // slots per refreshed block (LDS)
@@ -26,9 +28,23 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 int pad_dc(int d) { return (d + 3) & ~3; }
 
+// Lanes per row and elements per lane for d > 32 (see kernels_wide.hpp).
+struct WideShape { int G, CH; };
+WideShape wide_shape(int d, bool fp32) {
+  const int vw = fp32 ? 4 : 2;
+  const int G = (d + kHeader <= 4 * 16) ? 4 : 8;
+  int ch = (d + kHeader + G - 1) / G;
+  ch = (ch + vw - 1) / vw * vw;
+  return {G, ch};
+}
+
 int packed_ld(int d, bool fp32) {
   const int per64 = fp32 ? 16 : 8;
-  const int need = kHeader + pad_dc(d);
+  int need = kHeader + pad_dc(d);
+  if (d > kMaxNarrowD) {
+    const WideShape w = wide_shape(d, fp32);
+    need = w.G * w.CH;
+  }
   return (need + per64 - 1) / per64 * per64;
 }
 
@@ -139,6 +155,7 @@ smc_status validate(const smc_problem* pb) {
     return SMC_ERR_INVALID_ARG;
   if (pb->family == SMC_GAUSSIAN && !(pb->gauss_s2 > 0.0)) return SMC_ERR_INVALID_ARG;
   if (pb->d > kMaxD) return SMC_ERR_UNSUPPORTED;
+  if (pb->d > kMaxNarrowD && pb->family == SMC_GAUSSIAN) return SMC_ERR_UNSUPPORTED;
   return SMC_OK;
 }
 
@@ -186,8 +203,57 @@ hipError_t launch_move_p(int fam, int dc, int M, size_t lds, const MoveArgs& a, 
   }
 }
 
+// wide kernels: (precision, G, CH) instantiated for the shapes wide_shape() produces
+#define WIDE_SHAPES(X)                                                      \
+  X(float, 4, 12) X(float, 4, 16) X(float, 8, 12) X(float, 8, 16) X(float, 8, 20) \
+  X(double, 4, 10) X(double, 4, 12) X(double, 4, 14) X(double, 4, 16)             \
+  X(double, 8, 10) X(double, 8, 12) X(double, 8, 14) X(double, 8, 16) X(double, 8, 18)
+
+template <typename Real, int G, int CH>
+hipError_t launch_wide_est_fam(int fam, int count, const EstArgs& a, hipStream_t s) {
+  if (fam == kLogistic)
+    hipLaunchKernelGGL((estimator_kernel_wide<Real, G, CH, kLogistic>), dim3(count), dim3(kWave), 0, s, a);
+  else if (fam == kPoisson)
+    hipLaunchKernelGGL((estimator_kernel_wide<Real, G, CH, kPoisson>), dim3(count), dim3(kWave), 0, s, a);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+template <typename Real, int G, int CH>
+hipError_t launch_wide_move_fam(int fam, int M, size_t lds, const MoveArgs& a, hipStream_t s) {
+  if (fam == kLogistic)
+    hipLaunchKernelGGL((move_kernel_wide<Real, G, CH, kLogistic>), dim3(M), dim3(kWave), lds, s, a);
+  else if (fam == kPoisson)
+    hipLaunchKernelGGL((move_kernel_wide<Real, G, CH, kPoisson>), dim3(M), dim3(kWave), lds, s, a);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_wide_estimator(smc_ctx c, int count, const EstArgs& a) {
+  const bool fp32 = c->pb.precision == SMC_MIXED;
+  const WideShape w = wide_shape(c->pb.d, fp32);
+#define X(T, G_, CH_) \
+  if ((sizeof(T) == 4) == fp32 && w.G == G_ && w.CH == CH_) return launch_wide_est_fam<T, G_, CH_>(c->pb.family, count, a, c->stream);
+  WIDE_SHAPES(X)
+#undef X
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_wide_move(smc_ctx c, size_t lds, const MoveArgs& a) {
+  const bool fp32 = c->pb.precision == SMC_MIXED;
+  const WideShape w = wide_shape(c->pb.d, fp32);
+#define X(T, G_, CH_) \
+  if ((sizeof(T) == 4) == fp32 && w.G == G_ && w.CH == CH_) return launch_wide_move_fam<T, G_, CH_>(c->pb.family, c->pb.M, lds, a, c->stream);
+  WIDE_SHAPES(X)
+#undef X
+  return hipErrorInvalidValue;
+}
+
 hipError_t launch_estimator(smc_ctx c, int count, const EstArgs& a) {
   if (count <= 0) return hipSuccess;
+  if (c->pb.d > kMaxNarrowD) return launch_wide_estimator(c, count, a);
   const int dc = pad_dc(c->pb.d);
   return c->pb.precision == SMC_MIXED ? launch_estimator_p<float>(c->pb.family, dc, count, a, c->stream)
                                       : launch_estimator_p<double>(c->pb.family, dc, count, a, c->stream);
@@ -200,6 +266,7 @@ size_t block_lds_bytes(const smc_problem& pb) {
 hipError_t launch_move(smc_ctx c, const MoveArgs& a) {
   const int dc = pad_dc(c->pb.d);
   const size_t lds = block_lds_bytes(c->pb);
+  if (c->pb.d > kMaxNarrowD) return launch_wide_move(c, lds, a);
   return c->pb.precision == SMC_MIXED ? launch_move_p<float>(c->pb.family, dc, c->pb.M, lds, a, c->stream)
                                       : launch_move_p<double>(c->pb.family, dc, c->pb.M, lds, a, c->stream);
 }

@@ -183,9 +183,10 @@ CONFIGS = {1: config1, 2: config2, 4: config4, 5: config5}
 # small test workloads
 # ---------------------------------------------------------------------------
 
-def logistic_small(n, d, seed, precision=FP64, intercept=True, M=64, m=100, G=4, L=8, prior_var=10.0):
+def logistic_small(n, d, seed, precision=FP64, intercept=True, M=64, m=100, G=4, L=8, prior_var=10.0,
+                   theta_scale=1.0):
     g = _gen(5000 + seed, 0)
-    theta = g.standard_normal(d)
+    theta = theta_scale * g.standard_normal(d)
     X = g.standard_normal((n, d))
     if intercept:
         X[:, 0] = 1.0

@@ -71,7 +71,11 @@ def test_workspace_size_and_validation(lib):
         p = _problem(**bad)
         assert lib.smc_workspace_size(C.byref(p)) == 0, bad
     p = _problem(d=40, ld=48)
-    assert lib.smc_workspace_size(C.byref(p)) == 0  # d > 32 is not built
+    assert lib.smc_workspace_size(C.byref(p)) > 0   # lane-group rows for 32 < d <= 128
+    p = _problem(d=130, ld=136)
+    assert lib.smc_workspace_size(C.byref(p)) == 0  # d > 128 is not built
+    p = _problem(d=40, ld=48, family=2)
+    assert lib.smc_workspace_size(C.byref(p)) == 0  # Gaussian test family: d <= 32 only
 
 
 def test_init_rejects_bad_problem_without_touching_the_device(lib):

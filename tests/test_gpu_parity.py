@@ -55,6 +55,10 @@ CASES = [
     ("poisson_d20", lambda: W.poisson_small(20000, 20, seed=5, M=32, m=1000, G=100), 0.05),
     ("gaussian", lambda: W.gaussian_small(500, 4, seed=6, M=32, m=64, G=4), 0.3),
     ("logistic_m1", lambda: W.logistic_small(100, 2, seed=7, M=8, m=1, G=1), 0.5),
+    ("logistic_d33", lambda: W.logistic_small(3000, 33, seed=13, M=16, m=157, G=5, theta_scale=0.2), 0.05),
+    ("logistic_d50", lambda: W.logistic_small(4000, 50, seed=14, M=16, m=300, G=10, theta_scale=0.15), 0.03),
+    ("poisson_d65", lambda: W.poisson_small(6000, 65, seed=15, M=12, m=130, G=4), 0.02),
+    ("logistic_d116", lambda: W.logistic_small(5000, 116, seed=16, M=12, m=211, G=4, theta_scale=0.1), 0.02),
 ]
 
 
@@ -100,6 +104,11 @@ MIXED_CASES = [
     ("logistic_mixed", lambda: W.logistic_small(4000, 5, seed=1, precision=W.MIXED, M=64, m=500, G=4), 0.15),
     ("poisson_mixed_d20", lambda: W.poisson_small(20000, 20, seed=5, precision=W.MIXED, M=32, m=1000, G=100), 0.05),
     ("logistic_mixed_d12", lambda: W.logistic_small(3000, 12, seed=8, precision=W.MIXED, M=32, m=257, G=8), 0.1),
+    ("logistic_mixed_d50", lambda: W.logistic_small(4000, 50, seed=14, precision=W.MIXED, M=16, m=300, G=10,
+                                                    theta_scale=0.15), 0.03),
+    ("poisson_mixed_d65", lambda: W.poisson_small(6000, 65, seed=15, precision=W.MIXED, M=12, m=130, G=4), 0.02),
+    ("logistic_mixed_d116", lambda: W.logistic_small(5000, 116, seed=16, precision=W.MIXED, M=12, m=211, G=4,
+                                                     theta_scale=0.1), 0.02),
 ]
 
 
@@ -233,6 +242,10 @@ MOVE_CASES = [
     ("gaussian", lambda: W.gaussian_small(600, 3, seed=53, M=64, m=50, G=5, L=6), 1.0, 0.2),
     ("logistic_mixed", lambda: W.logistic_small(4000, 5, seed=54, precision=W.MIXED, M=96, m=300, G=4, L=8), 0.6, 0.12),
     ("poisson_mixed_d20", lambda: W.poisson_small(20000, 20, seed=55, precision=W.MIXED, M=64, m=1000, G=100, L=20), 1.0, 0.05),
+    ("logistic_d50", lambda: W.logistic_small(4000, 50, seed=56, M=24, m=200, G=10, L=6, theta_scale=0.15), 0.8, 0.1),
+    ("logistic_mixed_d116", lambda: W.logistic_small(5000, 116, seed=57, precision=W.MIXED, M=16, m=150, G=5, L=5,
+                                                     theta_scale=0.1), 0.8, 0.08),
+    ("poisson_d70", lambda: W.poisson_small(6000, 70, seed=58, M=16, m=160, G=8, L=5), 0.9, 0.08),
 ]
 
 
