@@ -37,6 +37,9 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-particles", type=int, default=64)
     ap.add_argument("--only", choices=["mixed", "fp64"], default=None, help="time one path only (profiling)")
+    ap.add_argument("--workload", choices=["config1", "config2", "config4", "config5"], default="config2",
+                    help="config2 (Poisson n=1e6 d=20) is the benchmark workload; the others are the "
+                         "logistic d=5 FP64, logistic d=50 and additive logistic d=116 configurations")
     return ap.parse_args()
 
 
@@ -94,12 +97,42 @@ def run_path(w, precision, Xy_dev, args, eps):
     return smc, res
 
 
+DEVICE_SOURCES = ["kernels.hpp", "kernels_wide.hpp", "glm.hpp", "rng.hpp"]
+
+
+def device_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in DEVICE_SOURCES:
+        with open(os.path.join(ROOT, "paper_1805_03317_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(w, precision):
+    """HBM bytes per move launch from the committed PMC summary, if it was
+    taken on the current device sources (else None)."""
+    path = os.path.join(ROOT, "profiles", f"move_kernel_{w.name}_{precision}_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as f:
+        for ln in f:
+            if ln.strip() and not ln.startswith("#") and len(ln.split()) == 2:
+                k, v = ln.split()
+                kv[k] = v
+    if kv.get("device_source_sha256") != device_source_hash():
+        return None
+    return float(kv["traffic_bytes_per_launch"])
+
+
 def roofline(w, fp32, move_ms):
     bpe = algorithmic_bytes_per_eval(w.d, fp32)
     evals = w.M * w.m * (w.L + 1)
     achieved = bpe * evals / (move_ms * 1e-3) / 1e9
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-            "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
+            "frac": round(achieved / PEAK_HBM_GBS, 4),
+            "traffic": measured_traffic(w, "mixed" if fp32 else "fp64"),
             "kernel": "move_kernel", "bytes_per_eval": bpe, "evals_per_launch": evals}
 
 
@@ -134,12 +167,17 @@ def main():
     import torch
     from paper_1805_03317_amd import workloads as W
 
-    w = W.config2()
+    t_gen = time.perf_counter()
+    w = {"config1": W.config1, "config2": W.config2, "config4": W.config4, "config5": W.config5}[args.workload]()
+    print(f"# generated {w.name} in {time.perf_counter() - t_gen:.1f} s", file=sys.stderr, flush=True)
     eps = 1.0 / w.L
-    Xy = torch.tensor(w.Xy(np.float32), device="cuda:0")
+    Xy = torch.tensor(w.Xy(np.float32 if w.precision == W.MIXED else np.float64), device="cuda:0")
     torch.cuda.synchronize()
 
-    paths = ["mixed", "fp64"] if args.only is None else [args.only]
+    if w.precision == W.FP64:
+        paths = ["fp64"]
+    else:
+        paths = ["mixed", "fp64"] if args.only is None else [args.only]
     if args.no_fp64 and "fp64" in paths and args.only is None:
         paths.remove("fp64")
     results = {}
@@ -188,6 +226,8 @@ def main():
         }
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_particles, eps)
+    if args.workload != "config2":
+        out["note"] = "not the benchmark workload (Poisson n=1e6 d=20); reported for the configuration table"
     print(json.dumps(out), flush=True)
 
 
