@@ -59,6 +59,15 @@ typedef enum {
                  /* control variates, reductions, weights and MH ratios in FP64       */
 } smc_precision;
 
+typedef enum {
+  SMC_MOVE_AUTO = 0,      /* resident when the subsample fits on chip, else streaming */
+  SMC_MOVE_STREAMING = 1, /* one wavefront per particle, rows gathered from HBM every pass */
+  SMC_MOVE_RESIDENT = 2   /* one 4-wavefront workgroup per particle, rows gathered once per
+                             move and kept in registers and LDS for all L + 1 passes
+                             (d <= 24, logistic or Poisson, m rows must fit; else
+                             SMC_ERR_UNSUPPORTED from smc_init) */
+} smc_move_path;
+
 typedef struct smc_ctx_s* smc_ctx;
 
 /*
@@ -79,6 +88,7 @@ typedef struct smc_problem {
   int32_t m;           /* subsample size (with replacement), 1 <= m */
   int32_t G;           /* blocks of u for the pseudo-marginal refresh, 1 <= G <= m,
                           ceil(m/G) <= 16384 */
+  int32_t move_path;   /* smc_move_path: which move kernel smc_move runs */
   uint64_t seed;       /* Philox key */
   double ess_frac;     /* target ESS = ess_frac * M, 0 < ess_frac <= 1 */
   const double* prior_mean; /* host d: Gaussian prior mean */
@@ -168,6 +178,7 @@ typedef struct smc_info {
   int32_t move;    /* moves done in this stage */
   int32_t have_mass;
   int32_t newton_iters;
+  int32_t move_path;  /* the move kernel in use: SMC_MOVE_STREAMING or SMC_MOVE_RESIDENT */
 } smc_info;
 smc_status smc_get_info(smc_ctx ctx, smc_info* out);
 

@@ -13,6 +13,7 @@ LIB_PATH = os.path.join(HERE, "libsubsmc.so")
 
 LOGISTIC, POISSON, GAUSSIAN = 0, 1, 2
 FP64, MIXED = 0, 1
+MOVE_AUTO, MOVE_STREAMING, MOVE_RESIDENT = 0, 1, 2
 STATUS = {0: "ok", 1: "invalid argument", 2: "call out of order", 3: "device error",
           4: "matrix not positive definite", 5: "non-finite weights", 6: "unsupported"}
 
@@ -22,7 +23,7 @@ class _Problem(C.Structure):
         ("family", C.c_int32), ("precision", C.c_int32), ("cv_order", C.c_int32), ("d", C.c_int32),
         ("n", C.c_int64), ("ld", C.c_int32), ("xy_fp32", C.c_int32), ("Xy", C.c_void_p),
         ("gauss_s2", C.c_double), ("M", C.c_int32), ("m", C.c_int32), ("G", C.c_int32),
-        ("seed", C.c_uint64), ("ess_frac", C.c_double),
+        ("move_path", C.c_int32), ("seed", C.c_uint64), ("ess_frac", C.c_double),
         ("prior_mean", C.c_void_p), ("prior_prec", C.c_void_p), ("theta_bar", C.c_void_p),
         ("theta", C.c_void_p), ("u", C.c_void_p), ("logw", C.c_void_p), ("lhat", C.c_void_p),
         ("sig2", C.c_void_p), ("accept", C.c_void_p), ("workspace", C.c_void_p),
@@ -32,7 +33,7 @@ class _Problem(C.Structure):
 
 class _Info(C.Structure):
     _fields_ = [("a", C.c_double), ("logz", C.c_double), ("stage", C.c_int32), ("move", C.c_int32),
-                ("have_mass", C.c_int32), ("newton_iters", C.c_int32)]
+                ("have_mass", C.c_int32), ("newton_iters", C.c_int32), ("move_path", C.c_int32)]
 
 
 EXPORTS = [
@@ -106,7 +107,7 @@ class SubsampledSMC:
     """
 
     def __init__(self, Xy, d, family, precision, M, m, G, prior_mean, prior_prec, seed,
-                 ess_frac=0.5, cv_order=2, theta_bar=None, gauss_s2=1.0):
+                 ess_frac=0.5, cv_order=2, theta_bar=None, gauss_s2=1.0, move_path=MOVE_AUTO):
         import numpy as np
 
         L = lib()
@@ -132,6 +133,7 @@ class SubsampledSMC:
         pb.Xy = Xy.data_ptr()
         pb.gauss_s2 = float(gauss_s2)
         pb.M, pb.m, pb.G = self.M, self.m, self.G
+        pb.move_path = int(move_path)
         pb.seed, pb.ess_frac = int(seed), float(ess_frac)
         pb.prior_mean = self._mu0.ctypes.data
         pb.prior_prec = self._Q0.ctypes.data
@@ -218,7 +220,7 @@ class SubsampledSMC:
         o = _Info()
         self._check(lib().smc_get_info(self._h, C.byref(o)))
         return {"a": o.a, "logz": o.logz, "stage": o.stage, "move": o.move, "have_mass": o.have_mass,
-                "newton_iters": o.newton_iters}
+                "newton_iters": o.newton_iters, "move_path": o.move_path}
 
     def set_stage(self, stage, move, a, logz=0.0):
         self._check(lib().smc_set_stage(self._h, int(stage), int(move), float(a), float(logz)))

@@ -1,0 +1,441 @@
+// Fused Markov move with the particle's subsample rows resident on chip.
+//
+// One workgroup of 4 wavefronts (256 lanes, one wavefront per SIMD, so each
+// lane may use the whole 512-entry VGPR + AGPR file) owns one particle for the
+// whole move. The m packed rows selected by u are gathered from HBM once per
+// move and kept for all L + 1 estimator passes of Algorithm 1: slot
+// j < 256*RPL in registers of lane j % 256 (RPL rows per lane), the remaining
+// slots in LDS. A pass then reads no global memory. Partial sums are reduced
+// inside each wavefront by a reduce-scatter butterfly and across the 4
+// wavefronts through LDS in fixed order; wavefront 0 assembles the estimator, runs the leapfrog
+// and MH arithmetic (component c of theta, p and the gradient in its lane c)
+// and broadcasts delta = theta - theta_bar through LDS. Draws, decisions and
+// the order of operations are those of move_kernel.
+#pragma once
+#include "kernels.hpp"
+
+namespace subsmc {
+
+constexpr int kResWaves = 4;
+constexpr int kResLanes = kResWaves * kWave;  // 256: one wavefront per SIMD
+
+// LDS carve of the resident kernel (all offsets in bytes, 16-byte aligned).
+struct ResLayout {
+  int nlds;     // rows held in LDS
+  int rs;       // LDS row stride in elements (= kHeader + DC)
+  int off_rows, off_row0, off_blk, off_redv, off_reds, off_dl, off_flag, off_mat, total;
+};
+
+__host__ __device__ inline int res_align16(int x) { return (x + 15) & ~15; }
+
+__host__ __device__ inline ResLayout res_layout(int m, int G, int dc, int rpl, int real_bytes, int d) {
+  ResLayout L;
+  L.rs = kHeader + dc;
+  L.nlds = m - kResLanes * rpl;
+  if (L.nlds < 0) L.nlds = 0;
+  int off = 0;
+  L.off_rows = off; off = res_align16(off + L.nlds * L.rs * real_bytes);
+  L.off_row0 = off; off = res_align16(off + L.rs * real_bytes);
+  L.off_blk = off; off = res_align16(off + ((m + G - 1) / G) * 4);
+  L.off_redv = off; off = res_align16(off + kResWaves * kWave * 8);
+  L.off_reds = off; off = res_align16(off + kResWaves * 2 * 8);
+  L.off_dl = off; off = res_align16(off + dc * real_bytes);
+  L.off_flag = off; off = res_align16(off + 16);
+  L.off_mat = off; off = res_align16(off + 3 * d * d * 8);  // C, Sigma, Q0
+  L.total = off;
+  return L;
+}
+
+// y_lane = sum_{e < d} Mx[lane*d + e] x_e for a d x d matrix in LDS, with
+// x_e held by lane e of this wavefront; unrolled to DC so that the reads
+// issue together.
+template <int DC>
+__device__ __forceinline__ double lds_matvec(const double* Mx, int d, double x, int lane) {
+  double acc = 0.0;
+  const int r = lane < d ? lane : 0;
+#pragma unroll
+  for (int e = 0; e < DC; ++e) {
+    const double xe = readlane_d(x, e);
+    const double me = (e < d) ? Mx[r * d + (e < d ? e : 0)] : 0.0;
+    acc += me * xe;
+  }
+  return lane < d ? acc : 0.0;
+}
+
+template <typename Real, int DC>
+struct ResRow {
+  Real eb, aux;
+  Real x[DC];
+};
+
+// LDS row copy: header + x, vector width 16 bytes
+template <typename Real, int DC>
+__device__ __forceinline__ void copy_row_to_lds(const Real* __restrict__ g, Real* s) {
+  constexpr int kElems = kHeader + DC;
+  if constexpr (sizeof(Real) == 4) {
+    const float4* a = reinterpret_cast<const float4*>(g);
+    float4* b = reinterpret_cast<float4*>(s);
+#pragma unroll
+    for (int q = 0; q < kElems / 4; ++q) b[q] = a[q];
+  } else {
+    const double2* a = reinterpret_cast<const double2*>(g);
+    double2* b = reinterpret_cast<double2*>(s);
+#pragma unroll
+    for (int q = 0; q < kElems / 2; ++q) b[q] = a[q];
+  }
+}
+
+// Reduce-scatter of N values over the 64 lanes: afterwards v[0] of lane l is
+// the wave total of component index res_component(l) (or a zero pad).
+template <typename T, int N, int MASK>
+__device__ __forceinline__ void rs_step(T (&v)[2 * 32 + 2], int lane) {
+  if constexpr (MASK >= 1 && N > 1) {
+    constexpr int H = (N + 1) / 2;
+    const bool up = (lane & MASK) != 0;
+#pragma unroll
+    for (int k = 0; k < H; ++k) {
+      const T lo = v[k];
+      const T hi = (H + k < N) ? v[H + k] : T(0);
+      const T send = up ? lo : hi;
+      const T keep = up ? hi : lo;
+      v[k] = keep + __shfl_xor(send, MASK, kWave);
+    }
+    rs_step<T, H, MASK / 2>(v, lane);
+  } else if constexpr (MASK >= 1) {
+    // one value left: the remaining lanes of the butterfly hold zero pads
+    const bool up = (lane & MASK) != 0;
+    const T send = up ? v[0] : T(0);
+    const T keep = up ? T(0) : v[0];
+    v[0] = keep + __shfl_xor(send, MASK, kWave);
+    rs_step<T, 1, MASK / 2>(v, lane);
+  }
+}
+
+// Original component index held by `lane` after rs_step<T, N, 32> (-1: a
+// zero pad). Every step halves the (padded) array size N_s -> ceil(N_s / 2)
+// for all lanes; walking back from the final position 0, a lane with the
+// step's mask bit came from position H_s + pos, which must be below N_s.
+template <int N>
+__device__ __forceinline__ int res_component(int lane) {
+  int ns[6];
+  int n = N;
+#pragma unroll
+  for (int s = 0; s < 6; ++s) {
+    ns[s] = n;
+    n = (n + 1) / 2;
+  }
+  int pos = 0;
+  bool valid = true;
+#pragma unroll
+  for (int s = 5; s >= 0; --s) {
+    const int mask = 32 >> s;
+    const int h = (ns[s] + 1) / 2;
+    if (lane & mask) pos += h;
+    valid = valid && (pos < ns[s]);
+  }
+  return valid ? pos : -1;
+}
+
+// Per-lane accumulation of one pass over the resident rows.
+template <typename Real, int DC, int FAM, int RPL>
+__device__ __forceinline__ void resident_accumulate(const Prob& P, const ResRow<Real, DC> (&rr)[RPL > 0 ? RPL : 1],
+                                                    const Real* lrows, int rs, int nlds, const Real* row0,
+                                                    const Real* dsh, int tid, double& se, double& se2,
+                                                    Real (&S1)[DC], Real (&T1)[DC], double& shift) {
+  const int m = P.m;
+  const Real inv_s2 = (Real)P.inv_s2;
+  Real dl[DC];
+#pragma unroll
+  for (int c = 0; c < DC; ++c) dl[c] = dsh[c];
+  auto eval = [&](Real eb, Real aux, const Real (&x)[DC], Real& dd, Real& dp) {
+    Real D = Real(0);
+#pragma unroll
+    for (int c = 0; c < DC; ++c) D += x[c] * dl[c];
+    cv_remainder<Real, FAM>(P.cv_order, eb, aux, D, inv_s2, dd, dp);
+  };
+  {
+    Real x[DC];
+#pragma unroll
+    for (int c = 0; c < DC; ++c) x[c] = row0[kHeader + c];
+    Real dd, dp;
+    eval(row0[0], row0[1], x, dd, dp);
+    shift = (double)dd;
+  }
+  se = 0.0;
+  se2 = 0.0;
+#pragma unroll
+  for (int c = 0; c < DC; ++c) { S1[c] = Real(0); T1[c] = Real(0); }
+  auto add = [&](const Real (&x)[DC], Real dd, Real dp) {
+    const double e = (double)dd - shift;
+    se += e;
+    se2 += e * e;
+    const Real edp = (Real)e * dp;
+#pragma unroll
+    for (int c = 0; c < DC; ++c) {
+      S1[c] += dp * x[c];
+      T1[c] += edp * x[c];
+    }
+  };
+#pragma unroll
+  for (int r = 0; r < RPL; ++r) {
+    if (tid + kResLanes * r < m) {
+      Real dd, dp;
+      eval(rr[r].eb, rr[r].aux, rr[r].x, dd, dp);
+      add(rr[r].x, dd, dp);
+    }
+  }
+  for (int t = tid; t < nlds; t += kResLanes) {
+    const Real* row = lrows + t * rs;
+    Real x[DC];
+#pragma unroll
+    for (int c = 0; c < DC; ++c) x[c] = row[kHeader + c];
+    Real dd, dp;
+    eval(row[0], row[1], x, dd, dp);
+    add(x, dd, dp);
+  }
+}
+
+template <typename Real, int DC, int FAM, int RPL>
+__global__ void __launch_bounds__(kResLanes) move_kernel_res(MoveArgs A, ResLayout Ly) {
+  extern __shared__ __attribute__((aligned(16))) char smem[];
+  Real* lrows = reinterpret_cast<Real*>(smem + Ly.off_rows);
+  Real* row0 = reinterpret_cast<Real*>(smem + Ly.off_row0);
+  int32_t* blk = reinterpret_cast<int32_t*>(smem + Ly.off_blk);
+  double* redv = reinterpret_cast<double*>(smem + Ly.off_redv);
+  double* reds = reinterpret_cast<double*>(smem + Ly.off_reds);
+  Real* dsh = reinterpret_cast<Real*>(smem + Ly.off_dl);
+  int* flag = reinterpret_cast<int*>(smem + Ly.off_flag);
+  double* Cm = reinterpret_cast<double*>(smem + Ly.off_mat);
+
+  const int i = blockIdx.x;
+  const Prob& P = A.P;
+  if (i >= P.M) return;
+  const int tid = threadIdx.x;
+  const int w = tid / kWave, lane = tid % kWave;
+  const int d = P.d;
+  const int m = P.m;
+  const int ld = P.ld;
+  const double a = A.a;
+  const double eps = A.eps;
+  const Real* __restrict__ X = static_cast<const Real*>(P.X);
+  int32_t* urow = A.u + (int64_t)i * m;
+  const bool lead = (w == 0);
+  double* Sm = Cm + d * d;
+  double* Qm = Sm + d * d;
+  for (int e = tid; e < d * d; e += kResLanes) {
+    Cm[e] = P.cvC[e];
+    Sm[e] = P.Sigma[e];
+    Qm[e] = P.Q0[e];
+  }
+
+  // wave 0 state (component c in lane c)
+  double tb = 0.0, th = 0.0, gl0 = 0.0, gs0 = 0.0, mu0l = 0.0;
+  if (lead && lane < d) {
+    tb = P.theta_bar[lane];
+    mu0l = P.mu0[lane];
+    th = A.theta[(int64_t)i * d + lane];
+    gl0 = A.grad_l[(int64_t)i * d + lane];
+    gs0 = A.grad_s[(int64_t)i * d + lane];
+  }
+  double lh0 = A.lhat[i], sg0 = A.sig2[i];
+
+  // ---- the proposed block of the pseudo-marginal refresh
+  const uint64_t cg = stream_ctr0(kBlockChoice, A.stage, A.move, 0);
+  const int g = (int)word_to_index(stream_word(P.seed, cg, (uint64_t)i, 0), (uint64_t)P.G);
+  const int b0 = (int)((int64_t)g * m / P.G);
+  const int b1 = (int)((int64_t)(g + 1) * m / P.G);
+  const uint64_t cb = stream_ctr0(kBlockIndex, A.stage, A.move, 0);
+  for (int t = tid; t < b1 - b0; t += kResLanes)
+    blk[t] = (int32_t)word_to_index(stream_word(P.seed, cb, (uint64_t)i, (uint64_t)t), (uint64_t)P.n);
+  __syncthreads();
+  const uint32_t n = (uint32_t)P.n;
+  // indices of u* (refreshed block) or of u; a caller index outside [0, n)
+  // reads row 0 and poisons the estimator
+  auto index_star = [&](int j) -> int32_t {
+    const bool in = (unsigned)(j - b0) < (unsigned)(b1 - b0);
+    const int32_t gk = urow[j];
+    const int32_t lk = blk[in ? j - b0 : 0];
+    return in ? lk : gk;
+  };
+  bool poisoned = false;
+  auto load_reg = [&](ResRow<Real, DC>& r, int32_t k) {
+    const bool bad = (uint32_t)k >= n;
+    poisoned |= bad;
+    RowLoad<Real, DC> t;
+    load_row<Real, DC>(X + (int64_t)(bad ? 0 : k) * ld, t);
+    r.eb = t.eb;
+    r.aux = t.aux;
+#pragma unroll
+    for (int c = 0; c < DC; ++c) r.x[c] = t.x[c];
+  };
+  auto load_lds = [&](Real* s, int32_t k) {
+    const bool bad = (uint32_t)k >= n;
+    poisoned |= bad;
+    copy_row_to_lds<Real, DC>(X + (int64_t)(bad ? 0 : k) * ld, s);
+  };
+
+  ResRow<Real, DC> rr[RPL > 0 ? RPL : 1];
+#pragma unroll
+  for (int r = 0; r < RPL; ++r) {
+    const int j = tid + kResLanes * r;
+    if (j < m) load_reg(rr[r], index_star(j));
+  }
+  for (int t = tid; t < Ly.nlds; t += kResLanes) load_lds(lrows + t * Ly.rs, index_star(kResLanes * RPL + t));
+  if (tid == 0) load_lds(row0, index_star(0));
+
+  // one estimator pass at delta (in dsh) over the resident rows; the reduced
+  // sums arrive in wave 0
+  double lhat_r = 0.0, sig2_r = 0.0, gl_r = 0.0, gs_r = 0.0;
+  auto pass = [&](double delta64) {
+    // delta64: wave 0 lane c holds component c (ignored elsewhere)
+    if (lead && lane < DC) dsh[lane] = (Real)(lane < d ? delta64 : 0.0);
+    __syncthreads();
+    double se, se2, shift;
+    Real S1[DC], T1[DC];
+    resident_accumulate<Real, DC, FAM, RPL>(P, rr, lrows, Ly.rs, Ly.nlds, row0, dsh, tid, se, se2, S1, T1, shift);
+    // poisoned rows (caller index out of range) make the pass NaN
+    const int bad = __syncthreads_or(poisoned ? 1 : 0);
+    se = wave_sum(se);
+    se2 = wave_sum(se2);
+    Real v[2 * 32 + 2];
+#pragma unroll
+    for (int c = 0; c < DC; ++c) {
+      v[c] = S1[c];
+      v[DC + c] = T1[c];
+    }
+    rs_step<Real, 2 * DC, 32>(v, lane);
+    const int comp = res_component<2 * DC>(lane);
+    if (comp >= 0) redv[w * kWave + comp] = (double)v[0];
+    if (lane == 0) {
+      reds[2 * w] = se;
+      reds[2 * w + 1] = se2;
+    }
+    __syncthreads();
+    if (lead) {
+      double tse = 0.0, tse2 = 0.0, s1c = 0.0, t1c = 0.0;
+#pragma unroll
+      for (int q = 0; q < kResWaves; ++q) {
+        tse += reds[2 * q];
+        tse2 += reds[2 * q + 1];
+        if (lane < DC) {
+          s1c += redv[q * kWave + lane];
+          t1c += redv[q * kWave + DC + lane];
+        }
+      }
+      if (bad) tse = tse2 = __builtin_nan("");
+      const double md = (double)m;
+      const double nm = P.n_over_m;
+      const double dsum = tse + md * shift;
+      const double dbms = tse / md;
+      const double m2 = tse2 - tse * dbms;
+      const double dhat = nm * dsum;
+      sig2_r = nm * nm * (m2 < 0.0 ? 0.0 : m2);
+      const double cdel = lds_matvec<DC>(Cm, d, delta64, lane);
+      const double bl = lane < d ? P.cvB[lane] : 0.0;
+      const double qpart = (P.cv_order == 2) ? (bl * delta64 + 0.5 * delta64 * cdel) : bl * delta64;
+      lhat_r = P.cvA[0] + wave_sum(qpart) + dhat;
+      gl_r = lane < d ? bl + (P.cv_order == 2 ? cdel : 0.0) + nm * s1c : 0.0;
+      gs_r = lane < d ? 2.0 * nm * nm * (t1c - dbms * s1c) : 0.0;
+    }
+  };
+
+  // ---- 1. u | theta
+  pass(th - tb);
+  if (lead) {
+    const double lam0 = a * lh0 - 0.5 * a * a * sg0;
+    const double lam1 = a * lhat_r - 0.5 * a * a * sig2_r;
+    const double logr = lam1 - lam0;
+    const double logU = log(word_to_uniform(stream_word(P.seed, stream_ctr0(kUAccept, A.stage, A.move, 0), (uint64_t)i, 0)));
+    const bool acc = isfinite(logr) && (logU < logr);
+    if (lane == 0) {
+      flag[0] = acc ? 1 : 0;
+      A.accept[2 * i] = acc ? 1 : 0;
+    }
+    if (acc) {
+      lh0 = lhat_r; sg0 = sig2_r; gl0 = gl_r; gs0 = gs_r;
+    }
+  }
+  __syncthreads();
+  const bool acc_u = flag[0] != 0;
+  if (acc_u) {
+    for (int t = tid; t < b1 - b0; t += kResLanes) urow[b0 + t] = blk[t];
+  } else {
+    // restore the rows of the current block from u
+    poisoned = false;
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) {
+      const int j = tid + kResLanes * r;
+      if (j < m && j >= b0 && j < b1) load_reg(rr[r], urow[j]);
+      else if (j < m) poisoned |= (uint32_t)urow[j] >= n;
+    }
+    for (int t = tid; t < Ly.nlds; t += kResLanes) {
+      const int j = kResLanes * RPL + t;
+      if (j >= b0 && j < b1) load_lds(lrows + t * Ly.rs, urow[j]);
+      else poisoned |= (uint32_t)urow[j] >= n;
+    }
+    if (tid == 0 && b0 == 0 && b1 > 0) load_lds(row0, urow[0]);
+  }
+  // (the next pass starts with a barrier)
+
+  // ---- 2. theta | u: HMC (scalar work on wave 0)
+  double p = 0.0, v = 0.0, rq = 0.0, lp = 0.0, H0 = 0.0, th1 = th, lp1 = 0.0;
+  if (lead) {
+    const uint64_t cm = stream_ctr0(kMomentum, A.stage, A.move, 0);
+    const double z = lane < d ? stream_normal(P.seed, cm, (uint64_t)i, (uint32_t)lane) : 0.0;
+    for (int e = 0; e < d; ++e) {
+      const double ze = readlane_d(z, e);
+      p += (lane < d && e >= lane ? P.Linv[e * d + lane] : 0.0) * ze;
+    }
+    v = lds_matvec<DC>(Sm, d, p, lane);
+    const double K0 = 0.5 * wave_sum(p * v);
+    {
+      const double dm = lane < d ? th - P.mu0[lane] : 0.0;
+      rq = lds_matvec<DC>(Qm, d, dm, lane);
+      lp = wave_sum(-0.5 * dm * rq);
+    }
+    const double logpi0 = (a * lh0 - 0.5 * a * a * sg0) + lp;
+    H0 = -logpi0 + K0;
+    const double grad = a * gl0 - 0.5 * a * a * gs0 - rq;
+    p += 0.5 * eps * grad;
+    lp1 = lp;
+    lhat_r = lh0; sig2_r = sg0; gl_r = gl0; gs_r = gs0;
+  }
+  for (int l = 1; l <= A.L; ++l) {
+    if (lead) {
+      v = lds_matvec<DC>(Sm, d, p, lane);
+      th1 += eps * v;
+    }
+    pass(th1 - tb);
+    if (lead) {
+      const double dm = lane < d ? th1 - mu0l : 0.0;
+      rq = lds_matvec<DC>(Qm, d, dm, lane);
+      lp1 = wave_sum(-0.5 * dm * rq);
+      const double grad = a * gl_r - 0.5 * a * a * gs_r - rq;
+      p += ((l < A.L) ? eps : 0.5 * eps) * grad;
+    }
+  }
+  if (lead) {
+    v = lds_matvec<DC>(Sm, d, p, lane);
+    const double K1 = 0.5 * wave_sum(p * v);
+    const double logpi1 = (a * lhat_r - 0.5 * a * a * sig2_r) + lp1;
+    const double H1 = -logpi1 + K1;
+    const double logr = H0 - H1;
+    const double logU = log(word_to_uniform(stream_word(P.seed, stream_ctr0(kThetaAccept, A.stage, A.move, 0), (uint64_t)i, 0)));
+    const bool acc = isfinite(logr) && (logU < logr);
+    if (acc) {
+      th = th1; lh0 = lhat_r; sg0 = sig2_r; gl0 = gl_r; gs0 = gs_r;
+    }
+    if (lane < d) {
+      A.theta[(int64_t)i * d + lane] = th;
+      A.grad_l[(int64_t)i * d + lane] = gl0;
+      A.grad_s[(int64_t)i * d + lane] = gs0;
+    }
+    if (lane == 0) {
+      A.lhat[i] = lh0;
+      A.sig2[i] = sg0;
+      A.accept[2 * i + 1] = acc ? 1 : 0;
+    }
+  }
+}
+
+}  // namespace subsmc

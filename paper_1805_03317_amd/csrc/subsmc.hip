@@ -13,6 +13,7 @@
 #include "../../include/subsmc.h"
 #include "kernels.hpp"
 #include "kernels_wide.hpp"
+#include "kernels_resident.hpp"
 
 using namespace subsmc;
 
@@ -112,6 +113,8 @@ struct smc_ctx_s {
   Prob prob;
   double a = 0.0, logz = 0.0;
   int stage = 0, move = 0, have_mass = 0, newton_iters = 0;
+  int res_rpl = -1;  // register rows per lane of the resident move kernel; -1: streaming
+  ResLayout res_ly{};
   std::vector<double> mu0, Q0;
   char err[512] = {0};
 
@@ -149,6 +152,7 @@ smc_status validate(const smc_problem* pb) {
   if (pb->ld < pb->d + 1 || !pb->Xy) return SMC_ERR_INVALID_ARG;
   if (pb->M < 1 || pb->M > kMaxM || pb->m < 1 || pb->G < 1 || pb->G > pb->m) return SMC_ERR_INVALID_ARG;
   if (!(pb->ess_frac > 0.0 && pb->ess_frac <= 1.0)) return SMC_ERR_INVALID_ARG;
+  if (pb->move_path < SMC_MOVE_AUTO || pb->move_path > SMC_MOVE_RESIDENT) return SMC_ERR_INVALID_ARG;
   if ((pb->m + pb->G - 1) / pb->G > kMaxBlock) return SMC_ERR_UNSUPPORTED;
   if (!pb->prior_mean || !pb->prior_prec) return SMC_ERR_INVALID_ARG;
   if (!pb->theta || !pb->u || !pb->logw || !pb->lhat || !pb->sig2 || !pb->accept || !pb->workspace)
@@ -251,6 +255,65 @@ hipError_t launch_wide_move(smc_ctx c, size_t lds, const MoveArgs& a) {
   return hipErrorInvalidValue;
 }
 
+// resident move kernels: (precision, padded d, family, register rows per lane)
+#define RES_SHAPES(X)                                                                                  \
+  X(float, 4, 1, 0) X(float, 4, 1, 14) X(float, 8, 1, 0) X(float, 8, 1, 14) X(float, 12, 1, 0)          \
+  X(float, 12, 1, 14) X(float, 16, 1, 0) X(float, 16, 1, 14) X(float, 20, 1, 0) X(float, 20, 1, 14)     \
+  X(float, 24, 1, 0) X(float, 4, 0, 0) X(float, 8, 0, 0) X(float, 12, 0, 0) X(float, 16, 0, 0)          \
+  X(float, 20, 0, 0) X(float, 24, 0, 0)                                                                 \
+  X(double, 4, 0, 0) X(double, 8, 0, 0) X(double, 12, 0, 0) X(double, 16, 0, 0) X(double, 20, 0, 0)     \
+  X(double, 24, 0, 0) X(double, 4, 1, 0) X(double, 8, 1, 0) X(double, 12, 1, 0) X(double, 16, 1, 0)     \
+  X(double, 20, 1, 0) X(double, 24, 1, 0)
+
+template <typename Real, int DC, int FAM, int RPL>
+hipError_t launch_res(int M, const ResLayout& ly, const MoveArgs& a, hipStream_t s) {
+  auto k = move_kernel_res<Real, DC, FAM, RPL>;
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     ly.total);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k, dim3(M), dim3(kResLanes), ly.total, s, a, ly);
+  return hipGetLastError();
+}
+
+// register-row candidates for (precision, padded d, family): the ones
+// instantiated above (the logistic remainder needs the registers the row
+// cache would use, so logistic keeps all rows in LDS)
+int res_candidates(bool fp32, int dc, int family, int out[2]) {
+  if (dc > 24) return 0;
+  out[0] = 0;
+  if (fp32 && family == SMC_POISSON && dc <= 20) { out[1] = 14; return 2; }
+  return 1;
+}
+
+// Smallest register-row count whose LDS part fits; -1 if the resident kernel
+// does not apply.
+int choose_resident(const smc_problem& pb, int max_lds, ResLayout& ly) {
+  if (pb.d > kMaxNarrowD || (pb.family != SMC_LOGISTIC && pb.family != SMC_POISSON)) return -1;
+  const bool fp32 = pb.precision == SMC_MIXED;
+  const int dc = pad_dc(pb.d);
+  int cand[2];
+  const int nc = res_candidates(fp32, dc, pb.family, cand);
+  for (int q = 0; q < nc; ++q) {
+    const ResLayout l = res_layout(pb.m, pb.G, dc, cand[q], fp32 ? 4 : 8, pb.d);
+    if (l.total <= max_lds) {
+      ly = l;
+      return cand[q];
+    }
+  }
+  return -1;
+}
+
+hipError_t launch_resident(smc_ctx c, const MoveArgs& a) {
+  const bool fp32 = c->pb.precision == SMC_MIXED;
+  const int dc = pad_dc(c->pb.d);
+#define X(T, DC_, FAM_, RPL_)                                                                    \
+  if ((sizeof(T) == 4) == fp32 && dc == DC_ && c->pb.family == FAM_ && c->res_rpl == RPL_)        \
+    return launch_res<T, DC_, FAM_, RPL_>(c->pb.M, c->res_ly, a, c->stream);
+  RES_SHAPES(X)
+#undef X
+  return hipErrorInvalidValue;
+}
+
 hipError_t launch_estimator(smc_ctx c, int count, const EstArgs& a) {
   if (count <= 0) return hipSuccess;
   if (c->pb.d > kMaxNarrowD) return launch_wide_estimator(c, count, a);
@@ -264,6 +327,7 @@ size_t block_lds_bytes(const smc_problem& pb) {
 }
 
 hipError_t launch_move(smc_ctx c, const MoveArgs& a) {
+  if (c->res_rpl >= 0) return launch_resident(c, a);
   const int dc = pad_dc(c->pb.d);
   const size_t lds = block_lds_bytes(c->pb);
   if (c->pb.d > kMaxNarrowD) return launch_wide_move(c, lds, a);
@@ -467,6 +531,16 @@ smc_status smc_init(const smc_problem* pb, void* stream, smc_ctx* out) {
   c->lay = lay;
   c->ws = static_cast<char*>(pb->workspace);
   const int d = pb->d;
+  if (pb->move_path != SMC_MOVE_STREAMING) {
+    int dev = 0, max_lds = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess)
+      c->res_rpl = choose_resident(*pb, max_lds, c->res_ly);
+    if (pb->move_path == SMC_MOVE_RESIDENT && c->res_rpl < 0) {
+      *out = c;
+      return fail(c, SMC_ERR_UNSUPPORTED, "resident move kernel does not apply to this problem");
+    }
+  }
   c->mu0.assign(pb->prior_mean, pb->prior_mean + d);
   c->Q0.assign(pb->prior_prec, pb->prior_prec + (size_t)d * d);
   c->pb.theta_bar = nullptr;  // host pointer not kept
@@ -705,6 +779,7 @@ smc_status smc_get_info(smc_ctx c, smc_info* o) {
   o->move = c->move;
   o->have_mass = c->have_mass;
   o->newton_iters = c->newton_iters;
+  o->move_path = c->res_rpl >= 0 ? SMC_MOVE_RESIDENT : SMC_MOVE_STREAMING;
   return SMC_OK;
 }
 

@@ -21,7 +21,7 @@ def _binding():
     return binding
 
 
-def make_pair(w, precision=None, theta_bar=None, M=None, m=None, G=None, cv_order=2):
+def make_pair(w, precision=None, theta_bar=None, M=None, m=None, G=None, cv_order=2, move_path=0):
     B = _binding()
     prec = w.precision if precision is None else precision
     P = oracle.Problem(w.Xy(np.float64), w.d, w.family, w.prior_mean, w.prior_prec,
@@ -32,7 +32,7 @@ def make_pair(w, precision=None, theta_bar=None, M=None, m=None, G=None, cv_orde
     data_dt = np.float32 if w.precision == W.MIXED else np.float64
     Xy = torch.tensor(w.Xy(data_dt), device=DEV)
     smc = B.SubsampledSMC(Xy, w.d, w.family, prec, M or w.M, m or w.m, G or w.G, w.prior_mean, w.prior_prec,
-                          w.seed, theta_bar=theta_bar, gauss_s2=w.gauss_s2, cv_order=cv_order)
+                          w.seed, theta_bar=theta_bar, gauss_s2=w.gauss_s2, cv_order=cv_order, move_path=move_path)
     return P, smc
 
 
@@ -246,19 +246,27 @@ MOVE_CASES = [
     ("logistic_mixed_d116", lambda: W.logistic_small(5000, 116, seed=57, precision=W.MIXED, M=16, m=150, G=5, L=5,
                                                      theta_scale=0.1), 0.8, 0.08),
     ("poisson_d70", lambda: W.poisson_small(6000, 70, seed=58, M=16, m=160, G=8, L=5), 0.9, 0.08),
+    ("poisson_mixed_m5000", lambda: W.poisson_small(30000, 20, seed=59, precision=W.MIXED, M=12, m=5000, G=100,
+                                                    L=4), 1.0, 0.05),
+    ("logistic_mixed_m1500", lambda: W.logistic_small(8000, 10, seed=60, precision=W.MIXED, M=12, m=1500, G=30,
+                                                      L=4), 0.7, 0.1),
 ]
 
 
+@pytest.mark.parametrize("path", [1, 0], ids=["streaming", "auto"])
+@pytest.mark.parametrize("spread", [0.02, 0.3], ids=["near", "far"])
 @pytest.mark.parametrize("name,mk,a,eps", MOVE_CASES, ids=[c[0] for c in MOVE_CASES])
-def test_move_parity(name, mk, a, eps):
-    """One Markov move from the same state on both sides (teacher forced)."""
+def test_move_parity(name, mk, a, eps, spread, path):
+    """One Markov move from the same state on both sides (teacher forced); the
+    automatic path runs the resident kernel wherever it applies."""
     w = mk()
-    say("move case", name)
-    P, smc = make_pair(w)
+    say("move case", name, spread, path)
+    P, smc = make_pair(w, move_path=path)
+    say("kernel", smc.info()["move_path"])
     mixed = w.precision == W.MIXED
-    # a particle cloud near the tempered posterior: the oracle's prior draws shrunk around theta_bar
+    # a particle cloud around theta_bar: the oracle's prior draws shrunk towards it
     thp, u0, _ = oracle.init_particles(w.M, w.d, w.m, w.n, w.seed, w.prior_mean, w.prior_prec)
-    th0 = P.theta_bar + 0.02 * (thp - w.prior_mean)
+    th0 = P.theta_bar + spread * (thp - w.prior_mean)
     _, Sig, Lc = oracle.moments(th0, np.full(w.M, -math.log(w.M)))
     smc.theta.copy_(torch.tensor(th0))
     smc.u.copy_(torch.tensor(u0))
@@ -286,8 +294,19 @@ def test_move_parity(name, mk, a, eps):
     np.testing.assert_allclose(smc.lhat.cpu().numpy()[same], lh1[same], rtol=rt)
     if w.family != W.GAUSSIAN:
         np.testing.assert_allclose(smc.sig2.cpu().numpy()[same], sg1[same], rtol=1e-4 if mixed else 1e-8)
-    assert 0 < acc[:, 1].mean()
+    assert 0 < acc[:, 1].mean() or spread > 0.1
     smc.close()
+
+
+def test_resident_path_is_selected():
+    B = _binding()
+    w = W.poisson_small(30000, 20, seed=59, precision=W.MIXED, M=8, m=5000, G=100)
+    P, smc = make_pair(w, move_path=B.MOVE_RESIDENT)
+    assert smc.info()["move_path"] == B.MOVE_RESIDENT
+    smc.close()
+    w = W.logistic_small(4000, 50, seed=14, M=8, m=300, G=10, theta_scale=0.15)
+    with pytest.raises(B.SMCError):
+        make_pair(w, move_path=B.MOVE_RESIDENT)   # d > 24: streaming only
 
 
 def test_full_run_matches_oracle_fp64():
