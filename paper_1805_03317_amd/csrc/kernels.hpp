@@ -17,6 +17,7 @@
 
 #include "glm.hpp"
 #include "rng.hpp"
+#include "xlane.hpp"
 
 namespace subsmc {
 
@@ -27,11 +28,7 @@ constexpr int kHeader = 4;  // eta_bar, aux, y, pad
 // wave-level helpers
 // --------------------------------------------------------------------------
 
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, kWave);
-  return v;
-}
+__device__ __forceinline__ double wave_sum(double v) { return xl::wave_allsum(v); }
 
 __device__ __forceinline__ double readlane_d(double v, int l) {
   const unsigned long long b = __double_as_longlong(v);

@@ -6,13 +6,26 @@
 // move and kept for all L + 1 estimator passes of Algorithm 1: slot
 // j < 256*RPL in registers of lane j % 256 (RPL rows per lane), the remaining
 // slots in LDS. A pass then reads no global memory. Partial sums are reduced
-// inside each wavefront by a reduce-scatter butterfly and across the 4
-// wavefronts through LDS in fixed order; wavefront 0 assembles the estimator, runs the leapfrog
-// and MH arithmetic (component c of theta, p and the gradient in its lane c)
-// and broadcasts delta = theta - theta_bar through LDS. Draws, decisions and
-// the order of operations are those of move_kernel.
+// inside each wavefront by a VALU-only reduce-scatter and across the 4
+// wavefronts through LDS in fixed order; wavefront 0 does the leapfrog and MH
+// arithmetic (component c of theta, p and the gradient in its lane c) and
+// broadcasts delta = theta - theta_bar through LDS.
+//
+// The leapfrog passes between the first and the last need the gradient of the
+// extended target only (section 3.3). With K = a C - Q0 (K = -Q0 for a
+// first-order control variate) and
+// g0 = a B - Q0 (theta_bar - mu0) it is
+//   g0 + K delta + a (n/m) S1 - a^2 (n/m)^2 (T1 - dbar S1),
+// S1 = sum_j d'_j x_j and T1 = sum_j (d_j - shift) d'_j x_j; the estimator
+// value, sigma^2 and the prior density are formed at the u-refresh pass and at
+// the last pass only. K delta is carried along the trajectory: after
+// p <- p + eps grad, delta <- delta + eps Sigma p and
+// K delta <- K delta + eps (K Sigma) p, where Sigma p and (K Sigma) p come
+// out of one sweep (lanes 0..d-1 and 32..32+d-1). Draws, decisions and the
+// order of the steps are those of move_kernel.
 #pragma once
 #include "kernels.hpp"
+#include "xlane.hpp"
 
 namespace subsmc {
 
@@ -41,25 +54,48 @@ __host__ __device__ inline ResLayout res_layout(int m, int G, int dc, int rpl, i
   L.off_reds = off; off = res_align16(off + kResWaves * 2 * 8);
   L.off_dl = off; off = res_align16(off + dc * real_bytes);
   L.off_flag = off; off = res_align16(off + 16);
-  L.off_mat = off; off = res_align16(off + 3 * d * d * 8);  // C, Sigma, Q0
+  L.off_mat = off; off = res_align16(off + 4 * d * d * 8);  // C, Q0, Sigma, K Sigma
   L.total = off;
   return L;
 }
 
-// y_lane = sum_{e < d} Mx[lane*d + e] x_e for a d x d matrix in LDS, with
-// x_e held by lane e of this wavefront; unrolled to DC so that the reads
-// issue together.
+// y_c = sum_{e < d} M[c*d + e] x_e for a d x d row-major matrix in LDS,
+// x_e held by lane e of the wavefront; lanes c >= d get 0.
 template <int DC>
-__device__ __forceinline__ double lds_matvec(const double* Mx, int d, double x, int lane) {
+__device__ __forceinline__ double lds_matvec(const double* M, int d, double x, int lane) {
   double acc = 0.0;
   const int r = lane < d ? lane : 0;
 #pragma unroll
   for (int e = 0; e < DC; ++e) {
     const double xe = readlane_d(x, e);
-    const double me = (e < d) ? Mx[r * d + (e < d ? e : 0)] : 0.0;
+    const double me = (e < d) ? M[r * d + (e < d ? e : 0)] : 0.0;
     acc += me * xe;
   }
   return lane < d ? acc : 0.0;
+}
+
+// Two products of one vector in one sweep: AB holds A (rows 0..d-1) above
+// B (rows d..2d-1); lane c < d returns (A x)_c, lane 32 + c returns (B x)_c.
+template <int DC>
+__device__ __forceinline__ double lds_matvec2(const double* AB, int d, double x, int lane) {
+  const int c = lane & 31;
+  const int r = (c < d ? c : 0) + (lane >> 5) * d;
+  double acc = 0.0;
+#pragma unroll
+  for (int e = 0; e < DC; ++e) {
+    const double xe = readlane_d(x, e);
+    const double me = (e < d) ? AB[r * d + (e < d ? e : 0)] : 0.0;
+    acc += me * xe;
+  }
+  return c < d ? acc : 0.0;
+}
+
+// Lane l < 32 receives the value of lane l + 32.
+__device__ __forceinline__ double from_upper_half(double y) {
+  uint32_t a0, b0, a1, b1;
+  xl::swap_words<0>(xl::lo_word(y), xl::lo_word(y), a0, b0);
+  xl::swap_words<0>(xl::hi_word(y), xl::hi_word(y), a1, b1);
+  return xl::make_double(b0, b1);
 }
 
 template <typename Real, int DC>
@@ -83,57 +119,6 @@ __device__ __forceinline__ void copy_row_to_lds(const Real* __restrict__ g, Real
 #pragma unroll
     for (int q = 0; q < kElems / 2; ++q) b[q] = a[q];
   }
-}
-
-// Reduce-scatter of N values over the 64 lanes: afterwards v[0] of lane l is
-// the wave total of component index res_component(l) (or a zero pad).
-template <typename T, int N, int MASK>
-__device__ __forceinline__ void rs_step(T (&v)[2 * 32 + 2], int lane) {
-  if constexpr (MASK >= 1 && N > 1) {
-    constexpr int H = (N + 1) / 2;
-    const bool up = (lane & MASK) != 0;
-#pragma unroll
-    for (int k = 0; k < H; ++k) {
-      const T lo = v[k];
-      const T hi = (H + k < N) ? v[H + k] : T(0);
-      const T send = up ? lo : hi;
-      const T keep = up ? hi : lo;
-      v[k] = keep + __shfl_xor(send, MASK, kWave);
-    }
-    rs_step<T, H, MASK / 2>(v, lane);
-  } else if constexpr (MASK >= 1) {
-    // one value left: the remaining lanes of the butterfly hold zero pads
-    const bool up = (lane & MASK) != 0;
-    const T send = up ? v[0] : T(0);
-    const T keep = up ? T(0) : v[0];
-    v[0] = keep + __shfl_xor(send, MASK, kWave);
-    rs_step<T, 1, MASK / 2>(v, lane);
-  }
-}
-
-// Original component index held by `lane` after rs_step<T, N, 32> (-1: a
-// zero pad). Every step halves the (padded) array size N_s -> ceil(N_s / 2)
-// for all lanes; walking back from the final position 0, a lane with the
-// step's mask bit came from position H_s + pos, which must be below N_s.
-template <int N>
-__device__ __forceinline__ int res_component(int lane) {
-  int ns[6];
-  int n = N;
-#pragma unroll
-  for (int s = 0; s < 6; ++s) {
-    ns[s] = n;
-    n = (n + 1) / 2;
-  }
-  int pos = 0;
-  bool valid = true;
-#pragma unroll
-  for (int s = 5; s >= 0; --s) {
-    const int mask = 32 >> s;
-    const int h = (ns[s] + 1) / 2;
-    if (lane & mask) pos += h;
-    valid = valid && (pos < ns[s]);
-  }
-  return valid ? pos : -1;
 }
 
 // Per-lane accumulation of one pass over the resident rows.
@@ -205,7 +190,6 @@ __global__ void __launch_bounds__(kResLanes) move_kernel_res(MoveArgs A, ResLayo
   double* reds = reinterpret_cast<double*>(smem + Ly.off_reds);
   Real* dsh = reinterpret_cast<Real*>(smem + Ly.off_dl);
   int* flag = reinterpret_cast<int*>(smem + Ly.off_flag);
-  double* Cm = reinterpret_cast<double*>(smem + Ly.off_mat);
 
   const int i = blockIdx.x;
   const Prob& P = A.P;
@@ -213,6 +197,7 @@ __global__ void __launch_bounds__(kResLanes) move_kernel_res(MoveArgs A, ResLayo
   const int tid = threadIdx.x;
   const int w = tid / kWave, lane = tid % kWave;
   const int d = P.d;
+  const int dd = d * d;
   const int m = P.m;
   const int ld = P.ld;
   const double a = A.a;
@@ -220,19 +205,24 @@ __global__ void __launch_bounds__(kResLanes) move_kernel_res(MoveArgs A, ResLayo
   const Real* __restrict__ X = static_cast<const Real*>(P.X);
   int32_t* urow = A.u + (int64_t)i * m;
   const bool lead = (w == 0);
-  double* Sm = Cm + d * d;
-  double* Qm = Sm + d * d;
-  for (int e = tid; e < d * d; e += kResLanes) {
+
+  // the small matrices of the move: C, Q0, Sigma and, below, (a C - Q0) Sigma
+  double* Cm = reinterpret_cast<double*>(smem + Ly.off_mat);
+  double* Qm = Cm + dd;
+  double* Sm = Qm + dd;   // Sigma, then K Sigma right below it
+  double* KSm = Sm + dd;
+  for (int e = tid; e < dd; e += kResLanes) {
     Cm[e] = P.cvC[e];
-    Sm[e] = P.Sigma[e];
     Qm[e] = P.Q0[e];
+    Sm[e] = P.Sigma[e];
   }
 
   // wave 0 state (component c in lane c)
-  double tb = 0.0, th = 0.0, gl0 = 0.0, gs0 = 0.0, mu0l = 0.0;
+  double tb = 0.0, th = 0.0, gl0 = 0.0, gs0 = 0.0, mu0l = 0.0, bl = 0.0;
   if (lead && lane < d) {
     tb = P.theta_bar[lane];
     mu0l = P.mu0[lane];
+    bl = P.cvB[lane];
     th = A.theta[(int64_t)i * d + lane];
     gl0 = A.grad_l[(int64_t)i * d + lane];
     gs0 = A.grad_s[(int64_t)i * d + lane];
@@ -248,6 +238,14 @@ __global__ void __launch_bounds__(kResLanes) move_kernel_res(MoveArgs A, ResLayo
   for (int t = tid; t < b1 - b0; t += kResLanes)
     blk[t] = (int32_t)word_to_index(stream_word(P.seed, cb, (uint64_t)i, (uint64_t)t), (uint64_t)P.n);
   __syncthreads();
+  // K = a C - Q0 (a first-order control variate has no C delta term)
+  const double ac = (P.cv_order == 2) ? a : 0.0;
+  for (int o = tid; o < dd; o += kResLanes) {
+    const int r = o / d, c = o - r * d;
+    double acc = 0.0;
+    for (int f = 0; f < d; ++f) acc += (ac * Cm[r * d + f] - Qm[r * d + f]) * Sm[f * d + c];
+    KSm[o] = acc;
+  }
   const uint32_t n = (uint32_t)P.n;
   // indices of u* (refreshed block) or of u; a caller index outside [0, n)
   // reads row 0 and poisons the estimator
@@ -283,28 +281,44 @@ __global__ void __launch_bounds__(kResLanes) move_kernel_res(MoveArgs A, ResLayo
   for (int t = tid; t < Ly.nlds; t += kResLanes) load_lds(lrows + t * Ly.rs, index_star(kResLanes * RPL + t));
   if (tid == 0) load_lds(row0, index_star(0));
 
-  // one estimator pass at delta (in dsh) over the resident rows; the reduced
-  // sums arrive in wave 0
+  const double nm = P.n_over_m;
+  const double md = (double)m;
+  const int L = A.L;
+  // wave 0 leapfrog state
+  double delta = th - tb;   // theta - theta_bar of the current pass
+  double th1 = th;          // theta of the current pass
+  double p = 0.0, kd = 0.0, g0 = 0.0, H0 = 0.0, cdel0 = 0.0, lp1 = 0.0;
   double lhat_r = 0.0, sig2_r = 0.0, gl_r = 0.0, gs_r = 0.0;
-  auto pass = [&](double delta64) {
-    // delta64: wave 0 lane c holds component c (ignored elsewhere)
-    if (lead && lane < DC) dsh[lane] = (Real)(lane < d ? delta64 : 0.0);
+  // theta <- theta + eps Sigma p, K delta <- K delta + eps K Sigma p
+  auto drift = [&]() {
+    const double y = lds_matvec2<DC>(Sm, d, p, lane);
+    const double ky = from_upper_half(y);
+    if (lane < d) {
+      delta += eps * y;
+      th1 += eps * y;
+      kd += eps * ky;
+    }
+  };
+
+  // pass 0: the u-refresh at theta; passes 1..L: the leapfrog positions
+  for (int l = 0; l <= L; ++l) {
+    if (lead && lane < DC) dsh[lane] = (Real)delta;
     __syncthreads();
     double se, se2, shift;
     Real S1[DC], T1[DC];
     resident_accumulate<Real, DC, FAM, RPL>(P, rr, lrows, Ly.rs, Ly.nlds, row0, dsh, tid, se, se2, S1, T1, shift);
     // poisoned rows (caller index out of range) make the pass NaN
     const int bad = __syncthreads_or(poisoned ? 1 : 0);
-    se = wave_sum(se);
-    se2 = wave_sum(se2);
-    Real v[2 * 32 + 2];
+    se = xl::wave_allsum(se);
+    se2 = xl::wave_allsum(se2);
+    Real v[2 * DC];
 #pragma unroll
     for (int c = 0; c < DC; ++c) {
       v[c] = S1[c];
       v[DC + c] = T1[c];
     }
-    rs_step<Real, 2 * DC, 32>(v, lane);
-    const int comp = res_component<2 * DC>(lane);
+    xl::reduce_scatter<Real, 2 * DC, 0>(v, lane);
+    const int comp = xl::scatter_index<2 * DC>(lane);
     if (comp >= 0) redv[w * kWave + comp] = (double)v[0];
     if (lane == 0) {
       reds[2 * w] = se;
@@ -323,104 +337,103 @@ __global__ void __launch_bounds__(kResLanes) move_kernel_res(MoveArgs A, ResLayo
         }
       }
       if (bad) tse = tse2 = __builtin_nan("");
-      const double md = (double)m;
-      const double nm = P.n_over_m;
-      const double dsum = tse + md * shift;
       const double dbms = tse / md;
-      const double m2 = tse2 - tse * dbms;
-      const double dhat = nm * dsum;
-      sig2_r = nm * nm * (m2 < 0.0 ? 0.0 : m2);
-      const double cdel = lds_matvec<DC>(Cm, d, delta64, lane);
-      const double bl = lane < d ? P.cvB[lane] : 0.0;
-      const double qpart = (P.cv_order == 2) ? (bl * delta64 + 0.5 * delta64 * cdel) : bl * delta64;
-      lhat_r = P.cvA[0] + wave_sum(qpart) + dhat;
-      gl_r = lane < d ? bl + (P.cv_order == 2 ? cdel : 0.0) + nm * s1c : 0.0;
-      gs_r = lane < d ? 2.0 * nm * nm * (t1c - dbms * s1c) : 0.0;
+      if (l == 0 || l == L) {
+        // the estimator and both gradients at delta
+        const double m2 = tse2 - tse * dbms;
+        const double dhat = nm * (tse + md * shift);
+        sig2_r = nm * nm * (m2 < 0.0 ? 0.0 : m2);
+        const double cdel = lds_matvec<DC>(Cm, d, delta, lane);
+        const double qpart = (P.cv_order == 2) ? (bl * delta + 0.5 * delta * cdel) : bl * delta;
+        lhat_r = P.cvA[0] + xl::wave_allsum(qpart) + dhat;
+        gl_r = lane < d ? bl + (P.cv_order == 2 ? cdel : 0.0) + nm * s1c : 0.0;
+        gs_r = lane < d ? 2.0 * nm * nm * (t1c - dbms * s1c) : 0.0;
+        if (l == 0) {
+          cdel0 = cdel;
+        } else {
+          // closing half step at theta_L
+          const double dm = lane < d ? th1 - mu0l : 0.0;
+          const double rq = lds_matvec<DC>(Qm, d, dm, lane);
+          lp1 = xl::wave_allsum(-0.5 * dm * rq);
+          p += 0.5 * eps * (a * gl_r - 0.5 * a * a * gs_r - rq);
+        }
+      } else {
+        const double grad = lane < d ? g0 + kd + a * nm * s1c - a * a * nm * nm * (t1c - dbms * s1c) : 0.0;
+        p += eps * grad;
+        drift();
+      }
     }
-  };
-
-  // ---- 1. u | theta
-  pass(th - tb);
-  if (lead) {
-    const double lam0 = a * lh0 - 0.5 * a * a * sg0;
-    const double lam1 = a * lhat_r - 0.5 * a * a * sig2_r;
-    const double logr = lam1 - lam0;
-    const double logU = log(word_to_uniform(stream_word(P.seed, stream_ctr0(kUAccept, A.stage, A.move, 0), (uint64_t)i, 0)));
-    const bool acc = isfinite(logr) && (logU < logr);
-    if (lane == 0) {
-      flag[0] = acc ? 1 : 0;
-      A.accept[2 * i] = acc ? 1 : 0;
-    }
-    if (acc) {
-      lh0 = lhat_r; sg0 = sig2_r; gl0 = gl_r; gs0 = gs_r;
-    }
-  }
-  __syncthreads();
-  const bool acc_u = flag[0] != 0;
-  if (acc_u) {
-    for (int t = tid; t < b1 - b0; t += kResLanes) urow[b0 + t] = blk[t];
-  } else {
-    // restore the rows of the current block from u
-    poisoned = false;
+    if (l == 0) {
+      // ---- 1. u | theta
+      if (lead) {
+        const double lam0 = a * lh0 - 0.5 * a * a * sg0;
+        const double lam1 = a * lhat_r - 0.5 * a * a * sig2_r;
+        const double logr = lam1 - lam0;
+        const double logU =
+            log(word_to_uniform(stream_word(P.seed, stream_ctr0(kUAccept, A.stage, A.move, 0), (uint64_t)i, 0)));
+        const bool acc = isfinite(logr) && (logU < logr);
+        if (lane == 0) {
+          flag[0] = acc ? 1 : 0;
+          A.accept[2 * i] = acc ? 1 : 0;
+        }
+        if (acc) {
+          lh0 = lhat_r; sg0 = sig2_r; gl0 = gl_r; gs0 = gs_r;
+        }
+      }
+      __syncthreads();
+      const bool acc_u = flag[0] != 0;
+      if (acc_u) {
+        for (int t = tid; t < b1 - b0; t += kResLanes) urow[b0 + t] = blk[t];
+      } else {
+        // restore the rows of the current block from u
+        poisoned = false;
 #pragma unroll
-    for (int r = 0; r < RPL; ++r) {
-      const int j = tid + kResLanes * r;
-      if (j < m && j >= b0 && j < b1) load_reg(rr[r], urow[j]);
-      else if (j < m) poisoned |= (uint32_t)urow[j] >= n;
-    }
-    for (int t = tid; t < Ly.nlds; t += kResLanes) {
-      const int j = kResLanes * RPL + t;
-      if (j >= b0 && j < b1) load_lds(lrows + t * Ly.rs, urow[j]);
-      else poisoned |= (uint32_t)urow[j] >= n;
-    }
-    if (tid == 0 && b0 == 0 && b1 > 0) load_lds(row0, urow[0]);
-  }
-  // (the next pass starts with a barrier)
-
-  // ---- 2. theta | u: HMC (scalar work on wave 0)
-  double p = 0.0, v = 0.0, rq = 0.0, lp = 0.0, H0 = 0.0, th1 = th, lp1 = 0.0;
-  if (lead) {
-    const uint64_t cm = stream_ctr0(kMomentum, A.stage, A.move, 0);
-    const double z = lane < d ? stream_normal(P.seed, cm, (uint64_t)i, (uint32_t)lane) : 0.0;
-    for (int e = 0; e < d; ++e) {
-      const double ze = readlane_d(z, e);
-      p += (lane < d && e >= lane ? P.Linv[e * d + lane] : 0.0) * ze;
-    }
-    v = lds_matvec<DC>(Sm, d, p, lane);
-    const double K0 = 0.5 * wave_sum(p * v);
-    {
-      const double dm = lane < d ? th - P.mu0[lane] : 0.0;
-      rq = lds_matvec<DC>(Qm, d, dm, lane);
-      lp = wave_sum(-0.5 * dm * rq);
-    }
-    const double logpi0 = (a * lh0 - 0.5 * a * a * sg0) + lp;
-    H0 = -logpi0 + K0;
-    const double grad = a * gl0 - 0.5 * a * a * gs0 - rq;
-    p += 0.5 * eps * grad;
-    lp1 = lp;
-    lhat_r = lh0; sig2_r = sg0; gl_r = gl0; gs_r = gs0;
-  }
-  for (int l = 1; l <= A.L; ++l) {
-    if (lead) {
-      v = lds_matvec<DC>(Sm, d, p, lane);
-      th1 += eps * v;
-    }
-    pass(th1 - tb);
-    if (lead) {
-      const double dm = lane < d ? th1 - mu0l : 0.0;
-      rq = lds_matvec<DC>(Qm, d, dm, lane);
-      lp1 = wave_sum(-0.5 * dm * rq);
-      const double grad = a * gl_r - 0.5 * a * a * gs_r - rq;
-      p += ((l < A.L) ? eps : 0.5 * eps) * grad;
+        for (int r = 0; r < RPL; ++r) {
+          const int j = tid + kResLanes * r;
+          if (j < m && j >= b0 && j < b1) load_reg(rr[r], urow[j]);
+          else if (j < m) poisoned |= (uint32_t)urow[j] >= n;
+        }
+        for (int t = tid; t < Ly.nlds; t += kResLanes) {
+          const int j = kResLanes * RPL + t;
+          if (j >= b0 && j < b1) load_lds(lrows + t * Ly.rs, urow[j]);
+          else poisoned |= (uint32_t)urow[j] >= n;
+        }
+        if (tid == 0 && b0 == 0 && b1 > 0) load_lds(row0, urow[0]);
+      }
+      // ---- 2. theta | u: HMC from (theta, u), opening half step and drift
+      if (lead) {
+        const uint64_t cm = stream_ctr0(kMomentum, A.stage, A.move, 0);
+        const double z = lane < d ? stream_normal(P.seed, cm, (uint64_t)i, (uint32_t)lane) : 0.0;
+        for (int e = 0; e < d; ++e) {
+          const double ze = readlane_d(z, e);
+          p += (lane < d && e >= lane ? P.Linv[e * d + lane] : 0.0) * ze;
+        }
+        const double sp = lds_matvec<DC>(Sm, d, p, lane);
+        const double K0 = 0.5 * xl::wave_allsum(p * sp);
+        const double dm = lane < d ? th - mu0l : 0.0;
+        const double rq = lds_matvec<DC>(Qm, d, dm, lane);
+        const double lp = xl::wave_allsum(-0.5 * dm * rq);
+        H0 = -((a * lh0 - 0.5 * a * a * sg0) + lp) + K0;
+        p += 0.5 * eps * (a * gl0 - 0.5 * a * a * gs0 - rq);
+        lp1 = lp;
+        lhat_r = lh0; sig2_r = sg0; gl_r = gl0; gs_r = gs0;
+        // constant and linear parts of the gradient along the trajectory
+        const double qb = lds_matvec<DC>(Qm, d, tb - mu0l, lane);
+        g0 = lane < d ? a * bl - qb : 0.0;
+        kd = lane < d ? ac * cdel0 - (rq - qb) : 0.0;
+        drift();
+      }
+      // (the next pass starts with a barrier)
     }
   }
   if (lead) {
-    v = lds_matvec<DC>(Sm, d, p, lane);
-    const double K1 = 0.5 * wave_sum(p * v);
+    const double sp = lds_matvec<DC>(Sm, d, p, lane);
+    const double K1 = 0.5 * xl::wave_allsum(p * sp);
     const double logpi1 = (a * lhat_r - 0.5 * a * a * sig2_r) + lp1;
     const double H1 = -logpi1 + K1;
     const double logr = H0 - H1;
-    const double logU = log(word_to_uniform(stream_word(P.seed, stream_ctr0(kThetaAccept, A.stage, A.move, 0), (uint64_t)i, 0)));
+    const double logU =
+        log(word_to_uniform(stream_word(P.seed, stream_ctr0(kThetaAccept, A.stage, A.move, 0), (uint64_t)i, 0)));
     const bool acc = isfinite(logr) && (logU < logr);
     if (acc) {
       th = th1; lh0 = lhat_r; sg0 = sig2_r; gl0 = gl_r; gs0 = gs_r;
