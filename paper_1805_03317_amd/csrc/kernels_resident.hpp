@@ -33,9 +33,16 @@ constexpr int kResWaves = 4;
 constexpr int kResLanes = kResWaves * kWave;  // 256: one wavefront per SIMD
 
 // LDS carve of the resident kernel (all offsets in bytes, 16-byte aligned).
+//
+// Rows kept in LDS are stored by groups of 256 (LDS slot t = 256 k + lane is
+// row k of lane `lane`), each group lane-major so that a wavefront's reads of
+// one field are consecutive 16-byte (or 8-byte) words and free of bank
+// conflicts: first the 256 (eta_bar, aux) pairs, then DC / (16 /
+// sizeof(Real)) slabs of 256 16-byte chunks of x. The last group is
+// allocated whole.
 struct ResLayout {
-  int nlds;     // rows held in LDS
-  int rs;       // LDS row stride in elements (= kHeader + DC)
+  int nlds;       // rows held in LDS
+  int row_bytes;  // (2 + DC) reals
   int off_rows, off_row0, off_blk, off_redv, off_reds, off_dl, off_flag, off_mat, total;
 };
 
@@ -43,48 +50,51 @@ __host__ __device__ inline int res_align16(int x) { return (x + 15) & ~15; }
 
 __host__ __device__ inline ResLayout res_layout(int m, int G, int dc, int rpl, int real_bytes, int d) {
   ResLayout L;
-  L.rs = kHeader + dc;
+  L.row_bytes = (2 + dc) * real_bytes;
   L.nlds = m - kResLanes * rpl;
   if (L.nlds < 0) L.nlds = 0;
+  const int rows_bytes = (L.nlds + kResLanes - 1) / kResLanes * kResLanes * L.row_bytes;
   int off = 0;
-  L.off_rows = off; off = res_align16(off + L.nlds * L.rs * real_bytes);
-  L.off_row0 = off; off = res_align16(off + L.rs * real_bytes);
+  L.off_rows = off; off = res_align16(off + rows_bytes);
+  L.off_row0 = off; off = res_align16(off + (kHeader + dc) * real_bytes);
   L.off_blk = off; off = res_align16(off + ((m + G - 1) / G) * 4);
   L.off_redv = off; off = res_align16(off + kResWaves * kWave * 8);
   L.off_reds = off; off = res_align16(off + kResWaves * 2 * 8);
   L.off_dl = off; off = res_align16(off + dc * real_bytes);
   L.off_flag = off; off = res_align16(off + 16);
-  L.off_mat = off; off = res_align16(off + 4 * d * d * 8);  // C, Q0, Sigma, K Sigma
+  L.off_mat = off; off = res_align16(off + 4 * dc * dc * 8);  // C, Q0, Sigma, K Sigma
   L.total = off;
   return L;
 }
 
-// y_c = sum_{e < d} M[c*d + e] x_e for a d x d row-major matrix in LDS,
-// x_e held by lane e of the wavefront; lanes c >= d get 0.
+// y_c = sum_{e < d} M_ce x_e for a d x d matrix stored transposed in LDS
+// with column stride DC (M_ce at MT[e*DC + c]), x_e held by lane e of the
+// wavefront; lanes c >= d get 0.
 template <int DC>
-__device__ __forceinline__ double lds_matvec(const double* M, int d, double x, int lane) {
+__device__ __forceinline__ double lds_matvec(const double* MT, int d, double x, int lane) {
   double acc = 0.0;
   const int r = lane < d ? lane : 0;
 #pragma unroll
   for (int e = 0; e < DC; ++e) {
     const double xe = readlane_d(x, e);
-    const double me = (e < d) ? M[r * d + (e < d ? e : 0)] : 0.0;
+    const double me = (e < d) ? MT[e * DC + r] : 0.0;
     acc += me * xe;
   }
   return lane < d ? acc : 0.0;
 }
 
-// Two products of one vector in one sweep: AB holds A (rows 0..d-1) above
-// B (rows d..2d-1); lane c < d returns (A x)_c, lane 32 + c returns (B x)_c.
+// Two products of one vector in one sweep: AT (transposed A) is followed by
+// BT (transposed B); lane c < d returns (A x)_c, lane 32 + c returns (B x)_c.
 template <int DC>
-__device__ __forceinline__ double lds_matvec2(const double* AB, int d, double x, int lane) {
+__device__ __forceinline__ double lds_matvec2(const double* AT, int d, double x, int lane) {
   const int c = lane & 31;
-  const int r = (c < d ? c : 0) + (lane >> 5) * d;
+  const double* base = AT + (lane >> 5) * DC * DC;
+  const int r = c < d ? c : 0;
   double acc = 0.0;
 #pragma unroll
   for (int e = 0; e < DC; ++e) {
     const double xe = readlane_d(x, e);
-    const double me = (e < d) ? AB[r * d + (e < d ? e : 0)] : 0.0;
+    const double me = (e < d) ? base[e * DC + r] : 0.0;
     acc += me * xe;
   }
   return c < d ? acc : 0.0;
@@ -104,27 +114,47 @@ struct ResRow {
   Real x[DC];
 };
 
-// LDS row copy: header + x, vector width 16 bytes
+// Lane `lane`'s slots in the LDS row groups (see ResLayout).
 template <typename Real, int DC>
-__device__ __forceinline__ void copy_row_to_lds(const Real* __restrict__ g, Real* s) {
-  constexpr int kElems = kHeader + DC;
-  if constexpr (sizeof(Real) == 4) {
-    const float4* a = reinterpret_cast<const float4*>(g);
-    float4* b = reinterpret_cast<float4*>(s);
-#pragma unroll
-    for (int q = 0; q < kElems / 4; ++q) b[q] = a[q];
-  } else {
-    const double2* a = reinterpret_cast<const double2*>(g);
-    double2* b = reinterpret_cast<double2*>(s);
-#pragma unroll
-    for (int q = 0; q < kElems / 2; ++q) b[q] = a[q];
+struct LdsSlots {
+  static constexpr int kPer = 16 / (int)sizeof(Real);  // reals per 16-byte chunk
+  static constexpr int kChunks = DC / kPer;
+  static constexpr int kHdrBytes = kResLanes * 2 * (int)sizeof(Real);
+  static constexpr int kGroupBytes = kResLanes * (2 + DC) * (int)sizeof(Real);
+  char* hdr0;  // group 0 (eta_bar, aux) of this lane
+  char* x0;    // group 0 chunk 0 of this lane
+  __device__ __forceinline__ LdsSlots(char* rows, int lane)
+      : hdr0(rows + lane * 2 * (int)sizeof(Real)), x0(rows + kHdrBytes + lane * 16) {}
+  __device__ __forceinline__ Real* hdr(int k) const { return reinterpret_cast<Real*>(hdr0 + k * kGroupBytes); }
+  __device__ __forceinline__ uint4* chunk(int k, int q) const {
+    return reinterpret_cast<uint4*>(x0 + k * kGroupBytes + q * kResLanes * 16);
   }
+};
+
+// global packed row -> LDS group k of this lane
+template <typename Real, int DC>
+__device__ __forceinline__ void copy_row_to_lds(const Real* __restrict__ g, const LdsSlots<Real, DC>& S, int k) {
+  Real* h = S.hdr(k);
+  h[0] = g[0];
+  h[1] = g[1];
+  const uint4* x = reinterpret_cast<const uint4*>(g + kHeader);
+#pragma unroll
+  for (int q = 0; q < LdsSlots<Real, DC>::kChunks; ++q) *S.chunk(k, q) = x[q];
+}
+
+// the shift row (read by every lane): plain packed layout
+template <typename Real, int DC>
+__device__ __forceinline__ void copy_row_plain(const Real* __restrict__ g, Real* s) {
+  const uint4* a = reinterpret_cast<const uint4*>(g);
+  uint4* b = reinterpret_cast<uint4*>(s);
+#pragma unroll
+  for (int q = 0; q < (kHeader + DC) * (int)sizeof(Real) / 16; ++q) b[q] = a[q];
 }
 
 // Per-lane accumulation of one pass over the resident rows.
 template <typename Real, int DC, int FAM, int RPL>
 __device__ __forceinline__ void resident_accumulate(const Prob& P, const ResRow<Real, DC> (&rr)[RPL > 0 ? RPL : 1],
-                                                    const Real* lrows, int rs, int nlds, const Real* row0,
+                                                    char* lrows, int nlds, const Real* row0,
                                                     const Real* dsh, int tid, double& se, double& se2,
                                                     Real (&S1)[DC], Real (&T1)[DC], double& shift) {
   const int m = P.m;
@@ -169,13 +199,23 @@ __device__ __forceinline__ void resident_accumulate(const Prob& P, const ResRow<
       add(rr[r].x, dd, dp);
     }
   }
-  for (int t = tid; t < nlds; t += kResLanes) {
-    const Real* row = lrows + t * rs;
+  const LdsSlots<Real, DC> S(lrows, tid);
+#pragma unroll 1
+  for (int k = 0; k * kResLanes + tid < nlds; ++k) {
     Real x[DC];
 #pragma unroll
-    for (int c = 0; c < DC; ++c) x[c] = row[kHeader + c];
+    for (int q = 0; q < LdsSlots<Real, DC>::kChunks; ++q) {
+      if constexpr (sizeof(Real) == 4) {
+        const float4 v = *reinterpret_cast<const float4*>(S.chunk(k, q));
+        x[4 * q] = v.x; x[4 * q + 1] = v.y; x[4 * q + 2] = v.z; x[4 * q + 3] = v.w;
+      } else {
+        const double2 v = *reinterpret_cast<const double2*>(S.chunk(k, q));
+        x[2 * q] = v.x; x[2 * q + 1] = v.y;
+      }
+    }
+    const Real* h = S.hdr(k);
     Real dd, dp;
-    eval(row[0], row[1], x, dd, dp);
+    eval(h[0], h[1], x, dd, dp);
     add(x, dd, dp);
   }
 }
@@ -183,7 +223,7 @@ __device__ __forceinline__ void resident_accumulate(const Prob& P, const ResRow<
 template <typename Real, int DC, int FAM, int RPL>
 __global__ void __launch_bounds__(kResLanes) move_kernel_res(MoveArgs A, ResLayout Ly) {
   extern __shared__ __attribute__((aligned(16))) char smem[];
-  Real* lrows = reinterpret_cast<Real*>(smem + Ly.off_rows);
+  char* lrows = smem + Ly.off_rows;
   Real* row0 = reinterpret_cast<Real*>(smem + Ly.off_row0);
   int32_t* blk = reinterpret_cast<int32_t*>(smem + Ly.off_blk);
   double* redv = reinterpret_cast<double*>(smem + Ly.off_redv);
@@ -206,15 +246,19 @@ __global__ void __launch_bounds__(kResLanes) move_kernel_res(MoveArgs A, ResLayo
   int32_t* urow = A.u + (int64_t)i * m;
   const bool lead = (w == 0);
 
-  // the small matrices of the move: C, Q0, Sigma and, below, (a C - Q0) Sigma
+  // the small matrices of the move, stored transposed with column stride DC
+  // (element (r, c) at c*DC + r) so that lanes c = 0..d-1 read consecutive
+  // words at compile-time offsets: C, Q0, Sigma and, below, (a C - Q0) Sigma
+  constexpr int kM = DC * DC;
   double* Cm = reinterpret_cast<double*>(smem + Ly.off_mat);
-  double* Qm = Cm + dd;
-  double* Sm = Qm + dd;   // Sigma, then K Sigma right below it
-  double* KSm = Sm + dd;
-  for (int e = tid; e < dd; e += kResLanes) {
-    Cm[e] = P.cvC[e];
-    Qm[e] = P.Q0[e];
-    Sm[e] = P.Sigma[e];
+  double* Qm = Cm + kM;
+  double* Sm = Qm + kM;   // Sigma, then K Sigma right below it
+  double* KSm = Sm + kM;
+  for (int o = tid; o < dd; o += kResLanes) {
+    const int r = o / d, c = o - r * d;
+    Cm[c * DC + r] = P.cvC[o];
+    Qm[c * DC + r] = P.Q0[o];
+    Sm[c * DC + r] = P.Sigma[o];
   }
 
   // wave 0 state (component c in lane c)
@@ -243,8 +287,8 @@ __global__ void __launch_bounds__(kResLanes) move_kernel_res(MoveArgs A, ResLayo
   for (int o = tid; o < dd; o += kResLanes) {
     const int r = o / d, c = o - r * d;
     double acc = 0.0;
-    for (int f = 0; f < d; ++f) acc += (ac * Cm[r * d + f] - Qm[r * d + f]) * Sm[f * d + c];
-    KSm[o] = acc;
+    for (int f = 0; f < d; ++f) acc += (ac * Cm[f * DC + r] - Qm[f * DC + r]) * Sm[c * DC + f];
+    KSm[c * DC + r] = acc;
   }
   const uint32_t n = (uint32_t)P.n;
   // indices of u* (refreshed block) or of u; a caller index outside [0, n)
@@ -266,10 +310,16 @@ __global__ void __launch_bounds__(kResLanes) move_kernel_res(MoveArgs A, ResLayo
 #pragma unroll
     for (int c = 0; c < DC; ++c) r.x[c] = t.x[c];
   };
-  auto load_lds = [&](Real* s, int32_t k) {
+  const LdsSlots<Real, DC> slots(lrows, tid);
+  auto load_lds = [&](int grp, int32_t k) {
     const bool bad = (uint32_t)k >= n;
     poisoned |= bad;
-    copy_row_to_lds<Real, DC>(X + (int64_t)(bad ? 0 : k) * ld, s);
+    copy_row_to_lds<Real, DC>(X + (int64_t)(bad ? 0 : k) * ld, slots, grp);
+  };
+  auto load_row0 = [&](int32_t k) {
+    const bool bad = (uint32_t)k >= n;
+    poisoned |= bad;
+    copy_row_plain<Real, DC>(X + (int64_t)(bad ? 0 : k) * ld, row0);
   };
 
   ResRow<Real, DC> rr[RPL > 0 ? RPL : 1];
@@ -278,8 +328,9 @@ __global__ void __launch_bounds__(kResLanes) move_kernel_res(MoveArgs A, ResLayo
     const int j = tid + kResLanes * r;
     if (j < m) load_reg(rr[r], index_star(j));
   }
-  for (int t = tid; t < Ly.nlds; t += kResLanes) load_lds(lrows + t * Ly.rs, index_star(kResLanes * RPL + t));
-  if (tid == 0) load_lds(row0, index_star(0));
+  for (int k = 0; k * kResLanes + tid < Ly.nlds; ++k)
+    load_lds(k, index_star(kResLanes * (RPL + k) + tid));
+  if (tid == 0) load_row0(index_star(0));
 
   const double nm = P.n_over_m;
   const double md = (double)m;
@@ -306,7 +357,7 @@ __global__ void __launch_bounds__(kResLanes) move_kernel_res(MoveArgs A, ResLayo
     __syncthreads();
     double se, se2, shift;
     Real S1[DC], T1[DC];
-    resident_accumulate<Real, DC, FAM, RPL>(P, rr, lrows, Ly.rs, Ly.nlds, row0, dsh, tid, se, se2, S1, T1, shift);
+    resident_accumulate<Real, DC, FAM, RPL>(P, rr, lrows, Ly.nlds, row0, dsh, tid, se, se2, S1, T1, shift);
     // poisoned rows (caller index out of range) make the pass NaN
     const int bad = __syncthreads_or(poisoned ? 1 : 0);
     se = xl::wave_allsum(se);
@@ -393,12 +444,12 @@ __global__ void __launch_bounds__(kResLanes) move_kernel_res(MoveArgs A, ResLayo
           if (j < m && j >= b0 && j < b1) load_reg(rr[r], urow[j]);
           else if (j < m) poisoned |= (uint32_t)urow[j] >= n;
         }
-        for (int t = tid; t < Ly.nlds; t += kResLanes) {
-          const int j = kResLanes * RPL + t;
-          if (j >= b0 && j < b1) load_lds(lrows + t * Ly.rs, urow[j]);
+        for (int k = 0; k * kResLanes + tid < Ly.nlds; ++k) {
+          const int j = kResLanes * (RPL + k) + tid;
+          if (j >= b0 && j < b1) load_lds(k, urow[j]);
           else poisoned |= (uint32_t)urow[j] >= n;
         }
-        if (tid == 0 && b0 == 0 && b1 > 0) load_lds(row0, urow[0]);
+        if (tid == 0 && b0 == 0 && b1 > 0) load_row0(urow[0]);
       }
       // ---- 2. theta | u: HMC from (theta, u), opening half step and drift
       if (lead) {
