@@ -36,10 +36,13 @@ constexpr int kResLanes = kResWaves * kWave;  // 256: one wavefront per SIMD
 //
 // Rows kept in LDS are stored by groups of 256 (LDS slot t = 256 k + lane is
 // row k of lane `lane`), each group lane-major so that a wavefront's reads of
-// one field are consecutive 16-byte (or 8-byte) words and free of bank
-// conflicts: first the 256 (eta_bar, aux) pairs, then DC / (16 /
-// sizeof(Real)) slabs of 256 16-byte chunks of x. The last group is
-// allocated whole.
+// one field are consecutive words and free of bank conflicts: the header
+// (FP32: 256 eta_bar then 256 aux; FP64: 256 (eta_bar, aux) pairs), then
+// DC / (16 / sizeof(Real)) slabs of 256 16-byte chunks of x. The last group
+// is allocated whole. This is also the layout in which gfx950's
+// global_load_lds (4 or 16 bytes per lane, lane-major at a wavefront base)
+// deposits rows, so rows reach LDS without passing through registers.
+constexpr int kResMaxLdsGroups = 16;
 struct ResLayout {
   int nlds;       // rows held in LDS
   int row_bytes;  // (2 + DC) reals
@@ -62,7 +65,7 @@ __host__ __device__ inline ResLayout res_layout(int m, int G, int dc, int rpl, i
   L.off_reds = off; off = res_align16(off + kResWaves * 2 * 8);
   L.off_dl = off; off = res_align16(off + dc * real_bytes);
   L.off_flag = off; off = res_align16(off + 16);
-  L.off_mat = off; off = res_align16(off + 4 * dc * dc * 8);  // C, Q0, Sigma, K Sigma
+  L.off_mat = off; off = res_align16(off + 5 * dc * dc * 8);  // C, Q0, Sigma, K Sigma, Linv
   L.total = off;
   return L;
 }
@@ -121,26 +124,52 @@ struct LdsSlots {
   static constexpr int kChunks = DC / kPer;
   static constexpr int kHdrBytes = kResLanes * 2 * (int)sizeof(Real);
   static constexpr int kGroupBytes = kResLanes * (2 + DC) * (int)sizeof(Real);
-  char* hdr0;  // group 0 (eta_bar, aux) of this lane
+  char* hdr0;  // group 0 header of this lane
   char* x0;    // group 0 chunk 0 of this lane
   __device__ __forceinline__ LdsSlots(char* rows, int lane)
-      : hdr0(rows + lane * 2 * (int)sizeof(Real)), x0(rows + kHdrBytes + lane * 16) {}
-  __device__ __forceinline__ Real* hdr(int k) const { return reinterpret_cast<Real*>(hdr0 + k * kGroupBytes); }
-  __device__ __forceinline__ uint4* chunk(int k, int q) const {
-    return reinterpret_cast<uint4*>(x0 + k * kGroupBytes + q * kResLanes * 16);
+      : hdr0(rows + lane * (sizeof(Real) == 4 ? 4 : 16)), x0(rows + kHdrBytes + lane * 16) {}
+  __device__ __forceinline__ Real eb(int k) const { return *reinterpret_cast<const Real*>(hdr0 + k * kGroupBytes); }
+  __device__ __forceinline__ Real aux(int k) const {
+    return *reinterpret_cast<const Real*>(hdr0 + k * kGroupBytes + (sizeof(Real) == 4 ? kResLanes * 4 : 8));
+  }
+  __device__ __forceinline__ const uint4* chunk(int k, int q) const {
+    return reinterpret_cast<const uint4*>(x0 + k * kGroupBytes + q * kResLanes * 16);
   }
 };
 
-// global packed row -> LDS group k of this lane
+typedef __attribute__((address_space(3))) void lds_void_t;
+typedef __attribute__((address_space(1))) void glb_void_t;
+
+// Asynchronous copy of this lane's packed row g into LDS group k (waited for
+// with vmcnt). The LDS base of each transfer is the wavefront's: group k +
+// field offset + 64 * wave * size.
 template <typename Real, int DC>
-__device__ __forceinline__ void copy_row_to_lds(const Real* __restrict__ g, const LdsSlots<Real, DC>& S, int k) {
-  Real* h = S.hdr(k);
-  h[0] = g[0];
-  h[1] = g[1];
-  const uint4* x = reinterpret_cast<const uint4*>(g + kHeader);
+__device__ __forceinline__ void dma_row_to_lds(const Real* g, char* rows, int k, int wave) {
+  using S = LdsSlots<Real, DC>;
+  char* grp = rows + k * S::kGroupBytes;
+  if constexpr (sizeof(Real) == 4) {
+    const int o_eb = __builtin_amdgcn_readfirstlane(k * S::kGroupBytes + wave * kWave * 4);
+    const int o_aux = __builtin_amdgcn_readfirstlane(k * S::kGroupBytes + kResLanes * 4 + wave * kWave * 4);
+    __builtin_amdgcn_global_load_lds((glb_void_t*)g, (lds_void_t*)(rows + o_eb), 4, 0, 0);
+    __builtin_amdgcn_global_load_lds((glb_void_t*)(g + 1), (lds_void_t*)(rows + o_aux), 4, 0, 0);
+  } else {
+    const int o_h = __builtin_amdgcn_readfirstlane(k * S::kGroupBytes + wave * kWave * 16);
+    __builtin_amdgcn_global_load_lds((glb_void_t*)g, (lds_void_t*)(rows + o_h), 16, 0, 0);
+  }
+  (void)grp;
 #pragma unroll
-  for (int q = 0; q < LdsSlots<Real, DC>::kChunks; ++q) *S.chunk(k, q) = x[q];
+  for (int q = 0; q < S::kChunks; ++q) {
+    const int o = __builtin_amdgcn_readfirstlane(k * S::kGroupBytes + S::kHdrBytes + q * kResLanes * 16 +
+                                                 wave * kWave * 16);
+    __builtin_amdgcn_global_load_lds((glb_void_t*)(g + kHeader + q * S::kPer), (lds_void_t*)(rows + o), 16, 0, 0);
+  }
 }
+
+// Wait for all of this wavefront's outstanding global loads (LDS transfers
+// included): s_waitcnt with vmcnt 0 and the expcnt / lgkmcnt fields at their
+// maxima (gfx9 encoding), emitted as the instruction the compiler's own
+// wait-count tracking knows.
+__device__ __forceinline__ void wait_vm() { __builtin_amdgcn_s_waitcnt(0x0F70); }
 
 // the shift row (read by every lane): plain packed layout
 template <typename Real, int DC>
@@ -213,9 +242,8 @@ __device__ __forceinline__ void resident_accumulate(const Prob& P, const ResRow<
         x[2 * q] = v.x; x[2 * q + 1] = v.y;
       }
     }
-    const Real* h = S.hdr(k);
     Real dd, dp;
-    eval(h[0], h[1], x, dd, dp);
+    eval(S.eb(k), S.aux(k), x, dd, dp);
     add(x, dd, dp);
   }
 }
@@ -248,17 +276,20 @@ __global__ void __launch_bounds__(kResLanes) move_kernel_res(MoveArgs A, ResLayo
 
   // the small matrices of the move, stored transposed with column stride DC
   // (element (r, c) at c*DC + r) so that lanes c = 0..d-1 read consecutive
-  // words at compile-time offsets: C, Q0, Sigma and, below, (a C - Q0) Sigma
+  // words at compile-time offsets: C, Q0, Sigma and, below, (a C - Q0)
+  // Sigma; then Linv' (the momentum draw p = Linv' z)
   constexpr int kM = DC * DC;
   double* Cm = reinterpret_cast<double*>(smem + Ly.off_mat);
   double* Qm = Cm + kM;
   double* Sm = Qm + kM;   // Sigma, then K Sigma right below it
   double* KSm = Sm + kM;
+  double* LTm = KSm + kM;
   for (int o = tid; o < dd; o += kResLanes) {
     const int r = o / d, c = o - r * d;
     Cm[c * DC + r] = P.cvC[o];
     Qm[c * DC + r] = P.Q0[o];
     Sm[c * DC + r] = P.Sigma[o];
+    LTm[r * DC + c] = P.Linv[o];
   }
 
   // wave 0 state (component c in lane c)
@@ -310,11 +341,10 @@ __global__ void __launch_bounds__(kResLanes) move_kernel_res(MoveArgs A, ResLayo
 #pragma unroll
     for (int c = 0; c < DC; ++c) r.x[c] = t.x[c];
   };
-  const LdsSlots<Real, DC> slots(lrows, tid);
   auto load_lds = [&](int grp, int32_t k) {
     const bool bad = (uint32_t)k >= n;
     poisoned |= bad;
-    copy_row_to_lds<Real, DC>(X + (int64_t)(bad ? 0 : k) * ld, slots, grp);
+    dma_row_to_lds<Real, DC>(X + (int64_t)(bad ? 0 : k) * ld, lrows, grp, w);
   };
   auto load_row0 = [&](int32_t k) {
     const bool bad = (uint32_t)k >= n;
@@ -322,15 +352,42 @@ __global__ void __launch_bounds__(kResLanes) move_kernel_res(MoveArgs A, ResLayo
     copy_row_plain<Real, DC>(X + (int64_t)(bad ? 0 : k) * ld, row0);
   };
 
+  // gather: every subsample index first (slots past m read a valid entry
+  // and are never used), then the rows (LDS slots by direct transfers,
+  // register slots by loads), then one wait
+  const int ngroups = (Ly.nlds + kResLanes - 1) / kResLanes;
+  auto u_at = [&](int j) -> int32_t { return urow[j < m ? j : m - 1]; };
+  auto refreshed = [&](int j, int32_t gk) -> int32_t {
+    const bool in = (unsigned)(j - b0) < (unsigned)(b1 - b0);
+    const int32_t lk = blk[in ? j - b0 : 0];
+    return in ? lk : gk;
+  };
+  int32_t kx_lds[kResMaxLdsGroups];
+#pragma unroll
+  for (int k = 0; k < kResMaxLdsGroups; ++k)
+    if (k < ngroups) kx_lds[k] = u_at(kResLanes * (RPL + k) + tid);
+  int32_t kx_reg[RPL > 0 ? RPL : 1];
+#pragma unroll
+  for (int r = 0; r < RPL; ++r) kx_reg[r] = u_at(kResLanes * r + tid);
+  wait_vm();
+#pragma unroll
+  for (int k = 0; k < kResMaxLdsGroups; ++k)
+    if (k < ngroups) kx_lds[k] = refreshed(kResLanes * (RPL + k) + tid, kx_lds[k]);
+#pragma unroll
+  for (int r = 0; r < RPL; ++r) kx_reg[r] = refreshed(kResLanes * r + tid, kx_reg[r]);
+#pragma unroll
+  for (int k = 0; k < kResMaxLdsGroups; ++k) {
+    if (k < ngroups) {
+      if (k * kResLanes + tid < Ly.nlds) load_lds(k, kx_lds[k]);
+    }
+  }
   ResRow<Real, DC> rr[RPL > 0 ? RPL : 1];
 #pragma unroll
   for (int r = 0; r < RPL; ++r) {
-    const int j = tid + kResLanes * r;
-    if (j < m) load_reg(rr[r], index_star(j));
+    if (tid + kResLanes * r < m) load_reg(rr[r], kx_reg[r]);
   }
-  for (int k = 0; k * kResLanes + tid < Ly.nlds; ++k)
-    load_lds(k, index_star(kResLanes * (RPL + k) + tid));
   if (tid == 0) load_row0(index_star(0));
+  wait_vm();
 
   const double nm = P.n_over_m;
   const double md = (double)m;
@@ -444,21 +501,21 @@ __global__ void __launch_bounds__(kResLanes) move_kernel_res(MoveArgs A, ResLayo
           if (j < m && j >= b0 && j < b1) load_reg(rr[r], urow[j]);
           else if (j < m) poisoned |= (uint32_t)urow[j] >= n;
         }
-        for (int k = 0; k * kResLanes + tid < Ly.nlds; ++k) {
+        for (int k = 0; k < ngroups; ++k) {
           const int j = kResLanes * (RPL + k) + tid;
-          if (j >= b0 && j < b1) load_lds(k, urow[j]);
-          else poisoned |= (uint32_t)urow[j] >= n;
+          if (j < kResLanes * RPL + Ly.nlds) {
+            if (j >= b0 && j < b1) load_lds(k, urow[j]);
+            else poisoned |= (uint32_t)urow[j] >= n;
+          }
         }
         if (tid == 0 && b0 == 0 && b1 > 0) load_row0(urow[0]);
+        wait_vm();
       }
       // ---- 2. theta | u: HMC from (theta, u), opening half step and drift
       if (lead) {
         const uint64_t cm = stream_ctr0(kMomentum, A.stage, A.move, 0);
         const double z = lane < d ? stream_normal(P.seed, cm, (uint64_t)i, (uint32_t)lane) : 0.0;
-        for (int e = 0; e < d; ++e) {
-          const double ze = readlane_d(z, e);
-          p += (lane < d && e >= lane ? P.Linv[e * d + lane] : 0.0) * ze;
-        }
+        p = lds_matvec<DC>(LTm, d, z, lane);  // Linv is lower triangular
         const double sp = lds_matvec<DC>(Sm, d, p, lane);
         const double K0 = 0.5 * xl::wave_allsum(p * sp);
         const double dm = lane < d ? th - mu0l : 0.0;
