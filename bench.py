@@ -26,6 +26,13 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
+# Vector ALU peak without packed FP32: 256 CUs x 4 SIMDs x 16 lanes x 2 flops
+# (FMA) x 2.4 GHz. The FP32 contractions run as plain (non-packed) FMAs, so
+# this, not the packed 157.3 TFLOP/s figure, is their attainable peak; it is
+# also the FP64 vector peak.
+PEAK_VALU_TFLOPS = 78.6
+PEAK_VALU_PACKED_TFLOPS = 157.3
+MOVE_STREAMING, MOVE_RESIDENT = 1, 2
 
 
 def parse():
@@ -40,6 +47,9 @@ def parse():
     ap.add_argument("--workload", choices=["config1", "config2", "config4", "config5"], default="config2",
                     help="config2 (Poisson n=1e6 d=20) is the benchmark workload; the others are the "
                          "logistic d=5 FP64, logistic d=50 and additive logistic d=116 configurations")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 1 GiB device copy three times (the reference kernel for scaling "
+                         "FETCH_SIZE / WRITE_SIZE counters) and exit")
     return ap.parse_args()
 
 
@@ -47,6 +57,24 @@ def algorithmic_bytes_per_eval(d, fp32):
     """x_k (d values) + y_k + the 4-byte subsample index."""
     s = 4 if fp32 else 8
     return d * s + s + 4
+
+
+def algorithmic_flops_per_eval(d):
+    """The three length-d contractions of one eval: Delta = x'delta, S1 += d' x
+    and T1 += (d - shift) d' x, one FMA (2 flops) per element each. The scalar
+    remainder and the FP64 sums are not counted."""
+    return 6 * d
+
+
+def calibrate_copy():
+    import torch
+    n = 256 * 1024 * 1024  # 1 GiB of float32
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": 4 * n, "dispatches": 3}), flush=True)
 
 
 def run_path(w, precision, Xy_dev, args, eps):
@@ -93,11 +121,12 @@ def run_path(w, precision, Xy_dev, args, eps):
         "accept_u": float(acc[0]),
         "accept_theta": float(acc[1]),
         "newton_iters": info["newton_iters"],
+        "move_path": info["move_path"],
     }
     return smc, res
 
 
-DEVICE_SOURCES = ["kernels.hpp", "kernels_wide.hpp", "glm.hpp", "rng.hpp"]
+DEVICE_SOURCES = ["kernels.hpp", "kernels_wide.hpp", "kernels_resident.hpp", "xlane.hpp", "glm.hpp", "rng.hpp"]
 
 
 def device_source_hash():
@@ -109,10 +138,16 @@ def device_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(w, precision):
+def move_kernel_name(w, move_path):
+    if move_path == MOVE_RESIDENT:
+        return "move_kernel_res"
+    return "move_kernel_wide" if w.d > 32 else "move_kernel"
+
+
+def measured_traffic(w, precision, kernel):
     """HBM bytes per move launch from the committed PMC summary, if it was
     taken on the current device sources (else None)."""
-    path = os.path.join(ROOT, "profiles", f"move_kernel_{w.name}_{precision}_traffic.txt")
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{w.name}_{precision}_traffic.txt")
     if not os.path.exists(path):
         return None
     kv = {}
@@ -126,14 +161,26 @@ def measured_traffic(w, precision):
     return float(kv["traffic_bytes_per_launch"])
 
 
-def roofline(w, fp32, move_ms):
-    bpe = algorithmic_bytes_per_eval(w.d, fp32)
+def roofline(w, fp32, move_ms, move_path):
+    """The move kernel against its bound. The streaming kernels re-read every
+    row on every pass and are bounded by memory bandwidth; the resident kernel
+    gathers the rows once per move and keeps them on chip, so its passes are
+    bounded by the vector ALU."""
     evals = w.M * w.m * (w.L + 1)
+    kernel = move_kernel_name(w, move_path)
+    traffic = measured_traffic(w, "mixed" if fp32 else "fp64", kernel)
+    if move_path == MOVE_RESIDENT:
+        fpe = algorithmic_flops_per_eval(w.d)
+        achieved = fpe * evals / (move_ms * 1e-3) / 1e12
+        return {"bound": "alu", "achieved": round(achieved, 2), "peak": PEAK_VALU_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(achieved / PEAK_VALU_TFLOPS, 4), "traffic": traffic, "kernel": kernel,
+                "flops_per_eval": fpe, "evals_per_launch": evals,
+                "frac_of_packed_fp32_peak": round(achieved / PEAK_VALU_PACKED_TFLOPS, 4)}
+    bpe = algorithmic_bytes_per_eval(w.d, fp32)
     achieved = bpe * evals / (move_ms * 1e-3) / 1e9
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-            "frac": round(achieved / PEAK_HBM_GBS, 4),
-            "traffic": measured_traffic(w, "mixed" if fp32 else "fp64"),
-            "kernel": "move_kernel", "bytes_per_eval": bpe, "evals_per_launch": evals}
+            "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
+            "kernel": kernel, "bytes_per_eval": bpe, "evals_per_launch": evals}
 
 
 def cpu_baseline(w, count, eps):
@@ -166,6 +213,10 @@ def main():
         sys.exit(2)
     import torch
     from paper_1805_03317_amd import workloads as W
+
+    if args.calibrate_copy:
+        calibrate_copy()
+        return
 
     t_gen = time.perf_counter()
     w = {"config1": W.config1, "config2": W.config2, "config4": W.config4, "config5": W.config5}[args.workload]()
@@ -204,7 +255,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "n": w.n, "d": w.d, "M": w.M, "m": w.m, "G": w.G, "L": w.L,
                    "R": 1, "eps": eps, "precision": head, "step": "temper+mass+resample+move"},
-        "roofline": roofline(w, head == "mixed", r["move_ms"]),
+        "roofline": roofline(w, head == "mixed", r["move_ms"], r["move_path"]),
         "move_ms": r["move_ms"],
         "move_evals_per_s": r["move_evals_per_s"],
         "run": {k: r[k] for k in ("a", "stage", "stages_tempered", "accept_u", "accept_theta", "newton_iters")},
@@ -212,7 +263,7 @@ def main():
     if "fp64" in results and head == "mixed":
         f = results["fp64"]
         out["fp64"] = {"value": f["evals_per_s"], "ms_per_step": f["ms_per_step"], "move_ms": f["move_ms"],
-                       "roofline": roofline(w, False, f["move_ms"]),
+                       "roofline": roofline(w, False, f["move_ms"], f["move_path"]),
                        "mixed_over_fp64": r["evals_per_s"] / f["evals_per_s"]}
         # error of the mixed path against the FP64 path on the same particles
         sm, sf = ctxs["mixed"], ctxs["fp64"]
