@@ -70,36 +70,30 @@ __host__ __device__ inline ResLayout res_layout(int m, int G, int dc, int rpl, i
   return L;
 }
 
-// y_c = sum_{e < d} M_ce x_e for a d x d matrix stored transposed in LDS
-// with column stride DC (M_ce at MT[e*DC + c]), x_e held by lane e of the
-// wavefront; lanes c >= d get 0.
+// y_c = sum_e M_ce x_e for a d x d matrix stored transposed in LDS with
+// column stride DC and zero padding to DC x DC (M_ce at MT[e*DC + c]), x_e
+// held by lane e of the wavefront (zero for e >= d); lanes c >= d get 0. The
+// reads are unconditional, so they issue together.
 template <int DC>
 __device__ __forceinline__ double lds_matvec(const double* MT, int d, double x, int lane) {
   double acc = 0.0;
-  const int r = lane < d ? lane : 0;
+  const int r = lane < DC ? lane : 0;
 #pragma unroll
-  for (int e = 0; e < DC; ++e) {
-    const double xe = readlane_d(x, e);
-    const double me = (e < d) ? MT[e * DC + r] : 0.0;
-    acc += me * xe;
-  }
+  for (int e = 0; e < DC; ++e) acc += MT[e * DC + r] * readlane_d(x, e);
   return lane < d ? acc : 0.0;
 }
 
 // Two products of one vector in one sweep: AT (transposed A) is followed by
-// BT (transposed B); lane c < d returns (A x)_c, lane 32 + c returns (B x)_c.
+// BT (transposed B), both padded as above; lane c < d returns (A x)_c, lane
+// 32 + c returns (B x)_c.
 template <int DC>
 __device__ __forceinline__ double lds_matvec2(const double* AT, int d, double x, int lane) {
   const int c = lane & 31;
   const double* base = AT + (lane >> 5) * DC * DC;
-  const int r = c < d ? c : 0;
+  const int r = c < DC ? c : 0;
   double acc = 0.0;
 #pragma unroll
-  for (int e = 0; e < DC; ++e) {
-    const double xe = readlane_d(x, e);
-    const double me = (e < d) ? base[e * DC + r] : 0.0;
-    acc += me * xe;
-  }
+  for (int e = 0; e < DC; ++e) acc += base[e * DC + r] * readlane_d(x, e);
   return c < d ? acc : 0.0;
 }
 
@@ -265,7 +259,6 @@ __global__ void __launch_bounds__(kResLanes) move_kernel_res(MoveArgs A, ResLayo
   const int tid = threadIdx.x;
   const int w = tid / kWave, lane = tid % kWave;
   const int d = P.d;
-  const int dd = d * d;
   const int m = P.m;
   const int ld = P.ld;
   const double a = A.a;
@@ -284,12 +277,14 @@ __global__ void __launch_bounds__(kResLanes) move_kernel_res(MoveArgs A, ResLayo
   double* Sm = Qm + kM;   // Sigma, then K Sigma right below it
   double* KSm = Sm + kM;
   double* LTm = KSm + kM;
-  for (int o = tid; o < dd; o += kResLanes) {
-    const int r = o / d, c = o - r * d;
-    Cm[c * DC + r] = P.cvC[o];
-    Qm[c * DC + r] = P.Q0[o];
-    Sm[c * DC + r] = P.Sigma[o];
-    LTm[r * DC + c] = P.Linv[o];
+  for (int o = tid; o < kM; o += kResLanes) {
+    const int r = o / DC, c = o - r * DC;  // element (r, c) of the padded matrices
+    const bool in = r < d && c < d;
+    const int g = in ? r * d + c : 0;
+    Cm[c * DC + r] = in ? P.cvC[g] : 0.0;
+    Qm[c * DC + r] = in ? P.Q0[g] : 0.0;
+    Sm[c * DC + r] = in ? P.Sigma[g] : 0.0;
+    LTm[r * DC + c] = in ? P.Linv[g] : 0.0;
   }
 
   // wave 0 state (component c in lane c)
@@ -315,11 +310,11 @@ __global__ void __launch_bounds__(kResLanes) move_kernel_res(MoveArgs A, ResLayo
   __syncthreads();
   // K = a C - Q0 (a first-order control variate has no C delta term)
   const double ac = (P.cv_order == 2) ? a : 0.0;
-  for (int o = tid; o < dd; o += kResLanes) {
-    const int r = o / d, c = o - r * d;
+  for (int o = tid; o < kM; o += kResLanes) {
+    const int r = o / DC, c = o - r * DC;
     double acc = 0.0;
     for (int f = 0; f < d; ++f) acc += (ac * Cm[f * DC + r] - Qm[f * DC + r]) * Sm[c * DC + f];
-    KSm[c * DC + r] = acc;
+    KSm[c * DC + r] = acc;  // zero outside d x d: the padded entries of C, Q0, Sigma are 0
   }
   const uint32_t n = (uint32_t)P.n;
   // indices of u* (refreshed block) or of u; a caller index outside [0, n)
@@ -388,6 +383,9 @@ __global__ void __launch_bounds__(kResLanes) move_kernel_res(MoveArgs A, ResLayo
   }
   if (tid == 0) load_row0(index_star(0));
   wait_vm();
+  // poisoned rows (caller index out of range) make every pass NaN; the
+  // barrier also publishes the LDS rows
+  int bad = __syncthreads_or(poisoned ? 1 : 0);
 
   const double nm = P.n_over_m;
   const double md = (double)m;
@@ -415,10 +413,9 @@ __global__ void __launch_bounds__(kResLanes) move_kernel_res(MoveArgs A, ResLayo
     double se, se2, shift;
     Real S1[DC], T1[DC];
     resident_accumulate<Real, DC, FAM, RPL>(P, rr, lrows, Ly.nlds, row0, dsh, tid, se, se2, S1, T1, shift);
-    // poisoned rows (caller index out of range) make the pass NaN
-    const int bad = __syncthreads_or(poisoned ? 1 : 0);
+    const bool full = (l == 0 || l == L);  // estimator value needed (not only the gradient)
     se = xl::wave_allsum(se);
-    se2 = xl::wave_allsum(se2);
+    if (full) se2 = xl::wave_allsum(se2);
     Real v[2 * DC];
 #pragma unroll
     for (int c = 0; c < DC; ++c) {
@@ -439,14 +436,13 @@ __global__ void __launch_bounds__(kResLanes) move_kernel_res(MoveArgs A, ResLayo
       for (int q = 0; q < kResWaves; ++q) {
         tse += reds[2 * q];
         tse2 += reds[2 * q + 1];
-        if (lane < DC) {
-          s1c += redv[q * kWave + lane];
-          t1c += redv[q * kWave + DC + lane];
-        }
+        const int c = lane < DC ? lane : 0;
+        s1c += redv[q * kWave + c];
+        t1c += redv[q * kWave + DC + c];
       }
       if (bad) tse = tse2 = __builtin_nan("");
       const double dbms = tse / md;
-      if (l == 0 || l == L) {
+      if (full) {
         // the estimator and both gradients at delta
         const double m2 = tse2 - tse * dbms;
         const double dhat = nm * (tse + md * shift);
@@ -510,6 +506,7 @@ __global__ void __launch_bounds__(kResLanes) move_kernel_res(MoveArgs A, ResLayo
         }
         if (tid == 0 && b0 == 0 && b1 > 0) load_row0(urow[0]);
         wait_vm();
+        bad = __syncthreads_or(poisoned ? 1 : 0);
       }
       // ---- 2. theta | u: HMC from (theta, u), opening half step and drift
       if (lead) {
