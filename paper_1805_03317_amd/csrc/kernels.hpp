@@ -525,13 +525,21 @@ __device__ __forceinline__ double incr_weight(double a, double a_prev, double lh
 }
 
 // Block reductions with one barrier each: every call writes the wave partials
-// into its own half of `sh` (the caller alternates `buf`), so a write never
-// races the previous call's reads. Fixed order: butterfly, then waves 0..15.
-__device__ __forceinline__ double block_max_1(double v, double* sh, int buf) {
-  const int w = threadIdx.x / kWave, l = threadIdx.x % kWave;
+// into its own slice of `sh` (the caller rotates `buf` over 4 slices), so a
+// write never races the previous call's reads. Fixed order: butterfly, then
+// waves 0..15.
+constexpr int kTemperSlice = 5 * kTemperWaves;
+
+__device__ __forceinline__ double wave_max(double v) {
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o, kWave));
-  double* b = sh + buf * 2 * kTemperWaves;
+  return v;
+}
+
+__device__ __forceinline__ double block_max_1(double v, double* sh, int buf) {
+  const int w = threadIdx.x / kWave, l = threadIdx.x % kWave;
+  v = wave_max(v);
+  double* b = sh + buf * kTemperSlice;
   if (l == 0) b[w] = v;
   __syncthreads();
   double t = -INFINITY;
@@ -540,30 +548,50 @@ __device__ __forceinline__ double block_max_1(double v, double* sh, int buf) {
   return t;
 }
 
-__device__ __forceinline__ void block_sum_2(double& v1, double& v2, double* sh, int buf) {
+template <int N>
+__device__ __forceinline__ void block_sum_n(double* v, double* sh, int buf) {
+  static_assert(N <= 5, "slice holds 5 values per wave");
   const int w = threadIdx.x / kWave, l = threadIdx.x % kWave;
-  v1 = wave_sum(v1);
-  v2 = wave_sum(v2);
-  double* b = sh + buf * 2 * kTemperWaves;
-  if (l == 0) { b[w] = v1; b[kTemperWaves + w] = v2; }
-  __syncthreads();
-  double t1 = 0.0, t2 = 0.0;
 #pragma unroll
-  for (int q = 0; q < kTemperWaves; ++q) { t1 += b[q]; t2 += b[kTemperWaves + q]; }
-  v1 = t1;
-  v2 = t2;
+  for (int k = 0; k < N; ++k) v[k] = wave_sum(v[k]);
+  double* b = sh + buf * kTemperSlice;
+  if (l == 0) {
+#pragma unroll
+    for (int k = 0; k < N; ++k) b[k * kTemperWaves + w] = v[k];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+    double t = 0.0;
+#pragma unroll
+    for (int q = 0; q < kTemperWaves; ++q) t += b[k * kTemperWaves + q];
+    v[k] = t;
+  }
+}
+
+__device__ __forceinline__ void block_sum_2(double& v1, double& v2, double* sh, int buf) {
+  double v[2] = {v1, v2};
+  block_sum_n<2>(v, sh, buf);
+  v1 = v[0];
+  v2 = v[1];
 }
 
 // Tempering exponent (section 2.2; Algorithm 2 step b): the root in
-// (a_prev, 1] of g(a) = log ESS(a) - log(ess_frac M), by false position with
-// the Illinois modification, keeping the bracket [lo, hi] with g(lo) >= 0 >
-// g(hi) and taking a bisection step every fourth iteration, until the bracket
-// is below 1e-15 (1 - a_prev). a = 1 when ESS(1) meets the target; a = lo
-// (the largest point found with ESS >= target), or hi if lo never moved.
+// (a_prev, 1] of g(a) = log ESS(a) - log(ess_frac M). a = 1 when ESS(1)
+// meets the target. Otherwise a safeguarded Newton iteration on g, whose
+// derivative comes with the same sums: with x_i(a) = log W_i + nu_i(a) and
+// nu_i' = lhat_i - a sig2_i,
+//   g'(a) = 2 sum w nu' / sum w - 2 sum w^2 nu' / sum w^2.
+// The bracket [lo, hi] keeps g(lo) >= 0 > g(hi); a step that leaves it, or a
+// non-negative slope, is replaced by bisection. The first trial point treats
+// the log weights as Gaussian in a: g(a) ~ g(a_prev) - (a - a_prev)^2 V with
+// V the weighted variance of nu' at a_prev. The iteration stops when a step
+// or the bracket is below 1e-15 (1 - a_prev); a = lo (the largest point found
+// with ESS >= target), or hi if lo never moved.
 // Then the reweighting, normalisation and the evidence increment
 // log sum_i W_i exp(nu_i) (sections 3.3, 3.5; Algorithm 2 step c).
 __global__ void __launch_bounds__(kTemperThreads) temper_kernel(TemperArgs A) {
-  __shared__ double sh[4 * 2 * kTemperWaves];
+  __shared__ double sh[4 * kTemperSlice];
   const int t = threadIdx.x;
   double lw[kTemperPer], lh[kTemperPer], s2[kTemperPer];
 #pragma unroll
@@ -576,50 +604,73 @@ __global__ void __launch_bounds__(kTemperThreads) temper_kernel(TemperArgs A) {
   }
   const double log_target = log(A.ess_frac * (double)A.M);
   int buf = 0, evals = 0;
-  auto log_ess = [&](double a) -> double {
+  // g(a), g'(a) and (with var) the weighted variance of nu' at a
+  auto eval = [&](double a, double& g, double& dg, double* var) {
     double mx = -INFINITY;
 #pragma unroll
     for (int q = 0; q < kTemperPer; ++q) mx = fmax(mx, lw[q] + incr_weight(a, A.a_prev, lh[q], s2[q]));
     mx = block_max_1(mx, sh, buf);
     buf = (buf + 1) & 3;
-    double w1 = 0.0, w2 = 0.0;
+    double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     if (isfinite(mx)) {
 #pragma unroll
       for (int q = 0; q < kTemperPer; ++q) {
-        const double w = exp(lw[q] + incr_weight(a, A.a_prev, lh[q], s2[q]) - mx);
-        w1 += w;
-        w2 += w * w;
+        const double x = lw[q] + incr_weight(a, A.a_prev, lh[q], s2[q]);
+        const double w = exp(x - mx);
+        const double nd = (w > 0.0) ? lh[q] - a * s2[q] : 0.0;
+        v[0] += w;
+        v[1] += w * w;
+        v[2] += w * nd;
+        v[3] += w * w * nd;
+        v[4] += w * nd * nd;
       }
     }
-    block_sum_2(w1, w2, sh, buf);
+    if (var) block_sum_n<5>(v, sh, buf);
+    else block_sum_n<4>(v, sh, buf);
     buf = (buf + 1) & 3;
     ++evals;
-    return isfinite(mx) ? 2.0 * log(w1) - log(w2) : -INFINITY;
+    if (!isfinite(mx)) {
+      g = -INFINITY;
+      dg = 0.0;
+      if (var) *var = 0.0;
+      return;
+    }
+    g = 2.0 * log(v[0]) - log(v[1]) - log_target;
+    dg = 2.0 * v[2] / v[0] - 2.0 * v[3] / v[1];
+    if (var) {
+      const double mu = v[2] / v[0];
+      *var = v[4] / v[0] - mu * mu;
+    }
   };
   double a = 1.0;
-  double ghi = log_ess(1.0) - log_target;
+  double ghi, dghi;
+  eval(1.0, ghi, dghi, nullptr);
   if (!(ghi >= 0.0)) {
     double lo = A.a_prev, hi = 1.0;
-    double glo = log_ess(lo) - log_target;
+    double glo, dglo, var;
+    eval(lo, glo, dglo, &var);
     const double tol = 1e-15 * (1.0 - A.a_prev);
     if (glo >= 0.0) {
-      int side = 0;
+      double c = (var > 0.0 && isfinite(var)) ? lo + sqrt(glo / var) : 0.5 * (lo + hi);
       for (int it = 0; it < kTemperMaxIter && (hi - lo) > tol; ++it) {
-        double c = (it % 4 == 3) ? 0.5 * (lo + hi) : hi - ghi * (hi - lo) / (ghi - glo);
         if (!(c > lo && c < hi)) c = 0.5 * (lo + hi);
         if (!(c > lo && c < hi)) break;  // no representable point inside the bracket
-        const double gc = log_ess(c) - log_target;
-        if (gc >= 0.0) {
-          lo = c;
-          glo = gc;
-          if (side == 1) ghi *= 0.5;
-          side = 1;
-        } else {
-          hi = c;
-          ghi = (gc > -INFINITY) ? gc : -1e300;
-          if (side == -1) glo *= 0.5;
-          side = -1;
+        double gc, dgc;
+        eval(c, gc, dgc, nullptr);
+        if (gc >= 0.0) lo = c; else hi = c;
+        // Newton from c, or bisection when the step is unusable
+        double nxt = (dgc < 0.0 && isfinite(gc)) ? c - gc / dgc : 0.5 * (lo + hi);
+        if (!(nxt > lo && nxt < hi)) nxt = 0.5 * (lo + hi);
+        if (fabs(nxt - c) <= tol) {
+          // converged: settle on the side of the root with ESS >= target
+          if (gc < 0.0 && nxt > lo && nxt < hi) {
+            double gn, dgn;
+            eval(nxt, gn, dgn, nullptr);
+            if (gn >= 0.0) lo = nxt; else hi = nxt;
+          }
+          break;
         }
+        c = nxt;
       }
     } else {
       // ESS already below the target at a_prev: the smallest step a 60-step
@@ -749,9 +800,74 @@ __device__ void factor_spd(const FactorArgs& F, double* sh) {
   (void)sh;
 }
 
+// The same factorisation with the matrices in LDS (d <= kFactorLdsMaxD):
+// left-looking by columns, L[r][j] = (S[r][j] - sum_{k<j} L[r][k] L[j][k]) /
+// L[j][j] with the subtractions in the order of the right-looking update
+// above, so the factor is the same; then the inverse by the same column-wise
+// forward substitution. Ls and Li are d*d doubles of LDS each.
+constexpr int kFactorLdsMaxD = 64;
+
+__device__ void factor_spd_lds(const FactorArgs& F, double* Ls, double* Li) {
+  const int d = F.d;
+  const int t = threadIdx.x;
+  double tr = 0.0;
+  for (int r = 0; r < d; ++r) tr += F.S[r * d + r];
+  bool ok = false;
+  for (int att = 0; att <= 10 && !ok; ++att) {
+    const double jit = att > 0 ? 1e-10 * (tr / d) * pow(10.0, (double)(att - 1)) : 0.0;
+    for (int e = t; e < d * d; e += kMomThreads) {
+      const int r = e / d, c = e % d;
+      Ls[e] = F.S[e] + (r == c ? jit : 0.0);
+    }
+    __syncthreads();
+    bool good = true;
+    for (int j = 0; j < d; ++j) {
+      double sj = 0.0;
+      if (t >= j && t < d) {
+        sj = Ls[t * d + j];
+        for (int k = 0; k < j; ++k) sj -= Ls[t * d + k] * Ls[j * d + k];
+      }
+      // row j's entries left of the diagonal are final; nobody reads (j, j) now
+      if (t == j) Ls[j * d + j] = sj;
+      __syncthreads();
+      const double p = Ls[j * d + j];
+      good = p > 0.0;
+      if (!good) break;  // the same value in every thread
+      const double ljj = sqrt(p);
+      if (t > j && t < d) Ls[t * d + j] = sj / ljj;
+      __syncthreads();
+      // (j, j) is read again only after the loop
+      if (t == j) Ls[j * d + j] = ljj;
+    }
+    ok = good;
+    __syncthreads();
+    if (ok && att > 0) {
+      for (int r = t; r < d; r += kMomThreads) F.S[r * d + r] += jit;
+    }
+  }
+  // inverse: column c of L^{-1} solves L x = e_c
+  for (int c = t; c < d; c += kMomThreads) {
+    for (int r = 0; r < d; ++r) {
+      if (r < c) { Li[r * d + c] = 0.0; continue; }
+      double s = (r == c) ? 1.0 : 0.0;
+      for (int k = c; k < r; ++k) s -= Ls[r * d + k] * Li[k * d + c];
+      Li[r * d + c] = s / Ls[r * d + r];
+    }
+  }
+  __syncthreads();
+  for (int e = t; e < d * d; e += kMomThreads) {
+    const int r = e / d, c = e % d;
+    F.L[e] = c > r ? 0.0 : Ls[e];
+    F.Linv[e] = Li[e];
+  }
+  if (t == 0) F.status[0] = ok ? 0.0 : 1.0;
+}
+
 __global__ void __launch_bounds__(kMomThreads) factor_kernel(FactorArgs F) {
   __shared__ double sh[kMomThreads / kWave];
-  factor_spd(F, sh);
+  extern __shared__ double fl[];  // 2 d*d when d <= kFactorLdsMaxD
+  if (F.d <= kFactorLdsMaxD) factor_spd_lds(F, fl, fl + F.d * F.d);
+  else factor_spd(F, sh);
 }
 
 // Weighted mean and covariance, accumulated about theta_bar (close to the
@@ -817,7 +933,7 @@ __global__ void __launch_bounds__(kMomThreads) moments_partial_kernel(MomentArgs
 
 __global__ void __launch_bounds__(kMomThreads) moments_final_kernel(MomentArgs A) {
   __shared__ double sh[kMomThreads / kWave];
-  extern __shared__ double tot[];  // d + d(d+1)/2
+  extern __shared__ double tot[];  // d + d(d+1)/2, then 2 d*d when d <= kFactorLdsMaxD
   const int t = threadIdx.x;
   const int d = A.d;
   const int ne = d + d * (d + 1) / 2;
@@ -836,7 +952,12 @@ __global__ void __launch_bounds__(kMomThreads) moments_final_kernel(MomentArgs A
     A.F.S[c * d + r] = v;
   }
   __syncthreads();
-  factor_spd(A.F, sh);
+  if (d <= kFactorLdsMaxD) {
+    double* Ls = tot + ne;
+    factor_spd_lds(A.F, Ls, Ls + d * d);
+  } else {
+    factor_spd(A.F, sh);
+  }
 }
 
 // --------------------------------------------------------------------------

@@ -475,7 +475,10 @@ smc_status factor_device(smc_ctx c, double* S, double* L, double* Linv) {
   f.L = L;
   f.Linv = Linv;
   f.status = c->at<double>(c->lay.status);
-  hipLaunchKernelGGL(factor_kernel, dim3(1), dim3(kMomThreads), 0, c->stream, f);
+  const size_t flds = (c->pb.d <= kFactorLdsMaxD) ? (size_t)2 * c->pb.d * c->pb.d * 8 : 0;
+  HIP_TRY(c, hipFuncSetAttribute(reinterpret_cast<const void*>(factor_kernel),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)flds));
+  hipLaunchKernelGGL(factor_kernel, dim3(1), dim3(kMomThreads), flds, c->stream, f);
   LAUNCH_CHECK(c);
   double stv = 0.0;
   HIP_TRY(c, hipMemcpyAsync(&stv, f.status, 8, hipMemcpyDeviceToHost, c->stream));
@@ -664,8 +667,10 @@ smc_status smc_mass(smc_ctx c) {
   hipLaunchKernelGGL(moments_partial_kernel, dim3(a.nblocks), dim3(kMomThreads), (size_t)kMomTile * d * 8,
                      c->stream, a);
   LAUNCH_CHECK(c);
-  hipLaunchKernelGGL(moments_final_kernel, dim3(1), dim3(kMomThreads), (size_t)(d + d * (d + 1) / 2) * 8,
-                     c->stream, a);
+  const size_t mlds = (size_t)(d + d * (d + 1) / 2) * 8 + (d <= kFactorLdsMaxD ? (size_t)2 * d * d * 8 : 0);
+  HIP_TRY(c, hipFuncSetAttribute(reinterpret_cast<const void*>(moments_final_kernel),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)mlds));
+  hipLaunchKernelGGL(moments_final_kernel, dim3(1), dim3(kMomThreads), mlds, c->stream, a);
   LAUNCH_CHECK(c);
   double stv = 0.0;
   HIP_TRY(c, hipMemcpyAsync(&stv, a.F.status, 8, hipMemcpyDeviceToHost, c->stream));
