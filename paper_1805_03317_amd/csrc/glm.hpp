@@ -44,9 +44,9 @@ template <> struct Tol<double> {
 template <> struct Tol<float> {
   static constexpr float series_logistic = 0.25f;
   static constexpr float direct_logistic = 2.0f;
-  static constexpr float series_exp = 0.5f;
+  static constexpr float series_exp = 1.0f;
   static constexpr int n_cumulant = 10;
-  static constexpr int n_exp = 10;
+  static constexpr int n_exp = 12;
 };
 
 __device__ __forceinline__ double dev_expm1(double x) { return expm1(x); }
@@ -121,6 +121,20 @@ __device__ __forceinline__ T inv_fact(int k) {
   }
 }
 
+// e^D - 1 for |D| >= 1 in FP32: e^D = 2^t (1 + ln2 r) with t = D log2(e)
+// rounded and r its rounding error (an FMA plus the low part of log2(e)),
+// 2^t from the hardware exponential; about 2 ulp, and for |D| >= 1 the
+// subtraction of 1 loses at most 1.3 bits.
+__device__ __forceinline__ float exp_minus_one_wide(float D) {
+  constexpr float kL2eHi = 1.44269502162933349609375f;   // log2(e) rounded to float
+  constexpr float kL2eLo = 1.925963033500011079e-8f;     // log2(e) - kL2eHi
+  constexpr float kLn2 = 0.693147180559945309f;
+  const float t = D * kL2eHi;
+  const float r = __builtin_fmaf(D, kL2eHi, -t) + D * kL2eLo;
+  const float p = __builtin_amdgcn_exp2f(t);
+  return __builtin_fmaf(p, kLn2 * r, p) - 1.0f;
+}
+
 // E2 = e^D - 1 - D and E3 = e^D - 1 - D - D^2/2
 template <typename T>
 __device__ __forceinline__ void exp_remainders(T D, T& E2, T& E3) {
@@ -132,7 +146,9 @@ __device__ __forceinline__ void exp_remainders(T D, T& E2, T& E3) {
     E3 = acc * D * D * D;
     E2 = E3 + T(0.5) * D * D;
   } else {
-    const T em1 = dev_expm1(D);
+    T em1;
+    if constexpr (sizeof(T) == 4) em1 = exp_minus_one_wide(D);
+    else em1 = dev_expm1(D);
     E2 = em1 - D;
     E3 = E2 - T(0.5) * D * D;
   }
