@@ -77,6 +77,17 @@ def lib():
         L.orc_resample_ancestors.argtypes = [C.c_int32, C.POINTER(C.c_double), C.c_uint32, C.POINTER(C.c_int32)]
         L.orc_resample_offset.restype = C.c_uint32
         L.orc_resample_offset.argtypes = [C.c_uint64, C.c_uint32]
+        L.orc_resample_multinomial_words.argtypes = [C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_uint64),
+                                                     C.POINTER(C.c_int32)]
+        L.orc_resample_multinomial.argtypes = [C.c_int32, C.POINTER(C.c_double), C.c_uint64, C.c_uint32,
+                                               C.POINTER(C.c_int32)]
+        L.orc_grid_point.restype = C.c_double
+        L.orc_grid_point.argtypes = [C.c_double, C.c_int32]
+        L.orc_temper_grid.restype = C.c_int
+        L.orc_temper_grid.argtypes = [C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                      C.POINTER(C.c_double), C.c_double, C.c_double, C.c_int32,
+                                      C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                      C.POINTER(C.c_double)]
         L.orc_init_particles.restype = C.c_int
         L.orc_init_particles.argtypes = [C.c_int32, C.c_int32, C.c_int32, C.c_int64, C.c_uint64,
                                          C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_double),
@@ -230,6 +241,44 @@ def resample_ancestors(logw, U32):
 
 def resample_offset(seed, stage):
     return int(lib().orc_resample_offset(seed, stage))
+
+
+def resample_multinomial(logw, seed, stage):
+    """Multinomial resampling (section 2.1) with the stage's Philox words."""
+    logw = np.ascontiguousarray(logw, dtype=np.float64)
+    anc = np.zeros(len(logw), dtype=np.int32)
+    lib().orc_resample_multinomial(len(logw), _dp(logw), int(seed), int(stage), _ip(anc))
+    return anc
+
+
+def resample_multinomial_words(logw, words):
+    """Multinomial resampling with given 64-bit uniform words (one per slot)."""
+    logw = np.ascontiguousarray(logw, dtype=np.float64)
+    words = np.ascontiguousarray(words, dtype=np.uint64)
+    anc = np.zeros(len(logw), dtype=np.int32)
+    lib().orc_resample_multinomial_words(len(logw), _dp(logw), words.ctypes.data_as(C.POINTER(C.c_uint64)),
+                                          _ip(anc))
+    return anc
+
+
+def grid_point(a_prev, j):
+    return float(lib().orc_grid_point(float(a_prev), int(j)))
+
+
+def temper_grid(lhat, sig2, logw, a_prev, ess_frac=0.8, S=129):
+    """The paper's grid rule (section 2.2); returns a, dlogz, ess, new logw, ESS on the grid."""
+    lhat = np.ascontiguousarray(lhat, dtype=np.float64)
+    sig2 = np.ascontiguousarray(sig2, dtype=np.float64)
+    lw = np.array(logw, dtype=np.float64)
+    grid = np.zeros(S)
+    a = C.c_double()
+    dz = C.c_double()
+    ess = C.c_double()
+    st = lib().orc_temper_grid(len(lw), _dp(lhat), _dp(sig2), _dp(lw), float(a_prev), float(ess_frac), int(S),
+                               _dp(grid), C.byref(a), C.byref(dz), C.byref(ess))
+    if st != 0:
+        raise FloatingPointError(f"oracle grid temper failed: {st}")
+    return a.value, dz.value, ess.value, lw, grid
 
 
 def init_particles(M, d, m, n, seed, mu0, Q0):

@@ -21,7 +21,8 @@
  * (seed, 0) with the counter layout
  *   word0 = purpose<<56 | stage<<32 | move<<16 | dataset
  *   word1 = particle, word2 = draw>>2, word3 = 0, output word = draw & 3.
- * Purposes: 0 prior normals, 1 initial subsample, 2 resampling offset,
+ * Purposes: 0 prior normals, 1 initial subsample, 2 resampling (systematic
+ * offset: particle 0 draw 0; multinomial slot k: particle k draw 1),
  * 3 block choice, 4 block indices, 5 u-accept uniform, 6 momentum normals,
  * 7 theta-accept uniform.
  *
@@ -513,6 +514,24 @@ static double logsumexp(int32_t M, const double *v)
     return mx + (double)logl(s);
 }
 
+/* Reweighting at the chosen exponent a (section 3.3) and the log-evidence
+ * increment log sum_i W_i exp(nu_i) (section 3.5). */
+static int reweight(int32_t M, const double *lhat, const double *sig2, double *logw, double a_prev,
+                    double a, double *a_out, double *dlogz_out, double *ess_out)
+{
+    double *lw = malloc(sizeof(double) * (size_t)M);
+    for (int32_t i = 0; i < M; ++i) lw[i] = logw[i] + incr(a, a_prev, lhat[i], sig2[i]);
+    double lse_new = logsumexp(M, lw);
+    double lse_old = logsumexp(M, logw);
+    if (!isfinite(lse_new)) { free(lw); return ORC_ERR_NONFINITE; }
+    *ess_out = ess_at(M, logw, lhat, sig2, a, a_prev);
+    *dlogz_out = lse_new - lse_old;
+    for (int32_t i = 0; i < M; ++i) logw[i] = lw[i] - lse_new;
+    *a_out = a;
+    free(lw);
+    return ORC_OK;
+}
+
 /*
  * Chooses a in (a_prev, 1] with ESS(a) = ess_frac*M by bisection (60 halvings
  * of [a_prev, 1], keeping the side whose ESS is at least the target; a = 1 when
@@ -535,17 +554,40 @@ int orc_temper(int32_t M, const double *lhat, const double *sig2, double *logw, 
         }
         a = (lo > a_prev) ? lo : hi;
     }
-    double *lw = malloc(sizeof(double) * (size_t)M);
-    for (int32_t i = 0; i < M; ++i) lw[i] = logw[i] + incr(a, a_prev, lhat[i], sig2[i]);
-    double lse_new = logsumexp(M, lw);
-    double lse_old = logsumexp(M, logw);
-    if (!isfinite(lse_new)) { free(lw); return ORC_ERR_NONFINITE; }
-    *ess_out = ess_at(M, logw, lhat, sig2, a, a_prev);
-    *dlogz_out = lse_new - lse_old;
-    for (int32_t i = 0; i < M; ++i) logw[i] = lw[i] - lse_new;
-    *a_out = a;
-    free(lw);
-    return ORC_OK;
+    return reweight(M, lhat, sig2, logw, a_prev, a, a_out, dlogz_out, ess_out);
+}
+
+/* The paper's own rule (section 2.2): evaluate the ESS on a grid of
+ * candidate exponents and take the one whose ESS is closest to the target
+ * (the paper uses 0.8 M). The paper does not give the grid; here it is
+ * geometric in the step, a_j = a_prev + (1 - a_prev) 2^(-j/4) for
+ * j = 0..S-1 (a_0 = 1), written with the correctly rounded constants
+ * 2^(-1/4), 2^(-1/2), 2^(-3/4). Ties go to the smaller j (the larger a).
+ * Only points above a_prev are candidates (near a = 1 the smallest steps
+ * round away), so every stage moves. */
+double orc_grid_point(double a_prev, int32_t j)
+{
+    static const double frac[4] = {1.0, 0x1.ae89f995ad3adp-1, 0x1.6a09e667f3bcdp-1, 0x1.306fe0a31b715p-1};
+    if (j == 0) return 1.0;
+    return a_prev + (1.0 - a_prev) * ldexp(frac[j & 3], -(j >> 2));
+}
+
+int orc_temper_grid(int32_t M, const double *lhat, const double *sig2, double *logw, double a_prev,
+                    double ess_frac, int32_t S, double *ess_grid, double *a_out, double *dlogz_out,
+                    double *ess_out)
+{
+    if (S < 1) return ORC_ERR_ARG;
+    double target = ess_frac * (double)M;
+    int32_t best = 0;
+    double bestd = INFINITY;
+    for (int32_t j = 0; j < S; ++j) {
+        double aj = orc_grid_point(a_prev, j);
+        double e = ess_at(M, logw, lhat, sig2, aj, a_prev);
+        if (ess_grid) ess_grid[j] = e;
+        double dist = fabs(e - target);
+        if (aj > a_prev && dist < bestd) { bestd = dist; best = j; }
+    }
+    return reweight(M, lhat, sig2, logw, a_prev, orc_grid_point(a_prev, best), a_out, dlogz_out, ess_out);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -628,6 +670,40 @@ void orc_resample_ancestors(int32_t M, const double *logw, uint32_t U32, int32_t
 uint32_t orc_resample_offset(uint64_t seed, uint32_t stage)
 {
     return (uint32_t)(orc_rng_word(seed, 2, stage, 0, 0, 0, 0) >> 32);
+}
+
+/* Multinomial resampling (section 2.1, the paper's choice): every slot k
+ * draws its ancestor independently with probability W_i. In integers, with
+ * c_i and S as in the systematic scheme above and a uniform 64-bit word r_k,
+ * t_k = floor(r_k S / 2^64) and the ancestor is the smallest j whose
+ * inclusive prefix sum exceeds t_k (so i is drawn with probability c_i / S). */
+void orc_resample_multinomial_words(int32_t M, const double *logw, const uint64_t *words, int32_t *anc)
+{
+    double mx = -INFINITY;
+    for (int32_t i = 0; i < M; ++i) if (logw[i] > mx) mx = logw[i];
+    uint64_t *cum = malloc(sizeof(uint64_t) * (size_t)M);
+    uint64_t S = 0;
+    for (int32_t i = 0; i < M; ++i) {
+        double w = exp(logw[i] - mx);
+        S += (uint64_t)floor(ldexp(w, 48));
+        cum[i] = S;
+    }
+    for (int32_t k = 0; k < M; ++k) {
+        uint64_t t = (uint64_t)(((unsigned __int128)words[k] * S) >> 64);
+        int32_t j = 0;
+        while (cum[j] <= t) ++j;
+        anc[k] = j;
+    }
+    free(cum);
+}
+
+/* The words: purpose 2 (resampling), the stage, particle slot k, draw 1. */
+void orc_resample_multinomial(int32_t M, const double *logw, uint64_t seed, uint32_t stage, int32_t *anc)
+{
+    uint64_t *words = malloc(sizeof(uint64_t) * (size_t)M);
+    for (int32_t k = 0; k < M; ++k) words[k] = orc_rng_word(seed, 2, stage, 0, 0, (uint64_t)k, 1);
+    orc_resample_multinomial_words(M, logw, words, anc);
+    free(words);
 }
 
 /* ------------------------------------------------------------------------ */
