@@ -122,14 +122,27 @@ smc_status smc_init(const smc_problem* pb, void* stream, smc_ctx* out);
 
 /*
  * Algorithm 2 steps a-c. Increments the stage, chooses the next exponent
- * a in (a_prev, 1] with ESS(a) = ess_frac * M by multisection (bisection
- * with 8 probes per step, 19 steps: resolution below 1e-18 of 1 - a_prev;
- * a = 1 when ESS(1) already meets it), reweights logw with the annealed estimator
+ * a in (a_prev, 1] with ESS(a) = ess_frac * M (section 2.2, with the target
+ * of smc_problem.ess_frac) by a safeguarded Newton iteration on log ESS
+ * (resolution 1e-15 of 1 - a_prev; a = 1 when ESS(1) already meets it),
+ * reweights logw with the annealed estimator
  * (a - a_prev) l_hat - (a^2 - a_prev^2) sigma2_hat / 2 (normalised), and adds
  * the log evidence increment log sum_i W_i exp(...) (section 3.5).
  * Host outputs (any may be NULL). Synchronises.
  */
 smc_status smc_temper(smc_ctx ctx, double* a_out, double* dlogz_out, double* ess_out);
+
+/*
+ * The same step with the paper's own exponent rule (section 2.2): the ESS is
+ * evaluated at the grid points a_j = a_prev + (1 - a_prev) 2^(-j/4),
+ * j = 0..grid_points-1 (a_0 = 1), and a is the point above a_prev whose ESS
+ * is closest to ess_frac * M (the paper uses ess_frac = 0.8; the first point
+ * on ties). grid_points in [1, 256]; ess_frac in (0, 1]. Reweighting and the
+ * evidence increment as in smc_temper. ess_grid_out (host, grid_points
+ * values, may be NULL) receives the ESS at every grid point. Synchronises.
+ */
+smc_status smc_temper_grid(smc_ctx ctx, int32_t grid_points, double ess_frac, double* a_out,
+                           double* dlogz_out, double* ess_out, double* ess_grid_out);
 
 /* Algorithm 2 step d: weighted particle covariance Sigma (inverse mass matrix),
  * its Cholesky factor and inverse factor (a jitter ladder 1e-10..1e-1 times
@@ -140,6 +153,13 @@ smc_status smc_mass(smc_ctx ctx);
  * (one Philox offset per stage); copies theta, u and the caches from the
  * ancestors and sets logw = -log M. */
 smc_status smc_resample(smc_ctx ctx);
+
+/* Algorithm 2 step e with the paper's multinomial resampling (section 2.1):
+ * slot k takes the ancestor of its own uniform (Philox purpose 2, particle k,
+ * draw 1) under the integer weights floor(2^48 W_i / max W), i.e. the
+ * smallest i whose inclusive prefix sum exceeds floor(r_k S / 2^64). Copies
+ * as smc_resample. */
+smc_status smc_resample_multinomial(smc_ctx ctx);
 
 /* Algorithm 2 step f: R Markov moves (Algorithm 1) of every particle at the
  * current exponent: block refresh of u (one of G blocks, uniform), then HMC

@@ -327,8 +327,14 @@ def num_threads():
 # Algorithm 2, driven step by step
 # ---------------------------------------------------------------------------
 
-def run_smc(prob, M, m, G, seed, eps_fn, L, R, ess_frac=0.5, max_stages=10000, callback=None):
-    """Subsampling SMC (Algorithm 2): returns dict with log Z, temperatures, particles."""
+def run_smc(prob, M, m, G, seed, eps_fn, L, R, ess_frac=0.5, max_stages=10000, callback=None,
+            schemes="default", grid_points=129):
+    """Subsampling SMC (Algorithm 2): returns dict with log Z, temperatures, particles.
+
+    schemes="default": ESS bisection and systematic resampling; schemes="paper":
+    the paper's grid rule (ess_frac is then the grid target, 0.8 in the paper)
+    and multinomial resampling (sections 2.1, 2.2)."""
+    paper = schemes == "paper"
     theta, u, logw = init_particles(M, prob.d, m, prob.n, seed, prob.mu0, prob.Q0)
     est = prob.estimate(theta, u)
     lhat, sig2 = est["lhat"], est["sig2"]
@@ -338,10 +344,16 @@ def run_smc(prob, M, m, G, seed, eps_fn, L, R, ess_frac=0.5, max_stages=10000, c
     stage = 0
     while a < 1.0 and stage < max_stages:
         stage += 1
-        a_new, dz, ess, logw = temper(lhat, sig2, logw, a, ess_frac)
+        if paper:
+            a_new, dz, ess, logw, _ = temper_grid(lhat, sig2, logw, a, ess_frac, grid_points)
+        else:
+            a_new, dz, ess, logw = temper(lhat, sig2, logw, a, ess_frac)
         logz += dz
         _, Sigma, Lc = moments(theta, logw)
-        anc = resample_ancestors(logw, resample_offset(seed, stage))
+        if paper:
+            anc = resample_multinomial(logw, seed, stage)
+        else:
+            anc = resample_ancestors(logw, resample_offset(seed, stage))
         theta, u, lhat, sig2 = theta[anc], u[anc], lhat[anc], sig2[anc]
         logw = np.full(M, -math.log(M))
         a = a_new

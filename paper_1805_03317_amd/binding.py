@@ -37,7 +37,8 @@ class _Info(C.Structure):
 
 
 EXPORTS = [
-    "smc_workspace_size", "smc_init", "smc_temper", "smc_mass", "smc_resample", "smc_move",
+    "smc_workspace_size", "smc_init", "smc_temper", "smc_temper_grid", "smc_mass", "smc_resample",
+    "smc_resample_multinomial", "smc_move",
     "loglik_est", "loglik_grad", "smc_refresh", "smc_get_info", "smc_set_stage", "smc_set_mass",
     "smc_get_mass", "smc_get_cv", "smc_full_loglik", "smc_destroy", "smc_status_string",
     "smc_last_error",
@@ -60,8 +61,10 @@ def lib():
     L.smc_workspace_size.argtypes = [C.POINTER(_Problem)]
     L.smc_init.argtypes = [C.POINTER(_Problem), vp, C.POINTER(vp)]
     L.smc_temper.argtypes = [vp, C.POINTER(dbl), C.POINTER(dbl), C.POINTER(dbl)]
+    L.smc_temper_grid.argtypes = [vp, i32, dbl, C.POINTER(dbl), C.POINTER(dbl), C.POINTER(dbl), vp]
     L.smc_mass.argtypes = [vp]
     L.smc_resample.argtypes = [vp]
+    L.smc_resample_multinomial.argtypes = [vp]
     L.smc_move.argtypes = [vp, dbl, i32, i32]
     L.loglik_est.argtypes = [vp, i32, vp, vp, vp, vp, vp]
     L.loglik_grad.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp]
@@ -179,11 +182,23 @@ class SubsampledSMC:
         self._check(lib().smc_temper(self._h, C.byref(a), C.byref(dz), C.byref(ess)))
         return a.value, dz.value, ess.value
 
+    def temper_grid(self, grid_points=129, ess_frac=0.8):
+        """The paper's grid rule for the next exponent; returns a, dlogz, ess and the ESS on the grid."""
+        import numpy as np
+        a, dz, ess = C.c_double(), C.c_double(), C.c_double()
+        grid = np.zeros(int(grid_points))
+        self._check(lib().smc_temper_grid(self._h, int(grid_points), float(ess_frac), C.byref(a), C.byref(dz),
+                                          C.byref(ess), _host_ptr(grid)))
+        return a.value, dz.value, ess.value, grid
+
     def mass(self):
         self._check(lib().smc_mass(self._h))
 
-    def resample(self):
-        self._check(lib().smc_resample(self._h))
+    def resample(self, multinomial=False):
+        if multinomial:
+            self._check(lib().smc_resample_multinomial(self._h))
+        else:
+            self._check(lib().smc_resample(self._h))
 
     def move(self, eps, L, R=1):
         self._check(lib().smc_move(self._h, float(eps), int(L), int(R)))
@@ -253,14 +268,22 @@ class SubsampledSMC:
         return float(A[0]), B, Cm
 
     # -- a full run ---------------------------------------------------------------
-    def run(self, eps_fn, L, R, max_stages=100000, callback=None):
-        """Algorithm 2 until a = 1; returns log Z and the per-stage record."""
+    def run(self, eps_fn, L, R, max_stages=100000, callback=None, schemes="default", grid_points=129,
+            grid_ess_frac=0.8):
+        """Algorithm 2 until a = 1; returns log Z and the per-stage record.
+
+        schemes="paper" uses the paper's grid rule for the exponent (target
+        grid_ess_frac * M) and multinomial resampling."""
+        paper = schemes == "paper"
         rec = []
         a = self.info()["a"]
         while a < 1.0 and len(rec) < max_stages:
-            a, dz, ess = self.temper()
+            if paper:
+                a, dz, ess, _ = self.temper_grid(grid_points, grid_ess_frac)
+            else:
+                a, dz, ess = self.temper()
             self.mass()
-            self.resample()
+            self.resample(multinomial=paper)
             eps = eps_fn(len(rec) + 1, a, self.d)
             self.move(eps, L, R)
             rec.append({"a": a, "dlogz": dz, "ess": ess, "eps": eps})

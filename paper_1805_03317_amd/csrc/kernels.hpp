@@ -517,6 +517,33 @@ struct TemperArgs {
   const double* sig2;
   double* logw;     // in/out
   double* out;      // [a, dlogz, ess, status, evaluations]
+  const double* grid_ess;  // null: root search; else the ESS at grid_n grid points
+  int grid_n;
+};
+
+// Grid of candidate exponents of the paper's grid rule (section 2.2):
+// a_j = a_prev + (1 - a_prev) 2^(-j/4), a_0 = 1 (2^(-1/4), 2^(-1/2) and
+// 2^(-3/4) correctly rounded), with the product and the sum rounded
+// separately (no fused multiply-add), so every grid point is a fixed function
+// of a_prev and j.
+__device__ inline double grid_exponent(double a_prev, int j) {
+#pragma clang fp contract(off)
+  if (j == 0) return 1.0;
+  const int r = j & 3;
+  const double f = r == 0 ? 1.0 : r == 1 ? 0x1.ae89f995ad3adp-1 : r == 2 ? 0x1.6a09e667f3bcdp-1 : 0x1.306fe0a31b715p-1;
+  return a_prev + (1.0 - a_prev) * ldexp(f, -(j >> 2));
+}
+
+constexpr int kGridMax = 256;
+constexpr int kGridThreads = 256;
+
+struct GridArgs {
+  int M;
+  double a_prev;
+  const double* lhat;
+  const double* sig2;
+  const double* logw;
+  double* ess;  // grid_n
 };
 
 __device__ __forceinline__ double incr_weight(double a, double a_prev, double lh, double s2) {
@@ -574,6 +601,45 @@ __device__ __forceinline__ void block_sum_2(double& v1, double& v2, double* sh, 
   block_sum_n<2>(v, sh, buf);
   v1 = v[0];
   v2 = v[1];
+}
+
+// ESS at grid point j = blockIdx.x (block_max over 256 threads, then the two
+// sums in fixed order).
+__global__ void __launch_bounds__(kGridThreads) grid_ess_kernel(GridArgs A) {
+  __shared__ double sh[3 * (kGridThreads / kWave)];
+  const int t = threadIdx.x, w = t / kWave, l = t % kWave;
+  const double a = grid_exponent(A.a_prev, blockIdx.x);
+  double mx = -INFINITY;
+  for (int i = t; i < A.M; i += kGridThreads) mx = fmax(mx, A.logw[i] + incr_weight(a, A.a_prev, A.lhat[i], A.sig2[i]));
+  mx = wave_max(mx);
+  if (l == 0) sh[w] = mx;
+  __syncthreads();
+  mx = -INFINITY;
+#pragma unroll
+  for (int q = 0; q < kGridThreads / kWave; ++q) mx = fmax(mx, sh[q]);
+  double s1 = 0.0, s2 = 0.0;
+  if (isfinite(mx)) {
+    for (int i = t; i < A.M; i += kGridThreads) {
+      const double e = exp(A.logw[i] + incr_weight(a, A.a_prev, A.lhat[i], A.sig2[i]) - mx);
+      s1 += e;
+      s2 += e * e;
+    }
+  }
+  s1 = wave_sum(s1);
+  s2 = wave_sum(s2);
+  if (l == 0) {
+    sh[kGridThreads / kWave + w] = s1;
+    sh[2 * (kGridThreads / kWave) + w] = s2;
+  }
+  __syncthreads();
+  if (t == 0) {
+    double t1 = 0.0, t2 = 0.0;
+    for (int q = 0; q < kGridThreads / kWave; ++q) {
+      t1 += sh[kGridThreads / kWave + q];
+      t2 += sh[2 * (kGridThreads / kWave) + q];
+    }
+    A.ess[blockIdx.x] = isfinite(mx) ? t1 * t1 / t2 : 0.0;
+  }
 }
 
 // Tempering exponent (section 2.2; Algorithm 2 step b): the root in
@@ -643,9 +709,25 @@ __global__ void __launch_bounds__(kTemperThreads) temper_kernel(TemperArgs A) {
     }
   };
   double a = 1.0;
-  double ghi, dghi;
-  eval(1.0, ghi, dghi, nullptr);
-  if (!(ghi >= 0.0)) {
+  double ghi = 0.0, dghi;
+  if (A.grid_ess) {
+    // the paper's grid rule: the grid point above a_prev whose ESS is closest
+    // to the target, the first on ties
+    const double target = A.ess_frac * (double)A.M;
+    int best = 0;
+    double bestd = INFINITY;
+    for (int j = 0; j < A.grid_n; ++j) {
+      const double dist = fabs(A.grid_ess[j] - target);
+      if (grid_exponent(A.a_prev, j) > A.a_prev && dist < bestd) {
+        bestd = dist;
+        best = j;
+      }
+    }
+    a = grid_exponent(A.a_prev, best);
+  } else {
+    eval(1.0, ghi, dghi, nullptr);
+  }
+  if (!A.grid_ess && !(ghi >= 0.0)) {
     double lo = A.a_prev, hi = 1.0;
     double glo, dglo, var;
     eval(lo, glo, dglo, &var);
@@ -969,6 +1051,7 @@ constexpr int kResPer = 8;  // M <= 8192
 
 struct ResampleArgs {
   int M;
+  int multinomial;  // 0: systematic, 1: multinomial
   uint64_t seed;
   uint32_t stage;
   const double* logw;
@@ -1029,14 +1112,21 @@ __global__ void __launch_bounds__(kResThreads) resample_kernel(ResampleArgs A) {
   for (int q = 0; q < kResPer; ++q) cum[t * kResPer + q] = excl + c[q];
   __syncthreads();
   const unsigned long long S = cum[M - 1];
-  const uint32_t U32 = (uint32_t)(stream_word(A.seed, stream_ctr0(kResampleOffset, A.stage, 0, 0), 0, 0) >> 32);
+  const uint64_t c0 = stream_ctr0(kResampleOffset, A.stage, 0, 0);
+  const uint32_t U32 = (uint32_t)(stream_word(A.seed, c0, 0, 0) >> 32);
   for (int k = t; k < M; k += kResThreads) {
-    // t_k = floor((k 2^32 + U32) S / (M 2^32)) = floor(floor(P / 2^32) / M)
-    const uint64_t a = ((uint64_t)k << 32) + U32;
-    const uint64_t plo = a * (uint64_t)S, phi = __umul64hi(a, (uint64_t)S);
-    const uint64_t shi = phi >> 32;
-    const uint64_t slo = (phi << 32) | (plo >> 32);
-    const uint64_t tk = div_u96_by_u32(shi, slo, (uint32_t)M);
+    uint64_t tk;
+    if (A.multinomial) {
+      // slot k's own uniform word (particle k, draw 1): t_k = floor(r_k S / 2^64)
+      tk = __umul64hi(stream_word(A.seed, c0, (uint64_t)k, 1), (uint64_t)S);
+    } else {
+      // t_k = floor((k 2^32 + U32) S / (M 2^32)) = floor(floor(P / 2^32) / M)
+      const uint64_t a = ((uint64_t)k << 32) + U32;
+      const uint64_t plo = a * (uint64_t)S, phi = __umul64hi(a, (uint64_t)S);
+      const uint64_t shi = phi >> 32;
+      const uint64_t slo = (phi << 32) | (plo >> 32);
+      tk = div_u96_by_u32(shi, slo, (uint32_t)M);
+    }
     // smallest j with cum[j] > tk
     int lo = 0, hi = M - 1;
     while (lo < hi) {

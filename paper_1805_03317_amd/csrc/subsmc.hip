@@ -52,7 +52,7 @@ int packed_ld(int d, bool fp32) {
 // Workspace regions, in carve order.
 struct Layout {
   size_t Xp, theta_bar, cvA, cvB, cvC, mu0, Q0, Qw, L0, L0inv, Sigma, Lchol, Linv, mean, status,
-      tout, scratch_theta, grad_l, grad_s, anc, th2, u2, lh2, sg2, gl2, gs2, partials, mpartials, total;
+      tout, grid, scratch_theta, grad_l, grad_s, anc, th2, u2, lh2, sg2, gl2, gs2, partials, mpartials, total;
   int ld;
   int cv_blocks;
   int mom_blocks;
@@ -86,6 +86,7 @@ bool compute_layout(const smc_problem* pb, Layout& L) {
   L.mean = take(d * 8);
   L.status = take(4 * 8);
   L.tout = take(8 * 8);
+  L.grid = take((size_t)kGridMax * 8);
   L.scratch_theta = take(d * 8);
   L.grad_l = take(M * d * 8);
   L.grad_s = take(M * d * 8);
@@ -619,17 +620,34 @@ smc_status smc_init(const smc_problem* pb, void* stream, smc_ctx* out) {
 #undef HTRY
 }
 
-smc_status smc_temper(smc_ctx c, double* a_out, double* dlogz_out, double* ess_out) {
-  if (!c) return SMC_ERR_INVALID_ARG;
+static smc_status temper_impl(smc_ctx c, int grid_points, double ess_frac, double* a_out, double* dlogz_out,
+                              double* ess_out, double* ess_grid_out) {
   if (c->a >= 1.0) return fail(c, SMC_ERR_STATE, "tempering already reached a = 1");
   TemperArgs t;
   t.M = c->pb.M;
   t.a_prev = c->a;
-  t.ess_frac = c->pb.ess_frac;
+  t.ess_frac = ess_frac;
   t.lhat = c->pb.lhat;
   t.sig2 = c->pb.sig2;
   t.logw = c->pb.logw;
   t.out = c->at<double>(c->lay.tout);
+  t.grid_ess = nullptr;
+  t.grid_n = 0;
+  if (grid_points > 0) {
+    GridArgs g;
+    g.M = c->pb.M;
+    g.a_prev = c->a;
+    g.lhat = c->pb.lhat;
+    g.sig2 = c->pb.sig2;
+    g.logw = c->pb.logw;
+    g.ess = c->at<double>(c->lay.grid);
+    hipLaunchKernelGGL(grid_ess_kernel, dim3(grid_points), dim3(kGridThreads), 0, c->stream, g);
+    LAUNCH_CHECK(c);
+    t.grid_ess = g.ess;
+    t.grid_n = grid_points;
+    if (ess_grid_out)
+      HIP_TRY(c, hipMemcpyAsync(ess_grid_out, g.ess, (size_t)grid_points * 8, hipMemcpyDeviceToHost, c->stream));
+  }
   hipLaunchKernelGGL(temper_kernel, dim3(1), dim3(kTemperThreads), 0, c->stream, t);
   LAUNCH_CHECK(c);
   double o[5];
@@ -645,6 +663,19 @@ smc_status smc_temper(smc_ctx c, double* a_out, double* dlogz_out, double* ess_o
   if (dlogz_out) *dlogz_out = o[1];
   if (ess_out) *ess_out = o[2];
   return SMC_OK;
+}
+
+smc_status smc_temper(smc_ctx c, double* a_out, double* dlogz_out, double* ess_out) {
+  if (!c) return SMC_ERR_INVALID_ARG;
+  return temper_impl(c, 0, c->pb.ess_frac, a_out, dlogz_out, ess_out, nullptr);
+}
+
+smc_status smc_temper_grid(smc_ctx c, int32_t grid_points, double ess_frac, double* a_out, double* dlogz_out,
+                           double* ess_out, double* ess_grid_out) {
+  if (!c) return SMC_ERR_INVALID_ARG;
+  if (grid_points < 1 || grid_points > kGridMax) return fail(c, SMC_ERR_INVALID_ARG, "grid_points must be in [1, 256]");
+  if (!(ess_frac > 0.0 && ess_frac <= 1.0)) return fail(c, SMC_ERR_INVALID_ARG, "ess_frac must be in (0, 1]");
+  return temper_impl(c, grid_points, ess_frac, a_out, dlogz_out, ess_out, ess_grid_out);
 }
 
 smc_status smc_mass(smc_ctx c) {
@@ -680,11 +711,11 @@ smc_status smc_mass(smc_ctx c) {
   return SMC_OK;
 }
 
-smc_status smc_resample(smc_ctx c) {
-  if (!c) return SMC_ERR_INVALID_ARG;
+static smc_status resample_impl(smc_ctx c, int multinomial) {
   const smc_problem& pb = c->pb;
   ResampleArgs r;
   r.M = pb.M;
+  r.multinomial = multinomial;
   r.seed = pb.seed;
   r.stage = (uint32_t)c->stage;
   r.logw = pb.logw;
@@ -709,6 +740,16 @@ smc_status smc_resample(smc_ctx c) {
   hipLaunchKernelGGL(copyback_kernel, dim3(pb.M), dim3(256), 0, c->stream, b);
   LAUNCH_CHECK(c);
   return SMC_OK;
+}
+
+smc_status smc_resample(smc_ctx c) {
+  if (!c) return SMC_ERR_INVALID_ARG;
+  return resample_impl(c, 0);
+}
+
+smc_status smc_resample_multinomial(smc_ctx c) {
+  if (!c) return SMC_ERR_INVALID_ARG;
+  return resample_impl(c, 1);
 }
 
 smc_status smc_move(smc_ctx c, double eps, int32_t L, int32_t R) {

@@ -1,0 +1,104 @@
+"""GPU parity of the paper's own schemes (multinomial resampling, section 2.1;
+grid-search tempering with ESS_target = 0.8 M, section 2.2) against the oracle."""
+import math
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+import oracle
+from paper_1805_03317_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def make_pair(w):
+    from paper_1805_03317_amd import binding as B
+    P = oracle.Problem(w.Xy(np.float64), w.d, w.family, w.prior_mean, w.prior_prec, gauss_s2=w.gauss_s2)
+    tb, _ = P.newton_mode()
+    P.set_cv_centre(tb)
+    Xy = torch.tensor(w.Xy(np.float64), device=DEV)
+    smc = B.SubsampledSMC(Xy, w.d, w.family, w.precision, w.M, w.m, w.G, w.prior_mean, w.prior_prec, w.seed,
+                          theta_bar=tb, gauss_s2=w.gauss_s2)
+    return P, smc
+
+
+@pytest.mark.parametrize("M,spread,a_prev", [(64, 30.0, 0.05), (2048, 30.0, 0.3), (8192, 3.0, 0.999), (1, 1.0, 0.0)])
+def test_temper_grid_parity(M, spread, a_prev):
+    w = W.logistic_small(500, 2, seed=44, M=M, m=16, G=2)
+    say("grid temper M", M, "a_prev", a_prev)
+    P, smc = make_pair(w)
+    g = np.random.default_rng(M + 7)
+    lhat = -3000 + spread * g.standard_normal(M)
+    sig2 = np.abs(g.standard_normal(M)) * 3
+    logw = 0.4 * g.standard_normal(M)
+    logw -= np.log(np.exp(logw - logw.max()).sum()) + logw.max()
+    smc.lhat.copy_(torch.tensor(lhat))
+    smc.sig2.copy_(torch.tensor(sig2))
+    smc.logw.copy_(torch.tensor(logw))
+    smc.set_stage(4, 0, a_prev, 0.0)
+    S = 129
+    a, dz, ess, grid = smc.temper_grid(S, 0.8)
+    a0, dz0, ess0, lw0, grid0 = oracle.temper_grid(lhat, sig2, logw, a_prev, 0.8, S)
+    np.testing.assert_allclose(grid, grid0, rtol=1e-11, atol=1e-11)
+    if a != a0:
+        # only a near tie of the two closest grid points may differ
+        pts = np.array([oracle.grid_point(a_prev, j) for j in range(S)])
+        jg, jo = int(np.flatnonzero(pts == a)[0]), int(np.flatnonzero(pts == a0)[0])
+        assert abs(abs(grid0[jg] - 0.8 * M) - abs(grid0[jo] - 0.8 * M)) <= 1e-9 * M
+    else:
+        assert abs(dz - dz0) <= 1e-9 * max(1.0, abs(dz0))
+        assert abs(ess - ess0) <= 1e-9 * M
+        np.testing.assert_allclose(smc.logw.cpu().numpy(), lw0, rtol=1e-9, atol=1e-9)
+    assert a > a_prev
+    info = smc.info()
+    assert info["stage"] == 5 and info["a"] == a
+    smc.close()
+
+
+@pytest.mark.parametrize("M", [1, 257, 2048, 8192])
+def test_resample_multinomial_parity(M):
+    w = W.logistic_small(800, 3, seed=45, M=M, m=24, G=2)
+    say("multinomial M", M)
+    P, smc = make_pair(w)
+    g = np.random.default_rng(M + 3)
+    lw = 2.5 * g.standard_normal(M)
+    lw -= np.log(np.exp(lw - lw.max()).sum()) + lw.max()
+    th, u = W.random_state(w, M, 0.5, P.theta_bar, seed=M)
+    lh = g.standard_normal(M)
+    smc.theta.copy_(torch.tensor(th))
+    smc.u.copy_(torch.tensor(u))
+    smc.lhat.copy_(torch.tensor(lh))
+    smc.logw.copy_(torch.tensor(lw))
+    smc.set_stage(6, 0, 0.4)
+    smc.resample(multinomial=True)
+    anc = oracle.resample_multinomial(lw, w.seed, 6)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(smc.u.cpu().numpy(), u[anc])
+    np.testing.assert_array_equal(smc.theta.cpu().numpy(), th[anc])
+    np.testing.assert_array_equal(smc.lhat.cpu().numpy(), lh[anc])
+    np.testing.assert_allclose(smc.logw.cpu().numpy(), -math.log(M), rtol=0, atol=1e-15)
+    smc.close()
+
+
+def test_full_run_paper_schemes_matches_oracle():
+    """Algorithm 2 with the paper's grid rule and multinomial resampling."""
+    w = W.logistic_small(3000, 3, seed=62, M=128, m=150, G=4, L=6)
+    say("full run (paper schemes)", w.name)
+    P, smc = make_pair(w)
+    eps_fn = lambda st, a, d: 1.0 / 6
+    logz, rec = smc.run(eps_fn, L=6, R=2, schemes="paper")
+    ref = oracle.run_smc(P, M=w.M, m=w.m, G=w.G, seed=w.seed, eps_fn=eps_fn, L=6, R=2, ess_frac=0.8,
+                         schemes="paper")
+    temps = np.array([r["a"] for r in rec])
+    assert len(temps) == len(ref["temps"])
+    np.testing.assert_array_equal(temps, ref["temps"])
+    assert abs(logz - ref["logz"]) <= 1e-7 * abs(ref["logz"])
+    np.testing.assert_allclose(smc.theta.cpu().numpy(), ref["theta"], rtol=1e-6, atol=1e-8)
+    np.testing.assert_array_equal(smc.u.cpu().numpy(), ref["u"])
+    smc.close()
