@@ -328,12 +328,16 @@ def num_threads():
 # ---------------------------------------------------------------------------
 
 def run_smc(prob, M, m, G, seed, eps_fn, L, R, ess_frac=0.5, max_stages=10000, callback=None,
-            schemes="default", grid_points=129):
+            schemes="default", grid_points=129, recentre=False):
     """Subsampling SMC (Algorithm 2): returns dict with log Z, temperatures, particles.
 
     schemes="default": ESS bisection and systematic resampling; schemes="paper":
     the paper's grid rule (ess_frac is then the grid target, 0.8 in the paper)
-    and multinomial resampling (sections 2.1, 2.2)."""
+    and multinomial resampling (sections 2.1, 2.2).
+    recentre=True: Algorithm 2 step d as written, the control variates are
+    rebuilt every stage at the weighted particle mean (after reweighting,
+    before resampling) and the estimator is re-evaluated there; prob keeps the
+    last centre."""
     paper = schemes == "paper"
     theta, u, logw = init_particles(M, prob.d, m, prob.n, seed, prob.mu0, prob.Q0)
     est = prob.estimate(theta, u)
@@ -349,7 +353,11 @@ def run_smc(prob, M, m, G, seed, eps_fn, L, R, ess_frac=0.5, max_stages=10000, c
         else:
             a_new, dz, ess, logw = temper(lhat, sig2, logw, a, ess_frac)
         logz += dz
-        _, Sigma, Lc = moments(theta, logw)
+        mean, Sigma, Lc = moments(theta, logw)
+        if recentre:
+            prob.set_cv_centre(mean)
+            est = prob.estimate(theta, u)
+            lhat, sig2 = est["lhat"], est["sig2"]
         if paper:
             anc = resample_multinomial(logw, seed, stage)
         else:

@@ -262,7 +262,8 @@ def test_move_leaves_conjugate_posterior_invariant():
 # whole Subsampling SMC runs (Algorithm 2)
 # ---------------------------------------------------------------------------
 
-def test_smc_conjugate_gaussian_evidence_and_posterior():
+@pytest.mark.parametrize("recentre", [False, True], ids=["fixed_centre", "per_stage_centre"])
+def test_smc_conjugate_gaussian_evidence_and_posterior(recentre):
     w = W.gaussian_small(150, 2, seed=7, s2=1.0, m=40, G=4, L=6)
     Pb = oracle.Problem(w.Xy(np.float64), w.d, w.family, w.prior_mean, w.prior_prec, gauss_s2=w.gauss_s2)
     mode, _ = Pb.newton_mode()
@@ -271,7 +272,8 @@ def test_smc_conjugate_gaussian_evidence_and_posterior():
     runs = []
     for s in range(6):
         temps = []
-        res = oracle.run_smc(Pb, M=256, m=w.m, G=w.G, seed=100 + s, eps_fn=lambda st, a, d: 1.0 / 6, L=6, R=2)
+        res = oracle.run_smc(Pb, M=256, m=w.m, G=w.G, seed=100 + s, eps_fn=lambda st, a, d: 1.0 / 6, L=6, R=2,
+                             recentre=recentre)
         runs.append(res)
     lz = np.array([r["logz"] for r in runs])
     se = lz.std(ddof=1) / math.sqrt(len(lz))
@@ -315,14 +317,18 @@ def quadrature_logistic(w, half_width=9.0, k=401):
     return logz, wts @ th, mode
 
 
-def test_smc_logistic_two_parameters_vs_quadrature():
+@pytest.mark.parametrize("recentre", [False, True], ids=["fixed_centre", "per_stage_centre"])
+def test_smc_logistic_two_parameters_vs_quadrature(recentre):
     w = W.logistic_small(600, 2, seed=11, m=80, G=4, L=6)
     truth, post_mean, mode = quadrature_logistic(w)
     Pb = oracle.Problem(w.Xy(np.float64), w.d, w.family, w.prior_mean, w.prior_prec)
     Pb.set_cv_centre(mode)
     lz, means = [], []
     for s in range(5):
-        res = oracle.run_smc(Pb, M=192, m=w.m, G=w.G, seed=300 + s, eps_fn=lambda st, a, d: 1.0 / 6, L=6, R=2)
+        if recentre:
+            Pb.set_cv_centre(w.prior_mean)   # the centre then follows the particles (Algorithm 2 step d)
+        res = oracle.run_smc(Pb, M=192, m=w.m, G=w.G, seed=300 + s, eps_fn=lambda st, a, d: 1.0 / 6, L=6, R=2,
+                             recentre=recentre)
         lz.append(res["logz"])
         means.append(res["theta"].mean(0))
     lz = np.array(lz)
