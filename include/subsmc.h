@@ -149,6 +149,19 @@ smc_status smc_temper_grid(smc_ctx ctx, int32_t grid_points, double ess_frac, do
  * the mean variance is tried before SMC_ERR_NOT_PD). Synchronises. */
 smc_status smc_mass(smc_ctx ctx);
 
+/*
+ * Algorithm 2 step d as the paper writes it (section 3.2): moves the
+ * control-variate centre theta_bar to theta_bar_host (host, d doubles) or,
+ * when it is NULL, to the weighted particle mean computed by the last
+ * smc_mass of this stage; rebuilds A, B, C and the per-row constants of the
+ * packed data at the new centre (a full pass over the n rows) and
+ * re-evaluates the cached estimator and gradients of every particle, so the
+ * next reweighting and move use the new control variates. SMC_ERR_STATE if
+ * theta_bar_host is NULL and there is no mass matrix for this stage.
+ * Synchronises.
+ */
+smc_status smc_recentre(smc_ctx ctx, const double* theta_bar_host);
+
 /* Algorithm 2 step e: systematic resampling with exact integer arithmetic
  * (one Philox offset per stage); copies theta, u and the caches from the
  * ancestors and sets logw = -log M. */

@@ -38,7 +38,7 @@ class _Info(C.Structure):
 
 EXPORTS = [
     "smc_workspace_size", "smc_init", "smc_temper", "smc_temper_grid", "smc_mass", "smc_resample",
-    "smc_resample_multinomial", "smc_move",
+    "smc_resample_multinomial", "smc_recentre", "smc_move",
     "loglik_est", "loglik_grad", "smc_refresh", "smc_get_info", "smc_set_stage", "smc_set_mass",
     "smc_get_mass", "smc_get_cv", "smc_full_loglik", "smc_destroy", "smc_status_string",
     "smc_last_error",
@@ -65,6 +65,7 @@ def lib():
     L.smc_mass.argtypes = [vp]
     L.smc_resample.argtypes = [vp]
     L.smc_resample_multinomial.argtypes = [vp]
+    L.smc_recentre.argtypes = [vp, vp]
     L.smc_move.argtypes = [vp, dbl, i32, i32]
     L.loglik_est.argtypes = [vp, i32, vp, vp, vp, vp, vp]
     L.loglik_grad.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp]
@@ -203,6 +204,15 @@ class SubsampledSMC:
     def move(self, eps, L, R=1):
         self._check(lib().smc_move(self._h, float(eps), int(L), int(R)))
 
+    def recentre(self, theta_bar=None):
+        """Move the control-variate centre (default: this stage's weighted mean) and re-evaluate the caches."""
+        import numpy as np
+        if theta_bar is None:
+            self._check(lib().smc_recentre(self._h, None))
+        else:
+            tb = np.ascontiguousarray(theta_bar, dtype=np.float64)
+            self._check(lib().smc_recentre(self._h, _host_ptr(tb)))
+
     def refresh(self):
         self._check(lib().smc_refresh(self._h))
 
@@ -269,11 +279,12 @@ class SubsampledSMC:
 
     # -- a full run ---------------------------------------------------------------
     def run(self, eps_fn, L, R, max_stages=100000, callback=None, schemes="default", grid_points=129,
-            grid_ess_frac=0.8):
+            grid_ess_frac=0.8, recentre=False):
         """Algorithm 2 until a = 1; returns log Z and the per-stage record.
 
         schemes="paper" uses the paper's grid rule for the exponent (target
-        grid_ess_frac * M) and multinomial resampling."""
+        grid_ess_frac * M) and multinomial resampling. recentre=True moves the
+        control-variate centre to each stage's weighted mean (step d)."""
         paper = schemes == "paper"
         rec = []
         a = self.info()["a"]
@@ -283,6 +294,8 @@ class SubsampledSMC:
             else:
                 a, dz, ess = self.temper()
             self.mass()
+            if recentre:
+                self.recentre()
             self.resample(multinomial=paper)
             eps = eps_fn(len(rec) + 1, a, self.d)
             self.move(eps, L, R)

@@ -817,6 +817,27 @@ smc_status smc_refresh(smc_ctx c) {
   return refresh(c);
 }
 
+smc_status smc_recentre(smc_ctx c, const double* theta_bar_host) {
+  if (!c) return SMC_ERR_INVALID_ARG;
+  const int d = c->pb.d;
+  double* tb = const_cast<double*>(c->prob.theta_bar);
+  if (theta_bar_host) {
+    for (int r = 0; r < d; ++r)
+      if (!std::isfinite(theta_bar_host[r])) return fail(c, SMC_ERR_INVALID_ARG, "theta_bar is not finite");
+    HIP_TRY(c, hipMemcpyAsync(tb, theta_bar_host, (size_t)d * 8, hipMemcpyHostToDevice, c->stream));
+  } else {
+    if (!c->have_mass) return fail(c, SMC_ERR_STATE, "no weighted mean for this stage (call smc_mass first)");
+    HIP_TRY(c, hipMemcpyAsync(tb, c->at<double>(c->lay.mean), (size_t)d * 8, hipMemcpyDeviceToDevice, c->stream));
+  }
+  smc_status st = run_cv(c, tb, true, const_cast<double*>(c->prob.cvA), const_cast<double*>(c->prob.cvB),
+                         const_cast<double*>(c->prob.cvC));
+  if (st != SMC_OK) return st;
+  st = refresh(c);
+  if (st != SMC_OK) return st;
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return SMC_OK;
+}
+
 smc_status smc_get_info(smc_ctx c, smc_info* o) {
   if (!c || !o) return SMC_ERR_INVALID_ARG;
   o->a = c->a;

@@ -102,3 +102,76 @@ def test_full_run_paper_schemes_matches_oracle():
     np.testing.assert_allclose(smc.theta.cpu().numpy(), ref["theta"], rtol=1e-6, atol=1e-8)
     np.testing.assert_array_equal(smc.u.cpu().numpy(), ref["u"])
     smc.close()
+
+
+# ---------------------------------------------------------------------------
+# per-stage control-variate centre (Algorithm 2 step d)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("precision", [W.FP64, W.MIXED], ids=["fp64", "mixed"])
+def test_recentre_parity(precision):
+    w = W.poisson_small(6000, 6, seed=46, precision=precision, M=96, m=300, G=10)
+    say("recentre", w.name, precision)
+    from paper_1805_03317_amd import binding as B
+    P = oracle.Problem(w.Xy(np.float64), w.d, w.family, w.prior_mean, w.prior_prec)
+    tb, _ = P.newton_mode()
+    P.set_cv_centre(tb)
+    data_dt = np.float32 if precision == W.MIXED else np.float64
+    smc = B.SubsampledSMC(torch.tensor(w.Xy(data_dt), device=DEV), w.d, w.family, precision, w.M, w.m, w.G,
+                          w.prior_mean, w.prior_prec, w.seed, theta_bar=tb)
+    th, u = W.random_state(w, w.M, 0.2, tb + 0.05, seed=3)
+    g = np.random.default_rng(4)
+    lw = 0.7 * g.standard_normal(w.M)
+    lw -= np.log(np.exp(lw - lw.max()).sum()) + lw.max()
+    smc.theta.copy_(torch.tensor(th))
+    smc.u.copy_(torch.tensor(u))
+    smc.logw.copy_(torch.tensor(lw))
+    smc.set_stage(2, 0, 0.3)
+    smc.mass()
+    smc.recentre()
+    mean, _, _ = oracle.moments(th, lw)
+    P.set_cv_centre(mean)
+    tb_g, A_g, B_g, C_g = smc.get_cv()
+    np.testing.assert_allclose(tb_g, mean, rtol=1e-12, atol=1e-14)
+    assert abs(A_g - P.A) <= 1e-11 * abs(P.A)
+    np.testing.assert_allclose(B_g, P.B, rtol=1e-10, atol=1e-9 * np.abs(P.B).max())
+    np.testing.assert_allclose(C_g, P.C, rtol=1e-10, atol=1e-10 * np.abs(P.C).max())
+    ref = P.estimate(th, u)
+    rt = 1e-5 if precision == W.MIXED else 1e-9
+    np.testing.assert_allclose(smc.lhat.cpu().numpy(), ref["lhat"], rtol=rt)
+    np.testing.assert_allclose(smc.sig2.cpu().numpy(), ref["sig2"], rtol=1e-4 if precision == W.MIXED else 1e-8)
+    # an explicit centre
+    c2 = mean + 0.01
+    smc.recentre(c2)
+    P.set_cv_centre(c2)
+    ref = P.estimate(th, u)
+    np.testing.assert_allclose(smc.lhat.cpu().numpy(), ref["lhat"], rtol=rt)
+    smc.close()
+
+
+def test_recentre_needs_a_mass_matrix():
+    from paper_1805_03317_amd import binding as B
+    w = W.logistic_small(500, 2, seed=47, M=16, m=20, G=2)
+    P, smc = make_pair(w)
+    with pytest.raises(B.SMCError):
+        smc.recentre()
+    smc.close()
+
+
+def test_full_run_recentre_matches_oracle():
+    """Algorithm 2 with the control-variate centre moved to every stage's weighted mean."""
+    w = W.logistic_small(3000, 3, seed=63, M=128, m=150, G=4, L=6)
+    say("full run (per-stage centre)", w.name)
+    P, smc = make_pair(w)
+    eps_fn = lambda st, a, d: 1.0 / 6
+    logz, rec = smc.run(eps_fn, L=6, R=2, recentre=True)
+    ref = oracle.run_smc(P, M=w.M, m=w.m, G=w.G, seed=w.seed, eps_fn=eps_fn, L=6, R=2, recentre=True)
+    temps = np.array([r["a"] for r in rec])
+    assert len(temps) == len(ref["temps"])
+    np.testing.assert_allclose(temps, ref["temps"], rtol=1e-8, atol=1e-10)
+    assert abs(logz - ref["logz"]) <= 1e-7 * abs(ref["logz"])
+    np.testing.assert_allclose(smc.theta.cpu().numpy(), ref["theta"], rtol=1e-6, atol=1e-8)
+    np.testing.assert_array_equal(smc.u.cpu().numpy(), ref["u"])
+    tb_g = smc.get_cv()[0]
+    np.testing.assert_allclose(tb_g, P.theta_bar, rtol=1e-9, atol=1e-12)
+    smc.close()
