@@ -47,6 +47,12 @@ def parse():
     ap.add_argument("--workload", choices=["config1", "config2", "config4", "config5"], default="config2",
                     help="config2 (Poisson n=1e6 d=20) is the benchmark workload; the others are the "
                          "logistic d=5 FP64, logistic d=50 and additive logistic d=116 configurations")
+    ap.add_argument("--schemes", choices=["default", "paper"], default="default",
+                    help="default: ESS root search (target M/2) and systematic resampling; paper: the grid "
+                         "rule with target 0.8 M (129 points) and multinomial resampling")
+    ap.add_argument("--recentre", action="store_true",
+                    help="move the control-variate centre to every stage's weighted mean (Algorithm 2 step d: "
+                         "a full-data CV rebuild and a re-evaluation of every particle per step)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy three times (the reference kernel for scaling "
                          "FETCH_SIZE / WRITE_SIZE counters) and exit")
@@ -86,12 +92,19 @@ def run_path(w, precision, Xy_dev, args, eps):
     evals_per_move = w.M * w.m * (w.L + 1)
     state = {"tempered": 0}
 
+    paper = args.schemes == "paper"
+
     def step(events=None):
         if smc.info()["a"] < 1.0:
-            smc.temper()
+            if paper:
+                smc.temper_grid(129, 0.8)
+            else:
+                smc.temper()
             state["tempered"] += 1
         smc.mass()
-        smc.resample()
+        if args.recentre:
+            smc.recentre()
+        smc.resample(multinomial=paper)
         if events is not None:
             events[0].record(stream)
         smc.move(eps, w.L, 1)
@@ -254,7 +267,8 @@ def main():
         "dtype": "f32+f64" if head == "mixed" else "f64",
         "data": "synthetic",
         "config": {"workload": w.name, "n": w.n, "d": w.d, "M": w.M, "m": w.m, "G": w.G, "L": w.L,
-                   "R": 1, "eps": eps, "precision": head, "step": "temper+mass+resample+move"},
+                   "R": 1, "eps": eps, "precision": head, "step": "temper+mass+resample+move",
+                   "schemes": args.schemes, "recentre": bool(args.recentre)},
         "roofline": roofline(w, head == "mixed", r["move_ms"], r["move_path"]),
         "move_ms": r["move_ms"],
         "move_evals_per_s": r["move_evals_per_s"],
@@ -279,6 +293,9 @@ def main():
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_particles, eps)
     if args.workload != "config2":
         out["note"] = "not the benchmark workload (Poisson n=1e6 d=20); reported for the configuration table"
+    if args.recentre or args.schemes != "default":
+        out["note"] = (out.get("note", "") + " variant: per-stage CV centre" * bool(args.recentre)
+                       + " variant: paper schemes (grid tempering 0.8M, multinomial)" * (args.schemes == "paper")).strip()
     print(json.dumps(out), flush=True)
 
 

@@ -223,8 +223,11 @@ __device__ __forceinline__ void cv_remainder(int cv_order, T eb, T aux, T D, T i
 
 // Full-data log-density and its first two eta-derivatives (FP64), for the
 // control-variate summaries A, B, C.
+// l_k and its first two eta-derivatives, without the terms that do not
+// depend on eta (log y! for Poisson, log(2 pi s2)/2 for Gaussian): those are
+// summed once by loglik_const.
 __device__ __forceinline__ void loglik_derivs(int family, double y, double eta, double inv_s2,
-                                              double log2pis2, double& f0, double& f1, double& f2) {
+                                              double& f0, double& f1, double& f2) {
   if (family == kLogistic) {
     const double s = sigmoid<double>(eta);
     const double sn = sigmoid<double>(-eta);
@@ -233,15 +236,21 @@ __device__ __forceinline__ void loglik_derivs(int family, double y, double eta, 
     f2 = -s * sn;
   } else if (family == kPoisson) {
     const double mu = exp(eta);
-    f0 = y * eta - mu - lgamma(y + 1.0);
+    f0 = y * eta - mu;
     f1 = y - mu;
     f2 = -mu;
   } else {
     const double r = y - eta;
-    f0 = -0.5 * log2pis2 - 0.5 * r * r * inv_s2;
+    f0 = -0.5 * r * r * inv_s2;
     f1 = r * inv_s2;
     f2 = -inv_s2;
   }
+}
+
+__device__ __forceinline__ double loglik_const(int family, double y, double log2pis2) {
+  if (family == kPoisson) return -lgamma(y + 1.0);
+  if (family == kGaussian) return -0.5 * log2pis2;
+  return 0.0;
 }
 
 }  // namespace subsmc

@@ -1206,17 +1206,21 @@ __global__ void __launch_bounds__(256) copyback_kernel(CopyBackArgs A) {
 
 // --------------------------------------------------------------------------
 // full-data control-variate summaries A, B, C at theta (section 3.2) and the
-// packed rows; FP64 throughout. Each block reduces its tiles of rows into one
-// partial vector [A, B (d), C upper triangle]; a second kernel sums the
-// partials in block order.
+// packed rows; FP64 throughout. A block takes tiles of up to 256 rows: in
+// phase 1 one thread per row forms eta, l_k, l_k', l_k'' and writes the packed
+// row, keeping x and the derivatives in LDS; in phase 2 each thread sums its
+// entries of [A, B, C upper triangle] over the tile (the row being read is the
+// same for every thread, so LDS reads broadcast). Per-block partials are then
+// summed by a reduction with one workgroup per entry, in fixed order. The
+// eta-free part of A (sum of log y!) is summed once by cv_const_kernel.
 // --------------------------------------------------------------------------
 
 constexpr int kCvThreads = 256;
-constexpr int kCvTile = 64;   // rows per tile
 constexpr int kCvMaxD = 128;
 
 struct CvArgs {
   int family, d, ld_in, ld_out, in_fp32, out_fp32;
+  int tile_rows;        // rows per tile (<= kCvThreads)
   int64_t n;
   double inv_s2, log2pis2;
   const void* Xin;      // caller rows [x (d) | y | ...], pitch ld_in
@@ -1225,118 +1229,176 @@ struct CvArgs {
   double* partials;     // gridDim.x * (1 + d + d(d+1)/2)
 };
 
+// LDS of cv_kernel: theta (d, padded to even), the per-thread accumulators
+// (ceil(ne / 256) * 256) and a tile of `rows` rows of (l, l', l'', x)
+__host__ __device__ inline int cv_acc_per(int d) { return (1 + d + d * (d + 1) / 2 + kCvThreads - 1) / kCvThreads; }
+__host__ __device__ inline size_t cv_lds_bytes(int d, int rows) {
+  return (size_t)(((d + 1) & ~1) + cv_acc_per(d) * kCvThreads + rows * (d + 3)) * sizeof(double);
+}
+
+// entry f of the upper triangle (row-major over r >= c) -> (r, c)
+__device__ __forceinline__ void tri_entry(int f, int& r, int& c) {
+  r = (int)((sqrt(8.0 * f + 1.0) - 1.0) * 0.5);
+  while ((r + 1) * (r + 2) / 2 <= f) ++r;
+  while (r * (r + 1) / 2 > f) --r;
+  c = f - r * (r + 1) / 2;
+}
+
 __global__ void __launch_bounds__(kCvThreads) cv_kernel(CvArgs A) {
-  extern __shared__ double tile[];  // kCvTile * (d + 3)
+  extern __shared__ double cvsm[];
   const int t = threadIdx.x;
   const int d = A.d;
   const int stride = d + 3;
   const int ne = 1 + d + d * (d + 1) / 2;
-  constexpr int kMaxPer = (1 + kCvMaxD + kCvMaxD * (kCvMaxD + 1) / 2 + kCvThreads - 1) / kCvThreads;
-  double acc[kMaxPer];
-#pragma unroll
-  for (int q = 0; q < kMaxPer; ++q) acc[q] = 0.0;
-  const int64_t ntiles = (A.n + kCvTile - 1) / kCvTile;
+  const int per = cv_acc_per(d);
+  double* th = cvsm;
+  double* acc = cvsm + ((d + 1) & ~1);    // entry t + q*256 at acc[q*256 + t]
+  double* tile = acc + per * kCvThreads;
+  for (int c = t; c < d; c += kCvThreads) th[c] = A.theta[c];
+  for (int q = 0; q < per; ++q) acc[q * kCvThreads + t] = 0.0;
+  __syncthreads();
+  const int TR = A.tile_rows;
+  const int64_t ntiles = (A.n + TR - 1) / TR;
   for (int64_t tl = blockIdx.x; tl < ntiles; tl += gridDim.x) {
-    const int64_t r0 = tl * kCvTile;
-    // phase 1: one thread per row computes eta, f0, f1, f2 and the packed row
-    if (t < kCvTile) {
+    const int64_t r0 = tl * TR;
+    const int rows = (int)((A.n - r0) < TR ? (A.n - r0) : TR);
+    if (t < rows) {
       const int64_t k = r0 + t;
       double* trow = tile + t * stride;
-      if (k < A.n) {
-        double eta = 0.0, y;
-        if (A.in_fp32) {
-          const float* row = static_cast<const float*>(A.Xin) + k * A.ld_in;
-          for (int c = 0; c < d; ++c) { trow[3 + c] = row[c]; eta += (double)row[c] * A.theta[c]; }
-          y = row[d];
-        } else {
-          const double* row = static_cast<const double*>(A.Xin) + k * A.ld_in;
-          for (int c = 0; c < d; ++c) { trow[3 + c] = row[c]; eta += row[c] * A.theta[c]; }
-          y = row[d];
-        }
-        double f0, f1, f2;
-        loglik_derivs(A.family, y, eta, A.inv_s2, A.log2pis2, f0, f1, f2);
-        trow[0] = f0; trow[1] = f1; trow[2] = f2;
-        if (A.Xout) {
-          double aux = 0.0;
-          if (A.family == kLogistic) aux = sigmoid<double>(-fabs(eta));
-          else if (A.family == kPoisson) aux = exp(eta);
-          if (A.out_fp32) {
-            float* o = static_cast<float*>(A.Xout) + k * A.ld_out;
-            o[0] = (float)eta; o[1] = (float)aux; o[2] = (float)y; o[3] = 0.f;
-            for (int c = 0; c < d; ++c) o[kHeader + c] = (float)trow[3 + c];
-            for (int c = kHeader + d; c < A.ld_out; ++c) o[c] = 0.f;
-          } else {
-            double* o = static_cast<double*>(A.Xout) + k * A.ld_out;
-            o[0] = eta; o[1] = aux; o[2] = y; o[3] = 0.0;
-            for (int c = 0; c < d; ++c) o[kHeader + c] = trow[3 + c];
-            for (int c = kHeader + d; c < A.ld_out; ++c) o[c] = 0.0;
-          }
-        }
+      double eta = 0.0, y;
+      if (A.in_fp32) {
+        const float* row = static_cast<const float*>(A.Xin) + k * A.ld_in;
+        for (int c = 0; c < d; ++c) { const double x = row[c]; trow[3 + c] = x; eta += x * th[c]; }
+        y = row[d];
       } else {
-        for (int c = 0; c < stride; ++c) trow[c] = 0.0;
+        const double* row = static_cast<const double*>(A.Xin) + k * A.ld_in;
+        for (int c = 0; c < d; ++c) { const double x = row[c]; trow[3 + c] = x; eta += x * th[c]; }
+        y = row[d];
+      }
+      double f0, f1, f2;
+      loglik_derivs(A.family, y, eta, A.inv_s2, f0, f1, f2);
+      trow[0] = f0; trow[1] = f1; trow[2] = f2;
+      if (A.Xout) {
+        double aux = 0.0;
+        if (A.family == kLogistic) aux = sigmoid<double>(-fabs(eta));
+        else if (A.family == kPoisson) aux = exp(eta);
+        if (A.out_fp32) {
+          float* o = static_cast<float*>(A.Xout) + k * A.ld_out;
+          o[0] = (float)eta; o[1] = (float)aux; o[2] = (float)y; o[3] = 0.f;
+          for (int c = 0; c < d; ++c) o[kHeader + c] = (float)trow[3 + c];
+          for (int c = kHeader + d; c < A.ld_out; ++c) o[c] = 0.f;
+        } else {
+          double* o = static_cast<double*>(A.Xout) + k * A.ld_out;
+          o[0] = eta; o[1] = aux; o[2] = y; o[3] = 0.0;
+          for (int c = 0; c < d; ++c) o[kHeader + c] = trow[3 + c];
+          for (int c = kHeader + d; c < A.ld_out; ++c) o[c] = 0.0;
+        }
       }
     }
     __syncthreads();
-    // phase 2: thread owns entries e = t, t + 256, ...
-    const int rows = (int)((A.n - r0) < kCvTile ? (A.n - r0) : kCvTile);
-#pragma unroll
-    for (int q = 0; q < kMaxPer; ++q) {
+#pragma unroll 1
+    for (int q = 0; q < per; ++q) {
       const int e = t + q * kCvThreads;
       if (e >= ne) break;
       double s = 0.0;
       if (e == 0) {
-        for (int rr = 0; rr < rows; ++rr) s += tile[rr * stride + 0];
+        for (int rr = 0; rr < rows; ++rr) s += tile[rr * stride];
       } else if (e <= d) {
-        const int c = e - 1;
-        for (int rr = 0; rr < rows; ++rr) s += tile[rr * stride + 1] * tile[rr * stride + 3 + c];
+        const int ib = 3 + (e - 1);
+        for (int rr = 0; rr < rows; ++rr) s += tile[rr * stride + 1] * tile[rr * stride + ib];
       } else {
-        const int f = e - 1 - d;  // f -> (r, c), c <= r
-        int r = (int)((sqrt(8.0 * f + 1.0) - 1.0) * 0.5);
-        while ((r + 1) * (r + 2) / 2 <= f) ++r;
-        while (r * (r + 1) / 2 > f) --r;
-        const int c = f - r * (r + 1) / 2;
-        for (int rr = 0; rr < rows; ++rr)
-          s += tile[rr * stride + 2] * tile[rr * stride + 3 + r] * tile[rr * stride + 3 + c];
+        int r, c;
+        tri_entry(e - 1 - d, r, c);
+        const int ia = 3 + r, ib = 3 + c;
+        for (int rr = 0; rr < rows; ++rr) {
+          const double* tr = tile + rr * stride;
+          s += tr[2] * tr[ia] * tr[ib];
+        }
       }
-      acc[q] += s;
+      acc[q * kCvThreads + t] += s;
     }
     __syncthreads();
   }
-#pragma unroll
-  for (int q = 0; q < kMaxPer; ++q) {
+  for (int q = 0; q < per; ++q) {
     const int e = t + q * kCvThreads;
-    if (e < ne) A.partials[(int64_t)blockIdx.x * ne + e] = acc[q];
+    if (e < ne) A.partials[(int64_t)blockIdx.x * ne + e] = acc[q * kCvThreads + t];
+  }
+}
+
+// Sum over all rows of the eta-free part of l_k (per-block partials).
+struct CvConstArgs {
+  int family, ld_in, in_fp32, d;
+  int64_t n;
+  double log2pis2;
+  const void* Xin;
+  double* partials;  // gridDim.x
+};
+
+__global__ void __launch_bounds__(kCvThreads) cv_const_kernel(CvConstArgs A) {
+  __shared__ double sh[kCvThreads / kWave];
+  const int t = threadIdx.x;
+  double s = 0.0;
+  for (int64_t k = (int64_t)blockIdx.x * kCvThreads + t; k < A.n; k += (int64_t)gridDim.x * kCvThreads) {
+    const double y = A.in_fp32 ? (double)static_cast<const float*>(A.Xin)[k * A.ld_in + A.d]
+                               : static_cast<const double*>(A.Xin)[k * A.ld_in + A.d];
+    s += loglik_const(A.family, y, A.log2pis2);
+  }
+  s = wave_sum(s);
+  if (t % kWave == 0) sh[t / kWave] = s;
+  __syncthreads();
+  if (t == 0) {
+    double tot = 0.0;
+    for (int q = 0; q < kCvThreads / kWave; ++q) tot += sh[q];
+    A.partials[blockIdx.x] = tot;
   }
 }
 
 struct CvReduceArgs {
   int nblocks, d;
   const double* partials;
+  const double* aconst;  // 1: added to A
   double* A;  // 1
   double* B;  // d
   double* C;  // d*d
 };
 
+// One workgroup per entry e: the nblocks partials of e in fixed order (strided
+// per thread, then the wavefront butterflies and the 4 wavefronts in order).
 __global__ void __launch_bounds__(256) cv_reduce_kernel(CvReduceArgs R) {
+  __shared__ double sh[4];
   const int d = R.d;
   const int ne = 1 + d + d * (d + 1) / 2;
-  for (int e = blockIdx.x * 256 + threadIdx.x; e < ne; e += gridDim.x * 256) {
-    double s = 0.0;
-    for (int b = 0; b < R.nblocks; ++b) s += R.partials[(int64_t)b * ne + e];
-    if (e == 0) {
-      R.A[0] = s;
-    } else if (e <= d) {
-      R.B[e - 1] = s;
-    } else {
-      const int f = e - 1 - d;
-      int r = (int)((sqrt(8.0 * f + 1.0) - 1.0) * 0.5);
-      while ((r + 1) * (r + 2) / 2 <= f) ++r;
-      while (r * (r + 1) / 2 > f) --r;
-      const int c = f - r * (r + 1) / 2;
-      R.C[r * d + c] = s;
-      R.C[c * d + r] = s;
-    }
+  const int e = blockIdx.x;
+  const int t = threadIdx.x;
+  double s = 0.0;
+  for (int b = t; b < R.nblocks; b += 256) s += R.partials[(int64_t)b * ne + e];
+  s = wave_sum(s);
+  if (t % kWave == 0) sh[t / kWave] = s;
+  __syncthreads();
+  if (t != 0 || e >= ne) return;
+  s = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+  if (e == 0) {
+    R.A[0] = s + (R.aconst ? R.aconst[0] : 0.0);
+  } else if (e <= d) {
+    R.B[e - 1] = s;
+  } else {
+    int r, c;
+    tri_entry(e - 1 - d, r, c);
+    R.C[r * d + c] = s;
+    R.C[c * d + r] = s;
   }
+}
+
+// sum of the const-kernel partials into one value
+__global__ void __launch_bounds__(256) cv_const_reduce_kernel(const double* partials, int nblocks, double* out) {
+  __shared__ double sh[4];
+  const int t = threadIdx.x;
+  double s = 0.0;
+  for (int b = t; b < nblocks; b += 256) s += partials[b];
+  s = wave_sum(s);
+  if (t % kWave == 0) sh[t / kWave] = s;
+  __syncthreads();
+  if (t == 0) out[0] = (sh[0] + sh[1]) + (sh[2] + sh[3]);
 }
 
 }  // namespace subsmc

@@ -22,7 +22,15 @@ namespace {
 constexpr int kMaxNarrowD = 32;   // one lane per row up to here
 constexpr int kMaxD = 128;        // lane groups per row beyond
 constexpr int kMaxM = kTemperThreads * kTemperPer;
-constexpr int kCvMaxBlocks = 1024;
+constexpr int kCvMaxBlocks = 768;   // 3 workgroups per CU
+
+// rows per CV tile: up to one per thread, the whole LDS carve within 56 KB
+// (d = 128 needs 32 rows and 102 KB)
+int cv_tile_rows(int d) {
+  int r = kCvThreads;
+  while (r > 32 && cv_lds_bytes(d, r) > 56 * 1024) r -= 32;
+  return r;
+}
 constexpr int kMaxBlock = 16384;  // slots per refreshed block (LDS)
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -52,9 +60,9 @@ int packed_ld(int d, bool fp32) {
 // Workspace regions, in carve order.
 struct Layout {
   size_t Xp, theta_bar, cvA, cvB, cvC, mu0, Q0, Qw, L0, L0inv, Sigma, Lchol, Linv, mean, status,
-      tout, grid, scratch_theta, grad_l, grad_s, anc, th2, u2, lh2, sg2, gl2, gs2, partials, mpartials, total;
+      tout, grid, aconst, scratch_theta, grad_l, grad_s, anc, th2, u2, lh2, sg2, gl2, gs2, partials, mpartials, total;
   int ld;
-  int cv_blocks;
+  int cv_blocks, cv_rows;
   int mom_blocks;
 };
 
@@ -64,7 +72,8 @@ bool compute_layout(const smc_problem* pb, Layout& L) {
   const int d = pb->d;
   const size_t M = pb->M, m = pb->m, n = (size_t)pb->n;
   L.ld = packed_ld(d, fp32);
-  const int64_t ntiles = (pb->n + kCvTile - 1) / kCvTile;
+  L.cv_rows = cv_tile_rows(d);
+  const int64_t ntiles = (pb->n + L.cv_rows - 1) / L.cv_rows;
   L.cv_blocks = (int)(ntiles < kCvMaxBlocks ? ntiles : kCvMaxBlocks);
   const size_t ne = 1 + d + (size_t)d * (d + 1) / 2;
   size_t off = 0;
@@ -87,6 +96,7 @@ bool compute_layout(const smc_problem* pb, Layout& L) {
   L.status = take(4 * 8);
   L.tout = take(8 * 8);
   L.grid = take((size_t)kGridMax * 8);
+  L.aconst = take(8);
   L.scratch_theta = take(d * 8);
   L.grad_l = take(M * d * 8);
   L.grad_s = take(M * d * 8);
@@ -353,18 +363,47 @@ smc_status run_cv(smc_ctx c, const double* dtheta, bool pack, double* dA, double
   a.theta = dtheta;
   a.Xout = pack ? c->ws + c->lay.Xp : nullptr;
   a.partials = c->at<double>(c->lay.partials);
-  const size_t shmem = (size_t)kCvTile * (pb.d + 3) * sizeof(double);
+  a.tile_rows = c->lay.cv_rows;
+  const size_t shmem = cv_lds_bytes(pb.d, c->lay.cv_rows);
+  HIP_TRY(c, hipFuncSetAttribute(reinterpret_cast<const void*>(cv_kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)shmem));
   hipLaunchKernelGGL(cv_kernel, dim3(c->lay.cv_blocks), dim3(kCvThreads), shmem, c->stream, a);
   LAUNCH_CHECK(c);
   CvReduceArgs r;
   r.nblocks = c->lay.cv_blocks;
   r.d = pb.d;
   r.partials = a.partials;
+  r.aconst = c->at<double>(c->lay.aconst);
   r.A = dA;
   r.B = dB;
   r.C = dC;
   const int ne = 1 + pb.d + pb.d * (pb.d + 1) / 2;
-  hipLaunchKernelGGL(cv_reduce_kernel, dim3((ne + 255) / 256), dim3(256), 0, c->stream, r);
+  hipLaunchKernelGGL(cv_reduce_kernel, dim3(ne), dim3(256), 0, c->stream, r);
+  LAUNCH_CHECK(c);
+  return SMC_OK;
+}
+
+// The eta-free part of A (sum of log y!), once per context.
+smc_status run_cv_const(smc_ctx c) {
+  const smc_problem& pb = c->pb;
+  const int ne = 1 + pb.d + pb.d * (pb.d + 1) / 2;
+  int64_t nb = (pb.n + kCvThreads - 1) / kCvThreads;
+  const int64_t cap = (int64_t)c->lay.cv_blocks * ne;
+  if (nb > 1024) nb = 1024;
+  if (nb > cap) nb = cap;
+  CvConstArgs a;
+  a.family = pb.family;
+  a.ld_in = pb.ld;
+  a.in_fp32 = pb.xy_fp32;
+  a.d = pb.d;
+  a.n = pb.n;
+  a.log2pis2 = c->prob.log2pis2;
+  a.Xin = pb.Xy;
+  a.partials = c->at<double>(c->lay.partials);
+  hipLaunchKernelGGL(cv_const_kernel, dim3((int)nb), dim3(kCvThreads), 0, c->stream, a);
+  LAUNCH_CHECK(c);
+  hipLaunchKernelGGL(cv_const_reduce_kernel, dim3(1), dim3(256), 0, c->stream, a.partials, (int)nb,
+                     c->at<double>(c->lay.aconst));
   LAUNCH_CHECK(c);
   return SMC_OK;
 }
@@ -591,6 +630,7 @@ smc_status smc_init(const smc_problem* pb, void* stream, smc_ctx* out) {
   HTRY(hipMemcpyAsync(c->at<double>(lay.Qw), pb->prior_prec, (size_t)d * d * 8, hipMemcpyHostToDevice, c->stream));
   TRY(factor_device(c, c->at<double>(lay.Qw), c->at<double>(lay.L0), c->at<double>(lay.L0inv)));
 
+  TRY(run_cv_const(c));
   std::vector<double> tb(d);
   if (pb->theta_bar) {
     tb.assign(pb->theta_bar, pb->theta_bar + d);
