@@ -38,7 +38,11 @@
 typedef __float128 qd;
 typedef long double xd;
 
-enum { ORC_LOGISTIC = 0, ORC_POISSON = 1, ORC_GAUSSIAN = 2 };
+enum { ORC_LOGISTIC = 0, ORC_POISSON = 1, ORC_GAUSSIAN = 2, ORC_STUDENT_T = 3 };
+
+/* Student-t regression (Experiment 2): y = x'theta + e, e ~ t_5 with unit
+ * scale, l(eta) = log t_5(y - eta). */
+#define ORC_T_NU 5
 enum { ORC_OK = 0, ORC_ERR_ARG = 1, ORC_ERR_NOT_PD = 4, ORC_ERR_NONFINITE = 5 };
 
 /* One dataset: row k of Xy holds x_k (d values) followed by y_k at column d. */
@@ -133,7 +137,8 @@ double orc_normal(uint64_t seed, uint32_t purpose, uint32_t stage, uint32_t move
 
 /* ------------------------------------------------------------------------ */
 /* Per-observation log-density and its eta-derivatives                       */
-/* logistic: Exp. 1; Poisson with log link: Exp. 2; Gaussian: test family    */
+/* logistic: Exp. 1; Poisson with log link and Student-t (t_5, unit scale):  */
+/* Exp. 2; Gaussian: test family                                             */
 /* ------------------------------------------------------------------------ */
 
 static qd q_softplus(qd x)
@@ -153,6 +158,10 @@ static qd q_f0(int fam, qd y, qd eta, qd s2)
     switch (fam) {
     case ORC_LOGISTIC: return y * eta - q_softplus(eta);
     case ORC_POISSON:  return y * eta - expq(eta) - lgammaq(y + 1);
+    case ORC_STUDENT_T: {
+        const qd nu = ORC_T_NU, r = y - eta;
+        return lgammaq((nu + 1) / 2) - lgammaq(nu / 2) - 0.5Q * logq(nu * M_PIq) - (nu + 1) / 2 * log1pq(r * r / nu);
+    }
     default: {
         qd r = y - eta;
         return -0.5Q * logq(2 * M_PIq * s2) - r * r / (2 * s2);
@@ -165,16 +174,20 @@ static qd q_f1(int fam, qd y, qd eta, qd s2)
     switch (fam) {
     case ORC_LOGISTIC: return y - q_sigmoid(eta);
     case ORC_POISSON:  return y - expq(eta);
+    case ORC_STUDENT_T: { const qd nu = ORC_T_NU, r = y - eta; return (nu + 1) * r / (nu + r * r); }
     default:           return (y - eta) / s2;
     }
 }
 
 static qd q_f2(int fam, qd y, qd eta, qd s2)
 {
-    (void)y;
     switch (fam) {
     case ORC_LOGISTIC: { qd s = q_sigmoid(eta); return -s * (1 - s); }
     case ORC_POISSON:  return -expq(eta);
+    case ORC_STUDENT_T: {
+        const qd nu = ORC_T_NU, r = y - eta, t = nu + r * r;
+        return (nu + 1) * (r * r - nu) / (t * t);
+    }
     default:           return -1 / s2;
     }
 }
@@ -202,6 +215,13 @@ static void x_derivs(int fam, xd y, xd eta, xd s2, xd *f0, xd *f1, xd *f2)
         *f0 = y * eta - mu - lgammal(y + 1);
         *f1 = y - mu;
         *f2 = -mu;
+        break;
+    }
+    case ORC_STUDENT_T: {
+        const xd nu = ORC_T_NU, r = y - eta, t = nu + r * r;
+        *f0 = lgammal((nu + 1) / 2) - lgammal(nu / 2) - 0.5L * logl(nu * (xd)M_PI) - (nu + 1) / 2 * log1pl(r * r / nu);
+        *f1 = (nu + 1) * r / t;
+        *f2 = (nu + 1) * (r * r - nu) / (t * t);
         break;
     }
     default: {

@@ -18,7 +18,7 @@ import math
 
 import numpy as np
 
-LOGISTIC, POISSON, GAUSSIAN = 0, 1, 2
+LOGISTIC, POISSON, GAUSSIAN, STUDENT_T = 0, 1, 2, 3
 FP64, MIXED = 0, 1
 CHUNK = 1 << 18
 
@@ -176,6 +176,24 @@ def config5(n=5_000_000, M=4096, m=50_000):
                     M=M, m=m, G=100, L=20, seed=2005)
 
 
+def student_t(n=500_000, d=50, M=2048, m=1250, L=15):
+    """Student-t regression of Experiment 2: y = x'theta + e, e ~ t_5; covariates with unit variances and
+    pairwise correlations 0.9; theta ~ U(-5, 5); prior N(0, 10 I); m = 0.0025 n; FP32 data."""
+    key = 1006
+    theta = _gen(key, 0).uniform(-5.0, 5.0, d)
+    X = np.empty((n, d))
+    y = np.empty(n)
+    for c0 in range(0, n, CHUNK):
+        c1 = min(n, c0 + CHUNK)
+        g = _gen(key, 1 + c0 // CHUNK)
+        z0 = g.standard_normal((c1 - c0, 1))
+        X[c0:c1] = math.sqrt(0.9) * z0 + math.sqrt(0.1) * g.standard_normal((c1 - c0, d))
+        y[c0:c1] = X[c0:c1] @ theta + g.standard_t(5, c1 - c0)
+    X, y = _finish(X, y, MIXED)
+    return Workload("student_t_n5e5_d50_rho09_fp32data", STUDENT_T, MIXED, n, d, X, y, np.zeros(d),
+                    np.eye(d) / 10.0, M=M, m=m, G=100, L=L, seed=2006, theta_true=theta)
+
+
 CONFIGS = {1: config1, 2: config2, 4: config4, 5: config5}
 
 
@@ -204,6 +222,18 @@ def poisson_small(n, d, seed, precision=FP64, M=64, m=100, G=4, L=8):
     X, y = _finish(X, y, precision)
     return Workload(f"poisson_n{n}_d{d}", POISSON, precision, n, d, X, y, np.zeros(d), np.eye(d),
                     M=M, m=m, G=G, L=L, seed=8000 + seed, theta_true=theta)
+
+
+def student_small(n, d, seed, precision=FP64, M=64, m=100, G=4, L=8, prior_var=10.0, theta_scale=1.0):
+    """Student-t regression (t_5 errors, unit scale) with an intercept."""
+    g = _gen(9700 + seed, 0)
+    theta = theta_scale * g.uniform(-1.0, 1.0, d)
+    X = g.standard_normal((n, d))
+    X[:, 0] = 1.0
+    y = X @ theta + g.standard_t(5, n)
+    X, y = _finish(X, y, precision)
+    return Workload(f"student_n{n}_d{d}", STUDENT_T, precision, n, d, X, y, np.zeros(d), np.eye(d) / prior_var,
+                    M=M, m=m, G=G, L=L, seed=9900 + seed, theta_true=theta)
 
 
 def gaussian_small(n, d, seed, s2=1.0, precision=FP64, M=64, m=50, G=4, L=8, prior_var=4.0):

@@ -19,6 +19,18 @@ import oracle
 from paper_1805_03317_amd import workloads as W
 
 
+FAMILIES = [W.LOGISTIC, W.POISSON, W.STUDENT_T]
+
+
+def small(family):
+    return {W.LOGISTIC: W.logistic_small, W.POISSON: W.poisson_small, W.STUDENT_T: W.student_small}[family]
+
+
+def t5_logpdf(r):
+    nu = 5.0
+    return gammaln((nu + 1) / 2) - gammaln(nu / 2) - 0.5 * np.log(nu * np.pi) - (nu + 1) / 2 * np.log1p(r * r / nu)
+
+
 def make_problem(w, theta_bar=None):
     P = oracle.Problem(w.Xy(np.float64), w.d, w.family, w.prior_mean, w.prior_prec, gauss_s2=w.gauss_s2)
     P.set_cv_centre(w.theta_true if theta_bar is None else theta_bar)
@@ -32,6 +44,8 @@ def full_loglik(w, theta):
         return float(np.sum(w.y * eta - np.logaddexp(0.0, eta)))
     if w.family == W.POISSON:
         return float(np.sum(w.y * eta - np.exp(eta) - gammaln(w.y + 1)))
+    if w.family == W.STUDENT_T:
+        return float(np.sum(t5_logpdf(w.y - eta)))
     r = w.y - eta
     return float(np.sum(-0.5 * np.log(2 * np.pi * w.gauss_s2) - r * r / (2 * w.gauss_s2)))
 
@@ -40,10 +54,10 @@ def full_loglik(w, theta):
 # exact enumeration over all u in {1..n}^m (difference estimator, section 3.2)
 # ---------------------------------------------------------------------------
 
-@pytest.mark.parametrize("family", [W.LOGISTIC, W.POISSON])
+@pytest.mark.parametrize("family", FAMILIES)
 def test_enumeration_unbiased_and_variance_divisor(family):
     n, m, d = 5, 3, 2
-    w = (W.logistic_small if family == W.LOGISTIC else W.poisson_small)(n, d, seed=3)
+    w = small(family)(n, d, seed=3)
     P = make_problem(w, theta_bar=w.theta_true + 0.1)
     theta = w.theta_true + np.array([1.6, -1.3])
     us = np.array(list(itertools.product(range(n), repeat=m)), dtype=np.int32)
@@ -84,21 +98,28 @@ def mp_remainder(family, y, eb, De):
         f0 = lambda e: y * e - mp.log(1 + mp.exp(e))
         f1 = lambda e: y - 1 / (1 + mp.exp(-e))
         f2 = lambda e: -mp.exp(-e) / (1 + mp.exp(-e)) ** 2
-    else:
+    elif family == W.POISSON:
         f0 = lambda e: y * e - mp.exp(e) - mp.loggamma(y + 1)
         f1 = lambda e: y - mp.exp(e)
         f2 = lambda e: -mp.exp(e)
+    else:
+        nu = mp.mpf(5)
+        f0 = lambda e: (mp.loggamma((nu + 1) / 2) - mp.loggamma(nu / 2) - mp.log(nu * mp.pi) / 2
+                        - (nu + 1) / 2 * mp.log(1 + (y - e) ** 2 / nu))
+        f1 = lambda e: (nu + 1) * (y - e) / (nu + (y - e) ** 2)
+        f2 = lambda e: (nu + 1) * ((y - e) ** 2 - nu) / (nu + (y - e) ** 2) ** 2
     d = f0(eb + De) - (f0(eb) + f1(eb) * De + f2(eb) * De * De / 2)
     dp = f1(eb + De) - f1(eb) - f2(eb) * De
     return float(d), float(dp)
 
 
-@pytest.mark.parametrize("family", [W.LOGISTIC, W.POISSON])
+@pytest.mark.parametrize("family", FAMILIES)
 def test_remainder_vs_mpmath(family):
-    w = (W.logistic_small if family == W.LOGISTIC else W.poisson_small)(10, 2, seed=1)
+    w = small(family)(10, 2, seed=1)
     P = make_problem(w)
-    ebs = [-8.0, -2.0, -0.3, 0.0, 0.7, 3.0, 9.0] if family == W.LOGISTIC else [-4.0, -0.5, 0.0, 1.2, 3.0]
-    ys = [0.0, 1.0] if family == W.LOGISTIC else [0.0, 3.0]
+    ebs = {W.LOGISTIC: [-8.0, -2.0, -0.3, 0.0, 0.7, 3.0, 9.0], W.POISSON: [-4.0, -0.5, 0.0, 1.2, 3.0],
+           W.STUDENT_T: [-3.0, -0.5, 0.0, 0.4, 2.0]}[family]
+    ys = {W.LOGISTIC: [0.0, 1.0], W.POISSON: [0.0, 3.0], W.STUDENT_T: [0.0, 1.9, -7.0]}[family]
     for eb in ebs:
         for y in ys:
             for De in [1e-7, 1e-5, 1e-4, 1e-3, 0.01, 0.1, 0.5, 1.0, 2.0, 5.0]:
@@ -138,9 +159,9 @@ def test_cv_gaussian_closed_form():
     np.testing.assert_allclose(Cm, -(w.X.T @ w.X) / w.gauss_s2, rtol=1e-12, atol=1e-10)
 
 
-@pytest.mark.parametrize("family", [W.LOGISTIC, W.POISSON])
+@pytest.mark.parametrize("family", FAMILIES)
 def test_cv_logistic_poisson_by_finite_differences(family):
-    w = (W.logistic_small if family == W.LOGISTIC else W.poisson_small)(800, 3, seed=4)
+    w = small(family)(800, 3, seed=4)
     P = make_problem(w)
     tb = w.theta_true + np.array([0.1, -0.2, 0.15])
     A, B, Cm = P.cv_build(tb)
@@ -156,9 +177,9 @@ def test_cv_logistic_poisson_by_finite_differences(family):
     np.testing.assert_allclose(Cm, Cm.T, rtol=0, atol=1e-12 * np.abs(Cm).max())
 
 
-@pytest.mark.parametrize("family", [W.LOGISTIC, W.POISSON])
+@pytest.mark.parametrize("family", FAMILIES)
 def test_newton_mode_vs_independent_optimiser(family):
-    w = (W.logistic_small if family == W.LOGISTIC else W.poisson_small)(1500, 3, seed=5)
+    w = small(family)(1500, 3, seed=5)
     P = make_problem(w)
     mode, iters = P.newton_mode()
     assert iters < 50
@@ -179,9 +200,9 @@ def test_newton_mode_vs_independent_optimiser(family):
 # gradients of l_hat and sigma2_hat
 # ---------------------------------------------------------------------------
 
-@pytest.mark.parametrize("family", [W.LOGISTIC, W.POISSON])
+@pytest.mark.parametrize("family", FAMILIES)
 def test_gradients_by_finite_differences(family):
-    w = (W.logistic_small if family == W.LOGISTIC else W.poisson_small)(2000, 3, seed=6, m=200)
+    w = small(family)(2000, 3, seed=6, m=200)
     P = make_problem(w)
     th, u = W.random_state(w, 4, 0.3, w.theta_true, seed=7)
     est = P.estimate(th, u, grad=True)
@@ -203,10 +224,10 @@ def test_gradients_by_finite_differences(family):
         np.testing.assert_allclose(est["grad_s"][i], fd_s, rtol=0, atol=1e-6 * scale_s)
 
 
-@pytest.mark.parametrize("family", [W.LOGISTIC, W.POISSON])
+@pytest.mark.parametrize("family", FAMILIES)
 def test_gradients_vs_torch_autograd(family):
     """Autograd of a float64 torch re-expression of the estimator's definition."""
-    w = (W.logistic_small if family == W.LOGISTIC else W.poisson_small)(1000, 4, seed=8, m=150)
+    w = small(family)(1000, 4, seed=8, m=150)
     P = make_problem(w)
     th, u = W.random_state(w, 3, 0.4, w.theta_true, seed=9)
     est = P.estimate(th, u, grad=True)
@@ -217,6 +238,10 @@ def test_gradients_vs_torch_autograd(family):
     def f(e):
         if family == W.LOGISTIC:
             return y_s * e - torch.nn.functional.softplus(e)
+        if family == W.STUDENT_T:
+            r = y_s - e
+            return (math.lgamma(3.0) - math.lgamma(2.5) - 0.5 * math.log(5 * math.pi)
+                    - 3.0 * torch.log1p(r * r / 5.0))
         return y_s * e - torch.exp(e) - torch.lgamma(y_s + 1)
 
     for i in range(len(th)):
