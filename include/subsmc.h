@@ -50,7 +50,8 @@ typedef enum {
 typedef enum {
   SMC_LOGISTIC = 0, /* y in {0,1}, l = y eta - log(1 + e^eta)        (Exp. 1)        */
   SMC_POISSON = 1,  /* y in N,     l = y eta - e^eta - log y!        (Exp. 2)        */
-  SMC_GAUSSIAN = 2  /* known noise variance gauss_s2; quadratic test family           */
+  SMC_GAUSSIAN = 2, /* known noise variance gauss_s2; quadratic test family           */
+  SMC_STUDENT_T = 3 /* y = x'theta + e, e ~ t_5 (unit scale)              (Exp. 2)        */
 } smc_family;
 
 typedef enum {

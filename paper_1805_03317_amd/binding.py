@@ -11,7 +11,7 @@ import torch
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libsubsmc.so")
 
-LOGISTIC, POISSON, GAUSSIAN = 0, 1, 2
+LOGISTIC, POISSON, GAUSSIAN, STUDENT_T = 0, 1, 2, 3
 FP64, MIXED = 0, 1
 MOVE_AUTO, MOVE_STREAMING, MOVE_RESIDENT = 0, 1, 2
 STATUS = {0: "ok", 1: "invalid argument", 2: "call out of order", 3: "device error",

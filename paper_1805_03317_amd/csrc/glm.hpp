@@ -3,8 +3,9 @@
 // expansion of l_k around theta_bar; gradient of d_k is d' x_k).
 //
 // Everything is evaluated from the per-row constants stored next to x_k:
-//   eta_bar = x_k' theta_bar and aux = sigmoid(-|eta_bar|) (logistic) or
-//   exp(eta_bar) (Poisson), plus Delta = x_k' (theta - theta_bar).
+//   eta_bar = x_k' theta_bar and aux = sigmoid(-|eta_bar|) (logistic),
+//   exp(eta_bar) (Poisson) or y_k - eta_bar (Student-t), plus
+//   Delta = x_k' (theta - theta_bar).
 // The remainder is O(Delta^3) while l_k is O(1), so it is never formed as a
 // difference of the two: each family uses an expansion whose terms are of the
 // size of the result.
@@ -23,6 +24,12 @@
 //   large |Delta| uses the softplus difference directly.
 // Poisson, l = y eta - e^eta - log y!: d = -e^{eta_bar} E3(Delta),
 //   d' = -e^{eta_bar} E2(Delta).
+// Student-t (t_5 errors), l = -(nu+1)/2 log(1 + r^2/nu) + const, r = y - eta:
+//   with r_bar = y - eta_bar (stored as aux), s = nu + r_bar^2,
+//   z = Delta (Delta - 2 r_bar) / s and t = nu + (r_bar - Delta)^2 = s (1 + z),
+//   d = (nu+1) [Delta^3 (Delta/4 - r_bar) / s^2 - L3(z)/2],
+//   d' = (nu+1) Delta^2 [r_bar (r_bar^2 - 3 nu) - Delta (r_bar^2 - nu)] / (s^2 t),
+//   the second-order terms cancelling exactly in both.
 // Gaussian (known variance, test family): d = d' = 0 exactly.
 // First-order control variate (cv_order 1): the dropped f'' Delta^2 / 2 term
 // is added back: d1 = d2 + f''(eta_bar) Delta^2 / 2, d1' = d2' + f''(eta_bar) Delta.
@@ -31,7 +38,10 @@
 
 namespace subsmc {
 
-enum Family : int { kLogistic = 0, kPoisson = 1, kGaussian = 2 };
+enum Family : int { kLogistic = 0, kPoisson = 1, kGaussian = 2, kStudentT = 3 };
+
+// Student-t regression (Experiment 2): e ~ t_nu with nu = 5 and unit scale.
+constexpr double kStudentNu = 5.0;
 
 template <typename T> struct Tol;
 template <> struct Tol<double> {
@@ -186,6 +196,21 @@ __device__ __forceinline__ void softplus_remainder(T eb, T s, T D, T& R, T& Rp) 
   }
 }
 
+// L3(z) = log1p(z) - z + z^2/2 = sum_{k>=3} (-1)^(k+1) z^k / k, z > -1
+template <typename T>
+__device__ __forceinline__ T log1p_remainder3(T z) {
+  constexpr T kSeries = sizeof(T) == 4 ? T(0.25) : T(0.125);
+  constexpr int kTerms = sizeof(T) == 4 ? 15 : 22;
+  const T az = z < T(0) ? -z : z;
+  if (az < kSeries) {
+    T acc = T(0);
+#pragma unroll
+    for (int k = kTerms; k >= 3; --k) acc = acc * z + ((k & 1) ? T(1) : T(-1)) / T(k);
+    return acc * z * z * z;
+  }
+  return dev_log1p(z) - z + T(0.5) * z * z;
+}
+
 // Returns d (remainder) and dp (its eta-derivative); FAM is the family.
 template <typename T, int FAM>
 __device__ __forceinline__ void cv_remainder(int cv_order, T eb, T aux, T D, T inv_s2, T& d, T& dp) {
@@ -210,6 +235,22 @@ __device__ __forceinline__ void cv_remainder(int cv_order, T eb, T aux, T D, T i
     if (cv_order == 1) {
       d -= T(0.5) * aux * D * D;
       dp -= aux * D;
+    }
+  } else if constexpr (FAM == kStudentT) {
+    const T nu = T(kStudentNu);
+    const T rb = aux;
+    const T rb2 = rb * rb;
+    const T s = nu + rb2;
+    const T is = T(1) / s;
+    const T z = D * (D - T(2) * rb) * is;
+    const T tt = nu + (rb - D) * (rb - D);
+    const T D2 = D * D;
+    d = (nu + T(1)) * (D2 * D * (T(0.25) * D - rb) * is * is - T(0.5) * log1p_remainder3<T>(z));
+    dp = (nu + T(1)) * D2 * (rb * (rb2 - T(3) * nu) - D * (rb2 - nu)) * is * is / tt;
+    if (cv_order == 1) {
+      const T f2 = (nu + T(1)) * (rb2 - nu) * is * is;
+      d += T(0.5) * f2 * D2;
+      dp += f2 * D;
     }
   } else {
     d = T(0);
@@ -239,6 +280,11 @@ __device__ __forceinline__ void loglik_derivs(int family, double y, double eta, 
     f0 = y * eta - mu;
     f1 = y - mu;
     f2 = -mu;
+  } else if (family == kStudentT) {
+    const double r = y - eta, t = kStudentNu + r * r;
+    f0 = -0.5 * (kStudentNu + 1.0) * log1p(r * r / kStudentNu);
+    f1 = (kStudentNu + 1.0) * r / t;
+    f2 = (kStudentNu + 1.0) * (r * r - kStudentNu) / (t * t);
   } else {
     const double r = y - eta;
     f0 = -0.5 * r * r * inv_s2;
@@ -249,6 +295,8 @@ __device__ __forceinline__ void loglik_derivs(int family, double y, double eta, 
 
 __device__ __forceinline__ double loglik_const(int family, double y, double log2pis2) {
   if (family == kPoisson) return -lgamma(y + 1.0);
+  if (family == kStudentT)
+    return lgamma(0.5 * (kStudentNu + 1.0)) - lgamma(0.5 * kStudentNu) - 0.5 * log(kStudentNu * M_PI);
   if (family == kGaussian) return -0.5 * log2pis2;
   return 0.0;
 }

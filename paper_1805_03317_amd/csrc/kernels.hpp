@@ -9,8 +9,9 @@
 //
 // Packed data row (Real = double for the FP64 path, float for mixed):
 //   [eta_bar, aux, y, 0, x_0 .. x_{d-1}, 0 ...], pitch ld (a multiple of 64 B)
-// with eta_bar = x' theta_bar and aux = sigmoid(-|eta_bar|) (logistic) or
-// exp(eta_bar) (Poisson), both computed in FP64 once per run.
+// with eta_bar = x' theta_bar and aux = sigmoid(-|eta_bar|) (logistic),
+// exp(eta_bar) (Poisson) or y - eta_bar (Student-t), all computed in FP64
+// whenever the control-variate centre is set.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -1282,6 +1283,7 @@ __global__ void __launch_bounds__(kCvThreads) cv_kernel(CvArgs A) {
         double aux = 0.0;
         if (A.family == kLogistic) aux = sigmoid<double>(-fabs(eta));
         else if (A.family == kPoisson) aux = exp(eta);
+        else if (A.family == kStudentT) aux = y - eta;
         if (A.out_fp32) {
           float* o = static_cast<float*>(A.Xout) + k * A.ld_out;
           o[0] = (float)eta; o[1] = (float)aux; o[2] = (float)y; o[3] = 0.f;

@@ -156,7 +156,7 @@ smc_status fail(smc_ctx c, smc_status s, const char* fmt, ...) {
 
 smc_status validate(const smc_problem* pb) {
   if (!pb) return SMC_ERR_INVALID_ARG;
-  if (pb->family < 0 || pb->family > 2) return SMC_ERR_INVALID_ARG;
+  if (pb->family < 0 || pb->family > 3) return SMC_ERR_INVALID_ARG;
   if (pb->precision != SMC_FP64 && pb->precision != SMC_MIXED) return SMC_ERR_INVALID_ARG;
   if (pb->cv_order != 1 && pb->cv_order != 2) return SMC_ERR_INVALID_ARG;
   if (pb->d < 1 || pb->n < 1 || pb->n >= (int64_t(1) << 31)) return SMC_ERR_INVALID_ARG;
@@ -205,6 +205,7 @@ hipError_t launch_estimator_p(int fam, int dc, int count, const EstArgs& a, hipS
   switch (fam) {
     case kLogistic: return launch_estimator_t<Real, kLogistic>(dc, count, a, s);
     case kPoisson: return launch_estimator_t<Real, kPoisson>(dc, count, a, s);
+    case kStudentT: return launch_estimator_t<Real, kStudentT>(dc, count, a, s);
     default: return launch_estimator_t<Real, kGaussian>(dc, count, a, s);
   }
 }
@@ -214,6 +215,7 @@ hipError_t launch_move_p(int fam, int dc, int M, size_t lds, const MoveArgs& a, 
   switch (fam) {
     case kLogistic: return launch_move_t<Real, kLogistic>(dc, M, lds, a, s);
     case kPoisson: return launch_move_t<Real, kPoisson>(dc, M, lds, a, s);
+    case kStudentT: return launch_move_t<Real, kStudentT>(dc, M, lds, a, s);
     default: return launch_move_t<Real, kGaussian>(dc, M, lds, a, s);
   }
 }
@@ -230,6 +232,8 @@ hipError_t launch_wide_est_fam(int fam, int count, const EstArgs& a, hipStream_t
     hipLaunchKernelGGL((estimator_kernel_wide<Real, G, CH, kLogistic>), dim3(count), dim3(kWave), 0, s, a);
   else if (fam == kPoisson)
     hipLaunchKernelGGL((estimator_kernel_wide<Real, G, CH, kPoisson>), dim3(count), dim3(kWave), 0, s, a);
+  else if (fam == kStudentT)
+    hipLaunchKernelGGL((estimator_kernel_wide<Real, G, CH, kStudentT>), dim3(count), dim3(kWave), 0, s, a);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
@@ -241,6 +245,8 @@ hipError_t launch_wide_move_fam(int fam, int M, size_t lds, const MoveArgs& a, h
     hipLaunchKernelGGL((move_kernel_wide<Real, G, CH, kLogistic>), dim3(M), dim3(kWave), lds, s, a);
   else if (fam == kPoisson)
     hipLaunchKernelGGL((move_kernel_wide<Real, G, CH, kPoisson>), dim3(M), dim3(kWave), lds, s, a);
+  else if (fam == kStudentT)
+    hipLaunchKernelGGL((move_kernel_wide<Real, G, CH, kStudentT>), dim3(M), dim3(kWave), lds, s, a);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();

@@ -59,6 +59,8 @@ CASES = [
     ("logistic_d50", lambda: W.logistic_small(4000, 50, seed=14, M=16, m=300, G=10, theta_scale=0.15), 0.03),
     ("poisson_d65", lambda: W.poisson_small(6000, 65, seed=15, M=12, m=130, G=4), 0.02),
     ("logistic_d116", lambda: W.logistic_small(5000, 116, seed=16, M=12, m=211, G=4, theta_scale=0.1), 0.02),
+    ("student", lambda: W.student_small(5000, 6, seed=17, M=48, m=300, G=10), 0.05),
+    ("student_d50", lambda: W.student_small(4000, 50, seed=18, M=16, m=200, G=8, theta_scale=0.3), 0.01),
 ]
 
 
@@ -109,6 +111,9 @@ MIXED_CASES = [
     ("poisson_mixed_d65", lambda: W.poisson_small(6000, 65, seed=15, precision=W.MIXED, M=12, m=130, G=4), 0.02),
     ("logistic_mixed_d116", lambda: W.logistic_small(5000, 116, seed=16, precision=W.MIXED, M=12, m=211, G=4,
                                                      theta_scale=0.1), 0.02),
+    ("student_mixed", lambda: W.student_small(5000, 6, seed=17, precision=W.MIXED, M=48, m=300, G=10), 0.05),
+    ("student_mixed_d50", lambda: W.student_small(4000, 50, seed=18, precision=W.MIXED, M=16, m=200, G=8,
+                                                  theta_scale=0.3), 0.01),
 ]
 
 
@@ -136,7 +141,7 @@ def test_estimator_mixed(name, mk, scale):
 
 def test_cv_and_newton_parity():
     for w in (W.logistic_small(5000, 6, seed=21), W.poisson_small(8000, 10, seed=22),
-              W.gaussian_small(700, 3, seed=23)):
+              W.gaussian_small(700, 3, seed=23), W.student_small(6000, 7, seed=24)):
         say("cv case", w.name)
         P = oracle.Problem(w.Xy(np.float64), w.d, w.family, w.prior_mean, w.prior_prec, gauss_s2=w.gauss_s2)
         mode, _ = P.newton_mode()
@@ -250,6 +255,9 @@ MOVE_CASES = [
                                                     L=4), 1.0, 0.05),
     ("logistic_mixed_m1500", lambda: W.logistic_small(8000, 10, seed=60, precision=W.MIXED, M=12, m=1500, G=30,
                                                       L=4), 0.7, 0.1),
+    ("student", lambda: W.student_small(6000, 6, seed=64, M=48, m=300, G=10, L=8), 0.8, 0.1),
+    ("student_mixed_d50", lambda: W.student_small(5000, 50, seed=65, precision=W.MIXED, M=16, m=200, G=8, L=5,
+                                                  theta_scale=0.3), 0.8, 0.08),
 ]
 
 
