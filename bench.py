@@ -44,9 +44,10 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-particles", type=int, default=64)
     ap.add_argument("--only", choices=["mixed", "fp64"], default=None, help="time one path only (profiling)")
-    ap.add_argument("--workload", choices=["config1", "config2", "config4", "config5"], default="config2",
+    ap.add_argument("--workload", choices=["config1", "config2", "config4", "config5", "student"], default="config2",
                     help="config2 (Poisson n=1e6 d=20) is the benchmark workload; the others are the "
-                         "logistic d=5 FP64, logistic d=50 and additive logistic d=116 configurations")
+                         "logistic d=5 FP64, logistic d=50 and additive logistic d=116 configurations and "
+                         "the Student-t regression n=5e5 d=50")
     ap.add_argument("--schemes", choices=["default", "paper"], default="default",
                     help="default: ESS root search (target M/2) and systematic resampling; paper: the grid "
                          "rule with target 0.8 M (129 points) and multinomial resampling")
@@ -201,7 +202,9 @@ def cpu_baseline(w, count, eps):
     import oracle
 
     P = oracle.Problem(w.Xy(np.float64), w.d, w.family, w.prior_mean, w.prior_prec)
-    tb, _ = P.newton_mode()
+    # the control-variate centre: the generating parameter where known (a point near the mode; the
+    # timing does not depend on it), else the oracle's own Newton mode
+    tb = w.theta_true if w.theta_true is not None else P.newton_mode()[0]
     P.set_cv_centre(tb)
     thp, u0, _ = oracle.init_particles(count, w.d, w.m, w.n, w.seed, w.prior_mean, w.prior_prec)
     _, B, Cm = P.cv_build(tb)
@@ -232,7 +235,8 @@ def main():
         return
 
     t_gen = time.perf_counter()
-    w = {"config1": W.config1, "config2": W.config2, "config4": W.config4, "config5": W.config5}[args.workload]()
+    w = {"config1": W.config1, "config2": W.config2, "config4": W.config4, "config5": W.config5,
+         "student": W.student_t}[args.workload]()
     print(f"# generated {w.name} in {time.perf_counter() - t_gen:.1f} s", file=sys.stderr, flush=True)
     eps = 1.0 / w.L
     Xy = torch.tensor(w.Xy(np.float32 if w.precision == W.MIXED else np.float64), device="cuda:0")

@@ -375,7 +375,21 @@ int orc_newton_mode(const orc_data *D, const double *mu0, const double *Q0,
             g[r] = B[r] - q;
             for (int c = 0; c < d; ++c) H[(size_t)r * d + c] = -C[(size_t)r * d + c] + Q0[(size_t)r * d + c];
         }
-        if (orc_cholesky(d, H, L) != ORC_OK) { status = ORC_ERR_NOT_PD; break; }
+        if (orc_cholesky(d, H, L) != ORC_OK) {
+            /* the log posterior is not concave here (e.g. Student-t far from
+             * the mode): shift the diagonal, 1e-6 (1 + max |H_rr|) 10^k,
+             * until the system is positive definite (a damped step) */
+            double hmax = 0;
+            for (int r = 0; r < d; ++r) if (fabs(H[(size_t)r * d + r]) > hmax) hmax = fabs(H[(size_t)r * d + r]);
+            int k;
+            for (k = 0; k < 24; ++k) {
+                double lam = 1e-6 * (1 + hmax) * pow(10.0, k);
+                for (int r = 0; r < d; ++r) H[(size_t)r * d + r] += lam;
+                if (orc_cholesky(d, H, L) == ORC_OK) break;
+                for (int r = 0; r < d; ++r) H[(size_t)r * d + r] -= lam;
+            }
+            if (k == 24) { status = ORC_ERR_NOT_PD; break; }
+        }
         solve_lower(d, L, g, y);
         solve_upper_from_lower(d, L, y, s);
         double t = 1.0, newobj = 0;

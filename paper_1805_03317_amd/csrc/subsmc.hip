@@ -488,7 +488,20 @@ smc_status newton_mode(smc_ctx c, std::vector<double>& th) {
       g[r] = B[r] - q;
       for (int k = 0; k < d; ++k) H[r * d + k] = -C[r * d + k] + c->Q0[r * d + k];
     }
-    if (!host_spd_solve(d, H, g, s)) return fail(c, SMC_ERR_NOT_PD, "Newton: negative Hessian not PD");
+    if (!host_spd_solve(d, H, g, s)) {
+      // not concave here (e.g. Student-t far from the mode): damp the step
+      // with a diagonal shift 1e-6 (1 + max |H_rr|) 10^k until H is PD
+      double hmax = 0.0;
+      for (int r = 0; r < d; ++r) hmax = std::fmax(hmax, std::fabs(H[r * d + r]));
+      int k = 0;
+      for (; k < 24; ++k) {
+        std::vector<double> Hs = H;
+        const double lam = 1e-6 * (1.0 + hmax) * std::pow(10.0, k);
+        for (int r = 0; r < d; ++r) Hs[r * d + r] += lam;
+        if (host_spd_solve(d, Hs, g, s)) break;
+      }
+      if (k == 24) return fail(c, SMC_ERR_NOT_PD, "Newton: no positive definite damped Hessian");
+    }
     double t = 1.0, newobj = 0.0;
     bool ok = false;
     std::vector<double> Bn, Cn;
