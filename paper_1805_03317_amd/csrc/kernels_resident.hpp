@@ -214,9 +214,14 @@ __device__ __forceinline__ void resident_accumulate(const Prob& P, const ResRow<
       T1[c] += edp * x[c];
     }
   };
+  // every register slot holds a row (the host launches RPL > 0 only when
+  // m >= 256 RPL), so the rows need no lane predication; the uniform test
+  // (always true) only keeps each row in a block of its own, so that rows are
+  // not interleaved beyond what the register file holds
+  const int nfull = (m / kResLanes < RPL) ? m / kResLanes : RPL;
 #pragma unroll
   for (int r = 0; r < RPL; ++r) {
-    if (tid + kResLanes * r < m) {
+    if (r < nfull) {
       Real dd, dp;
       eval(rr[r].eb, rr[r].aux, rr[r].x, dd, dp);
       add(rr[r].x, dd, dp);
@@ -378,9 +383,7 @@ __global__ void __launch_bounds__(kResLanes) move_kernel_res(MoveArgs A, ResLayo
   }
   ResRow<Real, DC> rr[RPL > 0 ? RPL : 1];
 #pragma unroll
-  for (int r = 0; r < RPL; ++r) {
-    if (tid + kResLanes * r < m) load_reg(rr[r], kx_reg[r]);
-  }
+  for (int r = 0; r < RPL; ++r) load_reg(rr[r], kx_reg[r]);
   if (tid == 0) load_row0(index_star(0));
   wait_vm();
   // poisoned rows (caller index out of range) make every pass NaN; the
@@ -494,8 +497,8 @@ __global__ void __launch_bounds__(kResLanes) move_kernel_res(MoveArgs A, ResLayo
 #pragma unroll
         for (int r = 0; r < RPL; ++r) {
           const int j = tid + kResLanes * r;
-          if (j < m && j >= b0 && j < b1) load_reg(rr[r], urow[j]);
-          else if (j < m) poisoned |= (uint32_t)urow[j] >= n;
+          if (j >= b0 && j < b1) load_reg(rr[r], urow[j]);
+          else poisoned |= (uint32_t)urow[j] >= n;
         }
         for (int k = 0; k < ngroups; ++k) {
           const int j = kResLanes * (RPL + k) + tid;

@@ -312,7 +312,9 @@ int choose_resident(const smc_problem& pb, int max_lds, ResLayout& ly) {
   const int nc = res_candidates(fp32, dc, pb.family, cand);
   for (int q = 0; q < nc; ++q) {
     const ResLayout l = res_layout(pb.m, pb.G, dc, cand[q], fp32 ? 4 : 8, pb.d);
-    if (l.total <= max_lds && (l.nlds + kResLanes - 1) / kResLanes <= kResMaxLdsGroups) {
+    // register rows are unpredicated in the kernel: every slot must hold a row
+    const bool regs_full = pb.m >= kResLanes * cand[q];
+    if (regs_full && l.total <= max_lds && (l.nlds + kResLanes - 1) / kResLanes <= kResMaxLdsGroups) {
       ly = l;
       return cand[q];
     }
