@@ -44,7 +44,9 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-particles", type=int, default=64)
     ap.add_argument("--only", choices=["mixed", "fp64"], default=None, help="time one path only (profiling)")
-    ap.add_argument("--workload", choices=["config1", "config2", "config4", "config5", "student"], default="config2",
+    ap.add_argument("--batch", type=int, default=64, help="members of the batched workload")
+    ap.add_argument("--workload", choices=["config1", "config2", "batched", "config4", "config5", "student"],
+                    default="config2",
                     help="config2 (Poisson n=1e6 d=20) is the benchmark workload; the others are the "
                          "logistic d=5 FP64, logistic d=50 and additive logistic d=116 configurations and "
                          "the Student-t regression n=5e5 d=50")
@@ -221,6 +223,170 @@ def cpu_baseline(w, count, eps):
                       f"state at a=1), {evals} algorithmic evals in {dt:.2f} s wall"}
 
 
+BATCH_KINDS = {0: "move_kernel_batch", 1: "move_kernel_wide_batch", 2: "move_kernel_res_batch"}
+
+
+def run_batched_path(ws, Xys, precision, args):
+    """One batch of contexts (one per dataset) stepped together; the move's
+    launches are timed with HIP events on the batch's stream."""
+    import torch
+    from paper_1805_03317_amd.binding import SMCBatch, SubsampledSMC
+
+    members = [SubsampledSMC(Xy, w.d, w.family, precision, w.M, w.m, w.G, w.prior_mean, w.prior_prec, w.seed,
+                             dataset=w.dataset) for w, Xy in zip(ws, Xys)]
+    batch = SMCBatch(members)
+    eps = np.array([1.0 / w.L for w in ws])
+    L = ws[0].L
+    per_member = np.array([w.M * w.m * (w.L + 1) for w in ws], dtype=np.float64)
+    stream = torch.cuda.current_stream()
+    state = {"evals": 0.0, "active": []}
+
+    def step(events=None, timed=False):
+        _, _, _, act = batch.temper()
+        batch.mass()
+        batch.resample()
+        if events is not None:
+            events[0].record(stream)
+        batch.move(eps, L, 1)
+        if events is not None:
+            events[1].record(stream)
+        if timed:
+            state["evals"] += float(per_member[act].sum())
+            state["active"].append(int(act.sum()))
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step(evs[k], timed=True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    move_ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+    # one more stage with the move's launches timed one by one
+    batch.set_timing(True)
+    step()
+    kinds, launch_ms, member_launch = batch.move_timing()
+    batch.set_timing(False)
+    torch.cuda.synchronize()
+    acc = np.array([m.accept.float().mean(0).cpu().numpy() for m in members])
+    res = {
+        "evals_per_s": state["evals"] / elapsed,
+        "ms_per_step": 1e3 * elapsed / args.steps,
+        "move_ms": move_ms,
+        "move_evals_per_s": state["evals"] / args.steps / (move_ms * 1e-3),
+        "active_members": state["active"],
+        "launch_kind": kinds.tolist(),
+        "launch_ms": launch_ms.tolist(),
+        "member_launch": member_launch.tolist(),
+        "stage": [m.info()["stage"] for m in members],
+        "accept_u": float(acc[:, 0].mean()),
+        "accept_theta": float(acc[:, 1].mean()),
+    }
+    return batch, members, res
+
+
+def batched_launches(ws, fp32, r):
+    """Per-launch algorithmic work and rate of the last timed batch move."""
+    out = []
+    ml = np.array(r["member_launch"])
+    for g, (kind, ms) in enumerate(zip(r["launch_kind"], r["launch_ms"])):
+        mem = [w for w, l in zip(ws, ml) if l == g]
+        evals = sum(w.M * w.m * (w.L + 1) for w in mem)
+        byts = sum(algorithmic_bytes_per_eval(w.d, fp32) * w.M * w.m * (w.L + 1) for w in mem)
+        flops = sum(algorithmic_flops_per_eval(w.d) * w.M * w.m * (w.L + 1) for w in mem)
+        out.append({"kernel": BATCH_KINDS[kind], "members": len(mem), "d": sorted({w.d for w in mem}),
+                    "evals": evals, "ms": round(ms, 4), "alg_bytes": byts, "alg_flops": flops})
+    return out
+
+
+def batched_roofline(launches):
+    """The dominant launch (largest device time) against its bound."""
+    g = max(launches, key=lambda x: x["ms"])
+    t = g["ms"] * 1e-3
+    if g["kernel"] == "move_kernel_res_batch":
+        achieved = g["alg_flops"] / t / 1e12
+        return {"bound": "alu", "achieved": round(achieved, 2), "peak": PEAK_VALU_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(achieved / PEAK_VALU_TFLOPS, 4), "traffic": None, "kernel": g["kernel"],
+                "evals_per_launch": g["evals"], "share_of_move_time": round(g["ms"] / sum(x["ms"] for x in launches), 3)}
+    achieved = g["alg_bytes"] / t / 1e9
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None, "kernel": g["kernel"],
+            "evals_per_launch": g["evals"], "share_of_move_time": round(g["ms"] / sum(x["ms"] for x in launches), 3)}
+
+
+def main_batched(args):
+    import torch
+    from paper_1805_03317_amd import workloads as W
+
+    t_gen = time.perf_counter()
+    ws, Xf, Xd = [], [], []
+    paths = ["mixed", "fp64"] if args.only is None else [args.only]
+    if args.no_fp64 and args.only is None:
+        paths = ["mixed"]
+    for k in range(args.batch):
+        w = W.config3_member(k, args.batch)
+        if "mixed" in paths:
+            Xf.append(torch.tensor(w.Xy(np.float32), device="cuda:0"))
+        if "fp64" in paths:
+            Xd.append(torch.tensor(w.Xy(np.float64), device="cuda:0"))
+        w.X = w.y = None                                 # host copies no longer needed
+        ws.append(w)
+    torch.cuda.synchronize()
+    print(f"# generated {len(ws)} datasets in {time.perf_counter() - t_gen:.1f} s", file=sys.stderr, flush=True)
+    results = {}
+    for p in paths:
+        prec = W.MIXED if p == "mixed" else W.FP64
+        t0 = time.perf_counter()
+        batch, members, res = run_batched_path(ws, Xf if p == "mixed" else Xd, prec, args)
+        batch.close()
+        for m in members:
+            m.close()
+        del batch, members
+        torch.cuda.synchronize()
+        res["launches"] = batched_launches(ws, p == "mixed", res)
+        results[p] = res
+        print(f"# {p} ({time.perf_counter() - t0:.1f} s): {res}", file=sys.stderr, flush=True)
+    head = "mixed" if "mixed" in results else "fp64"
+    r = results[head]
+    sizes = [(w.n, w.d, w.m) for w in ws]
+    out = {
+        "metric": "particle-obs loglik+grad evals/s (mixed vs FP64 plain, <=1e-5 rel err)",
+        "value": r["evals_per_s"],
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64" if head == "mixed" else "f64",
+        "data": "synthetic",
+        "config": {"workload": f"batched{len(ws)}_logistic_nloguniform1e4_2e6_d5_50", "members": len(ws),
+                   "n_total": int(sum(n for n, _, _ in sizes)), "M": ws[0].M, "m": "max(200, 0.01 n)",
+                   "G": ws[0].G, "L": ws[0].L, "R": 1, "eps": "1/L", "precision": head,
+                   "step": "batched temper+mass+resample+move"},
+        "roofline": batched_roofline(r["launches"]),
+        "move_ms": r["move_ms"],
+        "move_evals_per_s": r["move_evals_per_s"],
+        "launches": r["launches"],
+        "run": {k: r[k] for k in ("active_members", "accept_u", "accept_theta")},
+        "note": "not the benchmark workload (Poisson n=1e6 d=20); reported for the configuration table",
+    }
+    if "fp64" in results and head == "mixed":
+        f = results["fp64"]
+        out["fp64"] = {"value": f["evals_per_s"], "ms_per_step": f["ms_per_step"], "move_ms": f["move_ms"],
+                       "roofline": batched_roofline(f["launches"]), "launches": f["launches"],
+                       "mixed_over_fp64": r["evals_per_s"] / f["evals_per_s"]}
+    if not args.no_cpu:
+        w = W.config3_member(0, args.batch)
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_particles, 1.0 / w.L)
+        out["cpu_baseline"]["sample"] += f" (member 0 of the batch, n={w.n}, d={w.d})"
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -232,6 +398,9 @@ def main():
 
     if args.calibrate_copy:
         calibrate_copy()
+        return
+    if args.workload == "batched":
+        main_batched(args)
         return
 
     t_gen = time.perf_counter()

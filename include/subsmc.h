@@ -91,6 +91,9 @@ typedef struct smc_problem {
                           ceil(m/G) <= 16384 */
   int32_t move_path;   /* smc_move_path: which move kernel smc_move runs */
   uint64_t seed;       /* Philox key */
+  uint32_t dataset;    /* 0..65535: the dataset field of every random-number counter, so
+                          that the datasets of one batch draw independent streams under
+                          one seed */
   double ess_frac;     /* target ESS = ess_frac * M, 0 < ess_frac <= 1 */
   const double* prior_mean; /* host d: Gaussian prior mean */
   const double* prior_prec; /* host d*d: Gaussian prior precision (SPD) */
@@ -234,6 +237,68 @@ smc_status smc_full_loglik(smc_ctx ctx, const double* theta, double* A, double* 
 
 /* Release the context (device buffers stay with the caller). */
 void smc_destroy(smc_ctx ctx);
+
+/*
+ * Batches: many independent datasets (each its own context, with its own n, d,
+ * family, precision, M, m and G) advanced together, every per-stage step of
+ * Algorithm 2 issued once for all of them: one launch per kernel, and for the
+ * move one launch per kernel shape present among the members (the shape is
+ * fixed by precision, family, padded d and the move path). A member's result
+ * is the one its own context gives with the single-context calls; members
+ * should differ in seed or in smc_problem.dataset to draw independent streams.
+ *
+ * All members must share the stream given to smc_init. The batch keeps
+ * pointers to the contexts; destroy the batch before them.
+ */
+typedef struct smc_batch_s* smc_batch;
+
+/* Device workspace bytes for a batch of `count` members (0 if count is not
+ * in [1, 65536]). */
+size_t smc_batch_workspace_size(int32_t count);
+
+/* ctxs: host array of `count` distinct contexts; workspace: device, 256-byte
+ * aligned, at least smc_batch_workspace_size(count) bytes, kept. Also takes a
+ * pinned host mirror of the workspace. */
+smc_status smc_batch_create(const smc_ctx* ctxs, int32_t count, void* workspace, size_t workspace_bytes,
+                            smc_batch* out);
+
+/* smc_temper for every member whose exponent is still below 1 (the members
+ * active in this stage); the others are left as they are. Host outputs of
+ * `count` entries each (nullable): the member's exponent after the call, its
+ * log evidence increment and ESS (0 for inactive members) and 1 for an
+ * active member. SMC_ERR_STATE when every member has reached a = 1.
+ * Synchronises. */
+smc_status smc_batch_temper(smc_batch b, double* a_out, double* dlogz_out, double* ess_out, int32_t* active_out);
+
+/* smc_mass for the active members. Synchronises. */
+smc_status smc_batch_mass(smc_batch b);
+
+/* smc_resample (multinomial = 0) or smc_resample_multinomial (1) for the
+ * active members. */
+smc_status smc_batch_resample(smc_batch b, int32_t multinomial);
+
+/* smc_move for the active members: eps is a host array of `count` step sizes
+ * (entries of inactive members are ignored); L and R as in smc_move. */
+smc_status smc_batch_move(smc_batch b, const double* eps, int32_t L, int32_t R);
+
+/* Number of move launches per move of the current stage (distinct kernel
+ * shapes among the active members). */
+int32_t smc_batch_launches(smc_batch b);
+
+/* Timing of the move launches: with on = 1, smc_batch_move records a HIP
+ * event pair on the batch's stream around each of its launches. */
+smc_status smc_batch_set_timing(smc_batch b, int32_t on);
+
+/* The launches of the last smc_batch_move: their number (*launches), and for
+ * each (up to cap) its kernel (0 narrow streaming, 1 lane-group streaming,
+ * 2 resident) and its device time in ms summed over the R moves (0 unless
+ * timing was on), and per member (count entries) the launch that moved it
+ * (-1: inactive). Waits for the recorded events. */
+smc_status smc_batch_move_timing(smc_batch b, int32_t cap, int32_t* launches, int32_t* kind, double* ms,
+                                 int32_t* member_launch);
+
+void smc_batch_destroy(smc_batch b);
+const char* smc_batch_last_error(smc_batch b);
 
 const char* smc_status_string(smc_status s);
 const char* smc_last_error(smc_ctx ctx);

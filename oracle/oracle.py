@@ -34,7 +34,7 @@ class _CV(C.Structure):
 class _MoveCfg(C.Structure):
     _fields_ = [
         ("M", C.c_int32), ("m", C.c_int32), ("G", C.c_int32), ("seed", C.c_uint64),
-        ("stage", C.c_uint32), ("mu0", C.POINTER(C.c_double)), ("Q0", C.POINTER(C.c_double)),
+        ("stage", C.c_uint32), ("dataset", C.c_uint32), ("mu0", C.POINTER(C.c_double)), ("Q0", C.POINTER(C.c_double)),
         ("Sigma", C.POINTER(C.c_double)), ("Lchol", C.POINTER(C.c_double)),
     ]
 
@@ -55,7 +55,8 @@ def lib():
         L.orc_rng_word.restype = C.c_uint64
         L.orc_rng_word.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint64, C.c_uint64]
         L.orc_normal.restype = C.c_double
-        L.orc_normal.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint64, C.c_uint64]
+        L.orc_normal.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint64,
+                                 C.c_uint64]
         L.orc_remainder.argtypes = [C.POINTER(_Data), C.c_double, C.c_double, C.c_double,
                                     C.POINTER(C.c_double), C.POINTER(C.c_double)]
         L.orc_cv_build.argtypes = [C.POINTER(_Data), C.POINTER(C.c_double), C.POINTER(C.c_double),
@@ -76,11 +77,11 @@ def lib():
                                   C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_double)]
         L.orc_resample_ancestors.argtypes = [C.c_int32, C.POINTER(C.c_double), C.c_uint32, C.POINTER(C.c_int32)]
         L.orc_resample_offset.restype = C.c_uint32
-        L.orc_resample_offset.argtypes = [C.c_uint64, C.c_uint32]
+        L.orc_resample_offset.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32]
         L.orc_resample_multinomial_words.argtypes = [C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_uint64),
                                                      C.POINTER(C.c_int32)]
         L.orc_resample_multinomial.argtypes = [C.c_int32, C.POINTER(C.c_double), C.c_uint64, C.c_uint32,
-                                               C.POINTER(C.c_int32)]
+                                               C.c_uint32, C.POINTER(C.c_int32)]
         L.orc_grid_point.restype = C.c_double
         L.orc_grid_point.argtypes = [C.c_double, C.c_int32]
         L.orc_temper_grid.restype = C.c_int
@@ -89,7 +90,7 @@ def lib():
                                       C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_double),
                                       C.POINTER(C.c_double)]
         L.orc_init_particles.restype = C.c_int
-        L.orc_init_particles.argtypes = [C.c_int32, C.c_int32, C.c_int32, C.c_int64, C.c_uint64,
+        L.orc_init_particles.argtypes = [C.c_int32, C.c_int32, C.c_int32, C.c_int64, C.c_uint64, C.c_uint32,
                                          C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_double),
                                          C.POINTER(C.c_int32), C.POINTER(C.c_double)]
         L.orc_move.restype = C.c_int
@@ -122,8 +123,8 @@ def rng_word(seed, purpose, stage, move, dataset, particle, draw):
     return int(lib().orc_rng_word(seed, purpose, stage, move, dataset, particle, draw))
 
 
-def normal(seed, purpose, stage, move, particle, k):
-    return float(lib().orc_normal(seed, purpose, stage, move, particle, k))
+def normal(seed, purpose, stage, move, particle, k, dataset=0):
+    return float(lib().orc_normal(seed, purpose, stage, move, dataset, particle, k))
 
 
 # ---------------------------------------------------------------------------
@@ -239,15 +240,15 @@ def resample_ancestors(logw, U32):
     return anc
 
 
-def resample_offset(seed, stage):
-    return int(lib().orc_resample_offset(seed, stage))
+def resample_offset(seed, stage, dataset=0):
+    return int(lib().orc_resample_offset(seed, stage, dataset))
 
 
-def resample_multinomial(logw, seed, stage):
+def resample_multinomial(logw, seed, stage, dataset=0):
     """Multinomial resampling (section 2.1) with the stage's Philox words."""
     logw = np.ascontiguousarray(logw, dtype=np.float64)
     anc = np.zeros(len(logw), dtype=np.int32)
-    lib().orc_resample_multinomial(len(logw), _dp(logw), int(seed), int(stage), _ip(anc))
+    lib().orc_resample_multinomial(len(logw), _dp(logw), int(seed), int(stage), int(dataset), _ip(anc))
     return anc
 
 
@@ -281,19 +282,19 @@ def temper_grid(lhat, sig2, logw, a_prev, ess_frac=0.8, S=129):
     return a.value, dz.value, ess.value, lw, grid
 
 
-def init_particles(M, d, m, n, seed, mu0, Q0):
+def init_particles(M, d, m, n, seed, mu0, Q0, dataset=0):
     theta = np.zeros((M, d))
     u = np.zeros((M, m), dtype=np.int32)
     logw = np.zeros(M)
     mu0 = np.ascontiguousarray(mu0, dtype=np.float64)
     Q0 = np.ascontiguousarray(Q0, dtype=np.float64)
-    st = lib().orc_init_particles(M, d, m, n, seed, _dp(mu0), _dp(Q0), _dp(theta), _ip(u), _dp(logw))
+    st = lib().orc_init_particles(M, d, m, n, seed, dataset, _dp(mu0), _dp(Q0), _dp(theta), _ip(u), _dp(logw))
     if st != 0:
         raise RuntimeError(f"oracle init failed: {st}")
     return theta, u, logw
 
 
-def move(prob, theta, u, a, eps, L, seed, stage, mv, G, Sigma, Lchol, i0=0, diag=False):
+def move(prob, theta, u, a, eps, L, seed, stage, mv, G, Sigma, Lchol, i0=0, diag=False, dataset=0):
     """One Markov move (Algorithm 1) of particles i0, i0+1, ... held in theta/u (rows).
 
     With diag=True also returns (count, 4): log r and log U of the u-refresh
@@ -307,7 +308,7 @@ def move(prob, theta, u, a, eps, L, seed, stage, mv, G, Sigma, Lchol, i0=0, diag
     sig2 = np.zeros(cnt)
     Sigma = np.ascontiguousarray(Sigma, dtype=np.float64)
     Lchol = np.ascontiguousarray(Lchol, dtype=np.float64)
-    cfg = _MoveCfg(cnt, m, int(G), int(seed), int(stage), _dp(prob.mu0), _dp(prob.Q0), _dp(Sigma), _dp(Lchol))
+    cfg = _MoveCfg(cnt, m, int(G), int(seed), int(stage), int(dataset), _dp(prob.mu0), _dp(prob.Q0), _dp(Sigma), _dp(Lchol))
     dg = np.zeros((cnt, 4)) if diag else None
     st = lib().orc_move_range(C.byref(prob._data), C.byref(prob._cv), C.byref(cfg), float(a), float(eps),
                               int(L), int(mv), int(i0), cnt, _dp(theta), _ip(u), _ip(acc), _dp(lhat), _dp(sig2),
@@ -328,7 +329,7 @@ def num_threads():
 # ---------------------------------------------------------------------------
 
 def run_smc(prob, M, m, G, seed, eps_fn, L, R, ess_frac=0.5, max_stages=10000, callback=None,
-            schemes="default", grid_points=129, recentre=False):
+            schemes="default", grid_points=129, recentre=False, dataset=0):
     """Subsampling SMC (Algorithm 2): returns dict with log Z, temperatures, particles.
 
     schemes="default": ESS bisection and systematic resampling; schemes="paper":
@@ -337,9 +338,10 @@ def run_smc(prob, M, m, G, seed, eps_fn, L, R, ess_frac=0.5, max_stages=10000, c
     recentre=True: Algorithm 2 step d as written, the control variates are
     rebuilt every stage at the weighted particle mean (after reweighting,
     before resampling) and the estimator is re-evaluated there; prob keeps the
-    last centre."""
+    last centre. dataset: the dataset field of every random-number counter
+    (datasets of one batch draw independent streams under one seed)."""
     paper = schemes == "paper"
-    theta, u, logw = init_particles(M, prob.d, m, prob.n, seed, prob.mu0, prob.Q0)
+    theta, u, logw = init_particles(M, prob.d, m, prob.n, seed, prob.mu0, prob.Q0, dataset)
     est = prob.estimate(theta, u)
     lhat, sig2 = est["lhat"], est["sig2"]
     a = 0.0
@@ -359,15 +361,16 @@ def run_smc(prob, M, m, G, seed, eps_fn, L, R, ess_frac=0.5, max_stages=10000, c
             est = prob.estimate(theta, u)
             lhat, sig2 = est["lhat"], est["sig2"]
         if paper:
-            anc = resample_multinomial(logw, seed, stage)
+            anc = resample_multinomial(logw, seed, stage, dataset)
         else:
-            anc = resample_ancestors(logw, resample_offset(seed, stage))
+            anc = resample_ancestors(logw, resample_offset(seed, stage, dataset))
         theta, u, lhat, sig2 = theta[anc], u[anc], lhat[anc], sig2[anc]
         logw = np.full(M, -math.log(M))
         a = a_new
         eps = eps_fn(stage, a, prob.d)
         for r in range(R):
-            theta, u, acc, lhat, sig2 = move(prob, theta, u, a, eps, L, seed, stage, r, G, Sigma, Lc)
+            theta, u, acc, lhat, sig2 = move(prob, theta, u, a, eps, L, seed, stage, r, G, Sigma, Lc,
+                                             dataset=dataset)
             accs.append(acc.mean(axis=0))
         temps.append(a)
         dlogzs.append(dz)

@@ -117,11 +117,11 @@ static double rng_uniform_open0(uint64_t w)
 
 /* k-th standard normal of a stream, Box-Muller on words (2*(k/2), 2*(k/2)+1). */
 static double rng_normal(uint64_t seed, uint32_t purpose, uint32_t stage, uint32_t move,
-                         uint64_t particle, uint64_t k)
+                         uint32_t dataset, uint64_t particle, uint64_t k)
 {
     uint64_t base = 2 * (k / 2);
-    uint64_t wa = orc_rng_word(seed, purpose, stage, move, 0, particle, base);
-    uint64_t wb = orc_rng_word(seed, purpose, stage, move, 0, particle, base + 1);
+    uint64_t wa = orc_rng_word(seed, purpose, stage, move, dataset, particle, base);
+    uint64_t wb = orc_rng_word(seed, purpose, stage, move, dataset, particle, base + 1);
     double u1 = rng_uniform_open0(wa);
     double u2 = (double)(wb >> 11) * 0x1.0p-53;
     double r = sqrt(-2.0 * log(u1));
@@ -130,9 +130,9 @@ static double rng_normal(uint64_t seed, uint32_t purpose, uint32_t stage, uint32
 }
 
 double orc_normal(uint64_t seed, uint32_t purpose, uint32_t stage, uint32_t move,
-                  uint64_t particle, uint64_t k)
+                  uint32_t dataset, uint64_t particle, uint64_t k)
 {
-    return rng_normal(seed, purpose, stage, move, particle, k);
+    return rng_normal(seed, purpose, stage, move, dataset, particle, k);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -701,9 +701,9 @@ void orc_resample_ancestors(int32_t M, const double *logw, uint32_t U32, int32_t
     free(cum);
 }
 
-uint32_t orc_resample_offset(uint64_t seed, uint32_t stage)
+uint32_t orc_resample_offset(uint64_t seed, uint32_t stage, uint32_t dataset)
 {
-    return (uint32_t)(orc_rng_word(seed, 2, stage, 0, 0, 0, 0) >> 32);
+    return (uint32_t)(orc_rng_word(seed, 2, stage, 0, dataset, 0, 0) >> 32);
 }
 
 /* Multinomial resampling (section 2.1, the paper's choice): every slot k
@@ -732,10 +732,11 @@ void orc_resample_multinomial_words(int32_t M, const double *logw, const uint64_
 }
 
 /* The words: purpose 2 (resampling), the stage, particle slot k, draw 1. */
-void orc_resample_multinomial(int32_t M, const double *logw, uint64_t seed, uint32_t stage, int32_t *anc)
+void orc_resample_multinomial(int32_t M, const double *logw, uint64_t seed, uint32_t stage,
+                              uint32_t dataset, int32_t *anc)
 {
     uint64_t *words = malloc(sizeof(uint64_t) * (size_t)M);
-    for (int32_t k = 0; k < M; ++k) words[k] = orc_rng_word(seed, 2, stage, 0, 0, (uint64_t)k, 1);
+    for (int32_t k = 0; k < M; ++k) words[k] = orc_rng_word(seed, 2, stage, 0, dataset, (uint64_t)k, 1);
     orc_resample_multinomial_words(M, logw, words, anc);
     free(words);
 }
@@ -744,7 +745,7 @@ void orc_resample_multinomial(int32_t M, const double *logw, uint64_t seed, uint
 /* Initial particles (Algorithm 2 step 1)                                    */
 /* ------------------------------------------------------------------------ */
 
-int orc_init_particles(int32_t M, int32_t d, int32_t m, int64_t n, uint64_t seed,
+int orc_init_particles(int32_t M, int32_t d, int32_t m, int64_t n, uint64_t seed, uint32_t dataset,
                        const double *mu0, const double *Q0, double *theta, int32_t *u, double *logw)
 {
     double *L0 = malloc(sizeof(double) * d * d);
@@ -752,12 +753,12 @@ int orc_init_particles(int32_t M, int32_t d, int32_t m, int64_t n, uint64_t seed
     for (int32_t i = 0; i < M; ++i) {
         double z[512], x[512];
         if (d > 512) { free(L0); return ORC_ERR_ARG; }
-        for (int k = 0; k < d; ++k) z[k] = rng_normal(seed, 0, 0, 0, (uint64_t)i, (uint64_t)k);
+        for (int k = 0; k < d; ++k) z[k] = rng_normal(seed, 0, 0, 0, dataset, (uint64_t)i, (uint64_t)k);
         /* theta ~ N(mu0, Q0^{-1}): theta = mu0 + L0^{-T} z with Q0 = L0 L0' */
         solve_upper_from_lower(d, L0, z, x);
         for (int k = 0; k < d; ++k) theta[(size_t)i * d + k] = mu0[k] + x[k];
         for (int32_t j = 0; j < m; ++j)
-            u[(size_t)i * m + j] = (int32_t)rng_index(orc_rng_word(seed, 1, 0, 0, 0, (uint64_t)i, (uint64_t)j), n);
+            u[(size_t)i * m + j] = (int32_t)rng_index(orc_rng_word(seed, 1, 0, 0, dataset, (uint64_t)i, (uint64_t)j), n);
         logw[i] = -log((double)M);
     }
     free(L0);
@@ -773,6 +774,7 @@ typedef struct {
     int32_t M, m, G;
     uint64_t seed;
     uint32_t stage;
+    uint32_t dataset;    /* dataset field of the random-number counter */
     const double *mu0;   /* prior mean, d */
     const double *Q0;    /* prior precision, d*d */
     const double *Sigma; /* particle covariance (inverse mass matrix), d*d */
@@ -818,20 +820,20 @@ static void move_one(const orc_data *D, const orc_cv *cv, const orc_move_cfg *K,
     const int d = D->d;
     const int32_t m = K->m, G = K->G;
     const uint64_t seed = K->seed;
-    const uint32_t st = K->stage;
+    const uint32_t st = K->stage, ds = K->dataset;
 
     /* 1. u | theta: replace one block, chosen uniformly, by fresh uniform indices */
-    int32_t g = (int32_t)rng_index(orc_rng_word(seed, 3, st, mv, 0, (uint64_t)i, 0), G);
+    int32_t g = (int32_t)rng_index(orc_rng_word(seed, 3, st, mv, ds, (uint64_t)i, 0), G);
     int64_t b0 = (int64_t)g * m / G, b1 = (int64_t)(g + 1) * m / G;
     int32_t *ustar = malloc(sizeof(int32_t) * (size_t)m);
     memcpy(ustar, u, sizeof(int32_t) * (size_t)m);
     for (int64_t j = b0; j < b1; ++j)
-        ustar[j] = (int32_t)rng_index(orc_rng_word(seed, 4, st, mv, 0, (uint64_t)i, (uint64_t)(j - b0)), D->n);
+        ustar[j] = (int32_t)rng_index(orc_rng_word(seed, 4, st, mv, ds, (uint64_t)i, (uint64_t)(j - b0)), D->n);
     orc_est e_cur, e_new;
     estimate_one(D, cv, m, theta, u, &e_cur, NULL, NULL);
     estimate_one(D, cv, m, theta, ustar, &e_new, NULL, NULL);
     double logr_u = lambda_of(a, &e_new) - lambda_of(a, &e_cur);
-    double logU = log(rng_uniform_open0(orc_rng_word(seed, 5, st, mv, 0, (uint64_t)i, 0)));
+    double logU = log(rng_uniform_open0(orc_rng_word(seed, 5, st, mv, ds, (uint64_t)i, 0)));
     *acc_u = (isfinite(logr_u) && logU < logr_u) ? 1 : 0;
     if (diag) { diag[0] = logr_u; diag[1] = logU; }
     if (*acc_u) memcpy(u, ustar, sizeof(int32_t) * (size_t)m);
@@ -839,7 +841,7 @@ static void move_one(const orc_data *D, const orc_cv *cv, const orc_move_cfg *K,
 
     /* 2. theta | u: HMC with inverse mass matrix Sigma */
     double p[512], z[512], g0[512], th1[512], v[512];
-    for (int k = 0; k < d; ++k) z[k] = rng_normal(seed, 6, st, mv, (uint64_t)i, (uint64_t)k);
+    for (int k = 0; k < d; ++k) z[k] = rng_normal(seed, 6, st, mv, ds, (uint64_t)i, (uint64_t)k);
     solve_upper_from_lower(d, K->Lchol, z, p); /* p ~ N(0, Sigma^{-1}) */
     orc_est e0, e1;
     double lt0 = log_target(D, cv, K, a, theta, u, g0, &e0);
@@ -860,7 +862,7 @@ static void move_one(const orc_data *D, const orc_cv *cv, const orc_move_cfg *K,
     }
     double H1 = -lt1 + kinetic(d, K->Sigma, p);
     double logr = H0 - H1;
-    double logU2 = log(rng_uniform_open0(orc_rng_word(seed, 7, st, mv, 0, (uint64_t)i, 0)));
+    double logU2 = log(rng_uniform_open0(orc_rng_word(seed, 7, st, mv, ds, (uint64_t)i, 0)));
     *acc_th = (isfinite(logr) && logU2 < logr) ? 1 : 0;
     if (diag) { diag[2] = logr; diag[3] = logU2; }
     if (*acc_th) {

@@ -23,7 +23,7 @@ class _Problem(C.Structure):
         ("family", C.c_int32), ("precision", C.c_int32), ("cv_order", C.c_int32), ("d", C.c_int32),
         ("n", C.c_int64), ("ld", C.c_int32), ("xy_fp32", C.c_int32), ("Xy", C.c_void_p),
         ("gauss_s2", C.c_double), ("M", C.c_int32), ("m", C.c_int32), ("G", C.c_int32),
-        ("move_path", C.c_int32), ("seed", C.c_uint64), ("ess_frac", C.c_double),
+        ("move_path", C.c_int32), ("seed", C.c_uint64), ("dataset", C.c_uint32), ("ess_frac", C.c_double),
         ("prior_mean", C.c_void_p), ("prior_prec", C.c_void_p), ("theta_bar", C.c_void_p),
         ("theta", C.c_void_p), ("u", C.c_void_p), ("logw", C.c_void_p), ("lhat", C.c_void_p),
         ("sig2", C.c_void_p), ("accept", C.c_void_p), ("workspace", C.c_void_p),
@@ -41,7 +41,9 @@ EXPORTS = [
     "smc_resample_multinomial", "smc_recentre", "smc_move",
     "loglik_est", "loglik_grad", "smc_refresh", "smc_get_info", "smc_set_stage", "smc_set_mass",
     "smc_get_mass", "smc_get_cv", "smc_full_loglik", "smc_destroy", "smc_status_string",
-    "smc_last_error",
+    "smc_last_error", "smc_batch_workspace_size", "smc_batch_create", "smc_batch_temper", "smc_batch_mass",
+    "smc_batch_resample", "smc_batch_move", "smc_batch_launches", "smc_batch_set_timing", "smc_batch_move_timing",
+    "smc_batch_destroy", "smc_batch_last_error",
 ]
 
 _lib = None
@@ -82,8 +84,23 @@ def lib():
     L.smc_status_string.argtypes = [C.c_int]
     L.smc_last_error.restype = C.c_char_p
     L.smc_last_error.argtypes = [vp]
+    L.smc_batch_workspace_size.restype = C.c_size_t
+    L.smc_batch_workspace_size.argtypes = [i32]
+    L.smc_batch_create.argtypes = [vp, i32, vp, C.c_size_t, C.POINTER(vp)]
+    L.smc_batch_temper.argtypes = [vp, vp, vp, vp, vp]
+    L.smc_batch_mass.argtypes = [vp]
+    L.smc_batch_resample.argtypes = [vp, i32]
+    L.smc_batch_move.argtypes = [vp, vp, i32, i32]
+    L.smc_batch_launches.argtypes = [vp]
+    L.smc_batch_set_timing.argtypes = [vp, i32]
+    L.smc_batch_move_timing.argtypes = [vp, i32, vp, vp, vp, vp]
+    L.smc_batch_destroy.argtypes = [vp]
+    L.smc_batch_destroy.restype = None
+    L.smc_batch_last_error.restype = C.c_char_p
+    L.smc_batch_last_error.argtypes = [vp]
     for name in EXPORTS:
-        if name not in ("smc_workspace_size", "smc_destroy", "smc_status_string", "smc_last_error"):
+        if name not in ("smc_workspace_size", "smc_destroy", "smc_status_string", "smc_last_error",
+                        "smc_batch_workspace_size", "smc_batch_destroy", "smc_batch_last_error"):
             getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -111,7 +128,7 @@ class SubsampledSMC:
     """
 
     def __init__(self, Xy, d, family, precision, M, m, G, prior_mean, prior_prec, seed,
-                 ess_frac=0.5, cv_order=2, theta_bar=None, gauss_s2=1.0, move_path=MOVE_AUTO):
+                 ess_frac=0.5, cv_order=2, theta_bar=None, gauss_s2=1.0, move_path=MOVE_AUTO, dataset=0):
         import numpy as np
 
         L = lib()
@@ -139,6 +156,8 @@ class SubsampledSMC:
         pb.M, pb.m, pb.G = self.M, self.m, self.G
         pb.move_path = int(move_path)
         pb.seed, pb.ess_frac = int(seed), float(ess_frac)
+        pb.dataset = int(dataset)
+        self.dataset = int(dataset)
         pb.prior_mean = self._mu0.ctypes.data
         pb.prior_prec = self._Q0.ctypes.data
         pb.theta_bar = None if self._tb is None else self._tb.ctypes.data
@@ -303,6 +322,106 @@ class SubsampledSMC:
             if callback:
                 callback(self, rec[-1])
         return self.info()["logz"], rec
+
+
+class SMCBatch:
+    """Many SubsampledSMC runs advanced together (one launch per step for all
+    of them; the move: one launch per kernel shape among the members).
+
+    Each member's results are those of its own single-context run."""
+
+    def __init__(self, members):
+        import numpy as np
+        L = lib()
+        self.members = list(members)
+        self.count = len(self.members)
+        handles = (C.c_void_p * self.count)(*[m._h.value for m in self.members])
+        self._handles = handles
+        nbytes = L.smc_batch_workspace_size(self.count)
+        if nbytes == 0:
+            raise SMCError(1, "invalid batch size")
+        dev = self.members[0].device
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
+        base = (self.workspace.data_ptr() + 255) & ~255
+        h = C.c_void_p()
+        st = L.smc_batch_create(handles, self.count, C.c_void_p(base), nbytes, C.byref(h))
+        if st != 0:
+            raise SMCError(st, "smc_batch_create")
+        self._h = h
+        self._a = np.zeros(self.count)
+        self._dz = np.zeros(self.count)
+        self._ess = np.zeros(self.count)
+        self._act = np.zeros(self.count, dtype=np.int32)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().smc_batch_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st):
+        if st != 0:
+            raise SMCError(st, lib().smc_batch_last_error(self._h).decode())
+
+    def temper(self):
+        """Returns (a, dlogz, ess, active) arrays over the members."""
+        self._check(lib().smc_batch_temper(self._h, _host_ptr(self._a), _host_ptr(self._dz), _host_ptr(self._ess),
+                                           _host_ptr(self._act)))
+        return self._a.copy(), self._dz.copy(), self._ess.copy(), self._act.astype(bool)
+
+    def mass(self):
+        self._check(lib().smc_batch_mass(self._h))
+
+    def resample(self, multinomial=False):
+        self._check(lib().smc_batch_resample(self._h, 1 if multinomial else 0))
+
+    def move(self, eps, L, R=1):
+        import numpy as np
+        e = np.ascontiguousarray(np.broadcast_to(np.asarray(eps, dtype=np.float64), (self.count,)))
+        self._check(lib().smc_batch_move(self._h, _host_ptr(e), int(L), int(R)))
+
+    def launches(self):
+        return int(lib().smc_batch_launches(self._h))
+
+    def set_timing(self, on=True):
+        self._check(lib().smc_batch_set_timing(self._h, 1 if on else 0))
+
+    def move_timing(self):
+        """Launches of the last move: (kind per launch, device ms per launch, launch per member)."""
+        import numpy as np
+        cap = 64
+        n = C.c_int32()
+        kind = np.zeros(cap, dtype=np.int32)
+        ms = np.zeros(cap)
+        ml = np.zeros(self.count, dtype=np.int32)
+        self._check(lib().smc_batch_move_timing(self._h, cap, C.byref(n), _host_ptr(kind), _host_ptr(ms),
+                                                _host_ptr(ml)))
+        return kind[:n.value].copy(), ms[:n.value].copy(), ml
+
+    def run(self, eps_fn, L, R, max_stages=100000, callback=None):
+        """Algorithm 2 for every member until all reach a = 1; returns the
+        members' log Z and per-member stage records."""
+        import numpy as np
+        recs = [[] for _ in range(self.count)]
+        steps = 0
+        while steps < max_stages and any(m.info()["a"] < 1.0 for m in self.members):
+            a, dz, ess, act = self.temper()
+            self.mass()
+            self.resample()
+            eps = np.array([eps_fn(len(recs[k]) + 1, a[k], m.d) if act[k] else 1.0
+                            for k, m in enumerate(self.members)])
+            self.move(eps, L, R)
+            for k in np.flatnonzero(act):
+                recs[k].append({"a": a[k], "dlogz": dz[k], "ess": ess[k], "eps": eps[k]})
+            steps += 1
+            if callback:
+                callback(self, a, act)
+        return [m.info()["logz"] for m in self.members], recs
 
 
 class LogLikEstimate(torch.autograd.Function):

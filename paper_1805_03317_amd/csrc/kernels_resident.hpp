@@ -248,7 +248,7 @@ __device__ __forceinline__ void resident_accumulate(const Prob& P, const ResRow<
 }
 
 template <typename Real, int DC, int FAM, int RPL>
-__global__ void __launch_bounds__(kResLanes) move_kernel_res(MoveArgs A, ResLayout Ly) {
+__device__ __forceinline__ void move_res_body(const MoveArgs& A, const ResLayout& Ly, const int i) {
   extern __shared__ __attribute__((aligned(16))) char smem[];
   char* lrows = smem + Ly.off_rows;
   Real* row0 = reinterpret_cast<Real*>(smem + Ly.off_row0);
@@ -258,7 +258,6 @@ __global__ void __launch_bounds__(kResLanes) move_kernel_res(MoveArgs A, ResLayo
   Real* dsh = reinterpret_cast<Real*>(smem + Ly.off_dl);
   int* flag = reinterpret_cast<int*>(smem + Ly.off_flag);
 
-  const int i = blockIdx.x;
   const Prob& P = A.P;
   if (i >= P.M) return;
   const int tid = threadIdx.x;
@@ -305,11 +304,11 @@ __global__ void __launch_bounds__(kResLanes) move_kernel_res(MoveArgs A, ResLayo
   double lh0 = A.lhat[i], sg0 = A.sig2[i];
 
   // ---- the proposed block of the pseudo-marginal refresh
-  const uint64_t cg = stream_ctr0(kBlockChoice, A.stage, A.move, 0);
+  const uint64_t cg = stream_ctr0(kBlockChoice, A.stage, A.move, P.dataset);
   const int g = (int)word_to_index(stream_word(P.seed, cg, (uint64_t)i, 0), (uint64_t)P.G);
   const int b0 = (int)((int64_t)g * m / P.G);
   const int b1 = (int)((int64_t)(g + 1) * m / P.G);
-  const uint64_t cb = stream_ctr0(kBlockIndex, A.stage, A.move, 0);
+  const uint64_t cb = stream_ctr0(kBlockIndex, A.stage, A.move, P.dataset);
   for (int t = tid; t < b1 - b0; t += kResLanes)
     blk[t] = (int32_t)word_to_index(stream_word(P.seed, cb, (uint64_t)i, (uint64_t)t), (uint64_t)P.n);
   __syncthreads();
@@ -477,7 +476,7 @@ __global__ void __launch_bounds__(kResLanes) move_kernel_res(MoveArgs A, ResLayo
         const double lam1 = a * lhat_r - 0.5 * a * a * sig2_r;
         const double logr = lam1 - lam0;
         const double logU =
-            log(word_to_uniform(stream_word(P.seed, stream_ctr0(kUAccept, A.stage, A.move, 0), (uint64_t)i, 0)));
+            log(word_to_uniform(stream_word(P.seed, stream_ctr0(kUAccept, A.stage, A.move, P.dataset), (uint64_t)i, 0)));
         const bool acc = isfinite(logr) && (logU < logr);
         if (lane == 0) {
           flag[0] = acc ? 1 : 0;
@@ -513,7 +512,7 @@ __global__ void __launch_bounds__(kResLanes) move_kernel_res(MoveArgs A, ResLayo
       }
       // ---- 2. theta | u: HMC from (theta, u), opening half step and drift
       if (lead) {
-        const uint64_t cm = stream_ctr0(kMomentum, A.stage, A.move, 0);
+        const uint64_t cm = stream_ctr0(kMomentum, A.stage, A.move, P.dataset);
         const double z = lane < d ? stream_normal(P.seed, cm, (uint64_t)i, (uint32_t)lane) : 0.0;
         p = lds_matvec<DC>(LTm, d, z, lane);  // Linv is lower triangular
         const double sp = lds_matvec<DC>(Sm, d, p, lane);
@@ -541,7 +540,7 @@ __global__ void __launch_bounds__(kResLanes) move_kernel_res(MoveArgs A, ResLayo
     const double H1 = -logpi1 + K1;
     const double logr = H0 - H1;
     const double logU =
-        log(word_to_uniform(stream_word(P.seed, stream_ctr0(kThetaAccept, A.stage, A.move, 0), (uint64_t)i, 0)));
+        log(word_to_uniform(stream_word(P.seed, stream_ctr0(kThetaAccept, A.stage, A.move, P.dataset), (uint64_t)i, 0)));
     const bool acc = isfinite(logr) && (logU < logr);
     if (acc) {
       th = th1; lh0 = lhat_r; sg0 = sig2_r; gl0 = gl_r; gs0 = gs_r;
@@ -559,4 +558,24 @@ __global__ void __launch_bounds__(kResLanes) move_kernel_res(MoveArgs A, ResLayo
   }
 }
 
+template <typename Real, int DC, int FAM, int RPL>
+__global__ void __launch_bounds__(kResLanes) move_kernel_res(MoveArgs A, ResLayout Ly) {
+  move_res_body<Real, DC, FAM, RPL>(A, Ly, blockIdx.x);
+}
+
+// a batch member of the resident move: its arguments and its on-chip layout
+// (the launch reserves the largest member's LDS)
+struct ResMoveArgs {
+  MoveArgs A;
+  ResLayout Ly;
+};
+
+template <typename Real, int DC, int FAM, int RPL>
+__global__ void __launch_bounds__(kResLanes) move_kernel_res_batch(Batch<ResMoveArgs> B) {
+  const int k = batch_member(B.first, B.count, blockIdx.x);
+  const ResMoveArgs R = B.args[k];
+  move_res_body<Real, DC, FAM, RPL>(R.A, R.Ly, blockIdx.x - B.first[k]);
+}
+
 }  // namespace subsmc
+

@@ -248,11 +248,10 @@ __device__ __forceinline__ void matvec_wide(const double* __restrict__ Mx, const
 // Fused Markov move (Algorithm 1) for wide rows; same steps, draws and
 // decisions as move_kernel.
 template <typename Real, int G, int CH, int FAM>
-__global__ void __launch_bounds__(kWave) move_kernel_wide(MoveArgs A) {
+__device__ __forceinline__ void move_wide_body(const MoveArgs& A, const int i) {
   __shared__ Real red[kWave * CH];
   __shared__ double vec[128];
   extern __shared__ int32_t blk[];
-  const int i = blockIdx.x;
   const int lane = threadIdx.x;
   const Prob& P = A.P;
   if (i >= P.M) return;
@@ -274,11 +273,11 @@ __global__ void __launch_bounds__(kWave) move_kernel_wide(MoveArgs A) {
   double lh0 = A.lhat[i], sg0 = A.sig2[i];
 
   // ---- 1. u | theta
-  const uint64_t cg = stream_ctr0(kBlockChoice, A.stage, A.move, 0);
+  const uint64_t cg = stream_ctr0(kBlockChoice, A.stage, A.move, P.dataset);
   const int g = (int)word_to_index(stream_word(P.seed, cg, (uint64_t)i, 0), (uint64_t)P.G);
   const int b0 = (int)((int64_t)g * m / P.G);
   const int b1 = (int)((int64_t)(g + 1) * m / P.G);
-  const uint64_t cb = stream_ctr0(kBlockIndex, A.stage, A.move, 0);
+  const uint64_t cb = stream_ctr0(kBlockIndex, A.stage, A.move, P.dataset);
   for (int t = lane; t < b1 - b0; t += kWave)
     blk[t] = (int32_t)word_to_index(stream_word(P.seed, cb, (uint64_t)i, (uint64_t)t), (uint64_t)P.n);
   int ob0 = 0, ob1 = 0;
@@ -291,7 +290,7 @@ __global__ void __launch_bounds__(kWave) move_kernel_wide(MoveArgs A) {
     const double lam0 = a * lh0 - 0.5 * a * a * sg0;
     const double lam1 = a * r.lhat - 0.5 * a * a * r.sig2;
     const double logr = lam1 - lam0;
-    const double logU = log(word_to_uniform(stream_word(P.seed, stream_ctr0(kUAccept, A.stage, A.move, 0), (uint64_t)i, 0)));
+    const double logU = log(word_to_uniform(stream_word(P.seed, stream_ctr0(kUAccept, A.stage, A.move, P.dataset), (uint64_t)i, 0)));
     const bool acc = isfinite(logr) && (logU < logr);
     if (acc) {
       for (int t = lane; t < b1 - b0; t += kWave) urow[b0 + t] = blk[t];
@@ -304,7 +303,7 @@ __global__ void __launch_bounds__(kWave) move_kernel_wide(MoveArgs A) {
   }
 
   // ---- 2. theta | u: HMC
-  const uint64_t cm = stream_ctr0(kMomentum, A.stage, A.move, 0);
+  const uint64_t cm = stream_ctr0(kMomentum, A.stage, A.move, P.dataset);
   double z[kWideNC];
 #pragma unroll
   for (int s = 0; s < kWideNC; ++s) {
@@ -383,7 +382,7 @@ __global__ void __launch_bounds__(kWave) move_kernel_wide(MoveArgs A) {
   const double logpi1 = (a * lh1 - 0.5 * a * a * sg1) + lp1;
   const double H1 = -logpi1 + K1;
   const double logr = H0 - H1;
-  const double logU = log(word_to_uniform(stream_word(P.seed, stream_ctr0(kThetaAccept, A.stage, A.move, 0), (uint64_t)i, 0)));
+  const double logU = log(word_to_uniform(stream_word(P.seed, stream_ctr0(kThetaAccept, A.stage, A.move, P.dataset), (uint64_t)i, 0)));
   const bool acc = isfinite(logr) && (logU < logr);
   if (acc) {
     lh0 = lh1; sg0 = sg1;
@@ -406,4 +405,17 @@ __global__ void __launch_bounds__(kWave) move_kernel_wide(MoveArgs A) {
   }
 }
 
+template <typename Real, int G, int CH, int FAM>
+__global__ void __launch_bounds__(kWave) move_kernel_wide(MoveArgs A) {
+  move_wide_body<Real, G, CH, FAM>(A, blockIdx.x);
+}
+
+template <typename Real, int G, int CH, int FAM>
+__global__ void __launch_bounds__(kWave) move_kernel_wide_batch(Batch<MoveArgs> B) {
+  const int k = batch_member(B.first, B.count, blockIdx.x);
+  const MoveArgs A = B.args[k];
+  move_wide_body<Real, G, CH, FAM>(A, blockIdx.x - B.first[k]);
+}
+
 }  // namespace subsmc
+

@@ -7,13 +7,14 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <algorithm>
+#include <map>
 #include <new>
 #include <vector>
 
 #include "../../include/subsmc.h"
-#include "kernels.hpp"
-#include "kernels_wide.hpp"
-#include "kernels_resident.hpp"
+#include "dispatch.hpp"
+#include "kernels_stage.hpp"
 
 using namespace subsmc;
 
@@ -22,6 +23,7 @@ namespace {
 constexpr int kMaxNarrowD = 32;   // one lane per row up to here
 constexpr int kMaxD = 128;        // lane groups per row beyond
 constexpr int kMaxM = kTemperThreads * kTemperPer;
+constexpr int kMaxBatch = 65536;  // the dataset field of the random-number counter
 constexpr int kCvMaxBlocks = 768;   // 3 workgroups per CU
 
 // rows per CV tile: up to one per thread, the whole LDS carve within 56 KB
@@ -132,6 +134,26 @@ struct smc_ctx_s {
   template <typename T> T* at(size_t off) { return reinterpret_cast<T*>(ws + off); }
 };
 
+// A batch: member contexts on one stream whose per-stage steps run as one
+// launch per kernel (the move: one launch per kernel shape among the members).
+struct smc_batch_s {
+  std::vector<smc_ctx> ctx;
+  hipStream_t stream = nullptr;
+  char* dev = nullptr;          // caller's workspace: argument tables, then results
+  char* host = nullptr;         // pinned mirror of the workspace
+  size_t table_bytes = 0;       // capacity of the table region
+  hipEvent_t staged = nullptr;  // recorded after the last upload from `host`
+  std::vector<int> active;      // members tempered in the current stage
+  int have_stage = 0;
+  // optional timing of the move launches: an event pair per launch and move
+  int timing = 0;
+  std::vector<hipEvent_t> ev;          // 2 per (move, launch) of the last smc_batch_move
+  std::vector<int> launch_kind;        // per launch of the last smc_batch_move
+  std::vector<int> member_launch;      // per member: its launch, -1 if inactive
+  int timed_moves = 0;
+  char err[512] = {0};
+};
+
 namespace {
 
 smc_status fail(smc_ctx c, smc_status s, const char* fmt, ...) {
@@ -164,6 +186,7 @@ smc_status validate(const smc_problem* pb) {
   if (pb->M < 1 || pb->M > kMaxM || pb->m < 1 || pb->G < 1 || pb->G > pb->m) return SMC_ERR_INVALID_ARG;
   if (!(pb->ess_frac > 0.0 && pb->ess_frac <= 1.0)) return SMC_ERR_INVALID_ARG;
   if (pb->move_path < SMC_MOVE_AUTO || pb->move_path > SMC_MOVE_RESIDENT) return SMC_ERR_INVALID_ARG;
+  if (pb->dataset > 0xFFFFu) return SMC_ERR_INVALID_ARG;
   if ((pb->m + pb->G - 1) / pb->G > kMaxBlock) return SMC_ERR_UNSUPPORTED;
   if (!pb->prior_mean || !pb->prior_prec) return SMC_ERR_INVALID_ARG;
   if (!pb->theta || !pb->u || !pb->logw || !pb->lhat || !pb->sig2 || !pb->accept || !pb->workspace)
@@ -175,126 +198,13 @@ smc_status validate(const smc_problem* pb) {
 }
 
 // ------------------------------------------------------------------------
-// kernel dispatch on (precision, padded d)
+// kernel selection (the launchers live in launch_*.hip)
 // ------------------------------------------------------------------------
 
-template <typename Real, int FAM>
-hipError_t launch_estimator_t(int dc, int count, const EstArgs& a, hipStream_t s) {
-  switch (dc) {
-#define CASE(DC) case DC: hipLaunchKernelGGL((estimator_kernel<Real, DC, FAM>), dim3(count), dim3(kWave), 0, s, a); break;
-    CASE(4) CASE(8) CASE(12) CASE(16) CASE(20) CASE(24) CASE(28) CASE(32)
-#undef CASE
-    default: return hipErrorInvalidValue;
-  }
-  return hipGetLastError();
-}
-
-template <typename Real, int FAM>
-hipError_t launch_move_t(int dc, int M, size_t lds, const MoveArgs& a, hipStream_t s) {
-  switch (dc) {
-#define CASE(DC) case DC: hipLaunchKernelGGL((move_kernel<Real, DC, FAM>), dim3(M), dim3(kWave), lds, s, a); break;
-    CASE(4) CASE(8) CASE(12) CASE(16) CASE(20) CASE(24) CASE(28) CASE(32)
-#undef CASE
-    default: return hipErrorInvalidValue;
-  }
-  return hipGetLastError();
-}
-
-template <typename Real>
-hipError_t launch_estimator_p(int fam, int dc, int count, const EstArgs& a, hipStream_t s) {
-  switch (fam) {
-    case kLogistic: return launch_estimator_t<Real, kLogistic>(dc, count, a, s);
-    case kPoisson: return launch_estimator_t<Real, kPoisson>(dc, count, a, s);
-    case kStudentT: return launch_estimator_t<Real, kStudentT>(dc, count, a, s);
-    default: return launch_estimator_t<Real, kGaussian>(dc, count, a, s);
-  }
-}
-
-template <typename Real>
-hipError_t launch_move_p(int fam, int dc, int M, size_t lds, const MoveArgs& a, hipStream_t s) {
-  switch (fam) {
-    case kLogistic: return launch_move_t<Real, kLogistic>(dc, M, lds, a, s);
-    case kPoisson: return launch_move_t<Real, kPoisson>(dc, M, lds, a, s);
-    case kStudentT: return launch_move_t<Real, kStudentT>(dc, M, lds, a, s);
-    default: return launch_move_t<Real, kGaussian>(dc, M, lds, a, s);
-  }
-}
-
-// wide kernels: (precision, G, CH) instantiated for the shapes wide_shape() produces
-#define WIDE_SHAPES(X)                                                      \
-  X(float, 4, 12) X(float, 4, 16) X(float, 8, 12) X(float, 8, 16) X(float, 8, 20) \
-  X(double, 4, 10) X(double, 4, 12) X(double, 4, 14) X(double, 4, 16)             \
-  X(double, 8, 10) X(double, 8, 12) X(double, 8, 14) X(double, 8, 16) X(double, 8, 18)
-
-template <typename Real, int G, int CH>
-hipError_t launch_wide_est_fam(int fam, int count, const EstArgs& a, hipStream_t s) {
-  if (fam == kLogistic)
-    hipLaunchKernelGGL((estimator_kernel_wide<Real, G, CH, kLogistic>), dim3(count), dim3(kWave), 0, s, a);
-  else if (fam == kPoisson)
-    hipLaunchKernelGGL((estimator_kernel_wide<Real, G, CH, kPoisson>), dim3(count), dim3(kWave), 0, s, a);
-  else if (fam == kStudentT)
-    hipLaunchKernelGGL((estimator_kernel_wide<Real, G, CH, kStudentT>), dim3(count), dim3(kWave), 0, s, a);
-  else
-    return hipErrorInvalidValue;
-  return hipGetLastError();
-}
-
-template <typename Real, int G, int CH>
-hipError_t launch_wide_move_fam(int fam, int M, size_t lds, const MoveArgs& a, hipStream_t s) {
-  if (fam == kLogistic)
-    hipLaunchKernelGGL((move_kernel_wide<Real, G, CH, kLogistic>), dim3(M), dim3(kWave), lds, s, a);
-  else if (fam == kPoisson)
-    hipLaunchKernelGGL((move_kernel_wide<Real, G, CH, kPoisson>), dim3(M), dim3(kWave), lds, s, a);
-  else if (fam == kStudentT)
-    hipLaunchKernelGGL((move_kernel_wide<Real, G, CH, kStudentT>), dim3(M), dim3(kWave), lds, s, a);
-  else
-    return hipErrorInvalidValue;
-  return hipGetLastError();
-}
-
-hipError_t launch_wide_estimator(smc_ctx c, int count, const EstArgs& a) {
-  const bool fp32 = c->pb.precision == SMC_MIXED;
-  const WideShape w = wide_shape(c->pb.d, fp32);
-#define X(T, G_, CH_) \
-  if ((sizeof(T) == 4) == fp32 && w.G == G_ && w.CH == CH_) return launch_wide_est_fam<T, G_, CH_>(c->pb.family, count, a, c->stream);
-  WIDE_SHAPES(X)
-#undef X
-  return hipErrorInvalidValue;
-}
-
-hipError_t launch_wide_move(smc_ctx c, size_t lds, const MoveArgs& a) {
-  const bool fp32 = c->pb.precision == SMC_MIXED;
-  const WideShape w = wide_shape(c->pb.d, fp32);
-#define X(T, G_, CH_) \
-  if ((sizeof(T) == 4) == fp32 && w.G == G_ && w.CH == CH_) return launch_wide_move_fam<T, G_, CH_>(c->pb.family, c->pb.M, lds, a, c->stream);
-  WIDE_SHAPES(X)
-#undef X
-  return hipErrorInvalidValue;
-}
-
-// resident move kernels: (precision, padded d, family, register rows per lane)
-#define RES_SHAPES(X)                                                                                  \
-  X(float, 4, 1, 0) X(float, 4, 1, 14) X(float, 8, 1, 0) X(float, 8, 1, 14) X(float, 12, 1, 0)          \
-  X(float, 12, 1, 14) X(float, 16, 1, 0) X(float, 16, 1, 14) X(float, 20, 1, 0) X(float, 20, 1, 14)     \
-  X(float, 24, 1, 0) X(float, 4, 0, 0) X(float, 8, 0, 0) X(float, 12, 0, 0) X(float, 16, 0, 0)          \
-  X(float, 20, 0, 0) X(float, 24, 0, 0)                                                                 \
-  X(double, 4, 0, 0) X(double, 8, 0, 0) X(double, 12, 0, 0) X(double, 16, 0, 0) X(double, 20, 0, 0)     \
-  X(double, 24, 0, 0) X(double, 4, 1, 0) X(double, 8, 1, 0) X(double, 12, 1, 0) X(double, 16, 1, 0)     \
-  X(double, 20, 1, 0) X(double, 24, 1, 0)
-
-template <typename Real, int DC, int FAM, int RPL>
-hipError_t launch_res(int M, const ResLayout& ly, const MoveArgs& a, hipStream_t s) {
-  auto k = move_kernel_res<Real, DC, FAM, RPL>;
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k), hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     ly.total);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k, dim3(M), dim3(kResLanes), ly.total, s, a, ly);
-  return hipGetLastError();
-}
-
-// register-row candidates for (precision, padded d, family): the ones
-// instantiated above (the logistic remainder needs the registers the row
-// cache would use, so logistic keeps all rows in LDS)
+// register-row candidates for (precision, padded d, family) of the resident
+// move: the shapes instantiated in launch_resident.hip (the logistic
+// remainder needs the registers the row cache would use, so logistic keeps
+// all rows in LDS)
 int res_candidates(bool fp32, int dc, int family, int out[2]) {
   if (dc > 24) return 0;
   out[0] = 0;
@@ -322,36 +232,40 @@ int choose_resident(const smc_problem& pb, int max_lds, ResLayout& ly) {
   return -1;
 }
 
-hipError_t launch_resident(smc_ctx c, const MoveArgs& a) {
-  const bool fp32 = c->pb.precision == SMC_MIXED;
-  const int dc = pad_dc(c->pb.d);
-#define X(T, DC_, FAM_, RPL_)                                                                    \
-  if ((sizeof(T) == 4) == fp32 && dc == DC_ && c->pb.family == FAM_ && c->res_rpl == RPL_)        \
-    return launch_res<T, DC_, FAM_, RPL_>(c->pb.M, c->res_ly, a, c->stream);
-  RES_SHAPES(X)
-#undef X
-  return hipErrorInvalidValue;
+// The move kernel of a context (the estimator kernels use the narrow or wide
+// shape of the same d).
+KernelShape move_shape(smc_ctx c) {
+  KernelShape s{};
+  s.fp32 = c->pb.precision == SMC_MIXED ? 1 : 0;
+  s.fam = c->pb.family;
+  s.dc = pad_dc(c->pb.d);
+  const WideShape w = wide_shape(c->pb.d, s.fp32 != 0);
+  s.lanes = w.G;
+  s.ch = w.CH;
+  s.rpl = c->res_rpl;
+  s.kind = c->res_rpl >= 0 ? kMoveResident : (c->pb.d > kMaxNarrowD ? kMoveWide : kMoveNarrow);
+  return s;
 }
 
 hipError_t launch_estimator(smc_ctx c, int count, const EstArgs& a) {
   if (count <= 0) return hipSuccess;
-  if (c->pb.d > kMaxNarrowD) return launch_wide_estimator(c, count, a);
-  const int dc = pad_dc(c->pb.d);
-  return c->pb.precision == SMC_MIXED ? launch_estimator_p<float>(c->pb.family, dc, count, a, c->stream)
-                                      : launch_estimator_p<double>(c->pb.family, dc, count, a, c->stream);
+  const KernelShape s = move_shape(c);
+  return s.kind == kMoveWide ? launch_estimator_wide(s, count, a, c->stream)
+                             : launch_estimator_narrow(s, count, a, c->stream);
 }
 
+// dynamic LDS of the streaming moves: one refreshed block of indices
 size_t block_lds_bytes(const smc_problem& pb) {
   return (size_t)((pb.m + pb.G - 1) / pb.G) * sizeof(int32_t);
 }
 
 hipError_t launch_move(smc_ctx c, const MoveArgs& a) {
-  if (c->res_rpl >= 0) return launch_resident(c, a);
-  const int dc = pad_dc(c->pb.d);
-  const size_t lds = block_lds_bytes(c->pb);
-  if (c->pb.d > kMaxNarrowD) return launch_wide_move(c, lds, a);
-  return c->pb.precision == SMC_MIXED ? launch_move_p<float>(c->pb.family, dc, c->pb.M, lds, a, c->stream)
-                                      : launch_move_p<double>(c->pb.family, dc, c->pb.M, lds, a, c->stream);
+  const KernelShape s = move_shape(c);
+  switch (s.kind) {
+    case kMoveResident: return launch_move_resident(s, c->pb.M, c->res_ly, a, c->stream);
+    case kMoveWide: return launch_move_wide(s, c->pb.M, block_lds_bytes(c->pb), a, c->stream);
+    default: return launch_move_narrow(s, c->pb.M, block_lds_bytes(c->pb), a, c->stream);
+  }
 }
 
 // Full-data A, B, C at device theta; packs rows when pack != 0.
@@ -563,6 +477,113 @@ smc_status refresh(smc_ctx c) {
   return SMC_OK;
 }
 
+// ------------------------------------------------------------------------
+// argument blocks of the per-stage kernels, shared by the single-context
+// calls and the batched ones
+// ------------------------------------------------------------------------
+
+TemperArgs temper_args(smc_ctx c, double ess_frac, double* out) {
+  TemperArgs t;
+  t.M = c->pb.M;
+  t.a_prev = c->a;
+  t.ess_frac = ess_frac;
+  t.lhat = c->pb.lhat;
+  t.sig2 = c->pb.sig2;
+  t.logw = c->pb.logw;
+  t.out = out;
+  t.grid_ess = nullptr;
+  t.grid_n = 0;
+  return t;
+}
+
+// state after a successful exponent search with outputs o = [a, dlogz, ess, ...]
+void temper_commit(smc_ctx c, const double* o) {
+  c->stage += 1;
+  c->move = 0;
+  c->a = o[0];
+  c->logz += o[1];
+  c->have_mass = 0;
+}
+
+MomentArgs moment_args(smc_ctx c, double* status) {
+  const int d = c->pb.d;
+  MomentArgs a;
+  a.M = c->pb.M;
+  a.d = d;
+  a.theta = c->pb.theta;
+  a.logw = c->pb.logw;
+  a.centre = c->prob.theta_bar;
+  a.partials = c->at<double>(c->lay.mpartials);
+  a.nblocks = c->lay.mom_blocks;
+  a.mean = c->at<double>(c->lay.mean);
+  a.F.d = d;
+  a.F.S = c->at<double>(c->lay.Sigma);
+  a.F.L = c->at<double>(c->lay.Lchol);
+  a.F.Linv = c->at<double>(c->lay.Linv);
+  a.F.status = status;
+  return a;
+}
+
+size_t moments_partial_lds(int d) { return (size_t)kMomTile * d * 8; }
+size_t moments_final_lds(int d) {
+  return (size_t)(d + d * (d + 1) / 2) * 8 + (d <= kFactorLdsMaxD ? (size_t)2 * d * d * 8 : 0);
+}
+
+ResampleArgs resample_args(smc_ctx c, int multinomial) {
+  ResampleArgs r;
+  r.M = c->pb.M;
+  r.multinomial = multinomial;
+  r.seed = c->pb.seed;
+  r.dataset = c->pb.dataset;
+  r.stage = (uint32_t)c->stage;
+  r.logw = c->pb.logw;
+  r.anc = c->at<int32_t>(c->lay.anc);
+  return r;
+}
+
+GatherArgs gather_args(smc_ctx c) {
+  const smc_problem& pb = c->pb;
+  GatherArgs g;
+  g.M = pb.M; g.d = pb.d; g.m = pb.m;
+  g.anc = c->at<int32_t>(c->lay.anc);
+  g.theta = pb.theta; g.u = pb.u; g.lhat = pb.lhat; g.sig2 = pb.sig2;
+  g.gl = c->at<double>(c->lay.grad_l); g.gs = c->at<double>(c->lay.grad_s);
+  g.theta2 = c->at<double>(c->lay.th2); g.u2 = c->at<int32_t>(c->lay.u2);
+  g.lhat2 = c->at<double>(c->lay.lh2); g.sig22 = c->at<double>(c->lay.sg2);
+  g.gl2 = c->at<double>(c->lay.gl2); g.gs2 = c->at<double>(c->lay.gs2);
+  return g;
+}
+
+CopyBackArgs copyback_args(smc_ctx c) {
+  const smc_problem& pb = c->pb;
+  CopyBackArgs b;
+  b.M = pb.M; b.d = pb.d; b.m = pb.m;
+  b.theta2 = c->at<double>(c->lay.th2); b.u2 = c->at<int32_t>(c->lay.u2);
+  b.lhat2 = c->at<double>(c->lay.lh2); b.sig22 = c->at<double>(c->lay.sg2);
+  b.gl2 = c->at<double>(c->lay.gl2); b.gs2 = c->at<double>(c->lay.gs2);
+  b.theta = pb.theta; b.u = pb.u; b.lhat = pb.lhat; b.sig2 = pb.sig2;
+  b.gl = c->at<double>(c->lay.grad_l); b.gs = c->at<double>(c->lay.grad_s); b.logw = pb.logw;
+  return b;
+}
+
+MoveArgs move_args(smc_ctx c, double eps, int L) {
+  MoveArgs a;
+  a.P = c->prob;
+  a.a = c->a;
+  a.eps = eps;
+  a.L = L;
+  a.stage = (uint32_t)c->stage;
+  a.move = (uint32_t)c->move;
+  a.theta = c->pb.theta;
+  a.u = c->pb.u;
+  a.lhat = c->pb.lhat;
+  a.sig2 = c->pb.sig2;
+  a.grad_l = c->at<double>(c->lay.grad_l);
+  a.grad_s = c->at<double>(c->lay.grad_s);
+  a.accept = c->pb.accept;
+  return a;
+}
+
 }  // namespace
 
 extern "C" {
@@ -619,6 +640,7 @@ smc_status smc_init(const smc_problem* pb, void* stream, smc_ctx* out) {
   P.m = pb->m;
   P.G = pb->G;
   P.seed = pb->seed;
+  P.dataset = pb->dataset;
   P.inv_s2 = pb->family == SMC_GAUSSIAN ? 1.0 / pb->gauss_s2 : 0.0;
   P.log2pis2 = pb->family == SMC_GAUSSIAN ? std::log(2.0 * M_PI * pb->gauss_s2) : 0.0;
   P.n_over_m = (double)pb->n / (double)pb->m;
@@ -684,16 +706,7 @@ smc_status smc_init(const smc_problem* pb, void* stream, smc_ctx* out) {
 static smc_status temper_impl(smc_ctx c, int grid_points, double ess_frac, double* a_out, double* dlogz_out,
                               double* ess_out, double* ess_grid_out) {
   if (c->a >= 1.0) return fail(c, SMC_ERR_STATE, "tempering already reached a = 1");
-  TemperArgs t;
-  t.M = c->pb.M;
-  t.a_prev = c->a;
-  t.ess_frac = ess_frac;
-  t.lhat = c->pb.lhat;
-  t.sig2 = c->pb.sig2;
-  t.logw = c->pb.logw;
-  t.out = c->at<double>(c->lay.tout);
-  t.grid_ess = nullptr;
-  t.grid_n = 0;
+  TemperArgs t = temper_args(c, ess_frac, c->at<double>(c->lay.tout));
   if (grid_points > 0) {
     GridArgs g;
     g.M = c->pb.M;
@@ -715,11 +728,7 @@ static smc_status temper_impl(smc_ctx c, int grid_points, double ess_frac, doubl
   HIP_TRY(c, hipMemcpyAsync(o, t.out, sizeof(o), hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   if (o[3] != 0.0) return fail(c, SMC_ERR_NONFINITE, "all incremental weights non-finite");
-  c->stage += 1;
-  c->move = 0;
-  c->a = o[0];
-  c->logz += o[1];
-  c->have_mass = 0;
+  temper_commit(c, o);
   if (a_out) *a_out = o[0];
   if (dlogz_out) *dlogz_out = o[1];
   if (ess_out) *ess_out = o[2];
@@ -742,24 +751,11 @@ smc_status smc_temper_grid(smc_ctx c, int32_t grid_points, double ess_frac, doub
 smc_status smc_mass(smc_ctx c) {
   if (!c) return SMC_ERR_INVALID_ARG;
   const int d = c->pb.d;
-  MomentArgs a;
-  a.M = c->pb.M;
-  a.d = d;
-  a.theta = c->pb.theta;
-  a.logw = c->pb.logw;
-  a.centre = c->prob.theta_bar;
-  a.partials = c->at<double>(c->lay.mpartials);
-  a.nblocks = c->lay.mom_blocks;
-  a.mean = c->at<double>(c->lay.mean);
-  a.F.d = d;
-  a.F.S = c->at<double>(c->lay.Sigma);
-  a.F.L = c->at<double>(c->lay.Lchol);
-  a.F.Linv = c->at<double>(c->lay.Linv);
-  a.F.status = c->at<double>(c->lay.status);
-  hipLaunchKernelGGL(moments_partial_kernel, dim3(a.nblocks), dim3(kMomThreads), (size_t)kMomTile * d * 8,
+  const MomentArgs a = moment_args(c, c->at<double>(c->lay.status));
+  hipLaunchKernelGGL(moments_partial_kernel, dim3(a.nblocks), dim3(kMomThreads), moments_partial_lds(d),
                      c->stream, a);
   LAUNCH_CHECK(c);
-  const size_t mlds = (size_t)(d + d * (d + 1) / 2) * 8 + (d <= kFactorLdsMaxD ? (size_t)2 * d * d * 8 : 0);
+  const size_t mlds = moments_final_lds(d);
   HIP_TRY(c, hipFuncSetAttribute(reinterpret_cast<const void*>(moments_final_kernel),
                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)mlds));
   hipLaunchKernelGGL(moments_final_kernel, dim3(1), dim3(kMomThreads), mlds, c->stream, a);
@@ -774,30 +770,13 @@ smc_status smc_mass(smc_ctx c) {
 
 static smc_status resample_impl(smc_ctx c, int multinomial) {
   const smc_problem& pb = c->pb;
-  ResampleArgs r;
-  r.M = pb.M;
-  r.multinomial = multinomial;
-  r.seed = pb.seed;
-  r.stage = (uint32_t)c->stage;
-  r.logw = pb.logw;
-  r.anc = c->at<int32_t>(c->lay.anc);
+  const ResampleArgs r = resample_args(c, multinomial);
   hipLaunchKernelGGL(resample_kernel, dim3(1), dim3(kResThreads), 0, c->stream, r);
   LAUNCH_CHECK(c);
-  GatherArgs g;
-  g.M = pb.M; g.d = pb.d; g.m = pb.m;
-  g.anc = r.anc;
-  g.theta = pb.theta; g.u = pb.u; g.lhat = pb.lhat; g.sig2 = pb.sig2;
-  g.gl = c->at<double>(c->lay.grad_l); g.gs = c->at<double>(c->lay.grad_s);
-  g.theta2 = c->at<double>(c->lay.th2); g.u2 = c->at<int32_t>(c->lay.u2);
-  g.lhat2 = c->at<double>(c->lay.lh2); g.sig22 = c->at<double>(c->lay.sg2);
-  g.gl2 = c->at<double>(c->lay.gl2); g.gs2 = c->at<double>(c->lay.gs2);
+  const GatherArgs g = gather_args(c);
   hipLaunchKernelGGL(gather_kernel, dim3(pb.M), dim3(256), 0, c->stream, g);
   LAUNCH_CHECK(c);
-  CopyBackArgs b;
-  b.M = pb.M; b.d = pb.d; b.m = pb.m;
-  b.theta2 = g.theta2; b.u2 = g.u2; b.lhat2 = g.lhat2; b.sig22 = g.sig22; b.gl2 = g.gl2; b.gs2 = g.gs2;
-  b.theta = pb.theta; b.u = pb.u; b.lhat = pb.lhat; b.sig2 = pb.sig2;
-  b.gl = const_cast<double*>(g.gl); b.gs = const_cast<double*>(g.gs); b.logw = pb.logw;
+  const CopyBackArgs b = copyback_args(c);
   hipLaunchKernelGGL(copyback_kernel, dim3(pb.M), dim3(256), 0, c->stream, b);
   LAUNCH_CHECK(c);
   return SMC_OK;
@@ -819,21 +798,7 @@ smc_status smc_move(smc_ctx c, double eps, int32_t L, int32_t R) {
   if (!c->have_mass) return fail(c, SMC_ERR_STATE, "no mass matrix for this stage");
   if (c->move + R > 0xFFFF) return fail(c, SMC_ERR_INVALID_ARG, "too many moves in one stage");
   for (int r = 0; r < R; ++r) {
-    MoveArgs a;
-    a.P = c->prob;
-    a.a = c->a;
-    a.eps = eps;
-    a.L = L;
-    a.stage = (uint32_t)c->stage;
-    a.move = (uint32_t)c->move;
-    a.theta = c->pb.theta;
-    a.u = c->pb.u;
-    a.lhat = c->pb.lhat;
-    a.sig2 = c->pb.sig2;
-    a.grad_l = c->at<double>(c->lay.grad_l);
-    a.grad_s = c->at<double>(c->lay.grad_s);
-    a.accept = c->pb.accept;
-    HIP_TRY(c, launch_move(c, a));
+    HIP_TRY(c, launch_move(c, move_args(c, eps, L)));
     c->move += 1;
   }
   return SMC_OK;
@@ -965,6 +930,391 @@ smc_status smc_full_loglik(smc_ctx c, const double* theta, double* A, double* B,
   if (C) std::memcpy(C, Cv.data(), (size_t)d * d * 8);
   return SMC_OK;
 }
+
+// ------------------------------------------------------------------------
+// batches
+// ------------------------------------------------------------------------
+
+}  // extern "C"
+
+namespace {
+
+constexpr size_t kBatchArgBytes = 512;  // bound on every argument block
+static_assert(sizeof(ResMoveArgs) <= kBatchArgBytes && sizeof(MoveArgs) <= kBatchArgBytes &&
+                  sizeof(TemperArgs) <= kBatchArgBytes && sizeof(MomentArgs) <= kBatchArgBytes &&
+                  sizeof(ResampleArgs) <= kBatchArgBytes && sizeof(GatherArgs) <= kBatchArgBytes &&
+                  sizeof(CopyBackArgs) <= kBatchArgBytes,
+              "argument block larger than its table slot");
+constexpr size_t kBatchResultDoubles = 8;  // per member
+
+// the most any step stages: three tables of count blocks, a prefix array
+// per table and per move group, each placement 256-byte aligned
+size_t batch_table_bytes(int count) { return (size_t)count * (3 * kBatchArgBytes + 1024) + 4096; }
+
+smc_status bfail(smc_batch b, smc_status s, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(b->err, sizeof(b->err), fmt, ap);
+  va_end(ap);
+  return s;
+}
+
+#define BATCH_TRY(b, expr)                                                                     \
+  do {                                                                                         \
+    hipError_t e_ = (expr);                                                                    \
+    if (e_ != hipSuccess)                                                                      \
+      return bfail(b, SMC_ERR_DEVICE, "%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_),    \
+                   __FILE__, __LINE__);                                                        \
+  } while (0)
+
+// Argument tables of one step, laid out on the host and uploaded in one copy
+// on the batch's stream (kernels launched earlier on that stream have read
+// the previous tables by the time it lands).
+class Tables {
+ public:
+  explicit Tables(smc_batch b) : b_(b) {}
+  template <typename T>
+  size_t put(const std::vector<T>& v) {
+    const size_t off = align256(buf_.size());
+    buf_.resize(off + v.size() * sizeof(T));
+    std::memcpy(buf_.data() + off, v.data(), v.size() * sizeof(T));
+    return off;
+  }
+  template <typename T>
+  const T* at(size_t off) const { return reinterpret_cast<const T*>(b_->dev + off); }
+  smc_status upload() {
+    if (buf_.size() > b_->table_bytes) return bfail(b_, SMC_ERR_UNSUPPORTED, "argument tables exceed the workspace");
+    // the staging buffer is reused: wait until the previous upload has read it
+    BATCH_TRY(b_, hipEventSynchronize(b_->staged));
+    std::memcpy(b_->host, buf_.data(), buf_.size());
+    BATCH_TRY(b_, hipMemcpyAsync(b_->dev, b_->host, buf_.size(), hipMemcpyHostToDevice, b_->stream));
+    BATCH_TRY(b_, hipEventRecord(b_->staged, b_->stream));
+    return SMC_OK;
+  }
+
+ private:
+  smc_batch b_;
+  std::vector<char> buf_;
+};
+
+double* batch_results_dev(smc_batch b) { return reinterpret_cast<double*>(b->dev + b->table_bytes); }
+double* batch_results_host(smc_batch b) { return reinterpret_cast<double*>(b->host + b->table_bytes); }
+
+// results of the active members (kBatchResultDoubles each) to the host; synchronises
+smc_status batch_fetch(smc_batch b) {
+  const size_t bytes = b->active.size() * kBatchResultDoubles * 8;
+  BATCH_TRY(b, hipMemcpyAsync(batch_results_host(b), batch_results_dev(b), bytes, hipMemcpyDeviceToHost, b->stream));
+  BATCH_TRY(b, hipStreamSynchronize(b->stream));
+  return SMC_OK;
+}
+
+template <typename T>
+Batch<T> batch_of(const Tables& t, size_t args_off, size_t first_off, int count) {
+  Batch<T> r;
+  r.args = t.at<T>(args_off);
+  r.first = t.at<int>(first_off);
+  r.count = count;
+  return r;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t smc_batch_workspace_size(int32_t count) {
+  if (count < 1 || count > kMaxBatch) return 0;
+  return align256(batch_table_bytes(count)) + (size_t)count * kBatchResultDoubles * 8;
+}
+
+smc_status smc_batch_create(const smc_ctx* ctxs, int32_t count, void* workspace, size_t workspace_bytes,
+                            smc_batch* out) {
+  if (!out) return SMC_ERR_INVALID_ARG;
+  *out = nullptr;
+  if (!ctxs || count < 1 || count > kMaxBatch || !workspace) return SMC_ERR_INVALID_ARG;
+  if ((reinterpret_cast<uintptr_t>(workspace) & 255) != 0) return SMC_ERR_INVALID_ARG;
+  const size_t need = smc_batch_workspace_size(count);
+  if (workspace_bytes < need) return SMC_ERR_INVALID_ARG;
+  for (int k = 0; k < count; ++k) {
+    if (!ctxs[k] || ctxs[k]->stream != ctxs[0]->stream) return SMC_ERR_INVALID_ARG;
+    for (int q = 0; q < k; ++q)
+      if (ctxs[q] == ctxs[k]) return SMC_ERR_INVALID_ARG;
+  }
+  smc_batch b = new (std::nothrow) smc_batch_s;
+  if (!b) return SMC_ERR_DEVICE;
+  b->ctx.assign(ctxs, ctxs + count);
+  b->stream = ctxs[0]->stream;
+  b->dev = static_cast<char*>(workspace);
+  b->table_bytes = align256(batch_table_bytes(count));
+  if (hipHostMalloc(reinterpret_cast<void**>(&b->host), need, hipHostMallocDefault) != hipSuccess) {
+    delete b;
+    return SMC_ERR_DEVICE;
+  }
+  if (hipEventCreateWithFlags(&b->staged, hipEventDisableTiming) != hipSuccess ||
+      hipEventRecord(b->staged, b->stream) != hipSuccess) {
+    if (b->staged) (void)hipEventDestroy(b->staged);
+    (void)hipHostFree(b->host);
+    delete b;
+    return SMC_ERR_DEVICE;
+  }
+  *out = b;
+  return SMC_OK;
+}
+
+smc_status smc_batch_temper(smc_batch b, double* a_out, double* dlogz_out, double* ess_out, int32_t* active_out) {
+  if (!b) return SMC_ERR_INVALID_ARG;
+  const int count = (int)b->ctx.size();
+  b->active.clear();
+  b->have_stage = 0;
+  for (int k = 0; k < count; ++k)
+    if (b->ctx[k]->a < 1.0) b->active.push_back(k);
+  for (int k = 0; k < count; ++k) {
+    if (a_out) a_out[k] = b->ctx[k]->a;
+    if (dlogz_out) dlogz_out[k] = 0.0;
+    if (ess_out) ess_out[k] = 0.0;
+    if (active_out) active_out[k] = 0;
+  }
+  if (b->active.empty()) return bfail(b, SMC_ERR_STATE, "every member has reached a = 1");
+  const int na = (int)b->active.size();
+  std::vector<TemperArgs> ta(na);
+  for (int q = 0; q < na; ++q) {
+    smc_ctx c = b->ctx[b->active[q]];
+    ta[q] = temper_args(c, c->pb.ess_frac, batch_results_dev(b) + (size_t)q * kBatchResultDoubles);
+  }
+  Tables T(b);
+  const size_t off = T.put(ta);
+  smc_status st = T.upload();
+  if (st != SMC_OK) return st;
+  Batch<TemperArgs> bt;
+  bt.args = T.at<TemperArgs>(off);
+  bt.first = nullptr;
+  bt.count = na;
+  hipLaunchKernelGGL(temper_kernel_batch, dim3(na), dim3(kTemperThreads), 0, b->stream, bt);
+  BATCH_TRY(b, hipGetLastError());
+  if ((st = batch_fetch(b)) != SMC_OK) return st;
+  int bad = -1;
+  for (int q = 0; q < na; ++q) {
+    const int k = b->active[q];
+    const double* o = batch_results_host(b) + (size_t)q * kBatchResultDoubles;
+    if (o[3] != 0.0) {
+      if (bad < 0) bad = k;
+      continue;
+    }
+    temper_commit(b->ctx[k], o);
+    if (a_out) a_out[k] = o[0];
+    if (dlogz_out) dlogz_out[k] = o[1];
+    if (ess_out) ess_out[k] = o[2];
+    if (active_out) active_out[k] = 1;
+  }
+  if (bad >= 0) return bfail(b, SMC_ERR_NONFINITE, "member %d: all incremental weights non-finite", bad);
+  b->have_stage = 1;
+  return SMC_OK;
+}
+
+smc_status smc_batch_mass(smc_batch b) {
+  if (!b) return SMC_ERR_INVALID_ARG;
+  if (!b->have_stage) return bfail(b, SMC_ERR_STATE, "no tempered stage");
+  const int na = (int)b->active.size();
+  std::vector<MomentArgs> ma(na);
+  std::vector<int> first(na + 1, 0);
+  size_t lds_p = 0, lds_f = 0;
+  for (int q = 0; q < na; ++q) {
+    smc_ctx c = b->ctx[b->active[q]];
+    ma[q] = moment_args(c, batch_results_dev(b) + (size_t)q * kBatchResultDoubles);
+    first[q + 1] = first[q] + ma[q].nblocks;
+    lds_p = std::max(lds_p, moments_partial_lds(c->pb.d));
+    lds_f = std::max(lds_f, moments_final_lds(c->pb.d));
+  }
+  Tables T(b);
+  const size_t off = T.put(ma), foff = T.put(first);
+  smc_status st = T.upload();
+  if (st != SMC_OK) return st;
+  const Batch<MomentArgs> bm = batch_of<MomentArgs>(T, off, foff, na);
+  BATCH_TRY(b, hipFuncSetAttribute(reinterpret_cast<const void*>(moments_partial_kernel_batch),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_p));
+  hipLaunchKernelGGL(moments_partial_kernel_batch, dim3(first[na]), dim3(kMomThreads), lds_p, b->stream, bm);
+  BATCH_TRY(b, hipGetLastError());
+  BATCH_TRY(b, hipFuncSetAttribute(reinterpret_cast<const void*>(moments_final_kernel_batch),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_f));
+  hipLaunchKernelGGL(moments_final_kernel_batch, dim3(na), dim3(kMomThreads), lds_f, b->stream, bm);
+  BATCH_TRY(b, hipGetLastError());
+  if ((st = batch_fetch(b)) != SMC_OK) return st;
+  int bad = -1;
+  for (int q = 0; q < na; ++q) {
+    if (batch_results_host(b)[(size_t)q * kBatchResultDoubles] != 0.0) {
+      if (bad < 0) bad = b->active[q];
+      continue;
+    }
+    b->ctx[b->active[q]]->have_mass = 1;
+  }
+  if (bad >= 0) return bfail(b, SMC_ERR_NOT_PD, "member %d: particle covariance not positive definite", bad);
+  return SMC_OK;
+}
+
+smc_status smc_batch_resample(smc_batch b, int32_t multinomial) {
+  if (!b || (multinomial != 0 && multinomial != 1)) return SMC_ERR_INVALID_ARG;
+  if (!b->have_stage) return bfail(b, SMC_ERR_STATE, "no tempered stage");
+  const int na = (int)b->active.size();
+  std::vector<ResampleArgs> ra(na);
+  std::vector<GatherArgs> ga(na);
+  std::vector<CopyBackArgs> ca(na);
+  std::vector<int> first(na + 1, 0);
+  for (int q = 0; q < na; ++q) {
+    smc_ctx c = b->ctx[b->active[q]];
+    ra[q] = resample_args(c, multinomial);
+    ga[q] = gather_args(c);
+    ca[q] = copyback_args(c);
+    first[q + 1] = first[q] + c->pb.M;
+  }
+  Tables T(b);
+  const size_t roff = T.put(ra), goff = T.put(ga), coff = T.put(ca), foff = T.put(first);
+  smc_status st = T.upload();
+  if (st != SMC_OK) return st;
+  const Batch<ResampleArgs> br = batch_of<ResampleArgs>(T, roff, foff, na);
+  hipLaunchKernelGGL(resample_kernel_batch, dim3(na), dim3(kResThreads), 0, b->stream, br);
+  BATCH_TRY(b, hipGetLastError());
+  const Batch<GatherArgs> bg = batch_of<GatherArgs>(T, goff, foff, na);
+  hipLaunchKernelGGL(gather_kernel_batch, dim3(first[na]), dim3(256), 0, b->stream, bg);
+  BATCH_TRY(b, hipGetLastError());
+  const Batch<CopyBackArgs> bc = batch_of<CopyBackArgs>(T, coff, foff, na);
+  hipLaunchKernelGGL(copyback_kernel_batch, dim3(first[na]), dim3(256), 0, b->stream, bc);
+  BATCH_TRY(b, hipGetLastError());
+  return SMC_OK;
+}
+
+smc_status smc_batch_move(smc_batch b, const double* eps, int32_t L, int32_t R) {
+  if (!b || !eps || L < 1 || R < 0) return SMC_ERR_INVALID_ARG;
+  if (!b->have_stage) return bfail(b, SMC_ERR_STATE, "no tempered stage");
+  for (int k : b->active) {
+    smc_ctx c = b->ctx[k];
+    if (!(eps[k] > 0.0)) return bfail(b, SMC_ERR_INVALID_ARG, "member %d: eps must be positive", k);
+    if (!c->have_mass) return bfail(b, SMC_ERR_STATE, "member %d: no mass matrix for this stage", k);
+    if (c->move + R > 0xFFFF) return bfail(b, SMC_ERR_INVALID_ARG, "member %d: too many moves in one stage", k);
+  }
+  // members grouped by kernel shape: one launch per group
+  std::map<KernelShape, std::vector<int>> groups;
+  for (int k : b->active) groups[move_shape(b->ctx[k])].push_back(k);
+  const int ng = (int)groups.size();
+  b->launch_kind.clear();
+  b->member_launch.assign(b->ctx.size(), -1);
+  {
+    int gi = 0;
+    for (const auto& g : groups) {
+      b->launch_kind.push_back(g.first.kind);
+      for (int k : g.second) b->member_launch[k] = gi;
+      ++gi;
+    }
+  }
+  b->timed_moves = 0;
+  if (b->timing) {
+    const size_t need = (size_t)2 * ng * R;
+    while (b->ev.size() < need) {
+      hipEvent_t e;
+      BATCH_TRY(b, hipEventCreate(&e));
+      b->ev.push_back(e);
+    }
+  }
+  for (int r = 0; r < R; ++r) {
+    Tables T(b);
+    struct Launch { KernelShape s; size_t off, foff; int n, grid; size_t lds; };
+    std::vector<Launch> launches;
+    for (const auto& g : groups) {
+      const KernelShape& s = g.first;
+      const std::vector<int>& mem = g.second;
+      std::vector<int> first(mem.size() + 1, 0);
+      size_t lds = 0;
+      std::vector<MoveArgs> ma;
+      std::vector<ResMoveArgs> rma;
+      for (size_t q = 0; q < mem.size(); ++q) {
+        smc_ctx c = b->ctx[mem[q]];
+        const MoveArgs a = move_args(c, eps[mem[q]], L);
+        if (s.kind == kMoveResident) {
+          rma.push_back(ResMoveArgs{a, c->res_ly});
+          lds = std::max(lds, (size_t)c->res_ly.total);
+        } else {
+          ma.push_back(a);
+          lds = std::max(lds, block_lds_bytes(c->pb));
+        }
+        first[q + 1] = first[q] + c->pb.M;
+      }
+      Launch l;
+      l.s = s;
+      l.off = s.kind == kMoveResident ? T.put(rma) : T.put(ma);
+      l.foff = T.put(first);
+      l.n = (int)mem.size();
+      l.grid = first.back();
+      l.lds = lds;
+      launches.push_back(l);
+    }
+    smc_status st = T.upload();
+    if (st != SMC_OK) return st;
+    for (size_t li = 0; li < launches.size(); ++li) {
+      const Launch& l = launches[li];
+      hipEvent_t* ev = b->timing ? &b->ev[2 * ((size_t)r * ng + li)] : nullptr;
+      if (ev) BATCH_TRY(b, hipEventRecord(ev[0], b->stream));
+      hipError_t e;
+      if (l.s.kind == kMoveResident)
+        e = launch_move_resident_batch(l.s, l.grid, l.lds, batch_of<ResMoveArgs>(T, l.off, l.foff, l.n), b->stream);
+      else if (l.s.kind == kMoveWide)
+        e = launch_move_wide_batch(l.s, l.grid, l.lds, batch_of<MoveArgs>(T, l.off, l.foff, l.n), b->stream);
+      else
+        e = launch_move_narrow_batch(l.s, l.grid, l.lds, batch_of<MoveArgs>(T, l.off, l.foff, l.n), b->stream);
+      BATCH_TRY(b, e);
+      if (ev) BATCH_TRY(b, hipEventRecord(ev[1], b->stream));
+    }
+    for (int k : b->active) b->ctx[k]->move += 1;
+    if (b->timing) b->timed_moves += 1;
+  }
+  return SMC_OK;
+}
+
+smc_status smc_batch_set_timing(smc_batch b, int32_t on) {
+  if (!b || (on != 0 && on != 1)) return SMC_ERR_INVALID_ARG;
+  b->timing = on;
+  return SMC_OK;
+}
+
+smc_status smc_batch_move_timing(smc_batch b, int32_t cap, int32_t* launches, int32_t* kind, double* ms,
+                                 int32_t* member_launch) {
+  if (!b || !launches) return SMC_ERR_INVALID_ARG;
+  const int ng = (int)b->launch_kind.size();
+  *launches = ng;
+  if (member_launch)
+    for (size_t k = 0; k < b->ctx.size(); ++k) member_launch[k] = b->member_launch.empty() ? -1 : b->member_launch[k];
+  if (ng > cap) return bfail(b, SMC_ERR_INVALID_ARG, "%d launches, capacity %d", ng, cap);
+  for (int g = 0; g < ng; ++g) {
+    if (kind) kind[g] = b->launch_kind[g];
+    if (!ms) continue;
+    ms[g] = 0.0;
+    for (int r = 0; r < b->timed_moves; ++r) {
+      const hipEvent_t* ev = &b->ev[2 * ((size_t)r * ng + g)];
+      BATCH_TRY(b, hipEventSynchronize(ev[1]));
+      float t = 0.f;
+      BATCH_TRY(b, hipEventElapsedTime(&t, ev[0], ev[1]));
+      ms[g] += t;
+    }
+  }
+  return SMC_OK;
+}
+
+int32_t smc_batch_launches(smc_batch b) {
+  if (!b || !b->have_stage) return 0;
+  std::map<KernelShape, int> groups;
+  for (int k : b->active) groups[move_shape(b->ctx[k])] += 1;
+  return (int32_t)groups.size();
+}
+
+void smc_batch_destroy(smc_batch b) {
+  if (!b) return;
+  if (b->staged) {
+    (void)hipEventSynchronize(b->staged);
+    (void)hipEventDestroy(b->staged);
+  }
+  for (hipEvent_t e : b->ev) (void)hipEventDestroy(e);
+  if (b->host) (void)hipHostFree(b->host);
+  delete b;
+}
+
+const char* smc_batch_last_error(smc_batch b) { return b ? b->err : "no batch"; }
 
 void smc_destroy(smc_ctx c) { delete c; }
 

@@ -52,6 +52,7 @@ class Workload:
     gauss_s2: float = 1.0
     ess_frac: float = 0.5
     extra: dict = field(default_factory=dict)
+    dataset: int = 0              # dataset field of the random-number counters (batch member index)
 
     def Xy(self, dtype) -> np.ndarray:
         """Row-major [x | y | 0-padding] array in the given dtype."""
@@ -194,6 +195,36 @@ def student_t(n=500_000, d=50, M=2048, m=1250, L=15):
                     np.eye(d) / 10.0, M=M, m=m, G=100, L=L, seed=2006, theta_true=theta)
 
 
+def config3_sizes(count=64):
+    """(n_k, d_k) of the batched configuration: n log-uniform in [1e4, 2e6], d uniform in {5..50}."""
+    n = np.exp(_gen(1003, 0).uniform(math.log(1e4), math.log(2e6), count)).astype(np.int64)
+    d = _gen(1003, 1).integers(5, 51, count)
+    return n, d
+
+
+def config3_member(k, count=64, precision=MIXED, M=1024):
+    """Member k of the batched configuration: logistic regression with N(0,1) covariates,
+    theta_true ~ N(0, I), prior N(0, 10 I), P = 1024, m = 1% of n (at least 200), L = 10.
+    Rows of member k come from stream 16 + 4096 k + 1 + chunk of key 1003 (theta_true: stream
+    16 + 4096 k); every member uses SMC seed 2003 with its index k as the dataset counter field."""
+    n_all, d_all = config3_sizes(count)
+    n, d = int(n_all[k]), int(d_all[k])
+    key, base = 1003, 16 + 4096 * k
+    theta = _gen(key, base).standard_normal(d)
+    X = np.empty((n, d))
+    y = np.empty(n)
+    for c0 in range(0, n, CHUNK):
+        c1 = min(n, c0 + CHUNK)
+        g = _gen(key, base + 1 + c0 // CHUNK)
+        X[c0:c1] = g.standard_normal((c1 - c0, d))
+        p = 1.0 / (1.0 + np.exp(-(X[c0:c1] @ theta)))
+        y[c0:c1] = (g.random(c1 - c0) < p).astype(np.float64)
+    X, y = _finish(X, y, precision)
+    m = max(200, int(round(0.01 * n)))
+    return Workload(f"batch{count}_k{k}_logistic_n{n}_d{d}", LOGISTIC, precision, n, d, X, y, np.zeros(d),
+                    np.eye(d) / 10.0, M=M, m=m, G=100, L=10, seed=2003, theta_true=theta, dataset=k)
+
+
 CONFIGS = {1: config1, 2: config2, 4: config4, 5: config5}
 
 
@@ -248,6 +279,24 @@ def gaussian_small(n, d, seed, s2=1.0, precision=FP64, M=64, m=50, G=4, L=8, pri
     Q0 = np.eye(d) / prior_var + 0.05 * np.ones((d, d)) / d
     return Workload(f"gaussian_n{n}_d{d}", GAUSSIAN, precision, n, d, X, y, mu0, Q0,
                     M=M, m=m, G=G, L=L, seed=9500 + seed, theta_true=theta, gauss_s2=s2)
+
+
+def batched_small(count, seed, precision=FP64, M=48, L=6, n_range=(600, 6000), d_values=None):
+    """Small members of a batch for parity: logistic data as in logistic_small with per-member n
+    log-uniform in n_range and d from d_values (default: uniform in 2..40, so narrow and lane-group
+    rows both occur), m = max(40, n // 40), G = 4, member k with dataset field k."""
+    g = _gen(9800 + seed, 0)
+    out = []
+    for k in range(count):
+        n = int(math.exp(g.uniform(math.log(n_range[0]), math.log(n_range[1]))))
+        d = int(d_values[k % len(d_values)]) if d_values is not None else int(g.integers(2, 41))
+        w = logistic_small(n, d, seed=1000 * seed + k, precision=precision, M=M, m=max(40, n // 40), G=4, L=L,
+                           theta_scale=min(1.0, 2.0 / math.sqrt(d)))
+        w.seed = 9850 + seed
+        w.dataset = k
+        w.name = f"batch_small{seed}_k{k}_{w.name}"
+        out.append(w)
+    return out
 
 
 def random_state(w: Workload, count: int, scale: float, centre: np.ndarray, seed: int):

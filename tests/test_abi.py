@@ -17,7 +17,7 @@ HEADER = os.path.join(ROOT, "include", "subsmc.h")
 def declared_functions():
     src = open(HEADER).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    names = re.findall(r"^\s*(?:smc_status|size_t|void|const char\*)\s+(\w+)\s*\(", src, flags=re.M)
+    names = re.findall(r"^\s*(?:smc_status|size_t|void|int32_t|const char\*)\s+(\w+)\s*\(", src, flags=re.M)
     return sorted(set(names))
 
 

@@ -1,0 +1,168 @@
+"""GPU parity of the batched entry points (smc_batch_*): many datasets of
+uneven n and d advanced together, one launch per step (per kernel shape for
+the move).
+
+Each member of a batch must give exactly what its own context gives with the
+single-context calls (the same kernels and arguments, so bit for bit), and
+what the oracle gives for that dataset with its dataset counter field (within
+the full-run tolerances of the single-context tests). Members reach a = 1 at
+different stages, so later stages run with part of the batch inactive."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1805_03317_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def _binding():
+    from paper_1805_03317_amd import binding
+    return binding
+
+
+def _oracle_problem(w):
+    P = oracle.Problem(w.Xy(np.float64), w.d, w.family, w.prior_mean, w.prior_prec)
+    tb, _ = P.newton_mode()
+    P.set_cv_centre(tb)
+    return P, tb
+
+
+def _context(w, theta_bar, move_path=0):
+    B = _binding()
+    dt = np.float32 if w.precision == W.MIXED else np.float64
+    Xy = torch.tensor(w.Xy(dt), device=DEV)
+    return B.SubsampledSMC(Xy, w.d, w.family, w.precision, w.M, w.m, w.G, w.prior_mean, w.prior_prec, w.seed,
+                           theta_bar=theta_bar, move_path=move_path, dataset=w.dataset)
+
+
+def _eps(st, a, d):
+    return 0.8 / math.sqrt(d)
+
+
+def _state(smc):
+    torch.cuda.synchronize()
+    return (smc.theta.cpu().numpy().copy(), smc.u.cpu().numpy().copy(), smc.logw.cpu().numpy().copy(),
+            smc.lhat.cpu().numpy().copy(), smc.sig2.cpu().numpy().copy())
+
+
+@pytest.mark.parametrize("precision", [W.FP64, W.MIXED], ids=["fp64", "mixed"])
+def test_batch_equals_single_context_runs(precision):
+    """Full runs: the batch against each member run alone, bit for bit. The
+    members span the narrow, lane-group and resident move kernels (one member
+    forced onto the streaming path), so the move takes several launches."""
+    B = _binding()
+    ws = W.batched_small(6, seed=1, precision=precision, d_values=[3, 9, 17, 36, 24, 9])
+    paths = [0, 0, B.MOVE_STREAMING, 0, 0, B.MOVE_STREAMING]
+    say("batch members", [(w.n, w.d, w.m) for w in ws])
+    centres = [_oracle_problem(w)[1] for w in ws]
+    singles = []
+    for w, tb, mp in zip(ws, centres, paths):
+        smc = _context(w, tb, mp)
+        logz, rec = smc.run(_eps, L=w.L, R=2)
+        singles.append((logz, [r["a"] for r in rec], _state(smc)))
+        smc.close()
+    members = [_context(w, tb, mp) for w, tb, mp in zip(ws, centres, paths)]
+    batch = B.SMCBatch(members)
+    launches = []
+    logzs, recs = batch.run(_eps, L=ws[0].L, R=2, callback=lambda b, a, act: launches.append(b.launches()))
+    say("move launches per stage", launches)
+    assert max(launches) >= 3
+    stages = [len(r) for r in recs]
+    say("stages per member", stages)
+    assert len(set(stages)) > 1                        # members finish at different stages
+    for k, (w, s) in enumerate(zip(ws, singles)):
+        logz1, temps1, st1 = s
+        assert [r["a"] for r in recs[k]] == temps1, k
+        assert logzs[k] == logz1, k
+        for got, ref in zip(_state(members[k]), st1):
+            np.testing.assert_array_equal(got, ref)
+    batch.close()
+    for m in members:
+        m.close()
+
+
+def test_batch_matches_oracle_runs():
+    """Full runs of a mixed batch against the oracle run of every member with
+    its dataset field: same stages and temperatures, evidence, particles and
+    subsample indices."""
+    B = _binding()
+    ws = W.batched_small(4, seed=2, precision=W.FP64, d_values=[2, 6, 35, 13])
+    say("batch members", [(w.n, w.d, w.m) for w in ws])
+    probs = [_oracle_problem(w) for w in ws]
+    members = [_context(w, tb) for w, (P, tb) in zip(ws, probs)]
+    batch = B.SMCBatch(members)
+    logzs, recs = batch.run(_eps, L=ws[0].L, R=2)
+    for k, (w, (P, tb)) in enumerate(zip(ws, probs)):
+        ref = oracle.run_smc(P, M=w.M, m=w.m, G=w.G, seed=w.seed, eps_fn=_eps, L=w.L, R=2, dataset=w.dataset)
+        temps = np.array([r["a"] for r in recs[k]])
+        say("member", k, "stages", len(temps), "logz", logzs[k], ref["logz"])
+        assert len(temps) == len(ref["temps"])
+        np.testing.assert_allclose(temps, ref["temps"], rtol=1e-8, atol=1e-10)
+        assert abs(logzs[k] - ref["logz"]) <= 1e-7 * abs(ref["logz"])
+        th, u, lw, _, _ = _state(members[k])
+        np.testing.assert_allclose(th, ref["theta"], rtol=1e-6, atol=1e-8)
+        np.testing.assert_array_equal(u, ref["u"])
+    batch.close()
+    for m in members:
+        m.close()
+
+
+def test_dataset_field_separates_streams():
+    """Two contexts on identical data and seed draw different particles when
+    their dataset fields differ, and the oracle's init with the same field
+    agrees with each."""
+    w = W.logistic_small(2000, 4, seed=81, M=32, m=60, G=4)
+    P, tb = _oracle_problem(w)
+    got = []
+    for ds in (0, 5):
+        w.dataset = ds
+        smc = _context(w, tb)
+        th, u, _, _, _ = _state(smc)
+        th0, u0, _ = oracle.init_particles(w.M, w.d, w.m, w.n, w.seed, w.prior_mean, w.prior_prec, dataset=ds)
+        np.testing.assert_array_equal(u, u0)
+        np.testing.assert_allclose(th, th0, rtol=1e-13, atol=1e-13)
+        got.append(u)
+        smc.close()
+    assert (got[0] != got[1]).mean() > 0.9
+
+
+def test_batch_errors():
+    B = _binding()
+    ws = W.batched_small(2, seed=3, precision=W.FP64, d_values=[3, 4])
+    members = [_context(w, _oracle_problem(w)[1]) for w in ws]
+    batch = B.SMCBatch(members)
+    with pytest.raises(B.SMCError):
+        batch.move(0.1, 4)                             # no tempered stage yet
+    with pytest.raises(B.SMCError):
+        batch.mass()
+    batch.temper()
+    with pytest.raises(B.SMCError):
+        batch.move(0.1, 4)                             # no mass matrix for this stage
+    batch.mass()
+    with pytest.raises(B.SMCError):
+        batch.move([0.1, -1.0], 4)                     # a non-positive step
+    batch.resample()
+    batch.move(0.1, 4)
+    batch.close()
+    L = B.lib()
+    assert L.smc_batch_workspace_size(0) == 0
+    import ctypes as C
+    h = C.c_void_p()
+    handles = (C.c_void_p * 2)(members[0]._h.value, members[0]._h.value)
+    ws_t = torch.empty(L.smc_batch_workspace_size(2) + 256, dtype=torch.uint8, device=DEV)
+    base = (ws_t.data_ptr() + 255) & ~255
+    assert L.smc_batch_create(handles, 2, C.c_void_p(base), L.smc_batch_workspace_size(2), C.byref(h)) != 0
+    handles = (C.c_void_p * 2)(members[0]._h.value, members[1]._h.value)
+    assert L.smc_batch_create(handles, 2, C.c_void_p(base), 64, C.byref(h)) != 0
+    for m in members:
+        m.close()

@@ -115,3 +115,63 @@ def test_normals_distribution():
     z = (theta - mu0) @ np.linalg.cholesky(Q0)  # whitened
     for c in range(d):
         assert stats.kstest(z[:, c], "norm").pvalue > 1e-4
+
+
+def test_dataset_field_of_every_stream():
+    """Batch members draw with their index in the counter's low 16 bits: the
+    initial indices and prior normals, the resampling offset and words, and
+    the move's block choice follow numpy's words at that counter."""
+    M, d, m, n, seed = 4, 3, 9, 5003, 123
+    for ds in (0, 1, 63, 65535):
+        theta, u, _ = oracle.init_particles(M, d, m, n, seed, np.zeros(d), np.eye(d), dataset=ds)
+        for i in range(M):
+            for j in range(m):
+                w = numpy_block(stream_counter(1, 0, 0, ds, i, j), [seed, 0])[j & 3]
+                assert u[i, j] == (w * n) >> 64
+        for i in range(M):
+            for k in range(d):
+                base = 2 * (k // 2)
+                wa = numpy_block(stream_counter(0, 0, 0, ds, i, base), [seed, 0])[base & 3]
+                wb = numpy_block(stream_counter(0, 0, 0, ds, i, base + 1), [seed, 0])[(base + 1) & 3]
+                r = math.sqrt(-2 * math.log(((wa >> 11) + 1) * 2.0 ** -53))
+                ang = 2 * math.pi * ((wb >> 11) * 2.0 ** -53)
+                want = r * (math.sin(ang) if k & 1 else math.cos(ang))
+                assert abs(theta[i, k] - want) <= 1e-14 * max(1.0, abs(want))
+                assert oracle.normal(seed, 0, 0, 0, i, k, dataset=ds) == theta[i, k]
+        off = numpy_block(stream_counter(2, 7, 0, ds, 0, 0), [seed, 0])[0] >> 32
+        assert oracle.resample_offset(seed, 7, ds) == off
+        lw = np.zeros(8)                               # equal weights: ancestor = floor(8 word / 2^64)
+        anc = oracle.resample_multinomial(lw, seed, 7, ds)
+        for k in range(8):
+            wk = numpy_block(stream_counter(2, 7, 0, ds, k, 1), [seed, 0])[1]
+            assert anc[k] == (wk * 8) >> 64
+    a = oracle.init_particles(M, d, m, n, seed, np.zeros(d), np.eye(d), dataset=0)[1]
+    b = oracle.init_particles(M, d, m, n, seed, np.zeros(d), np.eye(d), dataset=1)[1]
+    assert (a != b).mean() > 0.9
+
+
+def test_move_draws_use_the_dataset_field():
+    """The u-refresh of a move with dataset field 9 replaces block g (purpose 3)
+    by the indices of purpose 4, both at that field."""
+    from paper_1805_03317_amd import workloads as W
+    w = W.logistic_small(1500, 3, seed=91, M=24, m=40, G=4)
+    P = oracle.Problem(w.Xy(np.float64), w.d, w.family, w.prior_mean, w.prior_prec)
+    tb, _ = P.newton_mode()
+    P.set_cv_centre(tb)
+    ds, stage, mv = 9, 4, 1
+    th0, u0, _ = oracle.init_particles(w.M, w.d, w.m, w.n, w.seed, w.prior_mean, w.prior_prec, dataset=ds)
+    th0 = tb + 0.05 * (th0 - w.prior_mean)
+    _, Sig, Lc = oracle.moments(th0, np.full(w.M, -math.log(w.M)))
+    th1, u1, acc, _, _ = oracle.move(P, th0, u0, 0.5, 0.1, 3, w.seed, stage, mv, w.G, Sig, Lc, dataset=ds)
+    assert acc[:, 0].sum() > 0
+    for i in range(w.M):
+        g = (numpy_block(stream_counter(3, stage, mv, ds, i, 0), [w.seed, 0])[0] * w.G) >> 64
+        b0, b1 = g * w.m // w.G, (g + 1) * w.m // w.G
+        outside = np.r_[0:b0, b1:w.m]
+        np.testing.assert_array_equal(u1[i, outside], u0[i, outside])
+        if acc[i, 0]:
+            fresh = [(numpy_block(stream_counter(4, stage, mv, ds, i, j - b0), [w.seed, 0])[(j - b0) & 3] * w.n) >> 64
+                     for j in range(b0, b1)]
+            np.testing.assert_array_equal(u1[i, b0:b1], fresh)
+        else:
+            np.testing.assert_array_equal(u1[i], u0[i])
