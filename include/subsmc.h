@@ -127,9 +127,11 @@ smc_status smc_init(const smc_problem* pb, void* stream, smc_ctx* out);
 /*
  * Algorithm 2 steps a-c. Increments the stage, chooses the next exponent
  * a in (a_prev, 1] with ESS(a) = ess_frac * M (section 2.2, with the target
- * of smc_problem.ess_frac) by a safeguarded Newton iteration on log ESS
- * (resolution 1e-15 of 1 - a_prev; a = 1 when ESS(1) already meets it),
- * reweights logw with the annealed estimator
+ * of smc_problem.ess_frac): a = 1 when ESS(1) already meets it, else 60
+ * halvings of [a_prev, 1], each keeping the half whose lower end has
+ * ESS >= target, and a = the final lower end (the crossing this sequence of
+ * halvings selects where the ESS is not monotone in a). Reweights logw with
+ * the annealed estimator
  * (a - a_prev) l_hat - (a^2 - a_prev^2) sigma2_hat / 2 (normalised), and adds
  * the log evidence increment log sum_i W_i exp(...) (section 3.5).
  * Host outputs (any may be NULL). Synchronises.

@@ -81,7 +81,6 @@ __device__ __forceinline__ double block_max(double v, double* sh) {
 constexpr int kTemperThreads = 1024;
 constexpr int kTemperWaves = kTemperThreads / kWave;
 constexpr int kTemperPer = 8;        // particles per thread: M <= 8192
-constexpr int kTemperMaxIter = 100;  // root-finding iterations (each one ESS evaluation)
 
 struct TemperArgs {
   int M;
@@ -90,8 +89,9 @@ struct TemperArgs {
   const double* sig2;
   double* logw;     // in/out
   double* out;      // [a, dlogz, ess, status, evaluations]
-  const double* grid_ess;  // null: root search; else the ESS at grid_n grid points
+  const double* grid_ess;  // null: the exponent search's result; else the ESS at grid_n grid points
   int grid_n;
+  struct SearchSlot* search;  // two slots of the exponent search
 };
 
 // Grid of candidate exponents of the paper's grid rule (section 2.2):
@@ -215,78 +215,168 @@ __global__ void __launch_bounds__(kGridThreads) grid_ess_kernel(GridArgs A) {
   }
 }
 
-// Tempering exponent (section 2.2; Algorithm 2 step b): the root in
-// (a_prev, 1] of g(a) = log ESS(a) - log(ess_frac M). a = 1 when ESS(1)
-// meets the target. Otherwise a safeguarded Newton iteration on g, whose
-// derivative comes with the same sums: with x_i(a) = log W_i + nu_i(a) and
-// nu_i' = lhat_i - a sig2_i,
-//   g'(a) = 2 sum w nu' / sum w - 2 sum w^2 nu' / sum w^2.
-// The bracket [lo, hi] keeps g(lo) >= 0 > g(hi); a step that leaves it, or a
-// non-negative slope, is replaced by bisection. The first trial point treats
-// the log weights as Gaussian in a: g(a) ~ g(a_prev) - (a - a_prev)^2 V with
-// V the weighted variance of nu' at a_prev. The iteration stops when a step
-// or the bracket is below 1e-15 (1 - a_prev); a = lo (the largest point found
-// with ESS >= target), or hi if lo never moved.
-// Then the reweighting, normalisation and the evidence increment
+// --------------------------------------------------------------------------
+// Exponent search (section 2.2; Algorithm 2 step b): a in (a_prev, 1] with
+// ESS(a) = ess_frac M. a = 1 when ESS(1) meets the target; otherwise 60
+// halvings of [a_prev, 1], each keeping the half whose lower end has ESS at
+// least the target (the midpoint becomes lo when its ESS >= target, else hi),
+// and a = lo (hi if lo never moved). The ESS need not be monotone in a, so the
+// crossing is the one this sequence of halvings selects.
+//
+// The halvings are spread over the chip: a pass evaluates, one workgroup per
+// point, the ESS at the 2^K - 1 midpoints the next K halvings can visit (the
+// same 0.5 (lo + hi) values a one-by-one halving forms, in tree order: node n
+// has children 2n and 2n + 1), and the next pass first follows the path
+// through them. 60 halvings take 8 passes (7 of 8 levels, then 4); pass 0
+// also evaluates ESS(1). The state travels between passes through two
+// alternating slots in device memory, so the passes run back to back on the
+// stream without the host.
+// --------------------------------------------------------------------------
+
+constexpr int kBisectLevels = 60;                   // halvings of (a_prev, 1]
+constexpr int kPassLevels = 8;                      // halvings resolved per pass
+constexpr int kPassPoints = (1 << kPassLevels) - 1;
+constexpr int kSearchPasses = (kBisectLevels + kPassLevels - 1) / kPassLevels;
+constexpr int kSearchThreads = 256;
+
+__host__ __device__ inline int pass_levels(int pass) {
+  const int left = kBisectLevels - pass * kPassLevels;
+  return left < kPassLevels ? left : kPassLevels;
+}
+
+// workgroups of a pass: its trial points, and ESS(1) on pass 0
+__host__ __device__ inline int pass_groups(int pass) { return (1 << pass_levels(pass)) - 1 + (pass == 0 ? 1 : 0); }
+
+struct SearchSlot {
+  double lo, hi;                 // the bracket the pass split
+  double ess[kPassPoints + 1];   // ESS at its trial points in tree order; [kPassPoints]: ESS(1)
+  int levels;                    // halvings of the pass
+  int done;                      // ESS(1) met the target
+};
+
+// The trial point of node n (1-based, tree order) over [lo, hi]: the
+// midpoints along the path from the root, each formed as 0.5 (lo + hi).
+__device__ __forceinline__ double tree_point(double lo, double hi, int n) {
+  int top = 31 - __clz(n);
+  for (int b = top - 1; b >= 0; --b) {
+    const double mid = 0.5 * (lo + hi);
+    if ((n >> b) & 1) lo = mid;
+    else hi = mid;
+  }
+  return 0.5 * (lo + hi);
+}
+
+// Follow `levels` halvings through the ESS values of a pass.
+__device__ __forceinline__ void search_descend(const double* ess, int levels, double target, double& lo,
+                                               double& hi) {
+  int n = 1;
+  for (int k = 0; k < levels; ++k) {
+    const double mid = 0.5 * (lo + hi);
+    const bool up = ess[n - 1] >= target;
+    if (up) lo = mid;
+    else hi = mid;
+    n = 2 * n + (up ? 1 : 0);
+  }
+}
+
+// ESS(a) = (sum w)^2 / sum w^2 over the M particles, w_i = exp(x_i - max x),
+// x_i = log W_i + nu_i(a); 0 when every x_i is -inf. One workgroup of
+// kSearchThreads, sums in a fixed order.
+__device__ __forceinline__ double ess_block(const TemperArgs& A, double a, double* sh) {
+  const int t = threadIdx.x, w = t / kWave, l = t % kWave;
+  constexpr int NW = kSearchThreads / kWave;
+  double mx = -INFINITY;
+  for (int i = t; i < A.M; i += kSearchThreads)
+    mx = fmax(mx, A.logw[i] + incr_weight(a, A.a_prev, A.lhat[i], A.sig2[i]));
+  mx = xl::wave_allmax(mx);
+  if (l == 0) sh[w] = mx;
+  __syncthreads();
+  mx = sh[0];
+#pragma unroll
+  for (int q = 1; q < NW; ++q) mx = fmax(mx, sh[q]);
+  if (!isfinite(mx)) return 0.0;
+  double s1 = 0.0, s2 = 0.0;
+  for (int i = t; i < A.M; i += kSearchThreads) {
+    const double e = exp(A.logw[i] + incr_weight(a, A.a_prev, A.lhat[i], A.sig2[i]) - mx);
+    s1 += e;
+    s2 += e * e;
+  }
+  s1 = xl::wave_allsum(s1);
+  s2 = xl::wave_allsum(s2);
+  if (l == 0) {
+    sh[NW + w] = s1;
+    sh[2 * NW + w] = s2;
+  }
+  __syncthreads();
+  double t1 = 0.0, t2 = 0.0;
+#pragma unroll
+  for (int q = 0; q < NW; ++q) {
+    t1 += sh[NW + q];
+    t2 += sh[2 * NW + q];
+  }
+  return t1 * t1 / t2;
+}
+
+// Pass `pass`, workgroup j: follow the previous pass's halvings, then the ESS
+// at trial point j of this pass (j = 2^K - 1 on pass 0: a = 1).
+__device__ __forceinline__ void search_pass_body(const TemperArgs& A, int pass, int j) {
+  __shared__ double sh[3 * (kSearchThreads / kWave)];
+  __shared__ double br[2];
+  __shared__ int dn;
+  const int t = threadIdx.x;
+  const int K = pass_levels(pass);
+  const double target = A.ess_frac * (double)A.M;
+  SearchSlot* cur = A.search + (pass & 1);
+  if (t == 0) {
+    double lo = A.a_prev, hi = 1.0;
+    int done = 0;
+    if (pass > 0) {
+      const SearchSlot* prev = A.search + ((pass - 1) & 1);
+      lo = prev->lo;
+      hi = prev->hi;
+      done = pass == 1 ? (prev->ess[kPassPoints] >= target ? 1 : 0) : prev->done;
+      if (!done) search_descend(prev->ess, prev->levels, target, lo, hi);
+    }
+    br[0] = lo;
+    br[1] = hi;
+    dn = done;
+    if (j == 0) {
+      cur->lo = lo;
+      cur->hi = hi;
+      cur->levels = K;
+      cur->done = done;
+    }
+  }
+  __syncthreads();
+  if (dn) return;
+  const int np = (1 << K) - 1;
+  const double a = j < np ? tree_point(br[0], br[1], j + 1) : 1.0;
+  const double e = ess_block(A, a, sh);
+  if (t == 0) cur->ess[j < np ? j : kPassPoints] = e;
+}
+
+// Then the exponent (the search's result, or the paper's grid rule), the
+// reweighting, normalisation and the evidence increment
 // log sum_i W_i exp(nu_i) (sections 3.3, 3.5; Algorithm 2 step c).
-__device__ __forceinline__ void temper_body(const TemperArgs& A) {
+template <int NQ>
+__device__ __forceinline__ void temper_run(const TemperArgs& A) {
   __shared__ double sh[4 * kTemperSlice];
   const int t = threadIdx.x;
-  double lw[kTemperPer], lh[kTemperPer], s2[kTemperPer];
+  double lw[NQ], lh[NQ], s2[NQ];
 #pragma unroll
-  for (int q = 0; q < kTemperPer; ++q) {
+  for (int q = 0; q < NQ; ++q) {
     const int i = t + q * kTemperThreads;
     const bool ok = i < A.M;
     lw[q] = ok ? A.logw[i] : -INFINITY;
     lh[q] = ok ? A.lhat[i] : 0.0;
     s2[q] = ok ? A.sig2[i] : 0.0;
   }
-  const double log_target = log(A.ess_frac * (double)A.M);
-  int buf = 0, evals = 0;
-  // g(a), g'(a) and (with var) the weighted variance of nu' at a
-  auto eval = [&](double a, double& g, double& dg, double* var) {
-    double mx = -INFINITY;
-#pragma unroll
-    for (int q = 0; q < kTemperPer; ++q) mx = fmax(mx, lw[q] + incr_weight(a, A.a_prev, lh[q], s2[q]));
-    mx = block_max_1(mx, sh, buf);
-    buf = (buf + 1) & 3;
-    double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    if (isfinite(mx)) {
-#pragma unroll
-      for (int q = 0; q < kTemperPer; ++q) {
-        const double x = lw[q] + incr_weight(a, A.a_prev, lh[q], s2[q]);
-        const double w = exp(x - mx);
-        const double nd = (w > 0.0) ? lh[q] - a * s2[q] : 0.0;
-        v[0] += w;
-        v[1] += w * w;
-        v[2] += w * nd;
-        v[3] += w * w * nd;
-        v[4] += w * nd * nd;
-      }
-    }
-    if (var) block_sum_n<5>(v, sh, buf);
-    else block_sum_n<4>(v, sh, buf);
-    buf = (buf + 1) & 3;
-    ++evals;
-    if (!isfinite(mx)) {
-      g = -INFINITY;
-      dg = 0.0;
-      if (var) *var = 0.0;
-      return;
-    }
-    g = 2.0 * log(v[0]) - log(v[1]) - log_target;
-    dg = 2.0 * v[2] / v[0] - 2.0 * v[3] / v[1];
-    if (var) {
-      const double mu = v[2] / v[0];
-      *var = v[4] / v[0] - mu * mu;
-    }
-  };
+  const double target = A.ess_frac * (double)A.M;
+  int evals = 0;
   double a = 1.0;
-  double ghi = 0.0, dghi;
   if (A.grid_ess) {
     // the paper's grid rule: the grid point above a_prev whose ESS is closest
     // to the target, the first on ties
-    const double target = A.ess_frac * (double)A.M;
     int best = 0;
     double bestd = INFINITY;
     for (int j = 0; j < A.grid_n; ++j) {
@@ -297,49 +387,23 @@ __device__ __forceinline__ void temper_body(const TemperArgs& A) {
       }
     }
     a = grid_exponent(A.a_prev, best);
+    evals = A.grid_n;
   } else {
-    eval(1.0, ghi, dghi, nullptr);
-  }
-  if (!A.grid_ess && !(ghi >= 0.0)) {
-    double lo = A.a_prev, hi = 1.0;
-    double glo, dglo, var;
-    eval(lo, glo, dglo, &var);
-    const double tol = 1e-15 * (1.0 - A.a_prev);
-    if (glo >= 0.0) {
-      double c = (var > 0.0 && isfinite(var)) ? lo + sqrt(glo / var) : 0.5 * (lo + hi);
-      for (int it = 0; it < kTemperMaxIter && (hi - lo) > tol; ++it) {
-        if (!(c > lo && c < hi)) c = 0.5 * (lo + hi);
-        if (!(c > lo && c < hi)) break;  // no representable point inside the bracket
-        double gc, dgc;
-        eval(c, gc, dgc, nullptr);
-        if (gc >= 0.0) lo = c; else hi = c;
-        // Newton from c, or bisection when the step is unusable
-        double nxt = (dgc < 0.0 && isfinite(gc)) ? c - gc / dgc : 0.5 * (lo + hi);
-        if (!(nxt > lo && nxt < hi)) nxt = 0.5 * (lo + hi);
-        if (fabs(nxt - c) <= tol) {
-          // converged: settle on the side of the root with ESS >= target
-          if (gc < 0.0 && nxt > lo && nxt < hi) {
-            double gn, dgn;
-            eval(nxt, gn, dgn, nullptr);
-            if (gn >= 0.0) lo = nxt; else hi = nxt;
-          }
-          break;
-        }
-        c = nxt;
-      }
-    } else {
-      // ESS already below the target at a_prev: the smallest step a 60-step
-      // bisection of (a_prev, 1] can take
-      hi = A.a_prev + (1.0 - A.a_prev) * 0x1.0p-60;
+    const SearchSlot* last = A.search + ((kSearchPasses - 1) & 1);
+    evals = 1;
+    if (!last->done) {
+      double lo = last->lo, hi = last->hi;
+      search_descend(last->ess, last->levels, target, lo, hi);
+      a = (lo > A.a_prev) ? lo : hi;
+      evals += kBisectLevels;
     }
-    a = (lo > A.a_prev) ? lo : hi;
   }
   __syncthreads();
   // reweight, normalise and the evidence increment
-  double nw[kTemperPer];
+  double nw[NQ];
   double mo = -INFINITY, mn = -INFINITY;
 #pragma unroll
-  for (int q = 0; q < kTemperPer; ++q) {
+  for (int q = 0; q < NQ; ++q) {
     const int i = t + q * kTemperThreads;
     nw[q] = i < A.M ? lw[q] + incr_weight(a, A.a_prev, lh[q], s2[q]) : -INFINITY;
     mo = fmax(mo, lw[q]);
@@ -349,7 +413,7 @@ __device__ __forceinline__ void temper_body(const TemperArgs& A) {
   mn = block_max_1(mn, sh, 1);
   double so = 0.0, sn = 0.0, sn2 = 0.0;
 #pragma unroll
-  for (int q = 0; q < kTemperPer; ++q) {
+  for (int q = 0; q < NQ; ++q) {
     so += exp(lw[q] - mo);
     const double e = exp(nw[q] - mn);
     sn += e;
@@ -362,7 +426,7 @@ __device__ __forceinline__ void temper_body(const TemperArgs& A) {
   const double lse_new = mn + log(sn);
   const bool ok = isfinite(lse_new);
 #pragma unroll
-  for (int q = 0; q < kTemperPer; ++q) {
+  for (int q = 0; q < NQ; ++q) {
     const int i = t + q * kTemperThreads;
     if (i < A.M && ok) A.logw[i] = nw[q] - lse_new;
   }
@@ -373,6 +437,14 @@ __device__ __forceinline__ void temper_body(const TemperArgs& A) {
     A.out[3] = ok ? 0.0 : 1.0;
     A.out[4] = (double)evals;
   }
+}
+
+// particles per thread: the smallest power of two that covers M
+__device__ __forceinline__ void temper_body(const TemperArgs& A) {
+  if (A.M <= kTemperThreads) temper_run<1>(A);
+  else if (A.M <= 2 * kTemperThreads) temper_run<2>(A);
+  else if (A.M <= 4 * kTemperThreads) temper_run<4>(A);
+  else temper_run<kTemperPer>(A);
 }
 
 // --------------------------------------------------------------------------
@@ -976,6 +1048,18 @@ __global__ void __launch_bounds__(256) cv_const_reduce_kernel(const double* part
 // --------------------------------------------------------------------------
 // Entry points: one dataset per launch, and the batched forms.
 // --------------------------------------------------------------------------
+
+__global__ void __launch_bounds__(kSearchThreads) search_pass_kernel(TemperArgs A, int pass) {
+  search_pass_body(A, pass, blockIdx.x);
+}
+
+// members own pass_groups(pass) consecutive workgroups each
+__global__ void __launch_bounds__(kSearchThreads) search_pass_kernel_batch(Batch<TemperArgs> B, int pass) {
+  const int per = pass_groups(pass);
+  const int k = blockIdx.x / per;
+  const TemperArgs A = B.args[k];
+  search_pass_body(A, pass, blockIdx.x - k * per);
+}
 
 __global__ void __launch_bounds__(kTemperThreads) temper_kernel(TemperArgs A) { temper_body(A); }
 

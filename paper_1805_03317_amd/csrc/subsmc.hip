@@ -62,7 +62,7 @@ int packed_ld(int d, bool fp32) {
 // Workspace regions, in carve order.
 struct Layout {
   size_t Xp, theta_bar, cvA, cvB, cvC, mu0, Q0, Qw, L0, L0inv, Sigma, Lchol, Linv, mean, status,
-      tout, grid, aconst, scratch_theta, grad_l, grad_s, anc, th2, u2, lh2, sg2, gl2, gs2, partials, mpartials, total;
+      tout, grid, search, aconst, scratch_theta, grad_l, grad_s, anc, th2, u2, lh2, sg2, gl2, gs2, partials, mpartials, total;
   int ld;
   int cv_blocks, cv_rows;
   int mom_blocks;
@@ -98,6 +98,7 @@ bool compute_layout(const smc_problem* pb, Layout& L) {
   L.status = take(4 * 8);
   L.tout = take(8 * 8);
   L.grid = take((size_t)kGridMax * 8);
+  L.search = take(2 * sizeof(SearchSlot));
   L.aconst = take(8);
   L.scratch_theta = take(d * 8);
   L.grad_l = take(M * d * 8);
@@ -493,7 +494,18 @@ TemperArgs temper_args(smc_ctx c, double ess_frac, double* out) {
   t.out = out;
   t.grid_ess = nullptr;
   t.grid_n = 0;
+  t.search = c->at<SearchSlot>(c->lay.search);
   return t;
+}
+
+// the passes of the exponent search (they end in the context's search slots)
+hipError_t launch_search(const TemperArgs& t, hipStream_t s) {
+  for (int pass = 0; pass < kSearchPasses; ++pass) {
+    hipLaunchKernelGGL(search_pass_kernel, dim3(pass_groups(pass)), dim3(kSearchThreads), 0, s, t, pass);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 // state after a successful exponent search with outputs o = [a, dlogz, ess, ...]
@@ -721,6 +733,8 @@ static smc_status temper_impl(smc_ctx c, int grid_points, double ess_frac, doubl
     t.grid_n = grid_points;
     if (ess_grid_out)
       HIP_TRY(c, hipMemcpyAsync(ess_grid_out, g.ess, (size_t)grid_points * 8, hipMemcpyDeviceToHost, c->stream));
+  } else {
+    HIP_TRY(c, launch_search(t, c->stream));
   }
   hipLaunchKernelGGL(temper_kernel, dim3(1), dim3(kTemperThreads), 0, c->stream, t);
   LAUNCH_CHECK(c);
@@ -1088,6 +1102,11 @@ smc_status smc_batch_temper(smc_batch b, double* a_out, double* dlogz_out, doubl
   bt.args = T.at<TemperArgs>(off);
   bt.first = nullptr;
   bt.count = na;
+  for (int pass = 0; pass < kSearchPasses; ++pass) {
+    hipLaunchKernelGGL(search_pass_kernel_batch, dim3(na * pass_groups(pass)), dim3(kSearchThreads), 0, b->stream,
+                       bt, pass);
+    BATCH_TRY(b, hipGetLastError());
+  }
   hipLaunchKernelGGL(temper_kernel_batch, dim3(na), dim3(kTemperThreads), 0, b->stream, bt);
   BATCH_TRY(b, hipGetLastError());
   if ((st = batch_fetch(b)) != SMC_OK) return st;

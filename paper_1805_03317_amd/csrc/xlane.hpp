@@ -117,6 +117,45 @@ __device__ __forceinline__ T wave_allsum(T x) {
   return pair_all<5>(x);
 }
 
+// max(x of this lane, x of its partner at step S).
+template <int S>
+__device__ __forceinline__ double pair_max(double x) {
+  if constexpr (S < 2) {
+    uint32_t a0, b0, a1, b1;
+    swap_words<S>(lo_word(x), lo_word(x), a0, b0);
+    swap_words<S>(hi_word(x), hi_word(x), a1, b1);
+    return fmax(make_double(a0, a1), make_double(b0, b1));
+  } else {
+    return fmax(x, make_double(dpp_word<S>(lo_word(x)), dpp_word<S>(hi_word(x))));
+  }
+}
+
+// Maximum over the 64 lanes, the same value in every lane.
+__device__ __forceinline__ double wave_allmax(double x) {
+  x = pair_max<0>(x);
+  x = pair_max<1>(x);
+  x = pair_max<2>(x);
+  x = pair_max<3>(x);
+  x = pair_max<4>(x);
+  return pair_max<5>(x);
+}
+
+// Sum and maximum over each row of 16 lanes (steps 2..5), the same value in
+// every lane of the row.
+__device__ __forceinline__ double row_allsum(double x) {
+  x = pair_all<2>(x);
+  x = pair_all<3>(x);
+  x = pair_all<4>(x);
+  return pair_all<5>(x);
+}
+
+__device__ __forceinline__ double row_allmax(double x) {
+  x = pair_max<2>(x);
+  x = pair_max<3>(x);
+  x = pair_max<4>(x);
+  return pair_max<5>(x);
+}
+
 // Reduce-scatter of N values held by every lane: afterwards v[0] of a lane is
 // the wavefront total of one value (or zero padding). The value a lane ends
 // with depends only on its role bits: the lane keeps the upper half of its

@@ -198,6 +198,37 @@ def test_temper_parity(M):
     smc.close()
 
 
+@pytest.mark.parametrize("M", [48, 2048, 5000])
+def test_temper_nonmonotone_ess(M):
+    """ESS(a) crosses the target three times (a small group with a large
+    l_hat and a large sigma2 takes the weight first and loses it again); the
+    exponent is the crossing the oracle's sequence of halvings selects."""
+    w = W.logistic_small(500, 2, seed=42, M=M, m=16, G=2)
+    P, smc = make_pair(w)
+    g = np.random.default_rng(7 + M)
+    A = g.random(M) < 0.1
+    lhat = np.where(A, -2000.0 + 5000.0, -2000.0) + np.where(A, 1.0, 3.0) * g.standard_normal(M)
+    sig2 = np.where(A, 2e5, 0.0) + np.abs(g.standard_normal(M))
+    logw = np.full(M, -math.log(M))
+    a_prev = 0.0
+    ess = [math.exp(2 * np.logaddexp.reduce(logw + x) - np.logaddexp.reduce(2 * (logw + x)))
+           for x in [(a - a_prev) * (lhat - 0.5 * (a + a_prev) * sig2) for a in np.linspace(1e-5, 1, 4000)]]
+    crossings = np.sum(np.diff(np.sign(np.array(ess) - 0.5 * M)) != 0)
+    say("temper nonmonotone M", M, "crossings", crossings)
+    assert crossings >= 3
+    smc.lhat.copy_(torch.tensor(lhat))
+    smc.sig2.copy_(torch.tensor(sig2))
+    smc.logw.copy_(torch.tensor(logw))
+    smc.set_stage(1, 0, a_prev, 0.0)
+    a, dz, e = smc.temper()
+    a0, dz0, e0, lw0 = oracle.temper(lhat, sig2, logw, a_prev, 0.5)
+    say("a", a, a0)
+    assert abs(a - a0) <= 1e-12 * a0
+    assert abs(dz - dz0) <= 1e-9 * max(1.0, abs(dz0))
+    assert abs(e - e0) <= 1e-9 * M
+    smc.close()
+
+
 def test_mass_parity():
     w = W.logistic_small(500, 6, seed=42, M=700, m=16, G=2)
     P, smc = make_pair(w)
