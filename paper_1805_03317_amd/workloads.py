@@ -195,34 +195,40 @@ def student_t(n=500_000, d=50, M=2048, m=1250, L=15):
                     np.eye(d) / 10.0, M=M, m=m, G=100, L=L, seed=2006, theta_true=theta)
 
 
+def _config3_draw(b):
+    g = _gen(1300 + b, 0)
+    n = int(round(math.exp(g.uniform(math.log(1e4), math.log(2e6)))))
+    d = int(g.integers(5, 51))
+    return n, d, g
+
+
 def config3_sizes(count=64):
-    """(n_k, d_k) of the batched configuration: n log-uniform in [1e4, 2e6], d uniform in {5..50}."""
-    n = np.exp(_gen(1003, 0).uniform(math.log(1e4), math.log(2e6), count)).astype(np.int64)
-    d = _gen(1003, 1).integers(5, 51, count)
-    return n, d
+    """(n_b, d_b) of the batched configuration: n log-uniform in [1e4, 2e6], d uniform in {5..50}."""
+    nd = [_config3_draw(b)[:2] for b in range(count)]
+    return np.array([x[0] for x in nd], dtype=np.int64), np.array([x[1] for x in nd], dtype=np.int64)
 
 
-def config3_member(k, count=64, precision=MIXED, M=1024):
-    """Member k of the batched configuration: logistic regression with N(0,1) covariates,
-    theta_true ~ N(0, I), prior N(0, 10 I), P = 1024, m = 1% of n (at least 200), L = 10.
-    Rows of member k come from stream 16 + 4096 k + 1 + chunk of key 1003 (theta_true: stream
-    16 + 4096 k); every member uses SMC seed 2003 with its index k as the dataset counter field."""
-    n_all, d_all = config3_sizes(count)
-    n, d = int(n_all[k]), int(d_all[k])
-    key, base = 1003, 16 + 4096 * k
-    theta = _gen(key, base).standard_normal(d)
+def config3_member(b, count=64, precision=MIXED, M=1024):
+    """Dataset b of the batched configuration: logistic regression, x = [1, N(0,1)^(d-1)],
+    theta_true ~ N(0, I), prior N(0, 10 I), P = 1024, m = max(200, round(0.01 n)), G = 100, L = 10.
+    Dataset b draws n, d and theta_true from stream 0 of Philox key 1300 + b and row chunk c
+    from stream 1 + c; every dataset uses SMC seed 2003 with b as the dataset counter field."""
+    n, d, g0 = _config3_draw(b)
+    key = 1300 + b
+    theta = g0.standard_normal(d)
     X = np.empty((n, d))
     y = np.empty(n)
     for c0 in range(0, n, CHUNK):
         c1 = min(n, c0 + CHUNK)
-        g = _gen(key, base + 1 + c0 // CHUNK)
-        X[c0:c1] = g.standard_normal((c1 - c0, d))
+        g = _gen(key, 1 + c0 // CHUNK)
+        X[c0:c1, 0] = 1.0
+        X[c0:c1, 1:] = g.standard_normal((c1 - c0, d - 1))
         p = 1.0 / (1.0 + np.exp(-(X[c0:c1] @ theta)))
         y[c0:c1] = (g.random(c1 - c0) < p).astype(np.float64)
     X, y = _finish(X, y, precision)
     m = max(200, int(round(0.01 * n)))
-    return Workload(f"batch{count}_k{k}_logistic_n{n}_d{d}", LOGISTIC, precision, n, d, X, y, np.zeros(d),
-                    np.eye(d) / 10.0, M=M, m=m, G=100, L=10, seed=2003, theta_true=theta, dataset=k)
+    return Workload(f"batch{count}_b{b}_logistic_n{n}_d{d}", LOGISTIC, precision, n, d, X, y, np.zeros(d),
+                    np.eye(d) / 10.0, M=M, m=m, G=100, L=10, seed=2003, theta_true=theta, dataset=b)
 
 
 CONFIGS = {1: config1, 2: config2, 4: config4, 5: config5}
