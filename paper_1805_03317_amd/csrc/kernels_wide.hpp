@@ -2,7 +2,8 @@
 // 32 < d <= 128. A group of G lanes (G = 4 or 8) shares one packed row, each
 // lane holding a contiguous chunk of CH elements of it, so a wavefront streams
 // 64/G rows per iteration with 16-byte loads. Parameter component c lives in
-// lane c % 64, slot c / 64 (NC = 2 slots per lane). Vectors that every lane
+// lane c % 64, slot c / 64 (NC slots per lane: 1 for 4-lane rows, 2 for
+// 8-lane rows). Vectors that every lane
 // needs at arbitrary positions (delta, momentum, theta) are broadcast through
 // LDS. Everything else (remainders, fixed-order reductions, RNG streams, the
 // structure of Algorithm 1) is as in the narrow kernels.
@@ -11,11 +12,15 @@
 
 namespace subsmc {
 
-constexpr int kWideNC = 2;  // parameter components per lane (d <= 128)
+// parameter components per lane: one for 4-lane rows (d <= 60), two for
+// 8-lane rows (d <= 128)
+template <int G>
+constexpr int wide_nc() { return G == 4 ? 1 : 2; }
 
+template <int NC>
 struct PassResultW {
   double lhat, sig2, dhat;
-  double gl[kWideNC], gs[kWideNC];
+  double gl[NC], gs[NC];
 };
 
 template <typename Real, int CH>
@@ -44,7 +49,7 @@ __device__ __forceinline__ void load_chunk(const Real* __restrict__ p, Real (&x)
 // elements of delta aligned with its chunk of the row (zero at the header and
 // padding positions).
 template <typename Real, int G, int CH, int FAM, bool BLK>
-__device__ __forceinline__ PassResultW estimator_pass_wide(const Prob& P, const int32_t* __restrict__ urow,
+__device__ __forceinline__ PassResultW<wide_nc<G>()> estimator_pass_wide(const Prob& P, const int32_t* __restrict__ urow,
                                                            int b0, int b1, const int32_t* blk, Real* red,
                                                            const double* vec /* LDS: delta, d values */,
                                                            int lane) {
@@ -57,7 +62,6 @@ __device__ __forceinline__ PassResultW estimator_pass_wide(const Prob& P, const 
   constexpr int kRows = kWave / G;  // rows per wave iteration
   const int q = lane % G;           // chunk index within the row
   const int grp = lane / G;         // row group
-  const int src0 = lane - q;        // lane holding the row header
 
   Real dl[CH];
 #pragma unroll
@@ -79,10 +83,9 @@ __device__ __forceinline__ PassResultW estimator_pass_wide(const Prob& P, const 
     Real part = Real(0);
 #pragma unroll
     for (int k = 0; k < CH; ++k) part += x[k] * dl[k];
-#pragma unroll
-    for (int o = 1; o < G; o <<= 1) part += __shfl_xor(part, o, kWave);
-    const Real eb = __shfl(x[0], src0, kWave);
-    const Real aux = __shfl(x[1], src0, kWave);
+    part = xl::group_sum<G>(part);
+    const Real eb = xl::group_lead<G>(x[0], lane);
+    const Real aux = xl::group_lead<G>(x[1], lane);
     cv_remainder<Real, FAM>(P.cv_order, eb, aux, part, inv_s2, dd, dp);
   };
 
@@ -102,47 +105,152 @@ __device__ __forceinline__ PassResultW estimator_pass_wide(const Prob& P, const 
 #pragma unroll
   for (int k = 0; k < CH; ++k) { S1[k] = Real(0); T1[k] = Real(0); }
 
-  int j = grp;
-  int32_t k_cur = j < m ? index_of(j) : 0;
-  int32_t k_nxt = j + kRows < m ? index_of(j + kRows) : 0;
-  Real x_nxt[CH];
-  if (j < m) load_chunk<Real, CH>(X + (int64_t)((uint32_t)k_cur < n ? k_cur : 0) * ld + q * CH, x_nxt);
-  // all lanes of a group share j, so groups exit together; the shuffles in
-  // eval_row only read lanes of the same group
-  for (; j < m; j += kRows) {
-    Real x[CH];
+  const int nit = (m + kRows - 1) / kRows;  // row iterations t (rows grp + kRows t)
+  auto index_at = [&](int t) -> int32_t {
+    const int jj = grp + kRows * t;
+    return jj < m ? index_of(jj) : 0;
+  };
+  auto load_row = [&](int32_t k, Real (&x)[CH]) {
+    load_chunk<Real, CH>(X + (int64_t)((uint32_t)k < n ? k : 0) * ld + q * CH, x);
+  };
+  // Iterations past the group's last row read row 0 and add nothing; all
+  // groups run the same number of steps. Row indices are loaded a step ahead
+  // of their rows, so a row load never waits behind the load of its own
+  // index, and every wait is for the oldest rows in flight.
+  if constexpr (sizeof(Real) == 4) {
+    // PT = 4 iterations per step, two steps of rows in flight (buffers xa, xb).
+    // Each group forms the PT dot products of a step; lane q then evaluates
+    // the remainder of iteration q % PT only (one remainder per lane, not one
+    // per row and lane), and the PT pairs (d, d') go back to every lane of the
+    // group by quad broadcasts for the accumulation.
+    constexpr int PT = 4;
+    static_assert(PT <= 4 && PT <= G, "one quad holds the step's remainders");
+    const int nsteps = (nit + PT - 1) / PT;
+    const int mine = q % PT;
+    Real xa[PT][CH], xb[PT][CH];
+    int32_t ka[PT], kb[PT], kf[PT];
 #pragma unroll
-    for (int k = 0; k < CH; ++k) x[k] = x_nxt[k];
-    const bool bad = (uint32_t)k_cur >= n;
-    if (j + kRows < m) load_chunk<Real, CH>(X + (int64_t)((uint32_t)k_nxt < n ? k_nxt : 0) * ld + q * CH, x_nxt);
-    k_cur = k_nxt;
-    k_nxt = j + 2 * kRows < m ? index_of(j + 2 * kRows) : 0;
-    Real dd, dp;
-    eval_row(x, dd, dp);
-    if (bad) dd = dp = Real(__builtin_nan(""));
-    const double e = (double)dd - shift;
-    if (q == 0) {
-      se += e;
-      se2 += e * e;
+    for (int s = 0; s < PT; ++s) ka[s] = index_at(s);
+#pragma unroll
+    for (int s = 0; s < PT; ++s) load_row(ka[s], xa[s]);
+#pragma unroll
+    for (int s = 0; s < PT; ++s) kb[s] = index_at(PT + s);
+#pragma unroll
+    for (int s = 0; s < PT; ++s) load_row(kb[s], xb[s]);
+#pragma unroll
+    for (int s = 0; s < PT; ++s) kf[s] = index_at(2 * PT + s);
+    // one step on buffer x (rows of step `step`, indices kx); refills x with
+    // the rows of step + 2
+    auto step_on = [&](Real (&x)[PT][CH], int32_t (&kx)[PT], int step) {
+      int32_t kg[PT];
+#pragma unroll
+      for (int s = 0; s < PT; ++s) kg[s] = index_at(PT * (step + 3) + s);
+      Real Dm = Real(0), ebm = Real(0), auxm = Real(0);
+      int32_t km = 0;
+#pragma unroll
+      for (int s = 0; s < PT; ++s) {
+        Real part = Real(0);
+#pragma unroll
+        for (int k = 0; k < CH; ++k) part += x[s][k] * dl[k];
+        part = xl::group_sum<G>(part);
+        const Real eb = xl::group_lead<G>(x[s][0], lane);
+        const Real aux = xl::group_lead<G>(x[s][1], lane);
+        Dm = (mine == s) ? part : Dm;
+        ebm = (mine == s) ? eb : ebm;
+        auxm = (mine == s) ? aux : auxm;
+        km = (mine == s) ? kx[s] : km;
+      }
+      Real dd, dp;
+      cv_remainder<Real, FAM>(P.cv_order, ebm, auxm, Dm, inv_s2, dd, dp);
+      const bool valid = grp + kRows * (PT * step + mine) < m;
+      if ((uint32_t)km >= n) dd = dp = Real(__builtin_nan(""));
+      if (!valid) dp = Real(0);
+      const double e = valid ? (double)dd - shift : 0.0;
+      if (q < PT) {
+        se += e;
+        se2 += e * e;
+      }
+      const Real edp = (Real)e * dp;
+#pragma unroll
+      for (int s = 0; s < PT; ++s) {
+        // (s is a constant once the loop is unrolled)
+        Real dps, edps;
+        switch (s) {
+          case 0: dps = xl::quad_pick<0>(dp); edps = xl::quad_pick<0>(edp); break;
+          case 1: dps = xl::quad_pick<1>(dp); edps = xl::quad_pick<1>(edp); break;
+          case 2: dps = xl::quad_pick<2>(dp); edps = xl::quad_pick<2>(edp); break;
+          default: dps = xl::quad_pick<3>(dp); edps = xl::quad_pick<3>(edp); break;
+        }
+#pragma unroll
+        for (int k = 0; k < CH; ++k) {
+          S1[k] += dps * x[s][k];
+          T1[k] += edps * x[s][k];
+        }
+        load_row(kf[s], x[s]);
+        kx[s] = kf[s];
+      }
+#pragma unroll
+      for (int s = 0; s < PT; ++s) kf[s] = kg[s];
+    };
+    for (int step = 0; step < nsteps; step += 2) {
+      step_on(xa, ka, step);
+      if (step + 1 < nsteps) step_on(xb, kb, step + 1);
     }
-    const Real edp = (Real)e * dp;
+  } else {
+    // PD iterations per step, their chunks in xb, each refilled with the next
+    // step's row as soon as it has been used.
+    constexpr int PD = 2;
+    const int nsteps = (nit + PD - 1) / PD;
+    Real xb[PD][CH];
+    int32_t kc[PD], kn[PD];
 #pragma unroll
-    for (int k = 0; k < CH; ++k) {
-      S1[k] += dp * x[k];
-      T1[k] += edp * x[k];
+    for (int s = 0; s < PD; ++s) kc[s] = index_at(s);
+#pragma unroll
+    for (int s = 0; s < PD; ++s) load_row(kc[s], xb[s]);
+#pragma unroll
+    for (int s = 0; s < PD; ++s) kn[s] = index_at(PD + s);
+    for (int step = 0; step < nsteps; ++step) {
+      int32_t kf[PD];
+#pragma unroll
+      for (int s = 0; s < PD; ++s) kf[s] = index_at(PD * (step + 2) + s);
+#pragma unroll
+      for (int s = 0; s < PD; ++s) {
+        const bool valid = grp + kRows * (PD * step + s) < m;
+        const bool bad = (uint32_t)kc[s] >= n;
+        Real dd, dp;
+        eval_row(xb[s], dd, dp);
+        if (bad) dd = dp = Real(__builtin_nan(""));
+        if (!valid) dp = Real(0);
+        const double e = valid ? (double)dd - shift : 0.0;
+        if (q == 0) {
+          se += e;
+          se2 += e * e;
+        }
+        const Real edp = (Real)e * dp;
+#pragma unroll
+        for (int k = 0; k < CH; ++k) {
+          S1[k] += dp * xb[s][k];
+          T1[k] += edp * xb[s][k];
+        }
+        load_row(kn[s], xb[s]);
+        kc[s] = kn[s];
+      }
+#pragma unroll
+      for (int s = 0; s < PD; ++s) kn[s] = kf[s];
     }
   }
 
   se = wave_sum(se);
   se2 = wave_sum(se2);
   // column sums: position p = c + header lives in chunk p / CH, element p % CH
-  auto column = [&](const Real (&v)[CH], double (&out)[kWideNC]) {
+  constexpr int NC = wide_nc<G>();
+  auto column = [&](const Real (&v)[CH], double (&out)[NC]) {
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < CH; ++k) red[lane * CH + k] = v[k];
     __syncthreads();
 #pragma unroll
-    for (int s = 0; s < kWideNC; ++s) {
+    for (int s = 0; s < NC; ++s) {
       const int c = lane + kWave * s;
       double acc = 0.0;
       if (c < d) {
@@ -153,7 +261,7 @@ __device__ __forceinline__ PassResultW estimator_pass_wide(const Prob& P, const 
       out[s] = acc;
     }
   };
-  double s1[kWideNC], t1[kWideNC];
+  double s1[NC], t1[NC];
   column(S1, s1);
   column(T1, t1);
 
@@ -162,12 +270,12 @@ __device__ __forceinline__ PassResultW estimator_pass_wide(const Prob& P, const 
   const double dsum = se + md * shift;
   const double dbar_minus_shift = se / md;
   const double m2 = se2 - se * dbar_minus_shift;
-  PassResultW out;
+  PassResultW<NC> out;
   out.dhat = nm * dsum;
   out.sig2 = nm * nm * (m2 < 0.0 ? 0.0 : m2);
   double qpart = 0.0;
 #pragma unroll
-  for (int s = 0; s < kWideNC; ++s) {
+  for (int s = 0; s < NC; ++s) {
     const int c = lane + kWave * s;
     double cdel = 0.0, bl = 0.0, dc = 0.0;
     if (c < d) {
@@ -184,10 +292,11 @@ __device__ __forceinline__ PassResultW estimator_pass_wide(const Prob& P, const 
 }
 
 // vec <- x (component slots of every lane), with the fences around it
-__device__ __forceinline__ void to_lds(double* vec, const double (&x)[kWideNC], int lane, int d) {
+template <int NC>
+__device__ __forceinline__ void to_lds(double* vec, const double (&x)[NC], int lane, int d) {
   __syncthreads();
 #pragma unroll
-  for (int s = 0; s < kWideNC; ++s) {
+  for (int s = 0; s < NC; ++s) {
     const int c = lane + kWave * s;
     if (c < d) vec[c] = x[s];
   }
@@ -203,14 +312,15 @@ __global__ void __launch_bounds__(kWave) estimator_kernel_wide(EstArgs A) {
   if (i >= A.count) return;
   const Prob& P = A.P;
   const int d = P.d;
-  double dl[kWideNC];
+  constexpr int NC = wide_nc<G>();
+  double dl[NC];
 #pragma unroll
-  for (int s = 0; s < kWideNC; ++s) {
+  for (int s = 0; s < NC; ++s) {
     const int c = lane + kWave * s;
     dl[s] = c < d ? A.theta[(int64_t)i * d + c] - P.theta_bar[c] : 0.0;
   }
   to_lds(vec, dl, lane, d);
-  const PassResultW r = estimator_pass_wide<Real, G, CH, FAM, false>(P, A.u + (int64_t)i * P.m, 0, 0, nullptr,
+  const auto r = estimator_pass_wide<Real, G, CH, FAM, false>(P, A.u + (int64_t)i * P.m, 0, 0, nullptr,
                                                                      red, vec, lane);
   if (lane == 0) {
     if (A.lhat) A.lhat[i] = r.lhat;
@@ -218,7 +328,7 @@ __global__ void __launch_bounds__(kWave) estimator_kernel_wide(EstArgs A) {
     if (A.dhat) A.dhat[i] = r.dhat;
   }
 #pragma unroll
-  for (int s = 0; s < kWideNC; ++s) {
+  for (int s = 0; s < NC; ++s) {
     const int c = lane + kWave * s;
     if (c < d) {
       if (A.grad_l) A.grad_l[(int64_t)i * d + c] = r.gl[s];
@@ -233,10 +343,11 @@ __global__ void __launch_bounds__(kWave) estimator_kernel_wide(EstArgs A) {
 }
 
 // y = M x for a d x d row-major matrix; x broadcast through LDS
+template <int NC>
 __device__ __forceinline__ void matvec_wide(const double* __restrict__ Mx, const double* vec, int d, int lane,
-                                            double (&y)[kWideNC]) {
+                                            double (&y)[NC]) {
 #pragma unroll
-  for (int s = 0; s < kWideNC; ++s) {
+  for (int s = 0; s < NC; ++s) {
     const int c = lane + kWave * s;
     double acc = 0.0;
     if (c < d)
@@ -260,10 +371,11 @@ __device__ __forceinline__ void move_wide_body(const MoveArgs& A, const int i) {
   const double a = A.a;
   const double eps = A.eps;
   int32_t* urow = A.u + (int64_t)i * m;
+  constexpr int NC = wide_nc<G>();
 
-  double tb[kWideNC], th[kWideNC], gl0[kWideNC], gs0[kWideNC];
+  double tb[NC], th[NC], gl0[NC], gs0[NC];
 #pragma unroll
-  for (int s = 0; s < kWideNC; ++s) {
+  for (int s = 0; s < NC; ++s) {
     const int c = lane + kWave * s;
     tb[s] = c < d ? P.theta_bar[c] : 0.0;
     th[s] = c < d ? A.theta[(int64_t)i * d + c] : 0.0;
@@ -282,11 +394,11 @@ __device__ __forceinline__ void move_wide_body(const MoveArgs& A, const int i) {
     blk[t] = (int32_t)word_to_index(stream_word(P.seed, cb, (uint64_t)i, (uint64_t)t), (uint64_t)P.n);
   int ob0 = 0, ob1 = 0;
   {
-    double dl[kWideNC];
+    double dl[NC];
 #pragma unroll
-    for (int s = 0; s < kWideNC; ++s) dl[s] = th[s] - tb[s];
+    for (int s = 0; s < NC; ++s) dl[s] = th[s] - tb[s];
     to_lds(vec, dl, lane, d);  // also fences the block indices
-    const PassResultW r = estimator_pass_wide<Real, G, CH, FAM, true>(P, urow, b0, b1, blk, red, vec, lane);
+    const auto r = estimator_pass_wide<Real, G, CH, FAM, true>(P, urow, b0, b1, blk, red, vec, lane);
     const double lam0 = a * lh0 - 0.5 * a * a * sg0;
     const double lam1 = a * r.lhat - 0.5 * a * a * r.sig2;
     const double logr = lam1 - lam0;
@@ -296,7 +408,7 @@ __device__ __forceinline__ void move_wide_body(const MoveArgs& A, const int i) {
       for (int t = lane; t < b1 - b0; t += kWave) urow[b0 + t] = blk[t];
       lh0 = r.lhat; sg0 = r.sig2;
 #pragma unroll
-      for (int s = 0; s < kWideNC; ++s) { gl0[s] = r.gl[s]; gs0[s] = r.gs[s]; }
+      for (int s = 0; s < NC; ++s) { gl0[s] = r.gl[s]; gs0[s] = r.gs[s]; }
       ob0 = b0; ob1 = b1;
     }
     if (lane == 0) A.accept[2 * i] = acc ? 1 : 0;
@@ -304,34 +416,34 @@ __device__ __forceinline__ void move_wide_body(const MoveArgs& A, const int i) {
 
   // ---- 2. theta | u: HMC
   const uint64_t cm = stream_ctr0(kMomentum, A.stage, A.move, P.dataset);
-  double z[kWideNC];
+  double z[NC];
 #pragma unroll
-  for (int s = 0; s < kWideNC; ++s) {
+  for (int s = 0; s < NC; ++s) {
     const int c = lane + kWave * s;
     z[s] = c < d ? stream_normal(P.seed, cm, (uint64_t)i, (uint32_t)c) : 0.0;
   }
   to_lds(vec, z, lane, d);
-  double p[kWideNC];  // p = Linv' z
+  double p[NC];  // p = Linv' z
 #pragma unroll
-  for (int s = 0; s < kWideNC; ++s) {
+  for (int s = 0; s < NC; ++s) {
     const int c = lane + kWave * s;
     double acc = 0.0;
     if (c < d)
       for (int e = c; e < d; ++e) acc += P.Linv[e * d + c] * vec[e];
     p[s] = acc;
   }
-  auto kinetic_and_velocity = [&](double (&v)[kWideNC]) -> double {
+  auto kinetic_and_velocity = [&](double (&v)[NC]) -> double {
     to_lds(vec, p, lane, d);
     matvec_wide(P.Sigma, vec, d, lane, v);
     double k = 0.0;
 #pragma unroll
-    for (int s = 0; s < kWideNC; ++s) k += p[s] * v[s];
+    for (int s = 0; s < NC; ++s) k += p[s] * v[s];
     return 0.5 * wave_sum(k);
   };
-  auto prior = [&](const double (&t)[kWideNC], double (&r)[kWideNC]) -> double {
-    double dm[kWideNC];
+  auto prior = [&](const double (&t)[NC], double (&r)[NC]) -> double {
+    double dm[NC];
 #pragma unroll
-    for (int s = 0; s < kWideNC; ++s) {
+    for (int s = 0; s < NC; ++s) {
       const int c = lane + kWave * s;
       dm[s] = c < d ? t[s] - P.mu0[c] : 0.0;
     }
@@ -339,40 +451,40 @@ __device__ __forceinline__ void move_wide_body(const MoveArgs& A, const int i) {
     matvec_wide(P.Q0, vec, d, lane, r);
     double lp = 0.0;
 #pragma unroll
-    for (int s = 0; s < kWideNC; ++s) lp += -0.5 * dm[s] * r[s];
+    for (int s = 0; s < NC; ++s) lp += -0.5 * dm[s] * r[s];
     return wave_sum(lp);
   };
-  double v[kWideNC], rq[kWideNC];
+  double v[NC], rq[NC];
   const double K0 = kinetic_and_velocity(v);
   const double lp0 = prior(th, rq);
   const double logpi0 = (a * lh0 - 0.5 * a * a * sg0) + lp0;
   const double H0 = -logpi0 + K0;
-  double th1[kWideNC];
+  double th1[NC];
 #pragma unroll
-  for (int s = 0; s < kWideNC; ++s) {
+  for (int s = 0; s < NC; ++s) {
     p[s] += 0.5 * eps * (a * gl0[s] - 0.5 * a * a * gs0[s] - rq[s]);
     th1[s] = th[s];
   }
-  double lh1 = lh0, sg1 = sg0, gl1[kWideNC], gs1[kWideNC], lp1 = lp0;
+  double lh1 = lh0, sg1 = sg0, gl1[NC], gs1[NC], lp1 = lp0;
 #pragma unroll
-  for (int s = 0; s < kWideNC; ++s) { gl1[s] = gl0[s]; gs1[s] = gs0[s]; }
+  for (int s = 0; s < NC; ++s) { gl1[s] = gl0[s]; gs1[s] = gs0[s]; }
   for (int l = 1; l <= A.L; ++l) {
     to_lds(vec, p, lane, d);
     matvec_wide(P.Sigma, vec, d, lane, v);
-    double dl[kWideNC];
+    double dl[NC];
 #pragma unroll
-    for (int s = 0; s < kWideNC; ++s) {
+    for (int s = 0; s < NC; ++s) {
       th1[s] += eps * v[s];
       dl[s] = th1[s] - tb[s];
     }
     to_lds(vec, dl, lane, d);
-    const PassResultW r = estimator_pass_wide<Real, G, CH, FAM, true>(P, urow, ob0, ob1, blk, red, vec, lane);
+    const auto r = estimator_pass_wide<Real, G, CH, FAM, true>(P, urow, ob0, ob1, blk, red, vec, lane);
     lh1 = r.lhat;
     sg1 = r.sig2;
     lp1 = prior(th1, rq);
     const double h = (l < A.L) ? eps : 0.5 * eps;
 #pragma unroll
-    for (int s = 0; s < kWideNC; ++s) {
+    for (int s = 0; s < NC; ++s) {
       gl1[s] = r.gl[s];
       gs1[s] = r.gs[s];
       p[s] += h * (a * gl1[s] - 0.5 * a * a * gs1[s] - rq[s]);
@@ -387,10 +499,10 @@ __device__ __forceinline__ void move_wide_body(const MoveArgs& A, const int i) {
   if (acc) {
     lh0 = lh1; sg0 = sg1;
 #pragma unroll
-    for (int s = 0; s < kWideNC; ++s) { th[s] = th1[s]; gl0[s] = gl1[s]; gs0[s] = gs1[s]; }
+    for (int s = 0; s < NC; ++s) { th[s] = th1[s]; gl0[s] = gl1[s]; gs0[s] = gs1[s]; }
   }
 #pragma unroll
-  for (int s = 0; s < kWideNC; ++s) {
+  for (int s = 0; s < NC; ++s) {
     const int c = lane + kWave * s;
     if (c < d) {
       A.theta[(int64_t)i * d + c] = th[s];

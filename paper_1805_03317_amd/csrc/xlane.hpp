@@ -156,6 +156,58 @@ __device__ __forceinline__ double row_allmax(double x) {
   return pair_max<5>(x);
 }
 
+// Row groups of G = 4 or 8 consecutive lanes (a row shared by G lanes).
+// Sum over the group, the same bits in every lane of the group: pairs i ^ 1,
+// i ^ 2, then (G = 8) i <-> 7 - i, which pairs the two quads.
+template <int G, typename T>
+__device__ __forceinline__ T group_sum(T x) {
+  static_assert(G == 4 || G == 8, "groups of 4 or 8 lanes");
+  x = pair_all<5>(x);
+  x = pair_all<4>(x);
+  if constexpr (G == 8) x = pair_all<3>(x);
+  return x;
+}
+
+constexpr int kQuadLead = 0x00;  // quad_perm [0,0,0,0]
+
+__device__ __forceinline__ uint32_t quad_lead_word(uint32_t x) {
+  return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, kQuadLead, 0xf, 0xf, false);
+}
+
+// The value of the group's first lane in every lane of the group: the quad's
+// first lane, and for G = 8 the upper quad takes the lower quad's through
+// i <-> 7 - i.
+template <int G>
+__device__ __forceinline__ float group_lead(float x, int lane) {
+  static_assert(G == 4 || G == 8, "groups of 4 or 8 lanes");
+  uint32_t w = quad_lead_word(__float_as_uint(x));
+  if constexpr (G == 8) {
+    const uint32_t m = dpp_word<3>(w);
+    w = (lane & 4) ? m : w;
+  }
+  return __uint_as_float(w);
+}
+
+template <int G>
+__device__ __forceinline__ double group_lead(double x, int lane) {
+  static_assert(G == 4 || G == 8, "groups of 4 or 8 lanes");
+  uint32_t lo = quad_lead_word(lo_word(x)), hi = quad_lead_word(hi_word(x));
+  if constexpr (G == 8) {
+    const uint32_t ml = dpp_word<3>(lo), mh = dpp_word<3>(hi);
+    lo = (lane & 4) ? ml : lo;
+    hi = (lane & 4) ? mh : hi;
+  }
+  return make_double(lo, hi);
+}
+
+// The value of lane S of each quad, in every lane of the quad.
+template <int S>
+__device__ __forceinline__ float quad_pick(float x) {
+  static_assert(S >= 0 && S < 4, "lane of a quad");
+  constexpr int ctrl = S | (S << 2) | (S << 4) | (S << 6);
+  return __uint_as_float((uint32_t)__builtin_amdgcn_mov_dpp((int)__float_as_uint(x), ctrl, 0xf, 0xf, false));
+}
+
 // Reduce-scatter of N values held by every lane: afterwards v[0] of a lane is
 // the wavefront total of one value (or zero padding). The value a lane ends
 // with depends only on its role bits: the lane keeps the upper half of its
