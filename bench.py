@@ -45,6 +45,7 @@ def parse():
     ap.add_argument("--cpu-particles", type=int, default=64)
     ap.add_argument("--only", choices=["mixed", "fp64"], default=None, help="time one path only (profiling)")
     ap.add_argument("--batch", type=int, default=64, help="members of the batched workload")
+    ap.add_argument("--no-graph", action="store_true", help="batched workload: direct launches instead of graph replay")
     ap.add_argument("--workload", choices=["config1", "config2", "batched", "config4", "config5", "student"],
                     default="config2",
                     help="config2 (Poisson n=1e6 d=20) is the benchmark workload; the others are the "
@@ -235,6 +236,7 @@ def run_batched_path(ws, Xys, precision, args):
     members = [SubsampledSMC(Xy, w.d, w.family, precision, w.M, w.m, w.G, w.prior_mean, w.prior_prec, w.seed,
                              dataset=w.dataset) for w, Xy in zip(ws, Xys)]
     batch = SMCBatch(members)
+    batch.set_graph(not args.no_graph)
     eps = np.array([1.0 / w.L for w in ws])
     L = ws[0].L
     per_member = np.array([w.M * w.m * (w.L + 1) for w in ws], dtype=np.float64)
@@ -281,6 +283,7 @@ def run_batched_path(ws, Xys, precision, args):
         "launch_ms": launch_ms.tolist(),
         "member_launch": member_launch.tolist(),
         "stage": [m.info()["stage"] for m in members],
+        "graph_captures": batch.graph_captures(),
         "accept_u": float(acc[:, 0].mean()),
         "accept_theta": float(acc[:, 1].mean()),
     }
@@ -367,12 +370,13 @@ def main_batched(args):
         "config": {"workload": f"batched{len(ws)}_logistic_nloguniform1e4_2e6_d5_50", "members": len(ws),
                    "n_total": int(sum(n for n, _, _ in sizes)), "M": ws[0].M, "m": "max(200, 0.01 n)",
                    "G": ws[0].G, "L": ws[0].L, "R": 1, "eps": "1/L", "precision": head,
-                   "step": "batched temper+mass+resample+move"},
+                   "step": "batched temper+mass+resample+move",
+                   "move_launch": "direct" if args.no_graph else "hip graph replay"},
         "roofline": batched_roofline(r["launches"]),
         "move_ms": r["move_ms"],
         "move_evals_per_s": r["move_evals_per_s"],
         "launches": r["launches"],
-        "run": {k: r[k] for k in ("active_members", "accept_u", "accept_theta")},
+        "run": {k: r[k] for k in ("active_members", "accept_u", "accept_theta", "graph_captures")},
         "note": "not the benchmark workload (Poisson n=1e6 d=20); reported for the configuration table",
     }
     if "fp64" in results and head == "mixed":

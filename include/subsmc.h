@@ -287,6 +287,17 @@ smc_status smc_batch_move(smc_batch b, const double* eps, int32_t L, int32_t R);
  * shapes among the active members). */
 int32_t smc_batch_launches(smc_batch b);
 
+/* Graph replay of the move: with on = 1, smc_batch_move captures its
+ * launches into a HIP graph (they take their arguments from tables uploaded
+ * before each move) and replays it for every move with the same launch
+ * structure, capturing again when the structure changes (a member reaching
+ * a = 1). Results are those of the direct launches. Ignored while timing is
+ * on. */
+smc_status smc_batch_set_graph(smc_batch b, int32_t on);
+
+/* Number of graph captures smc_batch_move has made. */
+int32_t smc_batch_graph_captures(smc_batch b);
+
 /* Timing of the move launches: with on = 1, smc_batch_move records a HIP
  * event pair on the batch's stream around each of its launches. */
 smc_status smc_batch_set_timing(smc_batch b, int32_t on);

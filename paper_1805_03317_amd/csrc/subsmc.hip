@@ -152,6 +152,12 @@ struct smc_batch_s {
   std::vector<int> launch_kind;        // per launch of the last smc_batch_move
   std::vector<int> member_launch;      // per member: its launch, -1 if inactive
   int timed_moves = 0;
+  // optional replay of the move's launches as one HIP graph, captured again
+  // whenever the launch structure changes
+  int use_graph = 0;
+  hipGraphExec_t gexec = nullptr;
+  std::vector<long long> graph_key;
+  int graph_captures = 0;
   char err[512] = {0};
 };
 
@@ -1266,25 +1272,66 @@ smc_status smc_batch_move(smc_batch b, const double* eps, int32_t L, int32_t R) 
     }
     smc_status st = T.upload();
     if (st != SMC_OK) return st;
-    for (size_t li = 0; li < launches.size(); ++li) {
-      const Launch& l = launches[li];
-      hipEvent_t* ev = b->timing ? &b->ev[2 * ((size_t)r * ng + li)] : nullptr;
-      if (ev) BATCH_TRY(b, hipEventRecord(ev[0], b->stream));
-      hipError_t e;
+    auto issue = [&](const Launch& l) -> hipError_t {
       if (l.s.kind == kMoveResident)
-        e = launch_move_resident_batch(l.s, l.grid, l.lds, batch_of<ResMoveArgs>(T, l.off, l.foff, l.n), b->stream);
-      else if (l.s.kind == kMoveWide)
-        e = launch_move_wide_batch(l.s, l.grid, l.lds, batch_of<MoveArgs>(T, l.off, l.foff, l.n), b->stream);
-      else
-        e = launch_move_narrow_batch(l.s, l.grid, l.lds, batch_of<MoveArgs>(T, l.off, l.foff, l.n), b->stream);
-      BATCH_TRY(b, e);
-      if (ev) BATCH_TRY(b, hipEventRecord(ev[1], b->stream));
+        return launch_move_resident_batch(l.s, l.grid, l.lds, batch_of<ResMoveArgs>(T, l.off, l.foff, l.n),
+                                          b->stream);
+      if (l.s.kind == kMoveWide)
+        return launch_move_wide_batch(l.s, l.grid, l.lds, batch_of<MoveArgs>(T, l.off, l.foff, l.n), b->stream);
+      return launch_move_narrow_batch(l.s, l.grid, l.lds, batch_of<MoveArgs>(T, l.off, l.foff, l.n), b->stream);
+    };
+    if (b->use_graph && !b->timing) {
+      // the launches read their arguments from the uploaded tables, so a graph
+      // captured once replays any move with the same launch structure
+      std::vector<long long> key;
+      for (const Launch& l : launches) {
+        const long long v[12] = {l.s.kind, l.s.fp32, l.s.fam, l.s.dc, l.s.lanes, l.s.ch, l.s.rpl,
+                                 l.grid, (long long)l.lds, l.n, (long long)l.off, (long long)l.foff};
+        key.insert(key.end(), v, v + 12);
+      }
+      if (!b->gexec || key != b->graph_key) {
+        if (b->gexec) {
+          BATCH_TRY(b, hipGraphExecDestroy(b->gexec));
+          b->gexec = nullptr;
+        }
+        BATCH_TRY(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+        hipError_t le = hipSuccess;
+        for (const Launch& l : launches) {
+          le = issue(l);
+          if (le != hipSuccess) break;
+        }
+        hipGraph_t g = nullptr;
+        const hipError_t ce = hipStreamEndCapture(b->stream, &g);
+        BATCH_TRY(b, le);
+        BATCH_TRY(b, ce);
+        const hipError_t ie = hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        BATCH_TRY(b, ie);
+        b->graph_key = key;
+        b->graph_captures += 1;
+      }
+      BATCH_TRY(b, hipGraphLaunch(b->gexec, b->stream));
+    } else {
+      for (size_t li = 0; li < launches.size(); ++li) {
+        hipEvent_t* ev = b->timing ? &b->ev[2 * ((size_t)r * ng + li)] : nullptr;
+        if (ev) BATCH_TRY(b, hipEventRecord(ev[0], b->stream));
+        BATCH_TRY(b, issue(launches[li]));
+        if (ev) BATCH_TRY(b, hipEventRecord(ev[1], b->stream));
+      }
     }
     for (int k : b->active) b->ctx[k]->move += 1;
     if (b->timing) b->timed_moves += 1;
   }
   return SMC_OK;
 }
+
+smc_status smc_batch_set_graph(smc_batch b, int32_t on) {
+  if (!b || (on != 0 && on != 1)) return SMC_ERR_INVALID_ARG;
+  b->use_graph = on;
+  return SMC_OK;
+}
+
+int32_t smc_batch_graph_captures(smc_batch b) { return b ? b->graph_captures : 0; }
 
 smc_status smc_batch_set_timing(smc_batch b, int32_t on) {
   if (!b || (on != 0 && on != 1)) return SMC_ERR_INVALID_ARG;
@@ -1329,6 +1376,7 @@ void smc_batch_destroy(smc_batch b) {
     (void)hipEventDestroy(b->staged);
   }
   for (hipEvent_t e : b->ev) (void)hipEventDestroy(e);
+  if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
   if (b->host) (void)hipHostFree(b->host);
   delete b;
 }

@@ -90,3 +90,28 @@ def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):
     monkeypatch.setattr(B, "_lib", None)
     with pytest.raises(RuntimeError, match="no fallback"):
         B.lib()
+
+
+def test_batch_workspace_size(lib):
+    assert lib.smc_batch_workspace_size(0) == 0
+    assert lib.smc_batch_workspace_size(-3) == 0
+    assert lib.smc_batch_workspace_size(65537) == 0
+    a, b = lib.smc_batch_workspace_size(1), lib.smc_batch_workspace_size(64)
+    assert 0 < a < b
+    assert b >= 64 * 8 * 8                            # a results slot per member
+    assert lib.smc_batch_workspace_size(65536) > 0
+
+
+def test_batch_calls_reject_null(lib):
+    import ctypes as C
+    h = C.c_void_p()
+    assert lib.smc_batch_create(None, 1, None, 0, C.byref(h)) == 1
+    assert lib.smc_batch_temper(None, None, None, None, None) == 1
+    assert lib.smc_batch_mass(None) == 1
+    assert lib.smc_batch_resample(None, 0) == 1
+    assert lib.smc_batch_move(None, None, 1, 1) == 1
+    assert lib.smc_batch_set_graph(None, 1) == 1
+    assert lib.smc_batch_graph_captures(None) == 0
+    assert lib.smc_batch_launches(None) == 0
+    assert lib.smc_batch_last_error(None) == b"no batch"
+    lib.smc_batch_destroy(None)
