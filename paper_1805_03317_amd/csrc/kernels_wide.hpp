@@ -117,7 +117,9 @@ __device__ __forceinline__ PassResultW<wide_nc<G>()> estimator_pass_wide(const P
   // groups run the same number of steps. Row indices are loaded a step ahead
   // of their rows, so a row load never waits behind the load of its own
   // index, and every wait is for the oldest rows in flight.
-  if constexpr (sizeof(Real) == 4) {
+  if constexpr (sizeof(Real) == 4 && G == 4 && FAM == kLogistic) {
+    // (the logistic remainder is the costly one; for 8-lane rows and the
+    // other families the register cost of two buffered steps outweighs it)
     // PT = 4 iterations per step, two steps of rows in flight (buffers xa, xb).
     // Each group forms the PT dot products of a step; lane q then evaluates
     // the remainder of iteration q % PT only (one remainder per lane, not one

@@ -155,6 +155,7 @@ struct smc_batch_s {
   // optional replay of the move's launches as one HIP graph, captured again
   // whenever the launch structure changes
   int use_graph = 0;
+  hipStream_t capture = nullptr;  // private stream the graph is captured on
   hipGraphExec_t gexec = nullptr;
   std::vector<long long> graph_key;
   int graph_captures = 0;
@@ -1272,13 +1273,12 @@ smc_status smc_batch_move(smc_batch b, const double* eps, int32_t L, int32_t R) 
     }
     smc_status st = T.upload();
     if (st != SMC_OK) return st;
-    auto issue = [&](const Launch& l) -> hipError_t {
+    auto issue = [&](const Launch& l, hipStream_t st) -> hipError_t {
       if (l.s.kind == kMoveResident)
-        return launch_move_resident_batch(l.s, l.grid, l.lds, batch_of<ResMoveArgs>(T, l.off, l.foff, l.n),
-                                          b->stream);
+        return launch_move_resident_batch(l.s, l.grid, l.lds, batch_of<ResMoveArgs>(T, l.off, l.foff, l.n), st);
       if (l.s.kind == kMoveWide)
-        return launch_move_wide_batch(l.s, l.grid, l.lds, batch_of<MoveArgs>(T, l.off, l.foff, l.n), b->stream);
-      return launch_move_narrow_batch(l.s, l.grid, l.lds, batch_of<MoveArgs>(T, l.off, l.foff, l.n), b->stream);
+        return launch_move_wide_batch(l.s, l.grid, l.lds, batch_of<MoveArgs>(T, l.off, l.foff, l.n), st);
+      return launch_move_narrow_batch(l.s, l.grid, l.lds, batch_of<MoveArgs>(T, l.off, l.foff, l.n), st);
     };
     if (b->use_graph && !b->timing) {
       // the launches read their arguments from the uploaded tables, so a graph
@@ -1294,14 +1294,17 @@ smc_status smc_batch_move(smc_batch b, const double* eps, int32_t L, int32_t R) 
           BATCH_TRY(b, hipGraphExecDestroy(b->gexec));
           b->gexec = nullptr;
         }
-        BATCH_TRY(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+        // captured on a stream of the batch's own (the caller's stream may be
+        // the null stream, which cannot capture); nothing runs during capture
+        if (!b->capture) BATCH_TRY(b, hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking));
+        BATCH_TRY(b, hipStreamBeginCapture(b->capture, hipStreamCaptureModeThreadLocal));
         hipError_t le = hipSuccess;
         for (const Launch& l : launches) {
-          le = issue(l);
+          le = issue(l, b->capture);
           if (le != hipSuccess) break;
         }
         hipGraph_t g = nullptr;
-        const hipError_t ce = hipStreamEndCapture(b->stream, &g);
+        const hipError_t ce = hipStreamEndCapture(b->capture, &g);
         BATCH_TRY(b, le);
         BATCH_TRY(b, ce);
         const hipError_t ie = hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0);
@@ -1315,7 +1318,7 @@ smc_status smc_batch_move(smc_batch b, const double* eps, int32_t L, int32_t R) 
       for (size_t li = 0; li < launches.size(); ++li) {
         hipEvent_t* ev = b->timing ? &b->ev[2 * ((size_t)r * ng + li)] : nullptr;
         if (ev) BATCH_TRY(b, hipEventRecord(ev[0], b->stream));
-        BATCH_TRY(b, issue(launches[li]));
+        BATCH_TRY(b, issue(launches[li], b->stream));
         if (ev) BATCH_TRY(b, hipEventRecord(ev[1], b->stream));
       }
     }
@@ -1377,6 +1380,7 @@ void smc_batch_destroy(smc_batch b) {
   }
   for (hipEvent_t e : b->ev) (void)hipEventDestroy(e);
   if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+  if (b->capture) (void)hipStreamDestroy(b->capture);
   if (b->host) (void)hipHostFree(b->host);
   delete b;
 }
