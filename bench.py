@@ -42,7 +42,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison path")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-particles", type=int, default=64)
+    ap.add_argument("--cpu-particles", type=int, default=256)
     ap.add_argument("--only", choices=["mixed", "fp64"], default=None, help="time one path only (profiling)")
     ap.add_argument("--batch", type=int, default=64, help="members of the batched workload")
     ap.add_argument("--no-graph", action="store_true", help="batched workload: direct launches instead of graph replay")
@@ -200,8 +200,9 @@ def roofline(w, fp32, move_ms, move_path):
             "kernel": kernel, "bytes_per_eval": bpe, "evals_per_launch": evals}
 
 
-def cpu_baseline(w, count, eps):
-    """The oracle's move on `count` particles of the same workload, at a = 1."""
+def cpu_baseline(w, count, eps, budget_s=12.0, chunk=32):
+    """The oracle's move on up to `count` particles of the same workload, at
+    a = 1, in chunks of `chunk` particles until about budget_s seconds."""
     import oracle
 
     P = oracle.Problem(w.Xy(np.float64), w.d, w.family, w.prior_mean, w.prior_prec)
@@ -209,20 +210,24 @@ def cpu_baseline(w, count, eps):
     # timing does not depend on it), else the oracle's own Newton mode
     tb = w.theta_true if w.theta_true is not None else P.newton_mode()[0]
     P.set_cv_centre(tb)
+    count = min(count, w.M)
     thp, u0, _ = oracle.init_particles(count, w.d, w.m, w.n, w.seed, w.prior_mean, w.prior_prec)
     _, B, Cm = P.cv_build(tb)
     cov = np.linalg.inv(-Cm + w.prior_prec)
     Lc = np.linalg.cholesky(cov)
     z = (thp - w.prior_mean) @ np.linalg.cholesky(w.prior_prec)  # standard normals
     th0 = tb + z @ Lc.T                                             # Laplace approximation draws
-    t0 = time.perf_counter()
-    oracle.move(P, th0, u0, 1.0, eps, w.L, w.seed, 1, 0, w.G, cov, Lc)
-    dt = time.perf_counter() - t0
-    evals = count * w.m * (w.L + 1)
+    dt, done = 0.0, 0
+    while done < count and dt < budget_s:
+        k = min(chunk, count - done)
+        t0 = time.perf_counter()
+        oracle.move(P, th0[done:done + k], u0[done:done + k], 1.0, eps, w.L, w.seed, 1, 0, w.G, cov, Lc, i0=done)
+        dt += time.perf_counter() - t0
+        done += k
+    evals = done * w.m * (w.L + 1)
     return {"value": evals / dt, "unit": "evals/s", "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": f"one Markov move of {count} of the {w.M} particles (same data, Laplace-approximation "
+            "sample": f"one Markov move of {done} of the {w.M} particles (same data, Laplace-approximation "
                       f"state at a=1), {evals} algorithmic evals in {dt:.2f} s wall"}
-
 
 BATCH_KINDS = {0: "move_kernel_batch", 1: "move_kernel_wide_batch", 2: "move_kernel_res_batch"}
 
