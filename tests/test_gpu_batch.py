@@ -201,3 +201,40 @@ def test_graph_replay_equals_direct_launches():
     for a, b in zip(s0, s1):
         for x, y in zip(a, b):
             np.testing.assert_array_equal(x, y)
+
+
+def test_heterogeneous_batch_equals_single_context_runs():
+    """One batch mixing families (logistic, Poisson, Student-t), precisions
+    (FP64 and mixed) and widths (narrow, lane-group and resident kernels):
+    every member's run equals its own single-context run bit for bit."""
+    B = _binding()
+    ws = [W.logistic_small(1500, 5, seed=91, M=40, m=60, G=4, L=5),
+          W.poisson_small(2500, 8, seed=92, precision=W.MIXED, M=48, m=80, G=4, L=5),
+          W.student_small(2000, 6, seed=93, M=32, m=70, G=5, L=5),
+          W.student_small(1800, 40, seed=94, precision=W.MIXED, M=24, m=90, G=3, L=5, theta_scale=0.3),
+          W.poisson_small(3000, 3, seed=95, M=56, m=50, G=2, L=5)]
+    for k, w in enumerate(ws):
+        w.dataset = 10 + k
+    paths = [0, 0, B.MOVE_STREAMING, 0, B.MOVE_STREAMING]
+    P = [oracle.Problem(w.Xy(np.float64), w.d, w.family, w.prior_mean, w.prior_prec) for w in ws]
+    centres = [p.newton_mode()[0] for p in P]
+    singles = []
+    for w, tb, mp in zip(ws, centres, paths):
+        smc = _context(w, tb, mp)
+        logz, rec = smc.run(_eps, L=w.L, R=1, max_stages=8)
+        singles.append((logz, [r["a"] for r in rec], _state(smc)))
+        smc.close()
+    members = [_context(w, tb, mp) for w, tb, mp in zip(ws, centres, paths)]
+    batch = B.SMCBatch(members)
+    batch.set_graph(True)
+    logzs, recs = batch.run(_eps, L=ws[0].L, R=1, max_stages=8)
+    say("launches", batch.launches(), "stages", [len(r) for r in recs])
+    for k, s in enumerate(singles):
+        logz1, temps1, st1 = s
+        assert [r["a"] for r in recs[k]] == temps1, k
+        assert logzs[k] == logz1, k
+        for got, ref in zip(_state(members[k]), st1):
+            np.testing.assert_array_equal(got, ref)
+    batch.close()
+    for m in members:
+        m.close()
