@@ -42,6 +42,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison path")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-e2e", action="store_true", help="skip the whole run to a = 1 (configurations 1 and 2)")
     ap.add_argument("--cpu-particles", type=int, default=256)
     ap.add_argument("--only", choices=["mixed", "fp64"], default=None, help="time one path only (profiling)")
     ap.add_argument("--batch", type=int, default=64, help="members of the batched workload")
@@ -198,6 +199,24 @@ def roofline(w, fp32, move_ms, move_path):
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
             "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
             "kernel": kernel, "bytes_per_eval": bpe, "evals_per_launch": evals}
+
+
+def run_to_end(w, precision, Xy_dev, eps):
+    """A whole run of Algorithm 2 from the prior to a = 1 on a fresh context
+    (one move per stage), wall clock from the first tempering step."""
+    import torch
+    from paper_1805_03317_amd.binding import SubsampledSMC
+
+    smc = SubsampledSMC(Xy_dev, w.d, w.family, precision, w.M, w.m, w.G, w.prior_mean, w.prior_prec, w.seed)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    logz, rec = smc.run(lambda st, a, d: eps, w.L, 1)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    acc = smc.accept.float().mean(0).cpu().numpy()
+    smc.close()
+    return {"stages": len(rec), "wall_s": round(wall, 4), "logz": logz, "final_accept_u": float(acc[0]),
+            "final_accept_theta": float(acc[1])}
 
 
 def cpu_baseline(w, count, eps, budget_s=12.0, chunk=32):
@@ -490,6 +509,8 @@ def main():
             "lhat_max": float(((lm - lf).abs() / lf.abs()).max()),
             "sig2_max": float(((s2m - s2f).abs() / s2f.abs().clamp_min(1e-300)).max()),
         }
+    if args.workload in ("config1", "config2") and not args.no_e2e:
+        out["run_to_end"] = run_to_end(w, W.MIXED if head == "mixed" else W.FP64, Xy, eps)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_particles, eps)
     if args.workload != "config2":
