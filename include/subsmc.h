@@ -152,7 +152,10 @@ smc_status smc_temper_grid(smc_ctx ctx, int32_t grid_points, double ess_frac, do
 
 /* Algorithm 2 step d: weighted particle covariance Sigma (inverse mass matrix),
  * its Cholesky factor and inverse factor (a jitter ladder 1e-10..1e-1 times
- * the mean variance is tried before SMC_ERR_NOT_PD). Synchronises. */
+ * the mean variance is tried before giving up). Does not wait for the device:
+ * a covariance that is not positive definite is reported as SMC_ERR_NOT_PD by
+ * the next call that uses the mass matrix (smc_move, smc_recentre without a
+ * centre, smc_batch_move), and smc_get_info then shows have_mass = 0. */
 smc_status smc_mass(smc_ctx ctx);
 
 /*

@@ -126,7 +126,12 @@ struct smc_ctx_s {
   char* ws = nullptr;
   Prob prob;
   double a = 0.0, logz = 0.0;
-  int stage = 0, move = 0, have_mass = 0, newton_iters = 0;
+  int stage = 0, move = 0, newton_iters = 0;
+  // mass matrix of this stage: 0 none, 1 ready, 2 computed with its
+  // positive-definiteness flag still on its way to the host (mass_ev, hstatus)
+  int have_mass = 0;
+  double* hstatus = nullptr;  // pinned
+  hipEvent_t mass_ev = nullptr;
   int res_rpl = -1;  // register rows per lane of the resident move kernel; -1: streaming
   ResLayout res_ly{};
   std::vector<double> mu0, Q0;
@@ -485,6 +490,20 @@ smc_status refresh(smc_ctx c) {
   return SMC_OK;
 }
 
+// Settles a mass matrix computed by smc_mass: waits for its
+// positive-definiteness flag and reports SMC_ERR_NOT_PD (dropping the matrix)
+// if the factorisation failed.
+smc_status mass_ready(smc_ctx c) {
+  if (c->have_mass != 2) return SMC_OK;
+  HIP_TRY(c, hipEventSynchronize(c->mass_ev));
+  if (c->hstatus[0] != 0.0) {
+    c->have_mass = 0;
+    return fail(c, SMC_ERR_NOT_PD, "particle covariance not positive definite");
+  }
+  c->have_mass = 1;
+  return SMC_OK;
+}
+
 // ------------------------------------------------------------------------
 // argument blocks of the per-stage kernels, shared by the single-context
 // calls and the batched ones
@@ -630,6 +649,11 @@ smc_status smc_init(const smc_problem* pb, void* stream, smc_ctx* out) {
     return SMC_ERR_INVALID_ARG;
   smc_ctx c = new (std::nothrow) smc_ctx_s;
   if (!c) return SMC_ERR_DEVICE;
+  if (hipHostMalloc(reinterpret_cast<void**>(&c->hstatus), 64, hipHostMallocDefault) != hipSuccess ||
+      hipEventCreateWithFlags(&c->mass_ev, hipEventDisableTiming) != hipSuccess) {
+    smc_destroy(c);
+    return SMC_ERR_DEVICE;
+  }
   c->pb = *pb;
   c->stream = reinterpret_cast<hipStream_t>(stream);
   c->lay = lay;
@@ -781,11 +805,11 @@ smc_status smc_mass(smc_ctx c) {
                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)mlds));
   hipLaunchKernelGGL(moments_final_kernel, dim3(1), dim3(kMomThreads), mlds, c->stream, a);
   LAUNCH_CHECK(c);
-  double stv = 0.0;
-  HIP_TRY(c, hipMemcpyAsync(&stv, a.F.status, 8, hipMemcpyDeviceToHost, c->stream));
-  HIP_TRY(c, hipStreamSynchronize(c->stream));
-  if (stv != 0.0) return fail(c, SMC_ERR_NOT_PD, "particle covariance not positive definite");
-  c->have_mass = 1;
+  // the positive-definiteness flag travels to the host behind the kernels;
+  // the first call that uses the mass matrix waits for it (mass_ready)
+  HIP_TRY(c, hipMemcpyAsync(c->hstatus, a.F.status, 8, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipEventRecord(c->mass_ev, c->stream));
+  c->have_mass = 2;
   return SMC_OK;
 }
 
@@ -816,6 +840,10 @@ smc_status smc_resample_multinomial(smc_ctx c) {
 smc_status smc_move(smc_ctx c, double eps, int32_t L, int32_t R) {
   if (!c) return SMC_ERR_INVALID_ARG;
   if (!(eps > 0.0) || L < 1 || R < 0) return fail(c, SMC_ERR_INVALID_ARG, "bad eps/L/R");
+  {
+    const smc_status ms = mass_ready(c);
+    if (ms != SMC_OK) return ms;
+  }
   if (!c->have_mass) return fail(c, SMC_ERR_STATE, "no mass matrix for this stage");
   if (c->move + R > 0xFFFF) return fail(c, SMC_ERR_INVALID_ARG, "too many moves in one stage");
   for (int r = 0; r < R; ++r) {
@@ -873,6 +901,8 @@ smc_status smc_recentre(smc_ctx c, const double* theta_bar_host) {
       if (!std::isfinite(theta_bar_host[r])) return fail(c, SMC_ERR_INVALID_ARG, "theta_bar is not finite");
     HIP_TRY(c, hipMemcpyAsync(tb, theta_bar_host, (size_t)d * 8, hipMemcpyHostToDevice, c->stream));
   } else {
+    const smc_status ms = mass_ready(c);
+    if (ms != SMC_OK) return ms;
     if (!c->have_mass) return fail(c, SMC_ERR_STATE, "no weighted mean for this stage (call smc_mass first)");
     HIP_TRY(c, hipMemcpyAsync(tb, c->at<double>(c->lay.mean), (size_t)d * 8, hipMemcpyDeviceToDevice, c->stream));
   }
@@ -891,6 +921,7 @@ smc_status smc_get_info(smc_ctx c, smc_info* o) {
   o->logz = c->logz;
   o->stage = c->stage;
   o->move = c->move;
+  (void)mass_ready(c);  // a failed factorisation shows as have_mass = 0
   o->have_mass = c->have_mass;
   o->newton_iters = c->newton_iters;
   o->move_path = c->res_rpl >= 0 ? SMC_MOVE_RESIDENT : SMC_MOVE_STREAMING;
@@ -1213,6 +1244,7 @@ smc_status smc_batch_move(smc_batch b, const double* eps, int32_t L, int32_t R) 
   for (int k : b->active) {
     smc_ctx c = b->ctx[k];
     if (!(eps[k] > 0.0)) return bfail(b, SMC_ERR_INVALID_ARG, "member %d: eps must be positive", k);
+    if (mass_ready(c) != SMC_OK) return bfail(b, SMC_ERR_NOT_PD, "member %d: particle covariance not positive definite", k);
     if (!c->have_mass) return bfail(b, SMC_ERR_STATE, "member %d: no mass matrix for this stage", k);
     if (c->move + R > 0xFFFF) return bfail(b, SMC_ERR_INVALID_ARG, "member %d: too many moves in one stage", k);
   }
@@ -1387,7 +1419,15 @@ void smc_batch_destroy(smc_batch b) {
 
 const char* smc_batch_last_error(smc_batch b) { return b ? b->err : "no batch"; }
 
-void smc_destroy(smc_ctx c) { delete c; }
+void smc_destroy(smc_ctx c) {
+  if (!c) return;
+  if (c->mass_ev) {
+    (void)hipEventSynchronize(c->mass_ev);
+    (void)hipEventDestroy(c->mass_ev);
+  }
+  if (c->hstatus) (void)hipHostFree(c->hstatus);
+  delete c;
+}
 
 const char* smc_status_string(smc_status s) {
   switch (s) {

@@ -393,6 +393,32 @@ def test_autograd_backward_matches_fd_and_oracle():
     smc.close()
 
 
+def test_mass_failure_is_reported_by_the_move():
+    """smc_mass does not wait for the device: a particle covariance that is
+    not positive definite (all particles equal, so every jitter is zero) is
+    reported by the next move, and the context then has no mass matrix."""
+    B = _binding()
+    w = W.logistic_small(300, 3, seed=82, M=16, m=10, G=2)
+    P, smc = make_pair(w)
+    smc.temper()
+    smc.theta.copy_(smc.theta[0:1].expand_as(smc.theta).clone())
+    smc.mass()                                      # returns before the factorisation is checked
+    with pytest.raises(B.SMCError) as e:
+        smc.move(0.1, 3, 1)
+    assert e.value.status == 4
+    assert smc.info()["have_mass"] == 0
+    with pytest.raises(B.SMCError):
+        smc.move(0.1, 3, 1)                          # still none
+    # a good cloud again: mass and move go through
+    th, _, _ = oracle.init_particles(w.M, w.d, w.m, w.n, w.seed, w.prior_mean, w.prior_prec)
+    smc.theta.copy_(torch.tensor(th))
+    smc.refresh()
+    smc.mass()
+    smc.move(0.1, 3, 1)
+    assert smc.info()["have_mass"] == 1
+    smc.close()
+
+
 def test_errors_are_reported():
     B = _binding()
     w = W.logistic_small(300, 3, seed=81, M=8, m=10, G=2)
