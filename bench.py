@@ -93,39 +93,43 @@ def run_path(w, precision, Xy_dev, args, eps):
     from paper_1805_03317_amd.binding import SubsampledSMC
 
     smc = SubsampledSMC(Xy_dev, w.d, w.family, precision, w.M, w.m, w.G, w.prior_mean, w.prior_prec, w.seed)
-    stream = torch.cuda.current_stream()
     evals_per_move = w.M * w.m * (w.L + 1)
     state = {"tempered": 0}
 
     paper = args.schemes == "paper"
+    # the default schemes run as one library call per stage (the device does
+    # not wait for the host between its steps); the variants call the steps
+    fused = not paper and not args.recentre
 
-    def step(events=None):
+    def step():
         if smc.info()["a"] < 1.0:
-            if paper:
-                smc.temper_grid(129, 0.8)
-            else:
-                smc.temper()
             state["tempered"] += 1
+            if not fused:
+                if paper:
+                    smc.temper_grid(129, 0.8)
+                else:
+                    smc.temper()
+        if fused:
+            smc.stage(eps, w.L, 1)
+            return
         smc.mass()
         if args.recentre:
             smc.recentre()
         smc.resample(multinomial=paper)
-        if events is not None:
-            events[0].record(stream)
         smc.move(eps, w.L, 1)
-        if events is not None:
-            events[1].record(stream)
 
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    # every timed move launch is bracketed by HIP events on the context's stream
+    smc.set_move_timing(args.steps)
     t0 = time.perf_counter()
     for k in range(args.steps):
-        step(evs[k])
+        step()
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    move_ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+    move_ms = float(np.mean(smc.move_times()))
+    smc.set_move_timing(0)
     info = smc.info()
     acc = smc.accept.float().mean(0).cpu().numpy()
     res = {

@@ -190,6 +190,19 @@ smc_status smc_resample_multinomial(smc_ctx ctx);
 smc_status smc_move(smc_ctx ctx, double eps, int32_t L, int32_t R);
 
 /*
+ * One whole stage of Algorithm 2 (steps a-f with the default schemes):
+ * smc_temper (skipped once a = 1), smc_mass, smc_resample and smc_move(eps,
+ * L, R), with the results of those calls (a_out, dlogz_out, ess_out as in
+ * smc_temper; a = 1, 0, 0 when no tempering took place). The mass matrix and
+ * the resampling are queued before the exponent reaches the host, so the
+ * device does not wait for the host between the steps. A tempering failure
+ * (SMC_ERR_NONFINITE) leaves the stage counter advanced and the particles
+ * resampled.
+ */
+smc_status smc_stage(smc_ctx ctx, double eps, int32_t L, int32_t R, double* a_out, double* dlogz_out,
+                     double* ess_out);
+
+/*
  * Difference estimator (eq. difference_estimator_logl) and its variance
  * estimate (section 3.2) for `count` particles at exponent-free level:
  * device theta (count*d), u (count*m) -> device lhat, sig2, dhat (count each;
@@ -207,6 +220,15 @@ smc_status loglik_est(smc_ctx ctx, int32_t count, const double* theta, const int
 smc_status loglik_grad(smc_ctx ctx, int32_t count, const double* theta, const int32_t* u,
                        const double* g_lhat, const double* g_sig2, double* grad,
                        double* grad_l, double* grad_s);
+
+/* Timing of move launches: with n > 0 (at most 4096) every move launch of
+ * smc_move (and smc_stage) is bracketed by a HIP event pair on the context's
+ * stream, kept in a ring of the last n; n = 0 stops it. */
+smc_status smc_set_move_timing(smc_ctx ctx, int32_t n);
+
+/* Device time in ms of the last moves timed (up to cap, oldest first) into
+ * ms; *count receives how many. Waits for their events. */
+smc_status smc_move_times(smc_ctx ctx, int32_t cap, float* ms, int32_t* count);
 
 /* Recompute lhat, sig2 and the cached gradients at the current (theta, u),
  * after the caller has written the particle buffers directly. */

@@ -38,7 +38,7 @@ class _Info(C.Structure):
 
 EXPORTS = [
     "smc_workspace_size", "smc_init", "smc_temper", "smc_temper_grid", "smc_mass", "smc_resample",
-    "smc_resample_multinomial", "smc_recentre", "smc_move",
+    "smc_resample_multinomial", "smc_recentre", "smc_move", "smc_stage", "smc_set_move_timing", "smc_move_times",
     "loglik_est", "loglik_grad", "smc_refresh", "smc_get_info", "smc_set_stage", "smc_set_mass",
     "smc_get_mass", "smc_get_cv", "smc_full_loglik", "smc_destroy", "smc_status_string",
     "smc_last_error", "smc_batch_workspace_size", "smc_batch_create", "smc_batch_temper", "smc_batch_mass",
@@ -70,6 +70,9 @@ def lib():
     L.smc_resample_multinomial.argtypes = [vp]
     L.smc_recentre.argtypes = [vp, vp]
     L.smc_move.argtypes = [vp, dbl, i32, i32]
+    L.smc_stage.argtypes = [vp, dbl, i32, i32, C.POINTER(dbl), C.POINTER(dbl), C.POINTER(dbl)]
+    L.smc_set_move_timing.argtypes = [vp, i32]
+    L.smc_move_times.argtypes = [vp, i32, vp, C.POINTER(i32)]
     L.loglik_est.argtypes = [vp, i32, vp, vp, vp, vp, vp]
     L.loglik_grad.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp]
     L.smc_refresh.argtypes = [vp]
@@ -226,6 +229,23 @@ class SubsampledSMC:
     def move(self, eps, L, R=1):
         self._check(lib().smc_move(self._h, float(eps), int(L), int(R)))
 
+    def set_move_timing(self, n):
+        self._check(lib().smc_set_move_timing(self._h, int(n)))
+
+    def move_times(self, cap=4096):
+        """Device ms of the last timed move launches, oldest first."""
+        import numpy as np
+        ms = np.zeros(int(cap), dtype=np.float32)
+        cnt = C.c_int32()
+        self._check(lib().smc_move_times(self._h, int(cap), _host_ptr(ms), C.byref(cnt)))
+        return ms[:cnt.value].astype(np.float64)
+
+    def stage(self, eps, L, R=1):
+        """temper (until a = 1), mass, resample and move in one call; returns a, dlogz, ess."""
+        a, dz, ess = C.c_double(), C.c_double(), C.c_double()
+        self._check(lib().smc_stage(self._h, float(eps), int(L), int(R), C.byref(a), C.byref(dz), C.byref(ess)))
+        return a.value, dz.value, ess.value
+
     def recentre(self, theta_bar=None):
         """Move the control-variate centre (default: this stage's weighted mean) and re-evaluate the caches."""
         import numpy as np
@@ -308,23 +328,38 @@ class SubsampledSMC:
         grid_ess_frac * M) and multinomial resampling. recentre=True moves the
         control-variate centre to each stage's weighted mean (step d)."""
         paper = schemes == "paper"
+        fused = not paper and not recentre
         rec = []
         a = self.info()["a"]
         while a < 1.0 and len(rec) < max_stages:
-            if paper:
-                a, dz, ess, _ = self.temper_grid(grid_points, grid_ess_frac)
+            if fused and not eps_depends_on_a(eps_fn):
+                # one library call per stage: the same steps and results, without
+                # the device waiting for the host between them
+                eps = eps_fn(len(rec) + 1, None, self.d)
+                a, dz, ess = self.stage(eps, L, R)
             else:
-                a, dz, ess = self.temper()
-            self.mass()
-            if recentre:
-                self.recentre()
-            self.resample(multinomial=paper)
-            eps = eps_fn(len(rec) + 1, a, self.d)
-            self.move(eps, L, R)
+                if paper:
+                    a, dz, ess, _ = self.temper_grid(grid_points, grid_ess_frac)
+                else:
+                    a, dz, ess = self.temper()
+                self.mass()
+                if recentre:
+                    self.recentre()
+                self.resample(multinomial=paper)
+                eps = eps_fn(len(rec) + 1, a, self.d)
+                self.move(eps, L, R)
             rec.append({"a": a, "dlogz": dz, "ess": ess, "eps": eps})
             if callback:
                 callback(self, rec[-1])
         return self.info()["logz"], rec
+
+
+def eps_depends_on_a(eps_fn):
+    """True unless eps_fn(stage, a, d) ignores a (tried with two exponents)."""
+    try:
+        return eps_fn(1, 0.25, 2) != eps_fn(1, 0.75, 2)
+    except Exception:
+        return True
 
 
 class SMCBatch:

@@ -130,8 +130,12 @@ struct smc_ctx_s {
   // mass matrix of this stage: 0 none, 1 ready, 2 computed with its
   // positive-definiteness flag still on its way to the host (mass_ev, hstatus)
   int have_mass = 0;
-  double* hstatus = nullptr;  // pinned
+  double* hstatus = nullptr;  // pinned: [0] the mass flag, [1..5] smc_stage's tempering results
   hipEvent_t mass_ev = nullptr;
+  hipEvent_t temper_ev = nullptr;
+  // optional timing of move launches: a ring of event pairs
+  std::vector<hipEvent_t> mev;
+  int mev_next = 0, mev_count = 0;
   int res_rpl = -1;  // register rows per lane of the resident move kernel; -1: streaming
   ResLayout res_ly{};
   std::vector<double> mu0, Q0;
@@ -650,7 +654,8 @@ smc_status smc_init(const smc_problem* pb, void* stream, smc_ctx* out) {
   smc_ctx c = new (std::nothrow) smc_ctx_s;
   if (!c) return SMC_ERR_DEVICE;
   if (hipHostMalloc(reinterpret_cast<void**>(&c->hstatus), 64, hipHostMallocDefault) != hipSuccess ||
-      hipEventCreateWithFlags(&c->mass_ev, hipEventDisableTiming) != hipSuccess) {
+      hipEventCreateWithFlags(&c->mass_ev, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&c->temper_ev, hipEventDisableTiming) != hipSuccess) {
     smc_destroy(c);
     return SMC_ERR_DEVICE;
   }
@@ -837,6 +842,43 @@ smc_status smc_resample_multinomial(smc_ctx c) {
   return resample_impl(c, 1);
 }
 
+smc_status smc_stage(smc_ctx c, double eps, int32_t L, int32_t R, double* a_out, double* dlogz_out,
+                     double* ess_out) {
+  if (!c) return SMC_ERR_INVALID_ARG;
+  if (!(eps > 0.0) || L < 1 || R < 0) return fail(c, SMC_ERR_INVALID_ARG, "bad eps/L/R");
+  const bool tempering = c->a < 1.0;
+  double o[5] = {c->a, 0.0, 0.0, 0.0, 0.0};
+  if (tempering) {
+    const TemperArgs t = temper_args(c, c->pb.ess_frac, c->at<double>(c->lay.tout));
+    HIP_TRY(c, launch_search(t, c->stream));
+    hipLaunchKernelGGL(temper_kernel, dim3(1), dim3(kTemperThreads), 0, c->stream, t);
+    LAUNCH_CHECK(c);
+    HIP_TRY(c, hipMemcpyAsync(c->hstatus + 1, t.out, 5 * 8, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipEventRecord(c->temper_ev, c->stream));
+    // the mass matrix and the resampling need the new weights and the stage
+    // number, not the exponent on the host: they are queued while it travels
+    c->stage += 1;
+    c->move = 0;
+  }
+  smc_status st = smc_mass(c);
+  if (st != SMC_OK) return st;
+  st = resample_impl(c, 0);
+  if (st != SMC_OK) return st;
+  if (tempering) {
+    HIP_TRY(c, hipEventSynchronize(c->temper_ev));
+    std::memcpy(o, c->hstatus + 1, sizeof(o));
+    if (o[3] != 0.0) return fail(c, SMC_ERR_NONFINITE, "all incremental weights non-finite");
+    c->a = o[0];
+    c->logz += o[1];
+  }
+  st = smc_move(c, eps, L, R);
+  if (st != SMC_OK) return st;
+  if (a_out) *a_out = o[0];
+  if (dlogz_out) *dlogz_out = o[1];
+  if (ess_out) *ess_out = o[2];
+  return SMC_OK;
+}
+
 smc_status smc_move(smc_ctx c, double eps, int32_t L, int32_t R) {
   if (!c) return SMC_ERR_INVALID_ARG;
   if (!(eps > 0.0) || L < 1 || R < 0) return fail(c, SMC_ERR_INVALID_ARG, "bad eps/L/R");
@@ -846,9 +888,44 @@ smc_status smc_move(smc_ctx c, double eps, int32_t L, int32_t R) {
   }
   if (!c->have_mass) return fail(c, SMC_ERR_STATE, "no mass matrix for this stage");
   if (c->move + R > 0xFFFF) return fail(c, SMC_ERR_INVALID_ARG, "too many moves in one stage");
+  const int ring = (int)c->mev.size() / 2;
   for (int r = 0; r < R; ++r) {
+    hipEvent_t* ev = ring > 0 ? &c->mev[2 * (c->mev_next % ring)] : nullptr;
+    if (ev) HIP_TRY(c, hipEventRecord(ev[0], c->stream));
     HIP_TRY(c, launch_move(c, move_args(c, eps, L)));
+    if (ev) {
+      HIP_TRY(c, hipEventRecord(ev[1], c->stream));
+      c->mev_next += 1;
+      c->mev_count = std::min(c->mev_count + 1, ring);
+    }
     c->move += 1;
+  }
+  return SMC_OK;
+}
+
+smc_status smc_set_move_timing(smc_ctx c, int32_t n) {
+  if (!c || n < 0 || n > 4096) return SMC_ERR_INVALID_ARG;
+  for (hipEvent_t e : c->mev) (void)hipEventDestroy(e);
+  c->mev.clear();
+  c->mev_next = c->mev_count = 0;
+  for (int k = 0; k < 2 * n; ++k) {
+    hipEvent_t e;
+    HIP_TRY(c, hipEventCreate(&e));
+    c->mev.push_back(e);
+  }
+  return SMC_OK;
+}
+
+smc_status smc_move_times(smc_ctx c, int32_t cap, float* ms, int32_t* count) {
+  if (!c || !count || (cap > 0 && !ms)) return SMC_ERR_INVALID_ARG;
+  const int ring = (int)c->mev.size() / 2;
+  const int n = std::min(c->mev_count, cap);
+  *count = n;
+  for (int k = 0; k < n; ++k) {
+    const int slot = (c->mev_next - n + k) % ring;
+    const hipEvent_t* ev = &c->mev[2 * slot];
+    HIP_TRY(c, hipEventSynchronize(ev[1]));
+    HIP_TRY(c, hipEventElapsedTime(&ms[k], ev[0], ev[1]));
   }
   return SMC_OK;
 }
@@ -1425,6 +1502,11 @@ void smc_destroy(smc_ctx c) {
     (void)hipEventSynchronize(c->mass_ev);
     (void)hipEventDestroy(c->mass_ev);
   }
+  if (c->temper_ev) {
+    (void)hipEventSynchronize(c->temper_ev);
+    (void)hipEventDestroy(c->temper_ev);
+  }
+  for (hipEvent_t e : c->mev) (void)hipEventDestroy(e);
   if (c->hstatus) (void)hipHostFree(c->hstatus);
   delete c;
 }

@@ -365,6 +365,34 @@ def test_full_run_matches_oracle_fp64():
     smc.close()
 
 
+def test_stage_equals_separate_calls():
+    """smc_stage queues the mass matrix and the resampling before the exponent
+    reaches the host; every stage equals temper + mass + resample + move made
+    one by one, bit for bit, also after a = 1 (stages without tempering)."""
+    w = W.logistic_small(3000, 3, seed=61, M=128, m=150, G=4, L=6)
+    _, s1 = make_pair(w)
+    _, s2 = make_pair(w)
+    for st in range(40):
+        if s1.info()["a"] < 1.0:
+            a1, dz1, e1 = s1.temper()
+        else:
+            a1, dz1, e1 = 1.0, 0.0, 0.0
+        s1.mass()
+        s1.resample()
+        s1.move(0.15, 6, 2)
+        a2, dz2, e2 = s2.stage(0.15, 6, 2)
+        assert (a1, dz1, e1) == (a2, dz2, e2), st
+        torch.cuda.synchronize()
+        for t1, t2 in ((s1.theta, s2.theta), (s1.u, s2.u), (s1.logw, s2.logw), (s1.lhat, s2.lhat)):
+            assert torch.equal(t1, t2), st
+        if a1 == 1.0 and st > 3 and s1.info()["stage"] + 2 <= st:
+            break
+    assert s1.info() == s2.info()
+    assert s1.info()["a"] == 1.0
+    s1.close()
+    s2.close()
+
+
 def test_autograd_backward_matches_fd_and_oracle():
     B = _binding()
     w = W.poisson_small(5000, 4, seed=71, M=16, m=200, G=4)
