@@ -534,49 +534,66 @@ __device__ void factor_spd(const FactorArgs& F, double* sh) {
 // forward substitution. Ls and Li are d*d doubles of LDS each.
 constexpr int kFactorLdsMaxD = 64;
 
+// LDS writes of this wavefront visible to its other lanes (no other wave waits)
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 __device__ void factor_spd_lds(const FactorArgs& F, double* Ls, double* Li) {
+  __shared__ int good_flag;
   const int d = F.d;
   const int t = threadIdx.x;
-  double tr = 0.0;
-  for (int r = 0; r < d; ++r) tr += F.S[r * d + r];
+  double tr = 0.0;  // trace, needed once a factorisation has failed
   bool ok = false;
   for (int att = 0; att <= 10 && !ok; ++att) {
+    if (att == 1)
+      for (int r = 0; r < d; ++r) tr += F.S[r * d + r];
     const double jit = att > 0 ? 1e-10 * (tr / d) * pow(10.0, (double)(att - 1)) : 0.0;
     for (int e = t; e < d * d; e += kMomThreads) {
       const int r = e / d, c = e % d;
       Ls[e] = F.S[e] + (r == c ? jit : 0.0);
     }
     __syncthreads();
-    bool good = true;
-    for (int j = 0; j < d; ++j) {
-      double sj = 0.0;
-      if (t >= j && t < d) {
-        sj = Ls[t * d + j];
-        for (int k = 0; k < j; ++k) sj -= Ls[t * d + k] * Ls[j * d + k];
+    // the columns by wavefront 0 alone (row t in lane t, d <= 64), so the
+    // steps of a column synchronise one wavefront only
+    if (t < kWave) {
+      bool good = true;
+      for (int j = 0; j < d; ++j) {
+        double sj = 0.0;
+        if (t >= j && t < d) {
+          sj = Ls[t * d + j];
+#pragma unroll 8
+          for (int k = 0; k < j; ++k) sj -= Ls[t * d + k] * Ls[j * d + k];
+        }
+        // row j's entries left of the diagonal are final; nobody reads (j, j) now
+        if (t == j) Ls[j * d + j] = sj;
+        wave_lds_sync();
+        const double p = Ls[j * d + j];
+        good = p > 0.0;
+        if (!good) break;  // the same value in every lane
+        const double ljj = sqrt(p);
+        if (t > j && t < d) Ls[t * d + j] = sj / ljj;
+        wave_lds_sync();
+        // (j, j) is read again only after the loop
+        if (t == j) Ls[j * d + j] = ljj;
       }
-      // row j's entries left of the diagonal are final; nobody reads (j, j) now
-      if (t == j) Ls[j * d + j] = sj;
-      __syncthreads();
-      const double p = Ls[j * d + j];
-      good = p > 0.0;
-      if (!good) break;  // the same value in every thread
-      const double ljj = sqrt(p);
-      if (t > j && t < d) Ls[t * d + j] = sj / ljj;
-      __syncthreads();
-      // (j, j) is read again only after the loop
-      if (t == j) Ls[j * d + j] = ljj;
+      if (t == 0) good_flag = good ? 1 : 0;
     }
-    ok = good;
     __syncthreads();
+    ok = good_flag != 0;
     if (ok && att > 0) {
       for (int r = t; r < d; r += kMomThreads) F.S[r * d + r] += jit;
     }
+    __syncthreads();
   }
   // inverse: column c of L^{-1} solves L x = e_c
   for (int c = t; c < d; c += kMomThreads) {
     for (int r = 0; r < d; ++r) {
       if (r < c) { Li[r * d + c] = 0.0; continue; }
       double s = (r == c) ? 1.0 : 0.0;
+#pragma unroll 8
       for (int k = c; k < r; ++k) s -= Ls[r * d + k] * Li[k * d + c];
       Li[r * d + c] = s / Ls[r * d + r];
     }
