@@ -237,7 +237,8 @@ constexpr int kBisectLevels = 60;                   // halvings of (a_prev, 1]
 constexpr int kPassLevels = 8;                      // halvings resolved per pass
 constexpr int kPassPoints = (1 << kPassLevels) - 1;
 constexpr int kSearchPasses = (kBisectLevels + kPassLevels - 1) / kPassLevels;
-constexpr int kSearchThreads = 256;
+constexpr int kSearchThreads = 1024;       // workgroup of one search point (one dataset)
+constexpr int kSearchThreadsBatch = 256;   // (batches: many more workgroups per pass)
 
 __host__ __device__ inline int pass_levels(int pass) {
   const int left = kBisectLevels - pass * kPassLevels;
@@ -281,12 +282,13 @@ __device__ __forceinline__ void search_descend(const double* ess, int levels, do
 
 // ESS(a) = (sum w)^2 / sum w^2 over the M particles, w_i = exp(x_i - max x),
 // x_i = log W_i + nu_i(a); 0 when every x_i is -inf. One workgroup of
-// kSearchThreads, sums in a fixed order.
+// NT threads, sums in a fixed order.
+template <int NT>
 __device__ __forceinline__ double ess_block(const TemperArgs& A, double a, double* sh) {
   const int t = threadIdx.x, w = t / kWave, l = t % kWave;
-  constexpr int NW = kSearchThreads / kWave;
+  constexpr int NW = NT / kWave;
   double mx = -INFINITY;
-  for (int i = t; i < A.M; i += kSearchThreads)
+  for (int i = t; i < A.M; i += NT)
     mx = fmax(mx, A.logw[i] + incr_weight(a, A.a_prev, A.lhat[i], A.sig2[i]));
   mx = xl::wave_allmax(mx);
   if (l == 0) sh[w] = mx;
@@ -296,7 +298,7 @@ __device__ __forceinline__ double ess_block(const TemperArgs& A, double a, doubl
   for (int q = 1; q < NW; ++q) mx = fmax(mx, sh[q]);
   if (!isfinite(mx)) return 0.0;
   double s1 = 0.0, s2 = 0.0;
-  for (int i = t; i < A.M; i += kSearchThreads) {
+  for (int i = t; i < A.M; i += NT) {
     const double e = exp(A.logw[i] + incr_weight(a, A.a_prev, A.lhat[i], A.sig2[i]) - mx);
     s1 += e;
     s2 += e * e;
@@ -319,8 +321,9 @@ __device__ __forceinline__ double ess_block(const TemperArgs& A, double a, doubl
 
 // Pass `pass`, workgroup j: follow the previous pass's halvings, then the ESS
 // at trial point j of this pass (j = 2^K - 1 on pass 0: a = 1).
+template <int NT>
 __device__ __forceinline__ void search_pass_body(const TemperArgs& A, int pass, int j) {
-  __shared__ double sh[3 * (kSearchThreads / kWave)];
+  __shared__ double sh[3 * (NT / kWave)];
   __shared__ double br[2];
   __shared__ int dn;
   const int t = threadIdx.x;
@@ -351,7 +354,7 @@ __device__ __forceinline__ void search_pass_body(const TemperArgs& A, int pass, 
   if (dn) return;
   const int np = (1 << K) - 1;
   const double a = j < np ? tree_point(br[0], br[1], j + 1) : 1.0;
-  const double e = ess_block(A, a, sh);
+  const double e = ess_block<NT>(A, a, sh);
   if (t == 0) cur->ess[j < np ? j : kPassPoints] = e;
 }
 
@@ -1067,15 +1070,15 @@ __global__ void __launch_bounds__(256) cv_const_reduce_kernel(const double* part
 // --------------------------------------------------------------------------
 
 __global__ void __launch_bounds__(kSearchThreads) search_pass_kernel(TemperArgs A, int pass) {
-  search_pass_body(A, pass, blockIdx.x);
+  search_pass_body<kSearchThreads>(A, pass, blockIdx.x);
 }
 
 // members own pass_groups(pass) consecutive workgroups each
-__global__ void __launch_bounds__(kSearchThreads) search_pass_kernel_batch(Batch<TemperArgs> B, int pass) {
+__global__ void __launch_bounds__(kSearchThreadsBatch) search_pass_kernel_batch(Batch<TemperArgs> B, int pass) {
   const int per = pass_groups(pass);
   const int k = blockIdx.x / per;
   const TemperArgs A = B.args[k];
-  search_pass_body(A, pass, blockIdx.x - k * per);
+  search_pass_body<kSearchThreadsBatch>(A, pass, blockIdx.x - k * per);
 }
 
 __global__ void __launch_bounds__(kTemperThreads) temper_kernel(TemperArgs A) { temper_body(A); }

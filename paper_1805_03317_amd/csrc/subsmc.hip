@@ -1218,7 +1218,7 @@ smc_status smc_batch_temper(smc_batch b, double* a_out, double* dlogz_out, doubl
   bt.first = nullptr;
   bt.count = na;
   for (int pass = 0; pass < kSearchPasses; ++pass) {
-    hipLaunchKernelGGL(search_pass_kernel_batch, dim3(na * pass_groups(pass)), dim3(kSearchThreads), 0, b->stream,
+    hipLaunchKernelGGL(search_pass_kernel_batch, dim3(na * pass_groups(pass)), dim3(kSearchThreadsBatch), 0, b->stream,
                        bt, pass);
     BATCH_TRY(b, hipGetLastError());
   }
