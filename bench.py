@@ -441,8 +441,8 @@ def cpu_baseline_batched(count, per_member, budget_s=12.0):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU design is described "
-              "in DESIGN.md and is not built", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): sharding the particles over "
+              "several GPUs is designed but not built", file=sys.stderr)
         sys.exit(2)
     import torch
     from paper_1805_03317_amd import workloads as W
