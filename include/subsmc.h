@@ -221,6 +221,20 @@ smc_status loglik_grad(smc_ctx ctx, int32_t count, const double* theta, const in
                        const double* g_lhat, const double* g_sig2, double* grad,
                        double* grad_l, double* grad_s);
 
+/*
+ * Picks the move kernel by measurement: times one move (after an untimed
+ * one) of every option the problem's move_path allows — the streaming kernel
+ * and each resident layout that fits (register rows per lane) — from the
+ * current state with step eps and L leapfrog steps, restores the particle
+ * state, the accept flags and the move counter exactly, and keeps the fastest
+ * for later moves (single and batched). *rpl_out (nullable) receives the
+ * choice: -1 streaming, else the register rows per lane of the resident
+ * kernel; ms_out (nullable, up to 3 entries) the timed durations in the order
+ * streaming (when allowed), then the resident layouts. Needs a mass matrix.
+ * Uses the resampling buffers of the workspace. Synchronises.
+ */
+smc_status smc_autotune_move(smc_ctx ctx, double eps, int32_t L, int32_t* rpl_out, float* ms_out);
+
 /* Timing of move launches: with n > 0 (at most 4096) every move launch of
  * smc_move (and smc_stage) is bracketed by a HIP event pair on the context's
  * stream, kept in a ring of the last n; n = 0 stops it. */

@@ -38,7 +38,7 @@ class _Info(C.Structure):
 
 EXPORTS = [
     "smc_workspace_size", "smc_init", "smc_temper", "smc_temper_grid", "smc_mass", "smc_resample",
-    "smc_resample_multinomial", "smc_recentre", "smc_move", "smc_stage", "smc_set_move_timing", "smc_move_times",
+    "smc_resample_multinomial", "smc_recentre", "smc_move", "smc_stage", "smc_autotune_move", "smc_set_move_timing", "smc_move_times",
     "loglik_est", "loglik_grad", "smc_refresh", "smc_get_info", "smc_set_stage", "smc_set_mass",
     "smc_get_mass", "smc_get_cv", "smc_full_loglik", "smc_destroy", "smc_status_string",
     "smc_last_error", "smc_batch_workspace_size", "smc_batch_create", "smc_batch_temper", "smc_batch_mass",
@@ -71,6 +71,7 @@ def lib():
     L.smc_recentre.argtypes = [vp, vp]
     L.smc_move.argtypes = [vp, dbl, i32, i32]
     L.smc_stage.argtypes = [vp, dbl, i32, i32, C.POINTER(dbl), C.POINTER(dbl), C.POINTER(dbl)]
+    L.smc_autotune_move.argtypes = [vp, dbl, i32, C.POINTER(i32), vp]
     L.smc_set_move_timing.argtypes = [vp, i32]
     L.smc_move_times.argtypes = [vp, i32, vp, C.POINTER(i32)]
     L.loglik_est.argtypes = [vp, i32, vp, vp, vp, vp, vp]
@@ -228,6 +229,16 @@ class SubsampledSMC:
 
     def move(self, eps, L, R=1):
         self._check(lib().smc_move(self._h, float(eps), int(L), int(R)))
+
+    def autotune_move(self, eps, L):
+        """Time the allowed move kernels from the current state (restored
+        afterwards) and keep the fastest; returns (register rows per lane or
+        -1 for streaming, the timed ms of each option)."""
+        import numpy as np
+        rpl = C.c_int32()
+        ms = np.zeros(3, dtype=np.float32)
+        self._check(lib().smc_autotune_move(self._h, float(eps), int(L), C.byref(rpl), _host_ptr(ms)))
+        return rpl.value, ms
 
     def set_move_timing(self, n):
         self._check(lib().smc_set_move_timing(self._h, int(n)))

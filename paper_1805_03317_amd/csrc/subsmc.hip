@@ -249,6 +249,26 @@ int choose_resident(const smc_problem& pb, int max_lds, ResLayout& ly) {
   return -1;
 }
 
+// Every register-row count whose layout fits (the candidates of choose_resident).
+int resident_options(const smc_problem& pb, int max_lds, int rpl[2], ResLayout ly[2]) {
+  if (pb.d > kMaxNarrowD || (pb.family != SMC_LOGISTIC && pb.family != SMC_POISSON)) return 0;
+  const bool fp32 = pb.precision == SMC_MIXED;
+  const int dc = pad_dc(pb.d);
+  int cand[2];
+  const int nc = res_candidates(fp32, dc, pb.family, cand);
+  int n = 0;
+  for (int q = 0; q < nc; ++q) {
+    const ResLayout l = res_layout(pb.m, pb.G, dc, cand[q], fp32 ? 4 : 8, pb.d);
+    const bool regs_full = pb.m >= kResLanes * cand[q];
+    if (regs_full && l.total <= max_lds && (l.nlds + kResLanes - 1) / kResLanes <= kResMaxLdsGroups) {
+      rpl[n] = cand[q];
+      ly[n] = l;
+      ++n;
+    }
+  }
+  return n;
+}
+
 // The move kernel of a context (the estimator kernels use the narrow or wide
 // shape of the same d).
 KernelShape move_shape(smc_ctx c) {
@@ -900,6 +920,96 @@ smc_status smc_move(smc_ctx c, double eps, int32_t L, int32_t R) {
     }
     c->move += 1;
   }
+  return SMC_OK;
+}
+
+smc_status smc_autotune_move(smc_ctx c, double eps, int32_t L, int32_t* rpl_out, float* ms_out) {
+  if (!c || !(eps > 0.0) || L < 1) return SMC_ERR_INVALID_ARG;
+  {
+    const smc_status ms = mass_ready(c);
+    if (ms != SMC_OK) return ms;
+  }
+  if (!c->have_mass) return fail(c, SMC_ERR_STATE, "no mass matrix for this stage");
+  const smc_problem& pb = c->pb;
+  // the options: the streaming kernel and every resident layout that fits,
+  // within the path the problem asked for
+  std::vector<int> rpl;
+  std::vector<ResLayout> lys;
+  if (pb.move_path != SMC_MOVE_RESIDENT) {
+    rpl.push_back(-1);
+    lys.push_back(ResLayout{});
+  }
+  if (pb.move_path != SMC_MOVE_STREAMING) {
+    int dev = 0, max_lds = 0;
+    HIP_TRY(c, hipGetDevice(&dev));
+    HIP_TRY(c, hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    int r[2];
+    ResLayout l[2];
+    const int n = resident_options(pb, max_lds, r, l);
+    for (int q = 0; q < n; ++q) {
+      rpl.push_back(r[q]);
+      lys.push_back(l[q]);
+    }
+  }
+  const size_t M = pb.M, d = pb.d, m = pb.m;
+  struct Buf { void* live; void* saved; size_t bytes; };
+  const Buf bufs[6] = {{pb.theta, c->at<double>(c->lay.th2), M * d * 8}, {pb.u, c->at<int32_t>(c->lay.u2), M * m * 4},
+                       {pb.lhat, c->at<double>(c->lay.lh2), M * 8}, {pb.sig2, c->at<double>(c->lay.sg2), M * 8},
+                       {c->at<double>(c->lay.grad_l), c->at<double>(c->lay.gl2), M * d * 8},
+                       {c->at<double>(c->lay.grad_s), c->at<double>(c->lay.gs2), M * d * 8}};
+  std::vector<int32_t> acc(M * 2);
+  HIP_TRY(c, hipMemcpyAsync(acc.data(), pb.accept, M * 2 * 4, hipMemcpyDeviceToHost, c->stream));
+  for (const Buf& b : bufs) HIP_TRY(c, hipMemcpyAsync(b.saved, b.live, b.bytes, hipMemcpyDeviceToDevice, c->stream));
+  auto restore = [&]() -> hipError_t {
+    for (const Buf& b : bufs) {
+      const hipError_t e = hipMemcpyAsync(b.live, b.saved, b.bytes, hipMemcpyDeviceToDevice, c->stream);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  };
+  const int move0 = c->move, rpl0 = c->res_rpl;
+  const ResLayout ly0 = c->res_ly;
+  std::vector<hipEvent_t> ev(2 * rpl.size(), nullptr);
+  for (hipEvent_t& e : ev) HIP_TRY(c, hipEventCreate(&e));
+  hipError_t err = hipSuccess;
+  for (size_t q = 0; q < rpl.size() && err == hipSuccess; ++q) {
+    c->res_rpl = rpl[q];
+    c->res_ly = lys[q];
+    // a first launch absorbs one-time costs, the second is timed; both
+    // start from the saved state
+    for (int rep = 0; rep < 2 && err == hipSuccess; ++rep) {
+      if ((err = restore()) != hipSuccess) break;
+      if (rep == 1 && (err = hipEventRecord(ev[2 * q], c->stream)) != hipSuccess) break;
+      err = launch_move(c, move_args(c, eps, L));
+      if (err == hipSuccess && rep == 1) err = hipEventRecord(ev[2 * q + 1], c->stream);
+    }
+  }
+  if (err == hipSuccess) err = restore();
+  if (err == hipSuccess) err = hipMemcpyAsync(pb.accept, acc.data(), M * 2 * 4, hipMemcpyHostToDevice, c->stream);
+  if (err == hipSuccess) err = hipStreamSynchronize(c->stream);
+  c->move = move0;
+  int best = -1;
+  float best_ms = 0.f;
+  for (size_t q = 0; q < rpl.size() && err == hipSuccess; ++q) {
+    float t = 0.f;
+    err = hipEventElapsedTime(&t, ev[2 * q], ev[2 * q + 1]);
+    if (ms_out) ms_out[q] = t;
+    if (best < 0 || t < best_ms) {
+      best = (int)q;
+      best_ms = t;
+    }
+  }
+  for (hipEvent_t e : ev)
+    if (e) (void)hipEventDestroy(e);
+  if (err != hipSuccess || best < 0) {
+    c->res_rpl = rpl0;
+    c->res_ly = ly0;
+    HIP_TRY(c, err);
+    return fail(c, SMC_ERR_STATE, "no move kernel to tune");
+  }
+  c->res_rpl = rpl[best];
+  c->res_ly = lys[best];
+  if (rpl_out) *rpl_out = rpl[best];
   return SMC_OK;
 }
 

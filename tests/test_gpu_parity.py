@@ -337,6 +337,43 @@ def test_move_parity(name, mk, a, eps, spread, path):
     smc.close()
 
 
+def test_autotune_restores_state_and_keeps_parity():
+    """smc_autotune_move times the streaming kernel and the resident layouts
+    that fit from the current state, restores that state exactly, and the
+    kernel it keeps moves as the oracle does."""
+    w = W.poisson_small(30000, 20, seed=59, precision=W.MIXED, M=48, m=5000, G=100, L=4)
+    P, smc = make_pair(w)
+    thp, u0, _ = oracle.init_particles(w.M, w.d, w.m, w.n, w.seed, w.prior_mean, w.prior_prec)
+    th0 = P.theta_bar + 0.05 * (thp - w.prior_mean)
+    _, Sig, Lc = oracle.moments(th0, np.full(w.M, -math.log(w.M)))
+    smc.theta.copy_(torch.tensor(th0))
+    smc.u.copy_(torch.tensor(u0))
+    smc.refresh()
+    smc.set_mass(Sig)
+    smc.set_stage(3, 1, 0.8)
+    torch.cuda.synchronize()
+    before = [t.clone() for t in (smc.theta, smc.u, smc.lhat, smc.sig2, smc.accept)]
+    info0 = smc.info()
+    rpl, ms = smc.autotune_move(0.1, w.L)
+    say("autotune", rpl, ms)
+    torch.cuda.synchronize()
+    for a, b in zip(before, (smc.theta, smc.u, smc.lhat, smc.sig2, smc.accept)):
+        assert torch.equal(a, b)
+    info1 = smc.info()
+    assert info1["move"] == info0["move"] and info1["stage"] == info0["stage"]
+    # 0 register rows would need all 5000 rows in LDS: only streaming and 14 fit
+    assert rpl in (-1, 14) and (ms[:2] > 0).all() and ms[2] == 0
+    assert info1["move_path"] == (1 if rpl < 0 else 2)
+    smc.move(0.1, w.L, 1)
+    torch.cuda.synchronize()
+    th1, u1, acc, lh1, sg1 = oracle.move(P, th0, u0, 0.8, 0.1, w.L, w.seed, 3, 1, w.G, Sig, Lc)
+    same = (smc.accept.cpu().numpy() == acc).all(axis=1)
+    assert same.mean() > 0.9
+    np.testing.assert_array_equal(smc.u.cpu().numpy()[same], u1[same])
+    np.testing.assert_allclose(smc.theta.cpu().numpy()[same], th1[same], rtol=1e-5, atol=1e-5 * np.abs(th1).max())
+    smc.close()
+
+
 def test_resident_path_is_selected():
     B = _binding()
     w = W.poisson_small(30000, 20, seed=59, precision=W.MIXED, M=8, m=5000, G=100)
