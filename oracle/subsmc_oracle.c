@@ -453,11 +453,13 @@ static void estimate_one(const orc_data *D, const orc_cv *cv, int32_t m, const d
     qd nq = (qd)D->n, mq = (qd)m;
     qd dbar = dsum / mq;
 
-    /* q(theta) = A + B'delta + 1/2 delta' C delta */
+    /* sum_k q_k(theta) = A + B'delta + 1/2 delta' C delta; the first-order
+     * control variate has no curvature term */
     qd qsum = (qd)cv->A;
     for (int r = 0; r < d; ++r) {
         qsum += (qd)cv->B[r] * delta[r];
-        for (int c = 0; c < d; ++c) qsum += 0.5Q * delta[r] * (qd)cv->C[(size_t)r * d + c] * delta[c];
+        if (D->cv_order == 2)
+            for (int c = 0; c < d; ++c) qsum += 0.5Q * delta[r] * (qd)cv->C[(size_t)r * d + c] * delta[c];
     }
     qd dhat = nq / mq * dsum;
     qd ss = 0;
@@ -478,7 +480,8 @@ static void estimate_one(const orc_data *D, const orc_cv *cv, int32_t m, const d
             }
             if (grad_l) {
                 qd gl = (qd)cv->B[r];
-                for (int c = 0; c < d; ++c) gl += (qd)cv->C[(size_t)r * d + c] * delta[c];
+                if (D->cv_order == 2)
+                    for (int c = 0; c < d; ++c) gl += (qd)cv->C[(size_t)r * d + c] * delta[c];
                 gl += nq / mq * s1;
                 grad_l[r] = (double)gl;
             }

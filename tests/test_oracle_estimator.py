@@ -31,8 +31,9 @@ def t5_logpdf(r):
     return gammaln((nu + 1) / 2) - gammaln(nu / 2) - 0.5 * np.log(nu * np.pi) - (nu + 1) / 2 * np.log1p(r * r / nu)
 
 
-def make_problem(w, theta_bar=None):
-    P = oracle.Problem(w.Xy(np.float64), w.d, w.family, w.prior_mean, w.prior_prec, gauss_s2=w.gauss_s2)
+def make_problem(w, theta_bar=None, cv_order=2):
+    P = oracle.Problem(w.Xy(np.float64), w.d, w.family, w.prior_mean, w.prior_prec, gauss_s2=w.gauss_s2,
+                       cv_order=cv_order)
     P.set_cv_centre(w.theta_true if theta_bar is None else theta_bar)
     return P
 
@@ -54,11 +55,14 @@ def full_loglik(w, theta):
 # exact enumeration over all u in {1..n}^m (difference estimator, section 3.2)
 # ---------------------------------------------------------------------------
 
+@pytest.mark.parametrize("cv_order", [2, 1])
 @pytest.mark.parametrize("family", FAMILIES)
-def test_enumeration_unbiased_and_variance_divisor(family):
+def test_enumeration_unbiased_and_variance_divisor(family, cv_order):
+    """Both control variates: the second-order one of section 3.2 and the
+    first-order one of Experiment 4 (q_k without its curvature term)."""
     n, m, d = 5, 3, 2
     w = small(family)(n, d, seed=3)
-    P = make_problem(w, theta_bar=w.theta_true + 0.1)
+    P = make_problem(w, theta_bar=w.theta_true + 0.1, cv_order=cv_order)
     theta = w.theta_true + np.array([1.6, -1.3])
     us = np.array(list(itertools.product(range(n), repeat=m)), dtype=np.int32)
     est = P.estimate(np.repeat(theta[None], len(us), 0), us)
@@ -70,8 +74,9 @@ def test_enumeration_unbiased_and_variance_divisor(family):
     assert var > 1e-3
     assert abs(est["sig2"].mean() - (m - 1) / m * var) < 1e-12 * var
     # the d-part alone is unbiased for sum_k d_k
-    assert abs(est["dhat"].mean() - (exact - (P.A + P.B @ (theta - P.theta_bar)
-                                              + 0.5 * (theta - P.theta_bar) @ P.C @ (theta - P.theta_bar)))) < 1e-11
+    dl = theta - P.theta_bar
+    qsum = P.A + P.B @ dl + (0.5 * dl @ P.C @ dl if cv_order == 2 else 0.0)
+    assert abs(est["dhat"].mean() - (exact - qsum)) < 1e-11
 
 
 def test_gaussian_family_estimator_is_exact():
@@ -224,11 +229,12 @@ def test_gradients_by_finite_differences(family):
         np.testing.assert_allclose(est["grad_s"][i], fd_s, rtol=0, atol=1e-6 * scale_s)
 
 
+@pytest.mark.parametrize("cv_order", [2, 1])
 @pytest.mark.parametrize("family", FAMILIES)
-def test_gradients_vs_torch_autograd(family):
+def test_gradients_vs_torch_autograd(family, cv_order):
     """Autograd of a float64 torch re-expression of the estimator's definition."""
     w = small(family)(1000, 4, seed=8, m=150)
-    P = make_problem(w)
+    P = make_problem(w, cv_order=cv_order)
     th, u = W.random_state(w, 3, 0.4, w.theta_true, seed=9)
     est = P.estimate(th, u, grad=True)
     X = torch.tensor(w.X)
@@ -253,12 +259,13 @@ def test_gradients_vs_torch_autograd(family):
         (g1,) = torch.autograd.grad(fb.sum(), eb, create_graph=True)
         (g2,) = torch.autograd.grad(g1.sum(), eb)
         De = Xs @ (t - tb)
-        dk = f(Xs @ t) - (fb.detach() + g1.detach() * De + 0.5 * g2.detach() * De * De)
+        c2 = 0.5 if cv_order == 2 else 0.0
+        dk = f(Xs @ t) - (fb.detach() + g1.detach() * De + c2 * g2.detach() * De * De)
         n, m = w.n, w.m
         Bq = torch.tensor(P.B)
         Cq = torch.tensor(P.C)
         dl = t - tb
-        lhat = P.A + Bq @ dl + 0.5 * dl @ Cq @ dl + n / m * dk.sum()
+        lhat = P.A + Bq @ dl + c2 * dl @ Cq @ dl + n / m * dk.sum()
         sig2 = n * n / (m * m) * ((dk - dk.mean()) ** 2).sum()
         gl, = torch.autograd.grad(lhat, t, retain_graph=True)
         gs, = torch.autograd.grad(sig2, t)
