@@ -58,6 +58,8 @@ def parse():
     ap.add_argument("--recentre", action="store_true",
                     help="move the control-variate centre to every stage's weighted mean (Algorithm 2 step d: "
                          "a full-data CV rebuild and a re-evaluation of every particle per step)")
+    ap.add_argument("--cv-order", type=int, choices=[1, 2], default=2,
+                    help="2: the second-order control variate (default); 1: the first-order one of Experiment 4")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy three times (the reference kernel for scaling "
                          "FETCH_SIZE / WRITE_SIZE counters) and exit")
@@ -92,7 +94,8 @@ def run_path(w, precision, Xy_dev, args, eps):
     import torch
     from paper_1805_03317_amd.binding import SubsampledSMC
 
-    smc = SubsampledSMC(Xy_dev, w.d, w.family, precision, w.M, w.m, w.G, w.prior_mean, w.prior_prec, w.seed)
+    smc = SubsampledSMC(Xy_dev, w.d, w.family, precision, w.M, w.m, w.G, w.prior_mean, w.prior_prec, w.seed,
+                        cv_order=args.cv_order)
     evals_per_move = w.M * w.m * (w.L + 1)
     state = {"tempered": 0}
 
@@ -205,13 +208,14 @@ def roofline(w, fp32, move_ms, move_path):
             "kernel": kernel, "bytes_per_eval": bpe, "evals_per_launch": evals}
 
 
-def run_to_end(w, precision, Xy_dev, eps):
+def run_to_end(w, precision, Xy_dev, eps, cv_order=2):
     """A whole run of Algorithm 2 from the prior to a = 1 on a fresh context
     (one move per stage), wall clock from the first tempering step."""
     import torch
     from paper_1805_03317_amd.binding import SubsampledSMC
 
-    smc = SubsampledSMC(Xy_dev, w.d, w.family, precision, w.M, w.m, w.G, w.prior_mean, w.prior_prec, w.seed)
+    smc = SubsampledSMC(Xy_dev, w.d, w.family, precision, w.M, w.m, w.G, w.prior_mean, w.prior_prec, w.seed,
+                        cv_order=cv_order)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     logz, rec = smc.run(lambda st, a, d: eps, w.L, 1)
@@ -223,12 +227,12 @@ def run_to_end(w, precision, Xy_dev, eps):
             "final_accept_theta": float(acc[1])}
 
 
-def cpu_baseline(w, count, eps, budget_s=12.0, chunk=32):
+def cpu_baseline(w, count, eps, budget_s=12.0, chunk=32, cv_order=2):
     """The oracle's move on up to `count` particles of the same workload, at
     a = 1, in chunks of `chunk` particles until about budget_s seconds."""
     import oracle
 
-    P = oracle.Problem(w.Xy(np.float64), w.d, w.family, w.prior_mean, w.prior_prec)
+    P = oracle.Problem(w.Xy(np.float64), w.d, w.family, w.prior_mean, w.prior_prec, cv_order=cv_order)
     # the control-variate centre: the generating parameter where known (a point near the mode; the
     # timing does not depend on it), else the oracle's own Newton mode
     tb = w.theta_true if w.theta_true is not None else P.newton_mode()[0]
@@ -492,7 +496,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "n": w.n, "d": w.d, "M": w.M, "m": w.m, "G": w.G, "L": w.L,
                    "R": 1, "eps": eps, "precision": head, "step": "temper+mass+resample+move",
-                   "schemes": args.schemes, "recentre": bool(args.recentre)},
+                   "schemes": args.schemes, "recentre": bool(args.recentre), "cv_order": args.cv_order},
         "roofline": roofline(w, head == "mixed", r["move_ms"], r["move_path"]),
         "move_ms": r["move_ms"],
         "move_evals_per_s": r["move_evals_per_s"],
@@ -514,13 +518,14 @@ def main():
             "sig2_max": float(((s2m - s2f).abs() / s2f.abs().clamp_min(1e-300)).max()),
         }
     if args.workload in ("config1", "config2") and not args.no_e2e:
-        out["run_to_end"] = run_to_end(w, W.MIXED if head == "mixed" else W.FP64, Xy, eps)
+        out["run_to_end"] = run_to_end(w, W.MIXED if head == "mixed" else W.FP64, Xy, eps, args.cv_order)
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(w, args.cpu_particles, eps)
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_particles, eps, cv_order=args.cv_order)
     if args.workload != "config2":
         out["note"] = "not the benchmark workload (Poisson n=1e6 d=20); reported for the configuration table"
-    if args.recentre or args.schemes != "default":
+    if args.recentre or args.schemes != "default" or args.cv_order != 2:
         out["note"] = (out.get("note", "") + " variant: per-stage CV centre" * bool(args.recentre)
+                       + " variant: first-order control variate" * (args.cv_order == 1)
                        + " variant: paper schemes (grid tempering 0.8M, multinomial)" * (args.schemes == "paper")).strip()
     print(json.dumps(out), flush=True)
 

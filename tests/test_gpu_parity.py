@@ -67,9 +67,25 @@ CASES = [
 @pytest.mark.parametrize("name,mk,scale", CASES, ids=[c[0] for c in CASES])
 @pytest.mark.parametrize("far", [False, True], ids=["near", "far"])
 def test_estimator_fp64(name, mk, scale, far):
-    w = mk()
-    say("case", name, "far" if far else "near", "n", w.n, "d", w.d, "m", w.m)
-    P, smc = make_pair(w)
+    _check_estimator_fp64(name, mk(), scale, far, 2)
+
+
+# the first-order control variate (Experiment 4) on every kernel family: narrow,
+# lane-group (d 33-128) and Student-t
+FIRST_ORDER = ["logistic", "logistic_ragged", "poisson_d20", "logistic_d33", "logistic_d50", "poisson_d65",
+               "logistic_d116", "student", "student_d50"]
+
+
+@pytest.mark.parametrize("name", FIRST_ORDER)
+@pytest.mark.parametrize("far", [False, True], ids=["near", "far"])
+def test_estimator_first_order_fp64(name, far):
+    _, mk, scale = next(c for c in CASES if c[0] == name)
+    _check_estimator_fp64(name, mk(), scale, far, 1)
+
+
+def _check_estimator_fp64(name, w, scale, far, cv_order):
+    say("case", name, "far" if far else "near", "n", w.n, "d", w.d, "m", w.m, "cv order", cv_order)
+    P, smc = make_pair(w, cv_order=cv_order)
     th, u = W.random_state(w, 24, scale * (8 if far else 1), P.theta_bar, seed=11)
     tht, ut = torch.tensor(th, device=DEV), torch.tensor(u, device=DEV)
     lh, s2, dh = smc.loglik_est(tht, ut)
@@ -119,9 +135,19 @@ MIXED_CASES = [
 
 @pytest.mark.parametrize("name,mk,scale", MIXED_CASES, ids=[c[0] for c in MIXED_CASES])
 def test_estimator_mixed(name, mk, scale):
-    w = mk()
-    say("case", name, "n", w.n, "d", w.d, "m", w.m)
-    P, smc = make_pair(w)
+    _check_estimator_mixed(name, mk(), scale, 2)
+
+
+@pytest.mark.parametrize("name", ["logistic_mixed", "poisson_mixed_d20", "logistic_mixed_d50",
+                                  "logistic_mixed_d116", "student_mixed_d50"])
+def test_estimator_first_order_mixed(name):
+    _, mk, scale = next(c for c in MIXED_CASES if c[0] == name)
+    _check_estimator_mixed(name, mk(), scale, 1)
+
+
+def _check_estimator_mixed(name, w, scale, cv_order):
+    say("case", name, "n", w.n, "d", w.d, "m", w.m, "cv order", cv_order)
+    P, smc = make_pair(w, cv_order=cv_order)
     th, u = W.random_state(w, 24, scale, P.theta_bar, seed=12)
     tht, ut = torch.tensor(th, device=DEV), torch.tensor(u, device=DEV)
     lh, s2, dh = smc.loglik_est(tht, ut)
@@ -298,9 +324,22 @@ MOVE_CASES = [
 def test_move_parity(name, mk, a, eps, spread, path):
     """One Markov move from the same state on both sides (teacher forced); the
     automatic path runs the resident kernel wherever it applies."""
-    w = mk()
-    say("move case", name, spread, path)
-    P, smc = make_pair(w, move_path=path)
+    _check_move(name, mk(), a, eps, spread, path, 2)
+
+
+@pytest.mark.parametrize("path", [1, 0], ids=["streaming", "auto"])
+@pytest.mark.parametrize("name", ["logistic", "poisson_mixed_d20", "logistic_d50", "logistic_mixed_d116",
+                                  "poisson_mixed_m5000", "logistic_mixed_m1500", "student_mixed_d50"])
+def test_move_first_order(name, path):
+    """The move with the first-order control variate, on the narrow,
+    lane-group and resident kernels."""
+    _, mk, a, eps = next(c for c in MOVE_CASES if c[0] == name)
+    _check_move(name, mk(), a, eps, 0.02, path, 1)
+
+
+def _check_move(name, w, a, eps, spread, path, cv_order):
+    say("move case", name, spread, path, "cv order", cv_order)
+    P, smc = make_pair(w, move_path=path, cv_order=cv_order)
     say("kernel", smc.info()["move_path"])
     mixed = w.precision == W.MIXED
     # a particle cloud around theta_bar: the oracle's prior draws shrunk towards it
