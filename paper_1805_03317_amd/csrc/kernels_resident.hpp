@@ -174,8 +174,9 @@ __device__ __forceinline__ void copy_row_plain(const Real* __restrict__ g, Real*
   for (int q = 0; q < (kHeader + DC) * (int)sizeof(Real) / 16; ++q) b[q] = a[q];
 }
 
-// Per-lane accumulation of one pass over the resident rows.
-template <typename Real, int DC, int FAM, int RPL>
+// Per-lane accumulation of one pass over the resident rows; CV is the order
+// of the control variate.
+template <typename Real, int DC, int FAM, int RPL, int CV>
 __device__ __forceinline__ void resident_accumulate(const Prob& P, const ResRow<Real, DC> (&rr)[RPL > 0 ? RPL : 1],
                                                     char* lrows, int nlds, const Real* row0,
                                                     const Real* dsh, int tid, double& se, double& se2,
@@ -189,7 +190,7 @@ __device__ __forceinline__ void resident_accumulate(const Prob& P, const ResRow<
     Real D = Real(0);
 #pragma unroll
     for (int c = 0; c < DC; ++c) D += x[c] * dl[c];
-    cv_remainder<Real, FAM>(P.cv_order, eb, aux, D, inv_s2, dd, dp);
+    cv_remainder<Real, FAM>(CV, eb, aux, D, inv_s2, dd, dp);
   };
   {
     Real x[DC];
@@ -222,9 +223,18 @@ __device__ __forceinline__ void resident_accumulate(const Prob& P, const ResRow<
 #pragma unroll
   for (int r = 0; r < RPL; ++r) {
     if (r < nfull) {
+      // one copy of the row into vector registers serves both contractions
+      // (the empty asm marks the copy as a new value, so that it is not
+      // re-read from the accumulation registers for the second)
+      Real x[DC];
+#pragma unroll
+      for (int c = 0; c < DC; ++c) {
+        x[c] = rr[r].x[c];
+        asm("" : "+v"(x[c]));
+      }
       Real dd, dp;
-      eval(rr[r].eb, rr[r].aux, rr[r].x, dd, dp);
-      add(rr[r].x, dd, dp);
+      eval(rr[r].eb, rr[r].aux, x, dd, dp);
+      add(x, dd, dp);
     }
   }
   const LdsSlots<Real, DC> S(lrows, tid);
@@ -414,7 +424,10 @@ __device__ __forceinline__ void move_res_body(const MoveArgs& A, const ResLayout
     __syncthreads();
     double se, se2, shift;
     Real S1[DC], T1[DC];
-    resident_accumulate<Real, DC, FAM, RPL>(P, rr, lrows, Ly.nlds, row0, dsh, tid, se, se2, S1, T1, shift);
+    if (P.cv_order == 2)
+      resident_accumulate<Real, DC, FAM, RPL, 2>(P, rr, lrows, Ly.nlds, row0, dsh, tid, se, se2, S1, T1, shift);
+    else
+      resident_accumulate<Real, DC, FAM, RPL, 1>(P, rr, lrows, Ly.nlds, row0, dsh, tid, se, se2, S1, T1, shift);
     const bool full = (l == 0 || l == L);  // estimator value needed (not only the gradient)
     se = xl::wave_allsum(se);
     if (full) se2 = xl::wave_allsum(se2);
