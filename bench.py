@@ -470,7 +470,7 @@ def main():
         paths = ["fp64"]
     else:
         paths = ["mixed", "fp64"] if args.only is None else [args.only]
-    if args.no_fp64 and "fp64" in paths and args.only is None:
+    if args.no_fp64 and len(paths) > 1 and args.only is None:  # FP64-only workloads keep their path
         paths.remove("fp64")
     results = {}
     ctxs = {}
