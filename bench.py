@@ -47,6 +47,8 @@ def parse():
     ap.add_argument("--only", choices=["mixed", "fp64"], default=None, help="time one path only (profiling)")
     ap.add_argument("--batch", type=int, default=64, help="members of the batched workload")
     ap.add_argument("--no-graph", action="store_true", help="batched workload: direct launches instead of graph replay")
+    ap.add_argument("--streams", type=int, default=8,
+                    help="batched workload: streams the move's launches are spread over (1 = one after another)")
     ap.add_argument("--workload", choices=["config1", "config2", "batched", "config4", "config5", "student"],
                     default="config2",
                     help="config2 (Poisson n=1e6 d=20) is the benchmark workload; the others are the "
@@ -269,6 +271,7 @@ def run_batched_path(ws, Xys, precision, args):
                              dataset=w.dataset) for w, Xy in zip(ws, Xys)]
     batch = SMCBatch(members)
     batch.set_graph(not args.no_graph)
+    batch.set_streams(args.streams)
     eps = np.array([1.0 / w.L for w in ws])
     L = ws[0].L
     per_member = np.array([w.M * w.m * (w.L + 1) for w in ws], dtype=np.float64)

@@ -326,6 +326,16 @@ smc_status smc_batch_move(smc_batch b, const double* eps, int32_t L, int32_t R);
  * shapes among the active members). */
 int32_t smc_batch_launches(smc_batch b);
 
+/* Concurrency of the move's launches: smc_batch_move spreads its launches
+ * (one per kernel shape) over n streams (1 <= n <= 8, default 8): the
+ * batch's stream and n - 1 private streams that fork from it before the
+ * launches and join it after them, so that launches too small to fill the
+ * GPU run side by side; the costliest launches are placed first, each on the
+ * least loaded stream. Results do not depend on n (every member is moved by
+ * exactly one launch). n = 1 issues everything on the batch's stream. With
+ * timing on, the launches run one after another on the batch's stream. */
+smc_status smc_batch_set_streams(smc_batch b, int32_t n);
+
 /* Graph replay of the move: with on = 1, smc_batch_move captures its
  * launches into a HIP graph (they take their arguments from tables uploaded
  * before each move) and replays it for every move with the same launch

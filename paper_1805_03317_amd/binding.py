@@ -42,7 +42,7 @@ EXPORTS = [
     "loglik_est", "loglik_grad", "smc_refresh", "smc_get_info", "smc_set_stage", "smc_set_mass",
     "smc_get_mass", "smc_get_cv", "smc_full_loglik", "smc_destroy", "smc_status_string",
     "smc_last_error", "smc_batch_workspace_size", "smc_batch_create", "smc_batch_temper", "smc_batch_mass",
-    "smc_batch_resample", "smc_batch_move", "smc_batch_launches", "smc_batch_set_graph", "smc_batch_graph_captures",
+    "smc_batch_resample", "smc_batch_move", "smc_batch_launches", "smc_batch_set_graph", "smc_batch_set_streams", "smc_batch_graph_captures",
     "smc_batch_set_timing", "smc_batch_move_timing",
     "smc_batch_destroy", "smc_batch_last_error",
 ]
@@ -98,6 +98,7 @@ def lib():
     L.smc_batch_move.argtypes = [vp, vp, i32, i32]
     L.smc_batch_launches.argtypes = [vp]
     L.smc_batch_set_graph.argtypes = [vp, i32]
+    L.smc_batch_set_streams.argtypes = [vp, i32]
     L.smc_batch_graph_captures.argtypes = [vp]
     L.smc_batch_set_timing.argtypes = [vp, i32]
     L.smc_batch_move_timing.argtypes = [vp, i32, vp, vp, vp, vp]
@@ -439,6 +440,10 @@ class SMCBatch:
 
     def set_graph(self, on=True):
         self._check(lib().smc_batch_set_graph(self._h, 1 if on else 0))
+
+    def set_streams(self, n):
+        """Streams the move's launches are spread over (1..8)."""
+        self._check(lib().smc_batch_set_streams(self._h, int(n)))
 
     def graph_captures(self):
         return int(lib().smc_batch_graph_captures(self._h))

@@ -10,6 +10,7 @@
 #include <algorithm>
 #include <map>
 #include <new>
+#include <numeric>
 #include <vector>
 
 #include "../../include/subsmc.h"
@@ -168,6 +169,13 @@ struct smc_batch_s {
   hipGraphExec_t gexec = nullptr;
   std::vector<long long> graph_key;
   int graph_captures = 0;
+  // the move's launches spread over `lanes` streams (the batch's stream and
+  // lanes - 1 private ones), forked from and joined back to the batch's
+  // stream, so that launches too small to fill the chip overlap
+  int lanes = 8;
+  std::vector<hipStream_t> side;  // lanes - 1 private streams
+  hipEvent_t fork = nullptr;
+  std::vector<hipEvent_t> join;
   char err[512] = {0};
 };
 
@@ -1460,7 +1468,7 @@ smc_status smc_batch_move(smc_batch b, const double* eps, int32_t L, int32_t R) 
   }
   for (int r = 0; r < R; ++r) {
     Tables T(b);
-    struct Launch { KernelShape s; size_t off, foff; int n, grid; size_t lds; };
+    struct Launch { KernelShape s; size_t off, foff; int n, grid; size_t lds; double cost; };
     std::vector<Launch> launches;
     for (const auto& g : groups) {
       const KernelShape& s = g.first;
@@ -1469,8 +1477,11 @@ smc_status smc_batch_move(smc_batch b, const double* eps, int32_t L, int32_t R) 
       size_t lds = 0;
       std::vector<MoveArgs> ma;
       std::vector<ResMoveArgs> rma;
+      double cost = 0.0;
       for (size_t q = 0; q < mem.size(); ++q) {
         smc_ctx c = b->ctx[mem[q]];
+        // rough work of the member: its row bytes over the move's passes
+        cost += (double)c->pb.M * c->pb.m * (L + 1) * (c->pb.d + 2) * (s.fp32 ? 4.0 : 8.0);
         const MoveArgs a = move_args(c, eps[mem[q]], L);
         if (s.kind == kMoveResident) {
           rma.push_back(ResMoveArgs{a, c->res_ly});
@@ -1488,7 +1499,35 @@ smc_status smc_batch_move(smc_batch b, const double* eps, int32_t L, int32_t R) 
       l.n = (int)mem.size();
       l.grid = first.back();
       l.lds = lds;
+      l.cost = cost;
       launches.push_back(l);
+    }
+    // launch -> stream: the costliest first, each onto the least loaded
+    // stream (lane 0 is the stream the move is issued on)
+    const int nl = b->timing ? 1 : std::min<int>(b->lanes, (int)launches.size());
+    std::vector<int> lane_of(launches.size(), 0);
+    {
+      std::vector<size_t> order(launches.size());
+      std::iota(order.begin(), order.end(), (size_t)0);
+      std::stable_sort(order.begin(), order.end(),
+                       [&](size_t x, size_t y) { return launches[x].cost > launches[y].cost; });
+      std::vector<double> load((size_t)std::max(nl, 1), 0.0);
+      for (size_t q : order) {
+        const int j = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        lane_of[q] = j;
+        load[j] += launches[q].cost;
+      }
+    }
+    while ((int)b->side.size() < nl - 1) {
+      hipStream_t sd;
+      BATCH_TRY(b, hipStreamCreateWithFlags(&sd, hipStreamNonBlocking));
+      b->side.push_back(sd);
+    }
+    if (nl > 1 && !b->fork) BATCH_TRY(b, hipEventCreateWithFlags(&b->fork, hipEventDisableTiming));
+    while ((int)b->join.size() < nl - 1) {
+      hipEvent_t e;
+      BATCH_TRY(b, hipEventCreateWithFlags(&e, hipEventDisableTiming));
+      b->join.push_back(e);
     }
     smc_status st = T.upload();
     if (st != SMC_OK) return st;
@@ -1499,14 +1538,33 @@ smc_status smc_batch_move(smc_batch b, const double* eps, int32_t L, int32_t R) 
         return launch_move_wide_batch(l.s, l.grid, l.lds, batch_of<MoveArgs>(T, l.off, l.foff, l.n), st);
       return launch_move_narrow_batch(l.s, l.grid, l.lds, batch_of<MoveArgs>(T, l.off, l.foff, l.n), st);
     };
+    // every launch, forked from and joined back to `main`
+    auto issue_all = [&](hipStream_t main) -> hipError_t {
+      hipError_t e = hipSuccess;
+      if (nl > 1) {
+        if ((e = hipEventRecord(b->fork, main)) != hipSuccess) return e;
+        for (int j = 1; j < nl; ++j)
+          if ((e = hipStreamWaitEvent(b->side[j - 1], b->fork, 0)) != hipSuccess) return e;
+      }
+      for (size_t li = 0; li < launches.size(); ++li) {
+        const hipStream_t st = lane_of[li] == 0 ? main : b->side[lane_of[li] - 1];
+        if ((e = issue(launches[li], st)) != hipSuccess) return e;
+      }
+      for (int j = 1; j < nl; ++j) {
+        if ((e = hipEventRecord(b->join[j - 1], b->side[j - 1])) != hipSuccess) return e;
+        if ((e = hipStreamWaitEvent(main, b->join[j - 1], 0)) != hipSuccess) return e;
+      }
+      return hipSuccess;
+    };
     if (b->use_graph && !b->timing) {
       // the launches read their arguments from the uploaded tables, so a graph
       // captured once replays any move with the same launch structure
       std::vector<long long> key;
-      for (const Launch& l : launches) {
-        const long long v[12] = {l.s.kind, l.s.fp32, l.s.fam, l.s.dc, l.s.lanes, l.s.ch, l.s.rpl,
-                                 l.grid, (long long)l.lds, l.n, (long long)l.off, (long long)l.foff};
-        key.insert(key.end(), v, v + 12);
+      for (size_t li = 0; li < launches.size(); ++li) {
+        const Launch& l = launches[li];
+        const long long v[13] = {l.s.kind, l.s.fp32, l.s.fam, l.s.dc, l.s.lanes, l.s.ch, l.s.rpl,
+                                 l.grid, (long long)l.lds, l.n, (long long)l.off, (long long)l.foff, lane_of[li]};
+        key.insert(key.end(), v, v + 13);
       }
       if (!b->gexec || key != b->graph_key) {
         if (b->gexec) {
@@ -1517,11 +1575,7 @@ smc_status smc_batch_move(smc_batch b, const double* eps, int32_t L, int32_t R) 
         // the null stream, which cannot capture); nothing runs during capture
         if (!b->capture) BATCH_TRY(b, hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking));
         BATCH_TRY(b, hipStreamBeginCapture(b->capture, hipStreamCaptureModeThreadLocal));
-        hipError_t le = hipSuccess;
-        for (const Launch& l : launches) {
-          le = issue(l, b->capture);
-          if (le != hipSuccess) break;
-        }
+        const hipError_t le = issue_all(b->capture);
         hipGraph_t g = nullptr;
         const hipError_t ce = hipStreamEndCapture(b->capture, &g);
         BATCH_TRY(b, le);
@@ -1533,17 +1587,26 @@ smc_status smc_batch_move(smc_batch b, const double* eps, int32_t L, int32_t R) 
         b->graph_captures += 1;
       }
       BATCH_TRY(b, hipGraphLaunch(b->gexec, b->stream));
-    } else {
+    } else if (b->timing) {
+      // one after another, each between its own event pair
       for (size_t li = 0; li < launches.size(); ++li) {
-        hipEvent_t* ev = b->timing ? &b->ev[2 * ((size_t)r * ng + li)] : nullptr;
-        if (ev) BATCH_TRY(b, hipEventRecord(ev[0], b->stream));
+        hipEvent_t* ev = &b->ev[2 * ((size_t)r * ng + li)];
+        BATCH_TRY(b, hipEventRecord(ev[0], b->stream));
         BATCH_TRY(b, issue(launches[li], b->stream));
-        if (ev) BATCH_TRY(b, hipEventRecord(ev[1], b->stream));
+        BATCH_TRY(b, hipEventRecord(ev[1], b->stream));
       }
+    } else {
+      BATCH_TRY(b, issue_all(b->stream));
     }
     for (int k : b->active) b->ctx[k]->move += 1;
     if (b->timing) b->timed_moves += 1;
   }
+  return SMC_OK;
+}
+
+smc_status smc_batch_set_streams(smc_batch b, int32_t n) {
+  if (!b || n < 1 || n > 8) return SMC_ERR_INVALID_ARG;
+  b->lanes = n;
   return SMC_OK;
 }
 
@@ -1600,6 +1663,12 @@ void smc_batch_destroy(smc_batch b) {
   for (hipEvent_t e : b->ev) (void)hipEventDestroy(e);
   if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
   if (b->capture) (void)hipStreamDestroy(b->capture);
+  for (hipStream_t sd : b->side) {
+    (void)hipStreamSynchronize(sd);
+    (void)hipStreamDestroy(sd);
+  }
+  if (b->fork) (void)hipEventDestroy(b->fork);
+  for (hipEvent_t e : b->join) (void)hipEventDestroy(e);
   if (b->host) (void)hipHostFree(b->host);
   delete b;
 }

@@ -203,6 +203,43 @@ def test_graph_replay_equals_direct_launches():
             np.testing.assert_array_equal(x, y)
 
 
+@pytest.mark.parametrize("graph", [False, True], ids=["direct", "graph"])
+def test_concurrent_launches_equal_serial(graph):
+    """The move's launches spread over several streams (forked from and
+    joined back to the batch's stream) give the one-stream results bit for
+    bit, with and without graph replay."""
+    B = _binding()
+    ws = W.batched_small(6, seed=5, precision=W.MIXED, d_values=[4, 11, 34, 20, 45, 7])
+    paths = [0, B.MOVE_STREAMING, 0, 0, 0, B.MOVE_STREAMING]
+    centres = [_oracle_problem(w)[1] for w in ws]
+    out = []
+    for n in (1, 4, 8):
+        members = [_context(w, tb, mp) for w, tb, mp in zip(ws, centres, paths)]
+        batch = B.SMCBatch(members)
+        batch.set_graph(graph)
+        batch.set_streams(n)
+        logzs, recs = batch.run(_eps, L=ws[0].L, R=2, max_stages=10)
+        say("streams", n, "launches", batch.launches(), "stages", [len(r) for r in recs])
+        out.append((logzs, [[r["a"] for r in rec] for rec in recs], [_state(m) for m in members]))
+        batch.close()
+        for m in members:
+            m.close()
+    for lz, t, st in out[1:]:
+        assert lz == out[0][0] and t == out[0][1]
+        for a, b in zip(st, out[0][2]):
+            for x, y in zip(a, b):
+                np.testing.assert_array_equal(x, y)
+    B2 = _binding()
+    with pytest.raises(B2.SMCError):
+        mem = [_context(ws[0], centres[0])]
+        bt = B2.SMCBatch(mem)
+        try:
+            bt.set_streams(9)
+        finally:
+            bt.close()
+            mem[0].close()
+
+
 def test_heterogeneous_batch_equals_single_context_runs():
     """One batch mixing families (logistic, Poisson, Student-t), precisions
     (FP64 and mixed) and widths (narrow, lane-group and resident kernels):
