@@ -465,13 +465,21 @@ __device__ __forceinline__ void move_body(const MoveArgs& A, const int i) {
 // for every member of a batch, the member's argument block copied in first).
 // --------------------------------------------------------------------------
 
+// Wavefronts per SIMD the streaming moves are compiled for. With float rows
+// two fit (at most 256 registers per lane, a few spilled for the widest
+// logistic shapes), which hides more of the random row reads: measured 27%
+// faster at d = 50, 8% at d = 30. The double-row kernels stay at one: their
+// rows need the whole register file and spilling them halves their speed.
+template <typename Real>
+constexpr int kMoveWaves = sizeof(Real) == 4 ? 2 : 1;
+
 template <typename Real, int DC, int FAM>
-__global__ void __launch_bounds__(kWave) move_kernel(MoveArgs A) {
+__global__ void __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(kMoveWaves<Real>))) move_kernel(MoveArgs A) {
   move_body<Real, DC, FAM>(A, blockIdx.x);
 }
 
 template <typename Real, int DC, int FAM>
-__global__ void __launch_bounds__(kWave) move_kernel_batch(Batch<MoveArgs> B) {
+__global__ void __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(kMoveWaves<Real>))) move_kernel_batch(Batch<MoveArgs> B) {
   const int k = batch_member(B.first, B.count, blockIdx.x);
   const MoveArgs A = B.args[k];
   move_body<Real, DC, FAM>(A, blockIdx.x - B.first[k]);

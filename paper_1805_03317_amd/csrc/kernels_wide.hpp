@@ -520,12 +520,12 @@ __device__ __forceinline__ void move_wide_body(const MoveArgs& A, const int i) {
 }
 
 template <typename Real, int G, int CH, int FAM>
-__global__ void __launch_bounds__(kWave) move_kernel_wide(MoveArgs A) {
+__global__ void __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(kMoveWaves<Real>))) move_kernel_wide(MoveArgs A) {
   move_wide_body<Real, G, CH, FAM>(A, blockIdx.x);
 }
 
 template <typename Real, int G, int CH, int FAM>
-__global__ void __launch_bounds__(kWave) move_kernel_wide_batch(Batch<MoveArgs> B) {
+__global__ void __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(kMoveWaves<Real>))) move_kernel_wide_batch(Batch<MoveArgs> B) {
   const int k = batch_member(B.first, B.count, blockIdx.x);
   const MoveArgs A = B.args[k];
   move_wide_body<Real, G, CH, FAM>(A, blockIdx.x - B.first[k]);
