@@ -145,22 +145,28 @@ __device__ __forceinline__ float exp_minus_one_wide(float D) {
   return __builtin_fmaf(p, kLn2 * r, p) - 1.0f;
 }
 
-// E2 = e^D - 1 - D and E3 = e^D - 1 - D - D^2/2
+// E2 = e^D - 1 - D and E3 = e^D - 1 - D - D^2/2: the Taylor series below
+// |D| = series_exp, e^D - 1 beyond. Every lane evaluates the series (no
+// change of the execution mask, so the series schedules together with the
+// surrounding arithmetic); the exponential branch runs only when some lane of
+// the wavefront needs it, and each lane keeps the result of its own branch.
 template <typename T>
 __device__ __forceinline__ void exp_remainders(T D, T& E2, T& E3) {
   const T aD = D < T(0) ? -D : D;
-  if (aD < Tol<T>::series_exp) {
-    T acc = T(0);
+  T acc = T(0);
 #pragma unroll
-    for (int k = Tol<T>::n_exp; k >= 3; --k) acc = acc * D + inv_fact<T>(k);
-    E3 = acc * D * D * D;
-    E2 = E3 + T(0.5) * D * D;
-  } else {
+  for (int k = Tol<T>::n_exp; k >= 3; --k) acc = acc * D + inv_fact<T>(k);
+  E3 = acc * D * D * D;
+  E2 = E3 + T(0.5) * D * D;
+  const bool wide = !(aD < Tol<T>::series_exp);  // NaN takes this branch too
+  if (__any(wide)) {
     T em1;
     if constexpr (sizeof(T) == 4) em1 = exp_minus_one_wide(D);
     else em1 = dev_expm1(D);
-    E2 = em1 - D;
-    E3 = E2 - T(0.5) * D * D;
+    const T E2w = em1 - D;
+    const T E3w = E2w - T(0.5) * D * D;
+    E2 = wide ? E2w : E2;
+    E3 = wide ? E3w : E3;
   }
 }
 
