@@ -965,8 +965,11 @@ smc_status smc_autotune_move(smc_ctx c, double eps, int32_t L, int32_t* rpl_out,
                        {pb.lhat, c->at<double>(c->lay.lh2), M * 8}, {pb.sig2, c->at<double>(c->lay.sg2), M * 8},
                        {c->at<double>(c->lay.grad_l), c->at<double>(c->lay.gl2), M * d * 8},
                        {c->at<double>(c->lay.grad_s), c->at<double>(c->lay.gs2), M * d * 8}};
+  // the accept flags go through host memory (no spare device buffer of their
+  // size); plain synchronous copies after the stream has drained
   std::vector<int32_t> acc(M * 2);
-  HIP_TRY(c, hipMemcpyAsync(acc.data(), pb.accept, M * 2 * 4, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  HIP_TRY(c, hipMemcpy(acc.data(), pb.accept, M * 2 * 4, hipMemcpyDeviceToHost));
   for (const Buf& b : bufs) HIP_TRY(c, hipMemcpyAsync(b.saved, b.live, b.bytes, hipMemcpyDeviceToDevice, c->stream));
   auto restore = [&]() -> hipError_t {
     for (const Buf& b : bufs) {
@@ -993,8 +996,8 @@ smc_status smc_autotune_move(smc_ctx c, double eps, int32_t L, int32_t* rpl_out,
     }
   }
   if (err == hipSuccess) err = restore();
-  if (err == hipSuccess) err = hipMemcpyAsync(pb.accept, acc.data(), M * 2 * 4, hipMemcpyHostToDevice, c->stream);
   if (err == hipSuccess) err = hipStreamSynchronize(c->stream);
+  if (err == hipSuccess) err = hipMemcpy(pb.accept, acc.data(), M * 2 * 4, hipMemcpyHostToDevice);
   c->move = move0;
   int best = -1;
   float best_ms = 0.f;
