@@ -556,7 +556,7 @@ static double logsumexp(int32_t M, const double *v)
 static int reweight(int32_t M, const double *lhat, const double *sig2, double *logw, double a_prev,
                     double a, double *a_out, double *dlogz_out, double *ess_out)
 {
-    double *lw = malloc(sizeof(double) * (size_t)M);
+    double *lw = calloc((size_t)M + 1, sizeof(double));
     for (int32_t i = 0; i < M; ++i) lw[i] = logw[i] + incr(a, a_prev, lhat[i], sig2[i]);
     double lse_new = logsumexp(M, lw);
     double lse_old = logsumexp(M, logw);
@@ -843,7 +843,7 @@ static void move_one(const orc_data *D, const orc_cv *cv, const orc_move_cfg *K,
     free(ustar);
 
     /* 2. theta | u: HMC with inverse mass matrix Sigma */
-    double p[512], z[512], g0[512], th1[512], v[512];
+    double p[512], z[512] = {0}, g0[512], th1[512], v[512];
     for (int k = 0; k < d; ++k) z[k] = rng_normal(seed, 6, st, mv, ds, (uint64_t)i, (uint64_t)k);
     solve_upper_from_lower(d, K->Lchol, z, p); /* p ~ N(0, Sigma^{-1}) */
     orc_est e0, e1;
