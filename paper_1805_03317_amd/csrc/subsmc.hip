@@ -233,7 +233,13 @@ smc_status validate(const smc_problem* pb) {
 int res_candidates(bool fp32, int dc, int family, int out[2]) {
   if (dc > 24) return 0;
   out[0] = 0;
-  if (fp32 && family == SMC_POISSON && dc <= 20) { out[1] = 14; return 2; }
+  // 14 register rows per lane: FP32 rows whose remainder leaves the register
+  // file room for them (the logistic remainder needs more registers than the
+  // Poisson one; at d = 20 its rows would spill)
+  if (fp32 && ((family == SMC_POISSON && dc <= 20) || (family == SMC_LOGISTIC && dc <= 16))) {
+    out[1] = 14;
+    return 2;
+  }
   return 1;
 }
 

@@ -321,6 +321,8 @@ MOVE_CASES = [
                                                     L=4), 1.0, 0.05),
     ("logistic_mixed_m1500", lambda: W.logistic_small(8000, 10, seed=60, precision=W.MIXED, M=12, m=1500, G=30,
                                                       L=4), 0.7, 0.1),
+    ("logistic_mixed_m4500", lambda: W.logistic_small(20000, 12, seed=61, precision=W.MIXED, M=12, m=4500, G=50,
+                                                      L=4), 0.7, 0.05),
     ("student", lambda: W.student_small(6000, 6, seed=64, M=48, m=300, G=10, L=8), 0.8, 0.1),
     ("student_mixed_d50", lambda: W.student_small(5000, 50, seed=65, precision=W.MIXED, M=16, m=200, G=8, L=5,
                                                   theta_scale=0.3), 0.8, 0.08),
@@ -428,6 +430,11 @@ def test_autotune_restores_state_and_keeps_parity():
 def test_resident_path_is_selected():
     B = _binding()
     w = W.poisson_small(30000, 20, seed=59, precision=W.MIXED, M=8, m=5000, G=100)
+    P, smc = make_pair(w, move_path=B.MOVE_RESIDENT)
+    assert smc.info()["move_path"] == B.MOVE_RESIDENT
+    smc.close()
+    # logistic d = 12 with 4500 rows: only the layout with 14 register rows per lane fits
+    w = W.logistic_small(20000, 12, seed=61, precision=W.MIXED, M=8, m=4500, G=50)
     P, smc = make_pair(w, move_path=B.MOVE_RESIDENT)
     assert smc.info()["move_path"] == B.MOVE_RESIDENT
     smc.close()
