@@ -227,15 +227,13 @@ smc_status validate(const smc_problem* pb) {
 // ------------------------------------------------------------------------
 
 // register-row candidates for (precision, padded d, family) of the resident
-// move: the shapes instantiated in launch_resident.hip (the logistic
-// remainder needs the registers the row cache would use, so logistic keeps
-// all rows in LDS)
+// move: the shapes instantiated in launch_resident.hip. All rows in LDS
+// always; 14 register rows per lane for FP32 rows whose remainder leaves the
+// register file room for them (the logistic remainder needs more registers
+// than the Poisson one: at d = 20 its rows would spill)
 int res_candidates(bool fp32, int dc, int family, int out[2]) {
   if (dc > 24) return 0;
   out[0] = 0;
-  // 14 register rows per lane: FP32 rows whose remainder leaves the register
-  // file room for them (the logistic remainder needs more registers than the
-  // Poisson one; at d = 20 its rows would spill)
   if (fp32 && ((family == SMC_POISSON && dc <= 20) || (family == SMC_LOGISTIC && dc <= 16))) {
     out[1] = 14;
     return 2;
@@ -243,27 +241,7 @@ int res_candidates(bool fp32, int dc, int family, int out[2]) {
   return 1;
 }
 
-// Smallest register-row count whose LDS part fits; -1 if the resident kernel
-// does not apply.
-int choose_resident(const smc_problem& pb, int max_lds, ResLayout& ly) {
-  if (pb.d > kMaxNarrowD || (pb.family != SMC_LOGISTIC && pb.family != SMC_POISSON)) return -1;
-  const bool fp32 = pb.precision == SMC_MIXED;
-  const int dc = pad_dc(pb.d);
-  int cand[2];
-  const int nc = res_candidates(fp32, dc, pb.family, cand);
-  for (int q = 0; q < nc; ++q) {
-    const ResLayout l = res_layout(pb.m, pb.G, dc, cand[q], fp32 ? 4 : 8, pb.d);
-    // register rows are unpredicated in the kernel: every slot must hold a row
-    const bool regs_full = pb.m >= kResLanes * cand[q];
-    if (regs_full && l.total <= max_lds && (l.nlds + kResLanes - 1) / kResLanes <= kResMaxLdsGroups) {
-      ly = l;
-      return cand[q];
-    }
-  }
-  return -1;
-}
-
-// Every register-row count whose layout fits (the candidates of choose_resident).
+// Every register-row count whose layout fits, smallest first.
 int resident_options(const smc_problem& pb, int max_lds, int rpl[2], ResLayout ly[2]) {
   if (pb.d > kMaxNarrowD || (pb.family != SMC_LOGISTIC && pb.family != SMC_POISSON)) return 0;
   const bool fp32 = pb.precision == SMC_MIXED;
@@ -273,6 +251,7 @@ int resident_options(const smc_problem& pb, int max_lds, int rpl[2], ResLayout l
   int n = 0;
   for (int q = 0; q < nc; ++q) {
     const ResLayout l = res_layout(pb.m, pb.G, dc, cand[q], fp32 ? 4 : 8, pb.d);
+    // register rows are unpredicated in the kernel: every slot must hold a row
     const bool regs_full = pb.m >= kResLanes * cand[q];
     if (regs_full && l.total <= max_lds && (l.nlds + kResLanes - 1) / kResLanes <= kResMaxLdsGroups) {
       rpl[n] = cand[q];
@@ -281,6 +260,16 @@ int resident_options(const smc_problem& pb, int max_lds, int rpl[2], ResLayout l
     }
   }
   return n;
+}
+
+// Smallest register-row count whose LDS part fits; -1 if the resident kernel
+// does not apply.
+int choose_resident(const smc_problem& pb, int max_lds, ResLayout& ly) {
+  int rpl[2];
+  ResLayout l[2];
+  if (resident_options(pb, max_lds, rpl, l) == 0) return -1;
+  ly = l[0];
+  return rpl[0];
 }
 
 // The move kernel of a context (the estimator kernels use the narrow or wide
