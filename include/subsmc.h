@@ -229,7 +229,7 @@ smc_status loglik_grad(smc_ctx ctx, int32_t count, const double* theta, const in
  * state, the accept flags and the move counter exactly, and keeps the fastest
  * for later moves (single and batched). *rpl_out (nullable) receives the
  * choice: -1 streaming, else the register rows per lane of the resident
- * kernel; ms_out (nullable, up to 3 entries) the timed durations in the order
+ * kernel; ms_out (nullable, up to 4 entries) the timed durations in the order
  * streaming (when allowed), then the resident layouts. Needs a mass matrix.
  * Uses the resampling buffers of the workspace. Synchronises.
  */

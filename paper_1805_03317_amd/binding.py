@@ -237,7 +237,7 @@ class SubsampledSMC:
         -1 for streaming, the timed ms of each option)."""
         import numpy as np
         rpl = C.c_int32()
-        ms = np.zeros(3, dtype=np.float32)
+        ms = np.zeros(4, dtype=np.float32)
         self._check(lib().smc_autotune_move(self._h, float(eps), int(L), C.byref(rpl), _host_ptr(ms)))
         return rpl.value, ms
 

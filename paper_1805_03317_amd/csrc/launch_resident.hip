@@ -11,7 +11,8 @@ namespace {
   X(float, 12, 1, 14) X(float, 16, 1, 0) X(float, 16, 1, 14) X(float, 20, 1, 0) X(float, 20, 1, 14)     \
   X(float, 24, 1, 0) X(float, 4, 0, 0) X(float, 8, 0, 0) X(float, 12, 0, 0) X(float, 16, 0, 0)          \
   X(float, 20, 0, 0) X(float, 24, 0, 0) X(float, 4, 0, 14) X(float, 8, 0, 14) X(float, 12, 0, 14)      \
-  X(float, 16, 0, 14)                                                                                   \
+  X(float, 16, 0, 14) X(float, 4, 1, 4) X(float, 8, 1, 4) X(float, 12, 1, 4) X(float, 16, 1, 4)        \
+  X(float, 20, 1, 4) X(float, 4, 0, 4) X(float, 8, 0, 4) X(float, 12, 0, 4) X(float, 16, 0, 4)          \
   X(double, 4, 0, 0) X(double, 8, 0, 0) X(double, 12, 0, 0) X(double, 16, 0, 0) X(double, 20, 0, 0)     \
   X(double, 24, 0, 0) X(double, 4, 1, 0) X(double, 8, 1, 0) X(double, 12, 1, 0) X(double, 16, 1, 0)     \
   X(double, 20, 1, 0) X(double, 24, 1, 0)

@@ -227,26 +227,30 @@ smc_status validate(const smc_problem* pb) {
 // ------------------------------------------------------------------------
 
 // register-row candidates for (precision, padded d, family) of the resident
-// move: the shapes instantiated in launch_resident.hip. All rows in LDS
-// always; 14 register rows per lane for FP32 rows whose remainder leaves the
-// register file room for them (the logistic remainder needs more registers
-// than the Poisson one: at d = 20 its rows would spill)
-int res_candidates(bool fp32, int dc, int family, int out[2]) {
+// move, smallest first: the shapes instantiated in launch_resident.hip. All
+// rows in LDS always; 4 or 14 register rows per lane for FP32 rows whose
+// remainder leaves the register file room for them (the logistic remainder
+// needs more registers than the Poisson one: at d = 20 its rows would spill).
+// 4 covers the subsamples just too large for LDS alone, 14 the largest.
+constexpr int kResMaxOptions = 3;
+
+int res_candidates(bool fp32, int dc, int family, int out[kResMaxOptions]) {
   if (dc > 24) return 0;
   out[0] = 0;
   if (fp32 && ((family == SMC_POISSON && dc <= 20) || (family == SMC_LOGISTIC && dc <= 16))) {
-    out[1] = 14;
-    return 2;
+    out[1] = 4;
+    out[2] = 14;
+    return 3;
   }
   return 1;
 }
 
 // Every register-row count whose layout fits, smallest first.
-int resident_options(const smc_problem& pb, int max_lds, int rpl[2], ResLayout ly[2]) {
+int resident_options(const smc_problem& pb, int max_lds, int rpl[kResMaxOptions], ResLayout ly[kResMaxOptions]) {
   if (pb.d > kMaxNarrowD || (pb.family != SMC_LOGISTIC && pb.family != SMC_POISSON)) return 0;
   const bool fp32 = pb.precision == SMC_MIXED;
   const int dc = pad_dc(pb.d);
-  int cand[2];
+  int cand[kResMaxOptions];
   const int nc = res_candidates(fp32, dc, pb.family, cand);
   int n = 0;
   for (int q = 0; q < nc; ++q) {
@@ -265,8 +269,8 @@ int resident_options(const smc_problem& pb, int max_lds, int rpl[2], ResLayout l
 // Smallest register-row count whose LDS part fits; -1 if the resident kernel
 // does not apply.
 int choose_resident(const smc_problem& pb, int max_lds, ResLayout& ly) {
-  int rpl[2];
-  ResLayout l[2];
+  int rpl[kResMaxOptions];
+  ResLayout l[kResMaxOptions];
   if (resident_options(pb, max_lds, rpl, l) == 0) return -1;
   ly = l[0];
   return rpl[0];
@@ -946,8 +950,8 @@ smc_status smc_autotune_move(smc_ctx c, double eps, int32_t L, int32_t* rpl_out,
     int dev = 0, max_lds = 0;
     HIP_TRY(c, hipGetDevice(&dev));
     HIP_TRY(c, hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
-    int r[2];
-    ResLayout l[2];
+    int r[kResMaxOptions];
+    ResLayout l[kResMaxOptions];
     const int n = resident_options(pb, max_lds, r, l);
     for (int q = 0; q < n; ++q) {
       rpl.push_back(r[q]);

@@ -323,6 +323,8 @@ MOVE_CASES = [
                                                       L=4), 0.7, 0.1),
     ("logistic_mixed_m4500", lambda: W.logistic_small(20000, 12, seed=61, precision=W.MIXED, M=12, m=4500, G=50,
                                                       L=4), 0.7, 0.05),
+    ("poisson_mixed_m3000", lambda: W.poisson_small(20000, 12, seed=62, precision=W.MIXED, M=12, m=3000, G=30,
+                                                    L=4), 1.0, 0.05),
     ("student", lambda: W.student_small(6000, 6, seed=64, M=48, m=300, G=10, L=8), 0.8, 0.1),
     ("student_mixed_d50", lambda: W.student_small(5000, 50, seed=65, precision=W.MIXED, M=16, m=200, G=8, L=5,
                                                   theta_scale=0.3), 0.8, 0.08),
@@ -414,8 +416,8 @@ def test_autotune_restores_state_and_keeps_parity():
         assert torch.equal(a, b)
     info1 = smc.info()
     assert info1["move"] == info0["move"] and info1["stage"] == info0["stage"]
-    # 0 register rows would need all 5000 rows in LDS: only streaming and 14 fit
-    assert rpl in (-1, 14) and (ms[:2] > 0).all() and ms[2] == 0
+    # 0 or 4 register rows would leave too many of the 5000 rows for LDS: only streaming and 14 fit
+    assert rpl in (-1, 14) and (ms[:2] > 0).all() and (ms[2:] == 0).all()
     assert info1["move_path"] == (1 if rpl < 0 else 2)
     smc.move(0.1, w.L, 1)
     torch.cuda.synchronize()
@@ -430,6 +432,11 @@ def test_autotune_restores_state_and_keeps_parity():
 def test_resident_path_is_selected():
     B = _binding()
     w = W.poisson_small(30000, 20, seed=59, precision=W.MIXED, M=8, m=5000, G=100)
+    P, smc = make_pair(w, move_path=B.MOVE_RESIDENT)
+    assert smc.info()["move_path"] == B.MOVE_RESIDENT
+    smc.close()
+    # Poisson d = 12 with 3000 rows: too many for LDS alone, too few for 14 register rows; 4 fit
+    w = W.poisson_small(20000, 12, seed=62, precision=W.MIXED, M=8, m=3000, G=30)
     P, smc = make_pair(w, move_path=B.MOVE_RESIDENT)
     assert smc.info()["move_path"] == B.MOVE_RESIDENT
     smc.close()
