@@ -103,6 +103,8 @@ def lib():
                                      C.POINTER(C.c_double), C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                                      C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_double)]
         L.orc_num_threads.restype = C.c_int
+        L.orc_set_num_threads.argtypes = [C.c_int]
+        L.orc_set_num_threads.restype = None
         _lib = L
     return _lib
 
@@ -167,6 +169,15 @@ class Problem:
     def set_cv_centre(self, theta_bar):
         self.theta_bar = np.ascontiguousarray(theta_bar, dtype=np.float64)
         self.A, self.B, self.C = self.cv_build(self.theta_bar)
+        self._cv = _CV(_dp(self.theta_bar), self.A, _dp(self.B), _dp(self.C))
+
+    def set_cv(self, theta_bar, A, B, Cm):
+        """Control-variate centre and summaries given directly (timing runs that build them from a
+        row subset; results then are not those of the full-data control variate)."""
+        self.theta_bar = np.ascontiguousarray(theta_bar, dtype=np.float64)
+        self.A = float(A)
+        self.B = np.ascontiguousarray(B, dtype=np.float64)
+        self.C = np.ascontiguousarray(Cm, dtype=np.float64)
         self._cv = _CV(_dp(self.theta_bar), self.A, _dp(self.B), _dp(self.C))
 
     # per-observation remainder --------------------------------------------
@@ -322,6 +333,11 @@ def move(prob, theta, u, a, eps, L, seed, stage, mv, G, Sigma, Lchol, i0=0, diag
 
 def num_threads():
     return int(lib().orc_num_threads())
+
+
+def set_num_threads(n):
+    """Threads of the oracle's loops over particles (timing only; no effect on results)."""
+    lib().orc_set_num_threads(int(n))
 
 
 # ---------------------------------------------------------------------------

@@ -914,6 +914,17 @@ int orc_move_range(const orc_data *D, const orc_cv *cv, const orc_move_cfg *K, d
     return ORC_OK;
 }
 
+/* Threads the parallel loops over particles use from now on (timing only). */
+void orc_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    extern void omp_set_num_threads(int);
+    omp_set_num_threads(n > 0 ? n : 1);
+#else
+    (void)n;
+#endif
+}
+
 int orc_num_threads(void)
 {
 #ifdef _OPENMP
