@@ -12,6 +12,11 @@ second; a move does M * m * (L + 1) of them (one estimator pass for the
 u-refresh and one per leapfrog step). `value` is the mixed-precision path
 (FP32 data and per-observation terms, FP64 control variates, reductions and
 accept ratios); the plain FP64 path on the same data is reported beside it.
+
+With no flags the line is the additive logistic model (n = 5e6, d = 116,
+M = 4096, m = 50,000, L = 20), the largest configuration; the logistic
+d = 50 (n = 1e7) and Poisson d = 20 (n = 1e6) configurations are reported
+beside it under "beside".
 """
 import argparse
 import json
@@ -26,13 +31,16 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
-# Vector ALU peak without packed FP32: 256 CUs x 4 SIMDs x 16 lanes x 2 flops
-# (FMA) x 2.4 GHz. The FP32 contractions run as plain (non-packed) FMAs, so
-# this, not the packed 157.3 TFLOP/s figure, is their attainable peak; it is
-# also the FP64 vector peak.
-PEAK_VALU_TFLOPS = 78.6
-PEAK_VALU_PACKED_TFLOPS = 157.3
+# Published FP32 vector peak of the chip: 256 CUs x 4 SIMDs x 16 lanes x 2 flops
+# (FMA) x 2 (packed dual FP32) x 2.4 GHz. The kernels issue no packed FP32
+# instructions, so their attainable vector rate is half of it (78.6 TFLOP/s,
+# also the FP64 vector peak); that view is reported beside the fraction.
+PEAK_FP32_TFLOPS = 157.3
+PEAK_VALU_NONPACKED_TFLOPS = 78.6
 MOVE_STREAMING, MOVE_RESIDENT = 1, 2
+HEADLINE = "config5"
+BESIDE = ("config4", "config2")
+METRIC = "particle-obs loglik+grad evals/s (mixed vs FP64 plain, <=1e-5 rel err)"
 
 
 def parse():
@@ -50,10 +58,18 @@ def parse():
     ap.add_argument("--streams", type=int, default=8,
                     help="batched workload: streams the move's launches are spread over (1 = one after another)")
     ap.add_argument("--workload", choices=["config1", "config2", "batched", "config4", "config5", "student"],
-                    default="config2",
-                    help="config2 (Poisson n=1e6 d=20) is the benchmark workload; the others are the "
-                         "logistic d=5 FP64, logistic d=50 and additive logistic d=116 configurations and "
-                         "the Student-t regression n=5e5 d=50")
+                    default=HEADLINE,
+                    help="config5 (additive logistic n=5e6 d=116, the largest configuration) is the default "
+                         "line, with config4 and config2 beside it; the others are the logistic d=5 FP64, "
+                         "Poisson d=20, logistic d=50 configurations, the 64-dataset batch and the Student-t "
+                         "regression n=5e5 d=50")
+    ap.add_argument("--no-beside", action="store_true", help="default line only: skip config4 and config2")
+    ap.add_argument("--move-path", type=int, choices=[0, 1, 2, 3], default=0,
+                    help="move kernel: 0 automatic, 1 streaming, 2 resident, 3 resident with x'delta on the "
+                         "matrix cores")
+    ap.add_argument("--autotune", action="store_true",
+                    help="after the warm-up steps, time every move kernel option on the live state "
+                         "(smc_autotune_move), report the times and keep the fastest for the timed steps")
     ap.add_argument("--schemes", choices=["default", "paper"], default="default",
                     help="default: ESS root search (target M/2) and systematic resampling; paper: the grid "
                          "rule with target 0.8 M (129 points) and multinomial resampling")
@@ -75,10 +91,12 @@ def algorithmic_bytes_per_eval(d, fp32):
 
 
 def algorithmic_flops_per_eval(d):
-    """The three length-d contractions of one eval: Delta = x'delta, S1 += d' x
-    and T1 += (d - shift) d' x, one FMA (2 flops) per element each. The scalar
+    """Four length-d contractions per eval (2 flops per element each): the
+    linear predictor at the centre and at theta (x'theta_bar, x'delta), and the
+    two gradient sums S1 += d' x and T1 += (d - shift) d' x. The kernels store
+    x'theta_bar in the packed row, so they execute 6d of these 8d; the scalar
     remainder and the FP64 sums are not counted."""
-    return 6 * d
+    return 8 * d
 
 
 def calibrate_copy():
@@ -96,8 +114,9 @@ def run_path(w, precision, Xy_dev, args, eps):
     import torch
     from paper_1805_03317_amd.binding import SubsampledSMC
 
+    path = args.move_path if (precision == 1 or args.move_path != 3) else 0
     smc = SubsampledSMC(Xy_dev, w.d, w.family, precision, w.M, w.m, w.G, w.prior_mean, w.prior_prec, w.seed,
-                        cv_order=args.cv_order)
+                        cv_order=args.cv_order, move_path=path)
     evals_per_move = w.M * w.m * (w.L + 1)
     state = {"tempered": 0}
 
@@ -126,6 +145,14 @@ def run_path(w, precision, Xy_dev, args, eps):
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
+    tuned = None
+    if args.autotune:
+        if smc.info()["have_mass"] == 0:
+            smc.mass()
+        rpl, ms = smc.autotune_move(eps, w.L)
+        i = smc.info()
+        tuned = {"ms": [round(float(x), 4) for x in ms if x > 0], "res_rows": rpl, "res_mfma": i["res_mfma"],
+                 "stream_tile": i["stream_tile"]}
     # every timed move launch is bracketed by HIP events on the context's stream
     smc.set_move_timing(args.steps)
     t0 = time.perf_counter()
@@ -137,6 +164,7 @@ def run_path(w, precision, Xy_dev, args, eps):
     smc.set_move_timing(0)
     info = smc.info()
     acc = smc.accept.float().mean(0).cpu().numpy()
+    ms = smc.move_stats()
     res = {
         "evals_per_s": args.steps * evals_per_move / elapsed,
         "ms_per_step": 1e3 * elapsed / args.steps,
@@ -149,8 +177,49 @@ def run_path(w, precision, Xy_dev, args, eps):
         "accept_theta": float(acc[1]),
         "newton_iters": info["newton_iters"],
         "move_path": info["move_path"],
+        "res_rows": info["res_rows"],
+        "res_mfma": info["res_mfma"],
+        "stream_tile": info["stream_tile"],
+        "near_ties_last_move": [ms["near_ties_u"], ms["near_ties_theta"]],
     }
+    if tuned is not None:
+        res["autotune"] = tuned
     return smc, res
+
+
+def laplace_state_move(smc, w, eps, reps=10, warm=3, seed=77):
+    """The move on the fixed benchmark state at a = 1: theta_i ~ N(theta_bar, (-C - Q0)^{-1}) (the
+    Laplace approximation at the control-variate centre), u uniform, inverse mass matrix
+    (-C - Q0)^{-1}; `warm` untimed moves, then the median device time of `reps` moves, each
+    from the same state."""
+    import torch
+    tb, _, _, Cm = smc.get_cv()
+    prec = -Cm + w.prior_prec
+    cov = np.linalg.inv(prec)
+    cov = 0.5 * (cov + cov.T)
+    g = np.random.Generator(np.random.Philox(key=seed))
+    th = tb + g.standard_normal((w.M, w.d)) @ np.linalg.cholesky(cov).T
+    u = g.integers(0, w.n, size=(w.M, w.m), dtype=np.int64).astype(np.int32)
+    th_d = torch.tensor(th, device=smc.device)
+    u_d = torch.tensor(u, device=smc.device)
+    smc.set_mass(cov)
+    info = smc.info()
+    smc.set_move_timing(reps)
+    for r in range(warm + reps):
+        if r == warm:
+            smc.set_move_timing(reps)          # clears the ring: only the timed moves remain
+        smc.theta.copy_(th_d)
+        smc.u.copy_(u_d)
+        smc.refresh()
+        smc.set_stage(info["stage"], 0, 1.0, info["logz"])
+        smc.move(eps, w.L, 1)
+    torch.cuda.synchronize()
+    ms = float(np.median(smc.move_times()))
+    smc.set_move_timing(0)
+    st = smc.move_stats()
+    return {"move_ms_median": ms, "move_evals_per_s": w.M * w.m * (w.L + 1) / (ms * 1e-3),
+            "accept_u": st["accept_u"], "accept_theta": st["accept_theta"],
+            "state": "a = 1, theta ~ Laplace approximation at the centre, u uniform, Sigma = (-C - Q0)^-1"}
 
 
 DEVICE_SOURCES = ["kernels.hpp", "kernels_wide.hpp", "kernels_resident.hpp", "xlane.hpp", "glm.hpp", "rng.hpp"]
@@ -199,10 +268,10 @@ def roofline(w, fp32, move_ms, move_path):
     if move_path == MOVE_RESIDENT:
         fpe = algorithmic_flops_per_eval(w.d)
         achieved = fpe * evals / (move_ms * 1e-3) / 1e12
-        return {"bound": "alu", "achieved": round(achieved, 2), "peak": PEAK_VALU_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved / PEAK_VALU_TFLOPS, 4), "traffic": traffic, "kernel": kernel,
+        return {"bound": "alu", "achieved": round(achieved, 2), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": traffic, "kernel": kernel,
                 "flops_per_eval": fpe, "evals_per_launch": evals,
-                "frac_of_packed_fp32_peak": round(achieved / PEAK_VALU_PACKED_TFLOPS, 4)}
+                "frac_of_nonpacked_fp32_peak": round(achieved / PEAK_VALU_NONPACKED_TFLOPS, 4)}
     bpe = algorithmic_bytes_per_eval(w.d, fp32)
     achieved = bpe * evals / (move_ms * 1e-3) / 1e9
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
@@ -229,34 +298,70 @@ def run_to_end(w, precision, Xy_dev, eps, cv_order=2):
             "final_accept_theta": float(acc[1])}
 
 
-def cpu_baseline(w, count, eps, budget_s=12.0, chunk=32, cv_order=2):
-    """The oracle's move on up to `count` particles of the same workload, at
-    a = 1, in chunks of `chunk` particles until about budget_s seconds."""
+def oracle_problem(w, cv_order=2, max_cost=4e8):
+    """The oracle on the workload's data with control variates at a centre near the mode: the
+    generating parameter where known, else the oracle's Newton mode. When a full-data pass of the
+    oracle (n d^2 extended-precision products, one thread) would take minutes, the summaries are
+    built from the first rows and scaled to n (the timed move does not depend on their values
+    beyond the branch mix of the remainders), at the prior mean where no generating parameter is
+    known."""
     import oracle
-
     P = oracle.Problem(w.Xy(np.float64), w.d, w.family, w.prior_mean, w.prior_prec, cv_order=cv_order)
-    # the control-variate centre: the generating parameter where known (a point near the mode; the
-    # timing does not depend on it), else the oracle's own Newton mode
-    tb = w.theta_true if w.theta_true is not None else P.newton_mode()[0]
-    P.set_cv_centre(tb)
-    count = min(count, w.M)
-    thp, u0, _ = oracle.init_particles(count, w.d, w.m, w.n, w.seed, w.prior_mean, w.prior_prec)
-    _, B, Cm = P.cv_build(tb)
-    cov = np.linalg.inv(-Cm + w.prior_prec)
+    cost = float(w.n) * w.d * w.d
+    if cost <= max_cost:
+        tb = w.theta_true if w.theta_true is not None else P.newton_mode()[0]
+        P.set_cv_centre(tb)
+        return P, "full-data control variates"
+    n_sub = max(1000, int(max_cost / (w.d * w.d)))
+    sub = oracle.Problem(w.Xy(np.float64)[:n_sub], w.d, w.family, w.prior_mean, w.prior_prec, cv_order=cv_order)
+    tb = w.theta_true if w.theta_true is not None else np.array(w.prior_mean, dtype=np.float64)
+    A, B, Cm = sub.cv_build(tb)
+    f = w.n / n_sub
+    P.set_cv(tb, A * f, B * f, Cm * f)
+    return P, f"control variates from the first {n_sub} rows scaled to n"
+
+
+def cpu_baseline(w, eps, budget_s=12.0, cv_order=2, one_thread=True):
+    """The oracle on a bounded sample of the workload: the estimator pass with both gradients
+    (eq. difference_estimator_logl and its derivative; the eval the metric counts, m per
+    particle) of particles at the a = 1 benchmark state (Laplace approximation at the oracle's
+    centre, u uniform), a batch of one particle per host thread at a time while the budget
+    lasts; then the same on one thread. A whole move is L + 1 such passes plus the HMC
+    arithmetic (one config-5 particle's move is about a minute of one core)."""
+    import oracle
+    P, cv_note = oracle_problem(w, cv_order)
+    thp, u0, _ = oracle.init_particles(w.M, w.d, w.m, w.n, w.seed, w.prior_mean, w.prior_prec)
+    cov = np.linalg.inv(-P.C + w.prior_prec)
+    cov = 0.5 * (cov + cov.T)
     Lc = np.linalg.cholesky(cov)
-    z = (thp - w.prior_mean) @ np.linalg.cholesky(w.prior_prec)  # standard normals
-    th0 = tb + z @ Lc.T                                             # Laplace approximation draws
-    dt, done = 0.0, 0
-    while done < count and dt < budget_s:
-        k = min(chunk, count - done)
-        t0 = time.perf_counter()
-        oracle.move(P, th0[done:done + k], u0[done:done + k], 1.0, eps, w.L, w.seed, 1, 0, w.G, cov, Lc, i0=done)
-        dt += time.perf_counter() - t0
-        done += k
-    evals = done * w.m * (w.L + 1)
-    return {"value": evals / dt, "unit": "evals/s", "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": f"one Markov move of {done} of the {w.M} particles (same data, Laplace-approximation "
-                      f"state at a=1), {evals} algorithmic evals in {dt:.2f} s wall"}
+    z = (thp - w.prior_mean) @ np.linalg.cholesky(w.prior_prec)   # standard normals
+    th0 = P.theta_bar + z @ Lc.T                                   # Laplace approximation draws
+
+    def timed(threads, budget):
+        oracle.set_num_threads(threads)
+        dt, done = 0.0, 0
+        while done < w.M and (done == 0 or dt < budget):
+            k = min(threads, w.M - done)
+            t0 = time.perf_counter()
+            P.estimate(th0[done:done + k], u0[done:done + k], grad=True)
+            dt += time.perf_counter() - t0
+            done += k
+        return done, dt
+
+    threads = oracle.num_threads()
+    done, dt = timed(threads, budget_s)
+    out = {"value": done * w.m / dt, "unit": "evals/s", "cores": threads, "kind": "oracle",
+           "sample": f"the estimator pass with gradients of {done} of the {w.M} particles ({threads} at a time; "
+                     f"same data, a=1 Laplace-approximation state, {cv_note}), {done * w.m} evals "
+                     f"in {dt:.2f} s wall",
+           "evals": done * w.m, "seconds": dt}
+    if one_thread:
+        done1, dt1 = timed(1, budget_s / 2)
+        out["one_thread"] = {"value": done1 * w.m / dt1, "cores": 1,
+                             "sample": f"the same pass for {done1} particles on one thread, {done1 * w.m} evals "
+                                       f"in {dt1:.2f} s"}
+    oracle.set_num_threads(threads)
+    return out
 
 BATCH_KINDS = {0: "move_kernel_batch", 1: "move_kernel_wide_batch", 2: "move_kernel_res_batch"}
 
@@ -345,8 +450,8 @@ def batched_roofline(launches):
     t = g["ms"] * 1e-3
     if g["kernel"] == "move_kernel_res_batch":
         achieved = g["alg_flops"] / t / 1e12
-        return {"bound": "alu", "achieved": round(achieved, 2), "peak": PEAK_VALU_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved / PEAK_VALU_TFLOPS, 4), "traffic": None, "kernel": g["kernel"],
+        return {"bound": "alu", "achieved": round(achieved, 2), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": None, "kernel": g["kernel"],
                 "evals_per_launch": g["evals"], "share_of_move_time": round(g["ms"] / sum(x["ms"] for x in launches), 3)}
     achieved = g["alg_bytes"] / t / 1e9
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
@@ -420,50 +525,40 @@ def main_batched(args):
                        "roofline": batched_roofline(f["launches"]), "launches": f["launches"],
                        "mixed_over_fp64": r["evals_per_s"] / f["evals_per_s"]}
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline_batched(args.batch, 1024)
+        out["cpu_baseline"] = cpu_baseline_batched(args.batch)
     print(json.dumps(out), flush=True)
 
 
-def cpu_baseline_batched(count, per_member, budget_s=12.0):
-    """The oracle's move on `per_member` particles of members 0, 1, ... of the
-    batch until about budget_s seconds of CPU work (at least one member)."""
+def cpu_baseline_batched(count, budget_s=12.0):
+    """The oracle's move on particles of members 0, 1, ... of the batch (each as in cpu_baseline,
+    all host threads) until about budget_s seconds of CPU work (at least one member)."""
     from paper_1805_03317_amd import workloads as W
-    evals, secs, used = 0, 0.0, []
+    evals, secs, used, cores = 0, 0.0, [], 1
     for b in range(count):
         w = W.config3_member(b, count)
-        r = cpu_baseline(w, per_member, 1.0 / w.L)
-        e = per_member * w.m * (w.L + 1)
-        evals += e
-        secs += e / r["value"]
+        r = cpu_baseline(w, 1.0 / w.L, budget_s=max(0.5, budget_s - secs), one_thread=False)
+        evals += r["evals"]
+        secs += r["seconds"]
         used.append(f"{b} (n={w.n}, d={w.d})")
         cores = r["cores"]
         if secs >= budget_s:
             break
     return {"value": evals / secs, "unit": "evals/s", "cores": cores, "kind": "oracle",
-            "sample": f"one Markov move of {per_member} of the 1024 particles of members {', '.join(used)} "
-                      f"(same data, Laplace-approximation state at a=1), {evals} algorithmic evals in "
-                      f"{secs:.1f} s wall"}
+            "sample": f"the estimator pass with gradients of particles of members {', '.join(used)} (same "
+                      f"data, a=1 Laplace-approximation state), {evals} evals in {secs:.1f} s wall"}
 
 
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): sharding the particles over "
-              "several GPUs is designed but not built", file=sys.stderr)
-        sys.exit(2)
+WORKLOADS = {"config1": "config1", "config2": "config2", "config4": "config4", "config5": "config5",
+             "student": "student_t"}
+
+
+def bench_workload(name, args, cpu, e2e):
+    """Timed steps of one workload on the mixed and FP64 paths; the result line's fields."""
     import torch
     from paper_1805_03317_amd import workloads as W
 
-    if args.calibrate_copy:
-        calibrate_copy()
-        return
-    if args.workload == "batched":
-        main_batched(args)
-        return
-
     t_gen = time.perf_counter()
-    w = {"config1": W.config1, "config2": W.config2, "config4": W.config4, "config5": W.config5,
-         "student": W.student_t}[args.workload]()
+    w = getattr(W, WORKLOADS[name])()
     print(f"# generated {w.name} in {time.perf_counter() - t_gen:.1f} s", file=sys.stderr, flush=True)
     eps = 1.0 / w.L
     Xy = torch.tensor(w.Xy(np.float32 if w.precision == W.MIXED else np.float64), device="cuda:0")
@@ -480,12 +575,12 @@ def main():
     for p in paths:
         prec = W.MIXED if p == "mixed" else W.FP64
         ctxs[p], results[p] = run_path(w, prec, Xy, args, eps)
-        print(f"# {p}: {results[p]}", file=sys.stderr, flush=True)
+        print(f"# {w.name} {p}: {results[p]}", file=sys.stderr, flush=True)
 
     head = "mixed" if "mixed" in results else "fp64"
     r = results[head]
     out = {
-        "metric": "particle-obs loglik+grad evals/s (mixed vs FP64 plain, <=1e-5 rel err)",
+        "metric": METRIC,
         "value": r["evals_per_s"],
         "unit": "evals/s",
         "n_gpus": 1,
@@ -503,33 +598,72 @@ def main():
         "roofline": roofline(w, head == "mixed", r["move_ms"], r["move_path"]),
         "move_ms": r["move_ms"],
         "move_evals_per_s": r["move_evals_per_s"],
-        "run": {k: r[k] for k in ("a", "stage", "stages_tempered", "accept_u", "accept_theta", "newton_iters")},
+        "run": {k: r[k] for k in ("a", "stage", "stages_tempered", "accept_u", "accept_theta", "newton_iters",
+                                  "move_path", "res_rows", "res_mfma", "stream_tile", "near_ties_last_move",
+                                  "autotune") if k in r},
     }
     if "fp64" in results and head == "mixed":
         f = results["fp64"]
         out["fp64"] = {"value": f["evals_per_s"], "ms_per_step": f["ms_per_step"], "move_ms": f["move_ms"],
                        "roofline": roofline(w, False, f["move_ms"], f["move_path"]),
                        "mixed_over_fp64": r["evals_per_s"] / f["evals_per_s"]}
-        # error of the mixed path against the FP64 path on the same particles
+        # error of the mixed path against the FP64 path on the same particles: l_hat (dominated by
+        # the exact FP64 constant A), and its FP32-computed part d_hat = (n/m) sum_j d_j on its own
         sm, sf = ctxs["mixed"], ctxs["fp64"]
         th = sm.theta[:256].clone()
         u = sm.u[:256].clone()
-        lm, s2m, _ = sm.loglik_est(th, u)
-        lf, s2f, _ = sf.loglik_est(th, u)
+        lm, s2m, dm = sm.loglik_est(th, u)
+        lf, s2f, df = sf.loglik_est(th, u)
         out["mixed_rel_err"] = {
             "lhat_max": float(((lm - lf).abs() / lf.abs()).max()),
+            "dhat_max": float(((dm - df).abs() / df.abs().clamp_min(1e-300)).max()),
+            "dhat_over_max_dhat": float((dm - df).abs().max() / df.abs().max()),
             "sig2_max": float(((s2m - s2f).abs() / s2f.abs().clamp_min(1e-300)).max()),
+            "particles": int(th.shape[0]),
         }
-    if args.workload in ("config1", "config2") and not args.no_e2e:
+    # the move on the fixed benchmark state (a = 1, Laplace approximation) for the dominant path
+    out["laplace_a1"] = laplace_state_move(ctxs[head], w, eps)
+    out["laplace_a1"]["roofline"] = roofline(w, head == "mixed", out["laplace_a1"]["move_ms_median"],
+                                             r["move_path"])
+    if name in ("config1", "config2") and e2e:
         out["run_to_end"] = run_to_end(w, W.MIXED if head == "mixed" else W.FP64, Xy, eps, args.cv_order)
-    if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(w, args.cpu_particles, eps, cv_order=args.cv_order)
-    if args.workload != "config2":
-        out["note"] = "not the benchmark workload (Poisson n=1e6 d=20); reported for the configuration table"
+    for c in ctxs.values():
+        c.close()
+    del ctxs, Xy
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    if cpu:
+        out["cpu_baseline"] = cpu_baseline(w, eps, cv_order=args.cv_order)
     if args.recentre or args.schemes != "default" or args.cv_order != 2:
-        out["note"] = (out.get("note", "") + " variant: per-stage CV centre" * bool(args.recentre)
+        out["note"] = (" variant: per-stage CV centre" * bool(args.recentre)
                        + " variant: first-order control variate" * (args.cv_order == 1)
                        + " variant: paper schemes (grid tempering 0.8M, multinomial)" * (args.schemes == "paper")).strip()
+    return out
+
+
+BESIDE_KEYS = ("value", "ms_per_step", "move_ms", "move_evals_per_s", "dtype", "config", "roofline", "fp64",
+               "mixed_rel_err", "laplace_a1", "run", "run_to_end")
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): sharding the particles over "
+              "several GPUs is designed but not built", file=sys.stderr)
+        sys.exit(2)
+    if args.calibrate_copy:
+        calibrate_copy()
+        return
+    if args.workload == "batched":
+        main_batched(args)
+        return
+    out = bench_workload(args.workload, args, cpu=not args.no_cpu, e2e=not args.no_e2e)
+    if args.workload == HEADLINE and not args.no_beside:
+        # the other single-GPU configurations, timed with the same steps (not part of `value`)
+        out["beside"] = {}
+        for name in BESIDE:
+            o = bench_workload(name, args, cpu=False, e2e=not args.no_e2e)
+            out["beside"][name] = {k: o[k] for k in BESIDE_KEYS if k in o}
     print(json.dumps(out), flush=True)
 
 

@@ -44,7 +44,7 @@ typedef enum {
   SMC_ERR_DEVICE = 3,      /* a HIP call failed; see smc_last_error */
   SMC_ERR_NOT_PD = 4,      /* covariance not positive definite even after jitter */
   SMC_ERR_NONFINITE = 5,   /* every incremental weight is non-finite */
-  SMC_ERR_UNSUPPORTED = 6  /* valid request this build does not implement (e.g. d > 32) */
+  SMC_ERR_UNSUPPORTED = 6  /* valid request this build does not implement (e.g. d > 128) */
 } smc_status;
 
 typedef enum {
@@ -63,10 +63,13 @@ typedef enum {
 typedef enum {
   SMC_MOVE_AUTO = 0,      /* resident when the subsample fits on chip, else streaming */
   SMC_MOVE_STREAMING = 1, /* one wavefront per particle, rows gathered from HBM every pass */
-  SMC_MOVE_RESIDENT = 2   /* one 4-wavefront workgroup per particle, rows gathered once per
+  SMC_MOVE_RESIDENT = 2,  /* one 4-wavefront workgroup per particle, rows gathered once per
                              move and kept in registers and LDS for all L + 1 passes
                              (d <= 24, logistic or Poisson, m rows must fit; else
                              SMC_ERR_UNSUPPORTED from smc_init) */
+  SMC_MOVE_RESIDENT_MFMA = 3  /* the resident move with each row's x'delta formed on the matrix
+                                 cores (v_mfma_f32_4x4x1f32, FP32 products and sums) beside the
+                                 vector work; SMC_MIXED only */
 } smc_move_path;
 
 typedef struct smc_ctx_s* smc_ctx;
@@ -79,7 +82,7 @@ typedef struct smc_problem {
   int32_t family;      /* smc_family */
   int32_t precision;   /* smc_precision */
   int32_t cv_order;    /* 2: second-order Taylor control variate (section 3.2); 1: first order */
-  int32_t d;           /* number of parameters, 1 <= d <= 32 in this build */
+  int32_t d;           /* number of parameters, 1 <= d <= 128 (Gaussian family: d <= 32) */
   int64_t n;           /* number of observations, 1 <= n < 2^31 */
   int32_t ld;          /* pitch of Xy in elements, ld >= d + 1 */
   int32_t xy_fp32;     /* 1: Xy holds float, 0: double */
@@ -190,6 +193,28 @@ smc_status smc_resample_multinomial(smc_ctx ctx);
 smc_status smc_move(smc_ctx ctx, double eps, int32_t L, int32_t R);
 
 /*
+ * Outcome of the last Markov move (Algorithm 1) of smc_move, smc_stage or
+ * smc_batch_move on this context: the fraction of particles whose u block
+ * refresh was accepted (eq. acc_prop_u) and whose HMC proposal was accepted,
+ * and how many of those decisions were near ties, i.e. had
+ * |log U - log r| <= tau (1 + |log r|) with tau = 1e-9 (FP64) or 1e-5
+ * (mixed): the decisions whose outcome rounding could change. Host outputs,
+ * any may be NULL. SMC_ERR_STATE before the first move. Synchronises.
+ */
+smc_status smc_move_stats(smc_ctx ctx, double* accept_u, double* accept_theta, int64_t* near_ties_u,
+                          int64_t* near_ties_theta);
+
+/*
+ * The Metropolis-Hastings quantities of every particle's decisions in the last
+ * move (eq. acc_prop_u for the u refresh; the HMC energy difference
+ * H(theta, p) - H(theta*, p*) for theta): host diag (M*4 doubles) receives,
+ * per particle, [log r, log U] of the u refresh, then [log r, log U] of the
+ * HMC step; a proposal is accepted iff log U < log r (and log r is finite).
+ * SMC_ERR_STATE before the first move. Synchronises.
+ */
+smc_status smc_move_diag(smc_ctx ctx, double* diag);
+
+/*
  * One whole stage of Algorithm 2 (steps a-f with the default schemes):
  * smc_temper (skipped once a = 1), smc_mass, smc_resample and smc_move(eps,
  * L, R), with the results of those calls (a_out, dlogz_out, ess_out as in
@@ -222,18 +247,42 @@ smc_status loglik_grad(smc_ctx ctx, int32_t count, const double* theta, const in
                        double* grad_l, double* grad_s);
 
 /*
+ * The annealed log-likelihood estimator of the extended target (section 3.1,
+ * eq. tempered_likelihood_estimator): lambda_a = a l_hat - a^2 sigma2_hat / 2
+ * at exponent a in [0, 1] for `count` particles: device theta (count*d) and
+ * u (count*m) -> device lam (count), and optionally lhat and sig2 (nullable).
+ */
+smc_status loglik_lambda(smc_ctx ctx, int32_t count, const double* theta, const int32_t* u, double a,
+                         double* lam, double* lhat, double* sig2);
+
+/*
  * Picks the move kernel by measurement: times one move (after an untimed
  * one) of every option the problem's move_path allows — the streaming kernel
- * and each resident layout that fits (register rows per lane) — from the
+ * (for FP32 logistic rows with d > 32 in both tile forms of its row loop,
+ * smc_info.stream_tile) and each resident layout that fits (register rows per
+ * lane; for FP32 rows each with x'delta on the vector ALU and on the matrix
+ * cores) — from the
  * current state with step eps and L leapfrog steps, restores the particle
  * state, the accept flags and the move counter exactly, and keeps the fastest
  * for later moves (single and batched). *rpl_out (nullable) receives the
  * choice: -1 streaming, else the register rows per lane of the resident
- * kernel; ms_out (nullable, up to 4 entries) the timed durations in the order
- * streaming (when allowed), then the resident layouts. Needs a mass matrix.
+ * kernel (smc_info.res_mfma tells the form of the product); ms_out (nullable,
+ * up to 8 entries) the timed durations in the order streaming (when allowed,
+ * tile forms 0 then 1), then the resident layouts by register rows, the
+ * vector form before the matrix-core form. Needs a mass matrix.
  * Uses the resampling buffers of the workspace. Synchronises.
  */
 smc_status smc_autotune_move(smc_ctx ctx, double eps, int32_t L, int32_t* rpl_out, float* ms_out);
+
+/*
+ * Sets the move kernel directly (a choice smc_autotune_move made on an
+ * earlier run, or a test): res_rows = -1 selects the streaming move with tile
+ * form stream_tile (0 or 1, where smc_info documents both), else the resident
+ * move with res_rows register rows per lane and x'delta on the matrix cores
+ * when res_mfma = 1. SMC_ERR_UNSUPPORTED when the option does not exist or
+ * does not fit this problem and device, or the problem's move_path excludes it.
+ */
+smc_status smc_set_move_option(smc_ctx ctx, int32_t res_rows, int32_t res_mfma, int32_t stream_tile);
 
 /* Timing of move launches: with n > 0 (at most 4096) every move launch of
  * smc_move (and smc_stage) is bracketed by a HIP event pair on the context's
@@ -257,11 +306,41 @@ typedef struct smc_info {
   int32_t have_mass;
   int32_t newton_iters;
   int32_t move_path;  /* the move kernel in use: SMC_MOVE_STREAMING or SMC_MOVE_RESIDENT */
+  int32_t res_rows;   /* resident move: subsample rows each lane keeps in registers (the rest
+                         sit in LDS); -1 with the streaming move */
+  int32_t res_mfma;   /* resident move: 1 when x'delta is formed on the matrix cores
+                         (v_mfma_f32_4x4x1f32), 0 on the vector ALU */
+  int32_t stream_tile; /* lane-group streaming move (d > 32): the tile form of its row loop,
+                          0 (default: FP32 logistic rows evaluate each row's remainder once,
+                          in one lane of the row's group) or 1 (in every lane of the group) */
 } smc_info;
 smc_status smc_get_info(smc_ctx ctx, smc_info* out);
 
 /* Overwrite the stage counters (checkpoint resume, tests). */
 smc_status smc_set_stage(smc_ctx ctx, int32_t stage, int32_t move, double a, double logz);
+
+/*
+ * Checkpoint of a run between calls (the state Algorithm 2 carries from one
+ * stage to the next): a host blob holding the problem's identity (family,
+ * precision, control-variate order, n, d, M, m, G, seed, dataset), the
+ * stage counters (stage, move, a, log Z), the control-variate centre, the
+ * move kernel in use, the mass matrix of the stage if there is one, and the
+ * particle state (theta, u, log W, the cached l_hat, sigma2_hat and both
+ * gradients, the last accept flags). With blob = NULL, *bytes receives the
+ * size; otherwise *bytes must be at least that size and receives it.
+ * Synchronises.
+ */
+smc_status smc_get_state(smc_ctx ctx, void* blob, size_t* bytes);
+
+/*
+ * Restores a blob written by smc_get_state into a context made by smc_init
+ * for the same problem (SMC_ERR_INVALID_ARG if the identity or the size
+ * differs). A different control-variate centre is rebuilt from the blob's
+ * (the same kernels on the same rows, so A, B, C and the packed row
+ * constants come back bit for bit). The run then continues exactly as the
+ * one that wrote the blob. Synchronises.
+ */
+smc_status smc_set_state(smc_ctx ctx, const void* blob, size_t bytes);
 
 /* Host d*d covariance -> device Sigma, factor and inverse factor. */
 smc_status smc_set_mass(smc_ctx ctx, const double* sigma_host);

@@ -13,7 +13,7 @@ LIB_PATH = os.path.join(HERE, "libsubsmc.so")
 
 LOGISTIC, POISSON, GAUSSIAN, STUDENT_T = 0, 1, 2, 3
 FP64, MIXED = 0, 1
-MOVE_AUTO, MOVE_STREAMING, MOVE_RESIDENT = 0, 1, 2
+MOVE_AUTO, MOVE_STREAMING, MOVE_RESIDENT, MOVE_RESIDENT_MFMA = 0, 1, 2, 3
 STATUS = {0: "ok", 1: "invalid argument", 2: "call out of order", 3: "device error",
           4: "matrix not positive definite", 5: "non-finite weights", 6: "unsupported"}
 
@@ -33,13 +33,16 @@ class _Problem(C.Structure):
 
 class _Info(C.Structure):
     _fields_ = [("a", C.c_double), ("logz", C.c_double), ("stage", C.c_int32), ("move", C.c_int32),
-                ("have_mass", C.c_int32), ("newton_iters", C.c_int32), ("move_path", C.c_int32)]
+                ("have_mass", C.c_int32), ("newton_iters", C.c_int32), ("move_path", C.c_int32),
+                ("res_rows", C.c_int32), ("res_mfma", C.c_int32), ("stream_tile", C.c_int32)]
 
 
 EXPORTS = [
     "smc_workspace_size", "smc_init", "smc_temper", "smc_temper_grid", "smc_mass", "smc_resample",
-    "smc_resample_multinomial", "smc_recentre", "smc_move", "smc_stage", "smc_autotune_move", "smc_set_move_timing", "smc_move_times",
-    "loglik_est", "loglik_grad", "smc_refresh", "smc_get_info", "smc_set_stage", "smc_set_mass",
+    "smc_resample_multinomial", "smc_recentre", "smc_move", "smc_stage", "smc_autotune_move", "smc_set_move_option",
+    "smc_set_move_timing", "smc_move_times",
+    "loglik_est", "loglik_grad", "loglik_lambda", "smc_move_stats", "smc_move_diag", "smc_get_state", "smc_set_state",
+    "smc_refresh", "smc_get_info", "smc_set_stage", "smc_set_mass",
     "smc_get_mass", "smc_get_cv", "smc_full_loglik", "smc_destroy", "smc_status_string",
     "smc_last_error", "smc_batch_workspace_size", "smc_batch_create", "smc_batch_temper", "smc_batch_mass",
     "smc_batch_resample", "smc_batch_move", "smc_batch_launches", "smc_batch_set_graph", "smc_batch_set_streams", "smc_batch_graph_captures",
@@ -72,10 +75,16 @@ def lib():
     L.smc_move.argtypes = [vp, dbl, i32, i32]
     L.smc_stage.argtypes = [vp, dbl, i32, i32, C.POINTER(dbl), C.POINTER(dbl), C.POINTER(dbl)]
     L.smc_autotune_move.argtypes = [vp, dbl, i32, C.POINTER(i32), vp]
+    L.smc_set_move_option.argtypes = [vp, i32, i32, i32]
     L.smc_set_move_timing.argtypes = [vp, i32]
     L.smc_move_times.argtypes = [vp, i32, vp, C.POINTER(i32)]
     L.loglik_est.argtypes = [vp, i32, vp, vp, vp, vp, vp]
     L.loglik_grad.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp]
+    L.loglik_lambda.argtypes = [vp, i32, vp, vp, dbl, vp, vp, vp]
+    L.smc_move_stats.argtypes = [vp, C.POINTER(dbl), C.POINTER(dbl), C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
+    L.smc_get_state.argtypes = [vp, vp, C.POINTER(C.c_size_t)]
+    L.smc_move_diag.argtypes = [vp, vp]
+    L.smc_set_state.argtypes = [vp, vp, C.c_size_t]
     L.smc_refresh.argtypes = [vp]
     L.smc_get_info.argtypes = [vp, C.POINTER(_Info)]
     L.smc_set_stage.argtypes = [vp, i32, i32, dbl, dbl]
@@ -237,9 +246,13 @@ class SubsampledSMC:
         -1 for streaming, the timed ms of each option)."""
         import numpy as np
         rpl = C.c_int32()
-        ms = np.zeros(4, dtype=np.float32)
+        ms = np.zeros(8, dtype=np.float32)
         self._check(lib().smc_autotune_move(self._h, float(eps), int(L), C.byref(rpl), _host_ptr(ms)))
         return rpl.value, ms
+
+    def set_move_option(self, res_rows=-1, res_mfma=0, stream_tile=0):
+        """Pick the move kernel: res_rows = -1 streaming (tile form stream_tile), else resident."""
+        self._check(lib().smc_set_move_option(self._h, int(res_rows), int(res_mfma), int(stream_tile)))
 
     def set_move_timing(self, n):
         self._check(lib().smc_set_move_timing(self._h, int(n)))
@@ -294,12 +307,53 @@ class SubsampledSMC:
                                       _ptr(grad), _ptr(gl), _ptr(gs)))
         return (grad, gl, gs) if separate else grad
 
+    def loglik_lambda(self, theta, u, a):
+        """lambda_a = a l_hat - a^2 sigma2_hat / 2 per particle; returns (lam, lhat, sig2)."""
+        theta = theta.contiguous()
+        u = u.contiguous()
+        cnt = theta.shape[0]
+        lam = torch.empty(cnt, dtype=torch.float64, device=self.device)
+        lh = torch.empty_like(lam)
+        s2 = torch.empty_like(lam)
+        self._check(lib().loglik_lambda(self._h, cnt, _ptr(theta), _ptr(u), float(a), _ptr(lam), _ptr(lh),
+                                        _ptr(s2)))
+        return lam, lh, s2
+
     # -- state access -----------------------------------------------------------
+    def move_stats(self):
+        """Last move: accept rates of the u refresh and of HMC, near-tie counts of both."""
+        au, at = C.c_double(), C.c_double()
+        tu, tt = C.c_int64(), C.c_int64()
+        self._check(lib().smc_move_stats(self._h, C.byref(au), C.byref(at), C.byref(tu), C.byref(tt)))
+        return {"accept_u": au.value, "accept_theta": at.value, "near_ties_u": tu.value,
+                "near_ties_theta": tt.value}
+
+    def move_diag(self):
+        """Last move, per particle: [log r, log U] of the u refresh, then of the HMC step (M x 4)."""
+        import numpy as np
+        out = np.zeros((self.M, 4))
+        self._check(lib().smc_move_diag(self._h, _host_ptr(out)))
+        return out
+
+    def get_state(self):
+        """Checkpoint of the run as bytes (smc_get_state)."""
+        n = C.c_size_t(0)
+        self._check(lib().smc_get_state(self._h, None, C.byref(n)))
+        buf = C.create_string_buffer(n.value)
+        self._check(lib().smc_get_state(self._h, buf, C.byref(n)))
+        return bytes(buf.raw[:n.value])
+
+    def set_state(self, blob):
+        """Resume from bytes written by get_state of a context of the same problem."""
+        buf = C.create_string_buffer(bytes(blob), len(blob))
+        self._check(lib().smc_set_state(self._h, buf, len(blob)))
+
     def info(self):
         o = _Info()
         self._check(lib().smc_get_info(self._h, C.byref(o)))
         return {"a": o.a, "logz": o.logz, "stage": o.stage, "move": o.move, "have_mass": o.have_mass,
-                "newton_iters": o.newton_iters, "move_path": o.move_path}
+                "newton_iters": o.newton_iters, "move_path": o.move_path, "res_rows": o.res_rows,
+                "res_mfma": o.res_mfma, "stream_tile": o.stream_tile}
 
     def set_stage(self, stage, move, a, logz=0.0):
         self._check(lib().smc_set_stage(self._h, int(stage), int(move), float(a), float(logz)))

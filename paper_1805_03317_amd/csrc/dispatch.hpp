@@ -23,12 +23,14 @@ struct KernelShape {
   int dc;         // padded d (narrow and resident kernels)
   int lanes, ch;  // lanes per row and elements per lane (wide kernels)
   int rpl;        // register rows per lane (resident kernel)
+  int mf;         // 1: the resident kernel forms x'delta on the matrix cores
+  int tile;       // lane-group streaming move: the tile form of its row loop
 };
 
 inline bool operator<(const KernelShape& a, const KernelShape& b) {
-  const int x[7] = {a.kind, a.fp32, a.fam, a.dc, a.lanes, a.ch, a.rpl};
-  const int y[7] = {b.kind, b.fp32, b.fam, b.dc, b.lanes, b.ch, b.rpl};
-  for (int k = 0; k < 7; ++k)
+  const int x[9] = {a.kind, a.fp32, a.fam, a.dc, a.lanes, a.ch, a.rpl, a.mf, a.tile};
+  const int y[9] = {b.kind, b.fp32, b.fam, b.dc, b.lanes, b.ch, b.rpl, b.mf, b.tile};
+  for (int k = 0; k < 9; ++k)
     if (x[k] != y[k]) return x[k] < y[k];
   return false;
 }

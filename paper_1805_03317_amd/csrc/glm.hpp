@@ -52,10 +52,21 @@ template <> struct Tol<double> {
   static constexpr int n_exp = 16;
 };
 template <> struct Tol<float> {
-  static constexpr float series_logistic = 0.25f;
+  // FP32 rows: the cumulant series up to |Delta| = 1.25. The log1p form below
+  // adds terms of order Delta^3 whose sum is of order Delta^4 near s = 1/2
+  // (kappa_3 = 0 there), which in FP32 costs up to ~1e-4 of the result for
+  // |Delta| in [0.25, 1); the series has no such cancellation. Its terms fall
+  // like (|Delta| / pi)^k (the nearest singularity of log(1 - s + s e^t) is at
+  // |t| >= pi), so 8, 12 and 16 terms reach FP32 rounding for |Delta| below
+  // 0.3, 0.7 and 1.25.
+  static constexpr float series_logistic = 1.25f;
   static constexpr float direct_logistic = 2.0f;
   static constexpr float series_exp = 1.0f;
-  static constexpr int n_cumulant = 10;
+  static constexpr float series_short = 0.3f;
+  static constexpr float series_mid = 0.7f;
+  static constexpr int n_cumulant = 16;
+  static constexpr int n_short = 8;
+  static constexpr int n_mid = 12;
   static constexpr int n_exp = 12;
 };
 
@@ -79,8 +90,10 @@ __device__ __forceinline__ T sigmoid(T x) {
   return e / (T(1) + e);
 }
 
-// Bernoulli cumulant kappa_k(s) divided by k! and by (k-1)!, k = 3..14.
-// Coefficients of P_k(v) (ascending powers of v).
+// Bernoulli cumulant kappa_k(s), k = 3..16, as v P_k(v) (k even) or
+// v (1 - 2s) P_k(v) (k odd), v = s (1 - s), w = 1 - 2s; the integer
+// coefficients of P_k (ascending powers of v) follow from
+// kappa_{k+1} = v d(kappa_k)/ds with kappa_1 = s.
 template <typename T>
 __device__ __forceinline__ T cumulant(int k, T v, T w) {
   T p;
@@ -100,9 +113,17 @@ __device__ __forceinline__ T cumulant(int k, T v, T w) {
     case 13:
       p = T(1) + v * (T(-4092) + v * (T(506880) + v * (T(-12640320) + v * (T(99792000) + v * T(-239500800)))));
       break;
-    default:
+    case 14:
       p = T(1) + v * (T(-8190) + v * (T(1561560) + v * (T(-57657600) +
               v * (T(726485760) + v * (T(-3632428800.0) + v * T(6227020800.0))))));
+      break;
+    case 15:
+      p = T(1) + v * (T(-16380) + v * (T(4684680) + v * (T(-230630400) +
+              v * (T(3632428800.0) + v * (T(-21794572800.0) + v * T(43589145600.0))))));
+      break;
+    default:
+      p = T(1) + v * (T(-32766) + v * (T(14217840) + v * (T(-988107120) + v * (T(22313491200.0) +
+              v * (T(-210680870400.0) + v * (T(871782912000.0) + v * T(-1307674368000.0)))))));
       break;
   }
   return (k & 1) ? v * w * p : v * p;
@@ -149,8 +170,9 @@ __device__ __forceinline__ float exp_minus_one_wide(float D) {
 // |D| = series_exp, e^D - 1 beyond. Every lane evaluates the series (no
 // change of the execution mask, so the series schedules together with the
 // surrounding arithmetic); the exponential branch runs only when some lane of
-// the wavefront needs it, and each lane keeps the result of its own branch.
-template <typename T>
+// the wavefront needs it (NB: on every lane, without a branch), and each lane
+// keeps the result of its own branch.
+template <typename T, bool NB = false>
 __device__ __forceinline__ void exp_remainders(T D, T& E2, T& E3) {
   const T aD = D < T(0) ? -D : D;
   T acc = T(0);
@@ -159,7 +181,7 @@ __device__ __forceinline__ void exp_remainders(T D, T& E2, T& E3) {
   E3 = acc * D * D * D;
   E2 = E3 + T(0.5) * D * D;
   const bool wide = !(aD < Tol<T>::series_exp);  // NaN takes this branch too
-  if (__any(wide)) {
+  if (NB || __any(wide)) {
     T em1;
     if constexpr (sizeof(T) == 4) em1 = exp_minus_one_wide(D);
     else em1 = dev_expm1(D);
@@ -170,6 +192,20 @@ __device__ __forceinline__ void exp_remainders(T D, T& E2, T& E3) {
   }
 }
 
+// R = sum_{k=3..K} kappa_k D^k / k! and R' = sum_{k=3..K} kappa_k D^(k-1) / (k-1)!
+template <typename T, int K>
+__device__ __forceinline__ void cumulant_series(T v, T w, T D, T& R, T& Rp) {
+  T r = T(0), rp = T(0);
+#pragma unroll
+  for (int k = K; k >= 3; --k) {
+    const T c = cumulant<T>(k, v, w);
+    r = r * D + c * inv_fact<T>(k);
+    rp = rp * D + c * inv_fact<T>(k - 1);
+  }
+  R = r * D * D * D;
+  Rp = rp * D * D;
+}
+
 // Second-order Taylor remainder of softplus at eta_bar <= 0 (s = sigmoid(eta_bar)).
 template <typename T>
 __device__ __forceinline__ void softplus_remainder(T eb, T s, T D, T& R, T& Rp) {
@@ -177,16 +213,20 @@ __device__ __forceinline__ void softplus_remainder(T eb, T s, T D, T& R, T& Rp) 
   const T v = s * sc;
   const T w = sc - s;
   const T aD = D < T(0) ? -D : D;
-  if (aD < Tol<T>::series_logistic) {
-    T r = T(0), rp = T(0);
-#pragma unroll
-    for (int k = Tol<T>::n_cumulant; k >= 3; --k) {
-      const T c = cumulant<T>(k, v, w);
-      r = r * D + c * inv_fact<T>(k);
-      rp = rp * D + c * inv_fact<T>(k - 1);
+  if constexpr (sizeof(T) == 4) {
+    // the number of series terms follows the largest |D| of the wavefront
+    // (a uniform branch); lanes beyond the series range take their own branch
+    if (!__any(!(aD < Tol<T>::series_short))) {
+      cumulant_series<T, Tol<T>::n_short>(v, w, D, R, Rp);
+      return;
     }
-    R = r * D * D * D;
-    Rp = rp * D * D;
+    if (!__any(!(aD < Tol<T>::series_mid))) {
+      cumulant_series<T, Tol<T>::n_mid>(v, w, D, R, Rp);
+      return;
+    }
+  }
+  if (aD < Tol<T>::series_logistic) {
+    cumulant_series<T, Tol<T>::n_cumulant>(v, w, D, R, Rp);
   } else if (aD <= Tol<T>::direct_logistic) {
     const T em1 = dev_expm1(D);
     const T E2 = em1 - D;
@@ -217,8 +257,10 @@ __device__ __forceinline__ T log1p_remainder3(T z) {
   return dev_log1p(z) - z + T(0.5) * z * z;
 }
 
-// Returns d (remainder) and dp (its eta-derivative); FAM is the family.
-template <typename T, int FAM>
+// Returns d (remainder) and dp (its eta-derivative); FAM is the family. NB:
+// the Poisson remainder without a branch (its exponential form evaluated on
+// every lane), so that it forms one block with the work around it.
+template <typename T, int FAM, bool NB = false>
 __device__ __forceinline__ void cv_remainder(int cv_order, T eb, T aux, T D, T inv_s2, T& d, T& dp) {
   if constexpr (FAM == kLogistic) {
     const bool flip = eb > T(0);
@@ -235,7 +277,7 @@ __device__ __forceinline__ void cv_remainder(int cv_order, T eb, T aux, T D, T i
     }
   } else if constexpr (FAM == kPoisson) {
     T E2, E3;
-    exp_remainders<T>(D, E2, E3);
+    exp_remainders<T, NB>(D, E2, E3);
     d = -aux * E3;
     dp = -aux * E2;
     if (cv_order == 1) {

@@ -293,6 +293,8 @@ struct EstArgs {
   const double* g_lhat;  // count (nullable): combined gradient g_l * grad l + g_s * grad s2
   const double* g_sig2;  // count (nullable)
   double* grad;          // count*d (nullable)
+  double a;              // exponent of lam
+  double* lam;           // count (nullable): a l_hat - a^2 sigma2_hat / 2
 };
 
 template <typename Real, int DC, int FAM>
@@ -310,6 +312,7 @@ __global__ void __launch_bounds__(kWave) estimator_kernel(EstArgs A) {
     if (A.lhat) A.lhat[i] = r.lhat;
     if (A.sig2) A.sig2[i] = r.sig2;
     if (A.dhat) A.dhat[i] = r.dhat;
+    if (A.lam) A.lam[i] = A.a * r.lhat - 0.5 * A.a * A.a * r.sig2;
   }
   if (lane < d) {
     if (A.grad_l) A.grad_l[(int64_t)i * d + lane] = r.gl;
@@ -340,7 +343,25 @@ struct MoveArgs {
   double* grad_l;  // M*d
   double* grad_s;  // M*d
   int32_t* accept; // M*2
+  int32_t* ties;   // M*2 (nullable): 1 where the decision was a near tie
+  double tie_tol;  // near tie: |log U - log r| <= tie_tol (1 + |log r|)
+  double* diag;    // M*4 (nullable): log r and log U of the u refresh, then of the HMC step
 };
+
+// A Metropolis-Hastings decision that rounding could change.
+__device__ __forceinline__ int32_t near_tie(double logU, double logr, double tol) {
+  return (isfinite(logr) && fabs(logU - logr) <= tol * (1.0 + fabs(logr))) ? 1 : 0;
+}
+
+// the move's record of one Metropolis-Hastings decision (k = 0: u refresh, 1: HMC)
+__device__ __forceinline__ void record_decision(const MoveArgs& A, int i, int k, double logU, double logr) {
+  if (A.ties) A.ties[2 * i + k] = near_tie(logU, logr, A.tie_tol);
+  if (A.diag) {
+    A.diag[4 * i + 2 * k] = logr;
+    A.diag[4 * i + 2 * k + 1] = logU;
+  }
+}
+
 
 template <int DC>
 __device__ __forceinline__ void prior_terms(const Prob& P, double th, int lane, double& r, double& lp) {
@@ -407,7 +428,10 @@ __device__ __forceinline__ void move_body(const MoveArgs& A, const int i) {
       lh0 = r.lhat; sg0 = r.sig2; gl0 = r.gl; gs0 = r.gs;
       ob0 = b0; ob1 = b1;
     }
-    if (lane == 0) A.accept[2 * i] = acc ? 1 : 0;
+    if (lane == 0) {
+      A.accept[2 * i] = acc ? 1 : 0;
+      record_decision(A, i, 0, logU, logr);
+    }
   }
 
   // ---- 2. theta | u: HMC
@@ -457,6 +481,7 @@ __device__ __forceinline__ void move_body(const MoveArgs& A, const int i) {
     A.lhat[i] = lh0;
     A.sig2[i] = sg0;
     A.accept[2 * i + 1] = acc ? 1 : 0;
+    record_decision(A, i, 1, logU, logr);
   }
 }
 

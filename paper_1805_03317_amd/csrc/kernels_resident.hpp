@@ -257,7 +257,127 @@ __device__ __forceinline__ void resident_accumulate(const Prob& P, const ResRow<
   }
 }
 
-template <typename Real, int DC, int FAM, int RPL>
+// x'delta of this lane's row on the matrix core. v_mfma_f32_4x4x1f32 works
+// on 16 blocks of 4 lanes: lane 4b + t receives D[i] += A(lane 4b + i) *
+// B(lane 4b + t) for i = 0..3. With delta_c as A in every lane and the row's
+// x_c as B (each lane its own row), every element of lane 4b + t's
+// accumulator is sum_c delta_c x_t[c]: the row's linear predictor, with no
+// exchange between lanes. Two accumulators (even and odd c) halve the chain
+// of dependent products. The row stays in the registers it lives in (the
+// matrix core reads VGPRs and AGPRs alike).
+typedef float mfma_f4 __attribute__((ext_vector_type(4)));
+
+template <int DC>
+__device__ __forceinline__ float mfma_row_dot(const float (&dl)[DC], const float (&x)[DC]) {
+  mfma_f4 a0 = {0.f, 0.f, 0.f, 0.f}, a1 = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int c = 0; c < DC; c += 2) {
+    a0 = __builtin_amdgcn_mfma_f32_4x4x1f32(dl[c], x[c], a0, 0, 0, 0);
+    if (c + 1 < DC) a1 = __builtin_amdgcn_mfma_f32_4x4x1f32(dl[c + 1], x[c + 1], a1, 0, 0, 0);
+  }
+  return a0[0] + a1[0];
+}
+
+// resident_accumulate with x'delta formed on the matrix core (FP32 rows).
+// Each row's product is issued one row ahead of the vector work on the row
+// before it (remainder, S1, T1, the FP64 sums), so the matrix pipe runs beside
+// the vector ALU. LDS rows are taken in whole groups of 256 (the last group
+// is allocated whole; lanes past the LDS rows zero their row and add
+// nothing), so every product runs with the full wavefront.
+template <int DC, int FAM, int RPL, int CV>
+__device__ __forceinline__ void resident_accumulate_mfma(const Prob& P, const ResRow<float, DC> (&rr)[RPL > 0 ? RPL : 1],
+                                                         char* lrows, int nlds, const float* row0, const float* dsh,
+                                                         int tid, double& se, double& se2, float (&S1)[DC],
+                                                         float (&T1)[DC], double& shift) {
+  const int m = P.m;
+  const float inv_s2 = (float)P.inv_s2;
+  float dl[DC];
+#pragma unroll
+  for (int c = 0; c < DC; ++c) dl[c] = dsh[c];
+  {
+    float x[DC];
+#pragma unroll
+    for (int c = 0; c < DC; ++c) x[c] = row0[kHeader + c];
+    float D = 0.f;
+#pragma unroll
+    for (int c = 0; c < DC; ++c) D += x[c] * dl[c];
+    float dd, dp;
+    cv_remainder<float, FAM>(CV, row0[0], row0[1], D, inv_s2, dd, dp);
+    shift = (double)dd;
+  }
+  se = 0.0;
+  se2 = 0.0;
+#pragma unroll
+  for (int c = 0; c < DC; ++c) { S1[c] = 0.f; T1[c] = 0.f; }
+  auto add = [&](const float (&x)[DC], float dd, float dp) {
+    const double e = (double)dd - shift;
+    se += e;
+    se2 += e * e;
+    const float edp = (float)e * dp;
+#pragma unroll
+    for (int c = 0; c < DC; ++c) {
+      S1[c] += dp * x[c];
+      T1[c] += edp * x[c];
+    }
+  };
+  // register rows: every slot holds a row (the host launches RPL > 0 only
+  // when m >= 256 RPL), so the rows need no test and run as one block, in
+  // which the scheduler can overlap a row's product with the row before
+  if constexpr (RPL > 0) {
+    float Dn = mfma_row_dot<DC>(dl, rr[0].x);
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) {
+      const float Dc = Dn;
+      if (r + 1 < RPL) Dn = mfma_row_dot<DC>(dl, rr[r + 1 < RPL ? r + 1 : r].x);
+      float x[DC];
+#pragma unroll
+      for (int c = 0; c < DC; ++c) {
+        x[c] = rr[r].x[c];
+        asm("" : "+v"(x[c]));
+      }
+      float dd, dp;
+      cv_remainder<float, FAM, true>(CV, rr[r].eb, rr[r].aux, Dc, inv_s2, dd, dp);
+      add(x, dd, dp);
+    }
+  }
+  // LDS rows, whole groups, the next group's row and product one step ahead
+  const LdsSlots<float, DC> S(lrows, tid);
+  const int ngroups = (nlds + kResLanes - 1) / kResLanes;
+  auto load = [&](int k, float (&x)[DC], float& eb, float& aux) {
+    const bool ok = k * kResLanes + tid < nlds;
+#pragma unroll
+    for (int q = 0; q < LdsSlots<float, DC>::kChunks; ++q) {
+      const float4 v = *reinterpret_cast<const float4*>(S.chunk(k, q));
+      x[4 * q] = ok ? v.x : 0.f; x[4 * q + 1] = ok ? v.y : 0.f;
+      x[4 * q + 2] = ok ? v.z : 0.f; x[4 * q + 3] = ok ? v.w : 0.f;
+    }
+    eb = ok ? S.eb(k) : 0.f;
+    aux = ok ? S.aux(k) : 0.f;
+  };
+  if (ngroups > 0) {
+    float xn[DC], ebn, auxn;
+    load(0, xn, ebn, auxn);
+    float Dn = mfma_row_dot<DC>(dl, xn);
+#pragma unroll 1
+    for (int k = 0; k < ngroups; ++k) {
+      float x[DC];
+#pragma unroll
+      for (int c = 0; c < DC; ++c) x[c] = xn[c];
+      const float eb = ebn, aux = auxn, Dc = Dn;
+      if (k + 1 < ngroups) {
+        load(k + 1, xn, ebn, auxn);
+        Dn = mfma_row_dot<DC>(dl, xn);
+      }
+      if (k * kResLanes + tid < nlds) {
+        float dd, dp;
+        cv_remainder<float, FAM, true>(CV, eb, aux, Dc, inv_s2, dd, dp);
+        add(x, dd, dp);
+      }
+    }
+  }
+}
+
+template <typename Real, int DC, int FAM, int RPL, int MF>
 __device__ __forceinline__ void move_res_body(const MoveArgs& A, const ResLayout& Ly, const int i) {
   extern __shared__ __attribute__((aligned(16))) char smem[];
   char* lrows = smem + Ly.off_rows;
@@ -424,10 +544,17 @@ __device__ __forceinline__ void move_res_body(const MoveArgs& A, const ResLayout
     __syncthreads();
     double se, se2, shift;
     Real S1[DC], T1[DC];
-    if (P.cv_order == 2)
-      resident_accumulate<Real, DC, FAM, RPL, 2>(P, rr, lrows, Ly.nlds, row0, dsh, tid, se, se2, S1, T1, shift);
-    else
-      resident_accumulate<Real, DC, FAM, RPL, 1>(P, rr, lrows, Ly.nlds, row0, dsh, tid, se, se2, S1, T1, shift);
+    if constexpr (MF != 0 && sizeof(Real) == 4) {
+      if (P.cv_order == 2)
+        resident_accumulate_mfma<DC, FAM, RPL, 2>(P, rr, lrows, Ly.nlds, row0, dsh, tid, se, se2, S1, T1, shift);
+      else
+        resident_accumulate_mfma<DC, FAM, RPL, 1>(P, rr, lrows, Ly.nlds, row0, dsh, tid, se, se2, S1, T1, shift);
+    } else {
+      if (P.cv_order == 2)
+        resident_accumulate<Real, DC, FAM, RPL, 2>(P, rr, lrows, Ly.nlds, row0, dsh, tid, se, se2, S1, T1, shift);
+      else
+        resident_accumulate<Real, DC, FAM, RPL, 1>(P, rr, lrows, Ly.nlds, row0, dsh, tid, se, se2, S1, T1, shift);
+    }
     const bool full = (l == 0 || l == L);  // estimator value needed (not only the gradient)
     se = xl::wave_allsum(se);
     if (full) se2 = xl::wave_allsum(se2);
@@ -494,6 +621,7 @@ __device__ __forceinline__ void move_res_body(const MoveArgs& A, const ResLayout
         if (lane == 0) {
           flag[0] = acc ? 1 : 0;
           A.accept[2 * i] = acc ? 1 : 0;
+          record_decision(A, i, 0, logU, logr);
         }
         if (acc) {
           lh0 = lhat_r; sg0 = sig2_r; gl0 = gl_r; gs0 = gs_r;
@@ -567,13 +695,14 @@ __device__ __forceinline__ void move_res_body(const MoveArgs& A, const ResLayout
       A.lhat[i] = lh0;
       A.sig2[i] = sg0;
       A.accept[2 * i + 1] = acc ? 1 : 0;
+      record_decision(A, i, 1, logU, logr);
     }
   }
 }
 
-template <typename Real, int DC, int FAM, int RPL>
+template <typename Real, int DC, int FAM, int RPL, int MF>
 __global__ void __launch_bounds__(kResLanes) move_kernel_res(MoveArgs A, ResLayout Ly) {
-  move_res_body<Real, DC, FAM, RPL>(A, Ly, blockIdx.x);
+  move_res_body<Real, DC, FAM, RPL, MF>(A, Ly, blockIdx.x);
 }
 
 // a batch member of the resident move: its arguments and its on-chip layout
@@ -583,11 +712,11 @@ struct ResMoveArgs {
   ResLayout Ly;
 };
 
-template <typename Real, int DC, int FAM, int RPL>
+template <typename Real, int DC, int FAM, int RPL, int MF>
 __global__ void __launch_bounds__(kResLanes) move_kernel_res_batch(Batch<ResMoveArgs> B) {
   const int k = batch_member(B.first, B.count, blockIdx.x);
   const ResMoveArgs R = B.args[k];
-  move_res_body<Real, DC, FAM, RPL>(R.A, R.Ly, blockIdx.x - B.first[k]);
+  move_res_body<Real, DC, FAM, RPL, MF>(R.A, R.Ly, blockIdx.x - B.first[k]);
 }
 
 }  // namespace subsmc

@@ -48,7 +48,17 @@ __device__ __forceinline__ void load_chunk(const Real* __restrict__ p, Real (&x)
 // `vec` (LDS) holds delta = theta - theta_bar. Each lane gathers the CH
 // elements of delta aligned with its chunk of the row (zero at the header and
 // padding positions).
-template <typename Real, int G, int CH, int FAM, bool BLK>
+// Tile forms of the row loop (TL): 0, the default, evaluates each row's
+// remainder once per row for FP32 logistic rows (one lane of the group per
+// row, four row iterations per step); 1 evaluates it in every lane of the
+// row's group (the only form for the other shapes). The autotuner measures
+// both where both exist.
+template <typename Real, int FAM, int G, int TL>
+constexpr bool wide_one_remainder_per_lane() {
+  return sizeof(Real) == 4 && FAM == kLogistic && (G == 4 || G == 8) && TL == 0;
+}
+
+template <typename Real, int G, int CH, int FAM, bool BLK, int TL = 0>
 __device__ __forceinline__ PassResultW<wide_nc<G>()> estimator_pass_wide(const Prob& P, const int32_t* __restrict__ urow,
                                                            int b0, int b1, const int32_t* blk, Real* red,
                                                            const double* vec /* LDS: delta, d values */,
@@ -117,14 +127,15 @@ __device__ __forceinline__ PassResultW<wide_nc<G>()> estimator_pass_wide(const P
   // groups run the same number of steps. Row indices are loaded a step ahead
   // of their rows, so a row load never waits behind the load of its own
   // index, and every wait is for the oldest rows in flight.
-  if constexpr (sizeof(Real) == 4 && G == 4 && FAM == kLogistic) {
-    // (the logistic remainder is the costly one; for 8-lane rows and the
-    // other families the register cost of two buffered steps outweighs it)
+  if constexpr (wide_one_remainder_per_lane<Real, FAM, G, TL>()) {
+    // (the logistic remainder is the costly one; for the other families the
+    // register cost of two buffered steps outweighs it)
     // PT = 4 iterations per step, two steps of rows in flight (buffers xa, xb).
     // Each group forms the PT dot products of a step; lane q then evaluates
-    // the remainder of iteration q % PT only (one remainder per lane, not one
-    // per row and lane), and the PT pairs (d, d') go back to every lane of the
-    // group by quad broadcasts for the accumulation.
+    // the remainder of iteration q % PT only (one remainder per lane of a
+    // quad, not one per row and lane; with 8-lane rows each quad of the group
+    // evaluates the same four), and the PT pairs (d, d') go back to every lane
+    // of the quad by quad broadcasts for the accumulation.
     constexpr int PT = 4;
     static_assert(PT <= 4 && PT <= G, "one quad holds the step's remainders");
     const int nsteps = (nit + PT - 1) / PT;
@@ -328,6 +339,7 @@ __global__ void __launch_bounds__(kWave) estimator_kernel_wide(EstArgs A) {
     if (A.lhat) A.lhat[i] = r.lhat;
     if (A.sig2) A.sig2[i] = r.sig2;
     if (A.dhat) A.dhat[i] = r.dhat;
+    if (A.lam) A.lam[i] = A.a * r.lhat - 0.5 * A.a * A.a * r.sig2;
   }
 #pragma unroll
   for (int s = 0; s < NC; ++s) {
@@ -360,7 +372,7 @@ __device__ __forceinline__ void matvec_wide(const double* __restrict__ Mx, const
 
 // Fused Markov move (Algorithm 1) for wide rows; same steps, draws and
 // decisions as move_kernel.
-template <typename Real, int G, int CH, int FAM>
+template <typename Real, int G, int CH, int FAM, int TL>
 __device__ __forceinline__ void move_wide_body(const MoveArgs& A, const int i) {
   __shared__ Real red[kWave * CH];
   __shared__ double vec[128];
@@ -400,7 +412,7 @@ __device__ __forceinline__ void move_wide_body(const MoveArgs& A, const int i) {
 #pragma unroll
     for (int s = 0; s < NC; ++s) dl[s] = th[s] - tb[s];
     to_lds(vec, dl, lane, d);  // also fences the block indices
-    const auto r = estimator_pass_wide<Real, G, CH, FAM, true>(P, urow, b0, b1, blk, red, vec, lane);
+    const auto r = estimator_pass_wide<Real, G, CH, FAM, true, TL>(P, urow, b0, b1, blk, red, vec, lane);
     const double lam0 = a * lh0 - 0.5 * a * a * sg0;
     const double lam1 = a * r.lhat - 0.5 * a * a * r.sig2;
     const double logr = lam1 - lam0;
@@ -413,7 +425,10 @@ __device__ __forceinline__ void move_wide_body(const MoveArgs& A, const int i) {
       for (int s = 0; s < NC; ++s) { gl0[s] = r.gl[s]; gs0[s] = r.gs[s]; }
       ob0 = b0; ob1 = b1;
     }
-    if (lane == 0) A.accept[2 * i] = acc ? 1 : 0;
+    if (lane == 0) {
+      A.accept[2 * i] = acc ? 1 : 0;
+      record_decision(A, i, 0, logU, logr);
+    }
   }
 
   // ---- 2. theta | u: HMC
@@ -480,7 +495,7 @@ __device__ __forceinline__ void move_wide_body(const MoveArgs& A, const int i) {
       dl[s] = th1[s] - tb[s];
     }
     to_lds(vec, dl, lane, d);
-    const auto r = estimator_pass_wide<Real, G, CH, FAM, true>(P, urow, ob0, ob1, blk, red, vec, lane);
+    const auto r = estimator_pass_wide<Real, G, CH, FAM, true, TL>(P, urow, ob0, ob1, blk, red, vec, lane);
     lh1 = r.lhat;
     sg1 = r.sig2;
     lp1 = prior(th1, rq);
@@ -516,19 +531,20 @@ __device__ __forceinline__ void move_wide_body(const MoveArgs& A, const int i) {
     A.lhat[i] = lh0;
     A.sig2[i] = sg0;
     A.accept[2 * i + 1] = acc ? 1 : 0;
+    record_decision(A, i, 1, logU, logr);
   }
 }
 
-template <typename Real, int G, int CH, int FAM>
+template <typename Real, int G, int CH, int FAM, int TL>
 __global__ void __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(kMoveWaves<Real>))) move_kernel_wide(MoveArgs A) {
-  move_wide_body<Real, G, CH, FAM>(A, blockIdx.x);
+  move_wide_body<Real, G, CH, FAM, TL>(A, blockIdx.x);
 }
 
-template <typename Real, int G, int CH, int FAM>
+template <typename Real, int G, int CH, int FAM, int TL>
 __global__ void __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(kMoveWaves<Real>))) move_kernel_wide_batch(Batch<MoveArgs> B) {
   const int k = batch_member(B.first, B.count, blockIdx.x);
   const MoveArgs A = B.args[k];
-  move_wide_body<Real, G, CH, FAM>(A, blockIdx.x - B.first[k]);
+  move_wide_body<Real, G, CH, FAM, TL>(A, blockIdx.x - B.first[k]);
 }
 
 }  // namespace subsmc

@@ -1,7 +1,9 @@
 // Instantiation and launch of the wide particle kernels (32 < d <= 128: a
 // group of `lanes` lanes per row, `ch` elements per lane). The shapes are
 // those the host's packing rule produces for d in (32, 128]; the Gaussian
-// test family is narrow only.
+// test family is narrow only. The move of FP32 logistic rows comes in both
+// tile forms of its row loop (one remainder per row or per lane); the other
+// moves and the estimator kernels in form 0.
 #include "kernels_wide.hpp"
 #include "launch_common.hpp"
 
@@ -25,11 +27,21 @@ hipError_t by_wide(const KernelShape& s, F&& f) {
   return hipErrorInvalidValue;
 }
 
+// f(real, family, lanes, ch, tile) for an instantiated shape; `tiles` allows tile form 1
 template <typename F>
-hipError_t wide_dispatch(const KernelShape& s, F&& f) {
+hipError_t wide_dispatch(const KernelShape& s, bool tiles, F&& f) {
   auto go = [&](auto real) -> hipError_t {
     using Real = decltype(real);
-    auto fam_go = [&](auto fam) { return by_wide<Real>(s, [&](auto g, auto ch) { return f(real, fam, g, ch); }); };
+    auto fam_go = [&](auto fam) {
+      return by_wide<Real>(s, [&](auto g, auto ch) -> hipError_t {
+        constexpr bool two = wide_one_remainder_per_lane<Real, decltype(fam)::value, decltype(g)::value, 0>();
+        if (s.tile == 0) return f(real, fam, g, ch, IntC<0>{});
+        if constexpr (two) {
+          if (tiles && s.tile == 1) return f(real, fam, g, ch, IntC<1>{});
+        }
+        return hipErrorInvalidValue;
+      });
+    };
     switch (s.fam) {
       case kLogistic: return fam_go(IntC<kLogistic>{});
       case kPoisson: return fam_go(IntC<kPoisson>{});
@@ -43,7 +55,9 @@ hipError_t wide_dispatch(const KernelShape& s, F&& f) {
 }  // namespace
 
 hipError_t launch_estimator_wide(const KernelShape& s, int grid, const EstArgs& a, hipStream_t st) {
-  return wide_dispatch(s, [&](auto real, auto fam, auto g, auto ch) {
+  KernelShape s0 = s;
+  s0.tile = 0;
+  return wide_dispatch(s0, false, [&](auto real, auto fam, auto g, auto ch, auto) {
     using Real = decltype(real);
     hipLaunchKernelGGL((estimator_kernel_wide<Real, decltype(g)::value, decltype(ch)::value, decltype(fam)::value>),
                        dim3(grid), dim3(kWave), 0, st, a);
@@ -52,9 +66,10 @@ hipError_t launch_estimator_wide(const KernelShape& s, int grid, const EstArgs& 
 }
 
 hipError_t launch_move_wide(const KernelShape& s, int grid, size_t lds, const MoveArgs& a, hipStream_t st) {
-  return wide_dispatch(s, [&](auto real, auto fam, auto g, auto ch) {
+  return wide_dispatch(s, true, [&](auto real, auto fam, auto g, auto ch, auto tl) {
     using Real = decltype(real);
-    hipLaunchKernelGGL((move_kernel_wide<Real, decltype(g)::value, decltype(ch)::value, decltype(fam)::value>),
+    hipLaunchKernelGGL((move_kernel_wide<Real, decltype(g)::value, decltype(ch)::value, decltype(fam)::value,
+                                         decltype(tl)::value>),
                        dim3(grid), dim3(kWave), lds, st, a);
     return hipGetLastError();
   });
@@ -62,10 +77,11 @@ hipError_t launch_move_wide(const KernelShape& s, int grid, size_t lds, const Mo
 
 hipError_t launch_move_wide_batch(const KernelShape& s, int grid, size_t lds, const Batch<MoveArgs>& b,
                                   hipStream_t st) {
-  return wide_dispatch(s, [&](auto real, auto fam, auto g, auto ch) {
+  return wide_dispatch(s, true, [&](auto real, auto fam, auto g, auto ch, auto tl) {
     using Real = decltype(real);
     hipLaunchKernelGGL(
-        (move_kernel_wide_batch<Real, decltype(g)::value, decltype(ch)::value, decltype(fam)::value>),
+        (move_kernel_wide_batch<Real, decltype(g)::value, decltype(ch)::value, decltype(fam)::value,
+                                decltype(tl)::value>),
         dim3(grid), dim3(kWave), lds, st, b);
     return hipGetLastError();
   });

@@ -63,7 +63,8 @@ int packed_ld(int d, bool fp32) {
 // Workspace regions, in carve order.
 struct Layout {
   size_t Xp, theta_bar, cvA, cvB, cvC, mu0, Q0, Qw, L0, L0inv, Sigma, Lchol, Linv, mean, status,
-      tout, grid, search, aconst, scratch_theta, grad_l, grad_s, anc, th2, u2, lh2, sg2, gl2, gs2, partials, mpartials, total;
+      tout, grid, search, aconst, scratch_theta, grad_l, grad_s, ties, diag, anc, th2, u2, lh2, sg2, gl2, gs2, partials, mpartials,
+      total;
   int ld;
   int cv_blocks, cv_rows;
   int mom_blocks;
@@ -104,6 +105,8 @@ bool compute_layout(const smc_problem* pb, Layout& L) {
   L.scratch_theta = take(d * 8);
   L.grad_l = take(M * d * 8);
   L.grad_s = take(M * d * 8);
+  L.ties = take(M * 2 * 4);
+  L.diag = take(M * 4 * 8);
   L.anc = take(M * 4);
   L.th2 = take(M * d * 8);
   L.u2 = take(M * m * 4);
@@ -137,7 +140,10 @@ struct smc_ctx_s {
   // optional timing of move launches: a ring of event pairs
   std::vector<hipEvent_t> mev;
   int mev_next = 0, mev_count = 0;
+  int moved = 0;     // a move has written the accept and near-tie flags
   int res_rpl = -1;  // register rows per lane of the resident move kernel; -1: streaming
+  int res_mf = 0;    // the resident move forms x'delta on the matrix cores
+  int wide_tile = 0; // tile form of the lane-group streaming move's row loop
   ResLayout res_ly{};
   std::vector<double> mu0, Q0;
   char err[512] = {0};
@@ -210,7 +216,7 @@ smc_status validate(const smc_problem* pb) {
   if (pb->ld < pb->d + 1 || !pb->Xy) return SMC_ERR_INVALID_ARG;
   if (pb->M < 1 || pb->M > kMaxM || pb->m < 1 || pb->G < 1 || pb->G > pb->m) return SMC_ERR_INVALID_ARG;
   if (!(pb->ess_frac > 0.0 && pb->ess_frac <= 1.0)) return SMC_ERR_INVALID_ARG;
-  if (pb->move_path < SMC_MOVE_AUTO || pb->move_path > SMC_MOVE_RESIDENT) return SMC_ERR_INVALID_ARG;
+  if (pb->move_path < SMC_MOVE_AUTO || pb->move_path > SMC_MOVE_RESIDENT_MFMA) return SMC_ERR_INVALID_ARG;
   if (pb->dataset > 0xFFFFu) return SMC_ERR_INVALID_ARG;
   if ((pb->m + pb->G - 1) / pb->G > kMaxBlock) return SMC_ERR_UNSUPPORTED;
   if (!pb->prior_mean || !pb->prior_prec) return SMC_ERR_INVALID_ARG;
@@ -232,9 +238,13 @@ smc_status validate(const smc_problem* pb) {
 // remainder leaves the register file room for them (the logistic remainder
 // needs more registers than the Poisson one: at d = 20 its rows would spill).
 // 4 covers the subsamples just too large for LDS alone, 14 the largest.
-constexpr int kResMaxOptions = 3;
+constexpr int kResMaxRows = 3;
+// each FP32 layout in both forms of the x'delta product (vector ALU, matrix cores)
+constexpr int kResMaxOptions = 2 * kResMaxRows;
+// the form smc_init picks for FP32 rows (smc_autotune_move measures both)
+constexpr int kResMfmaDefault = 0;
 
-int res_candidates(bool fp32, int dc, int family, int out[kResMaxOptions]) {
+int res_candidates(bool fp32, int dc, int family, int out[kResMaxRows]) {
   if (dc > 24) return 0;
   out[0] = 0;
   if (fp32 && ((family == SMC_POISSON && dc <= 20) || (family == SMC_LOGISTIC && dc <= 16))) {
@@ -245,12 +255,26 @@ int res_candidates(bool fp32, int dc, int family, int out[kResMaxOptions]) {
   return 1;
 }
 
-// Every register-row count whose layout fits, smallest first.
-int resident_options(const smc_problem& pb, int max_lds, int rpl[kResMaxOptions], ResLayout ly[kResMaxOptions]) {
+struct ResOption {
+  int rpl, mf;
+  ResLayout ly;
+  int tile;  // streaming options (rpl = -1): the lane-group row loop's tile form
+};
+
+// tile forms of the lane-group streaming move for a problem (see launch_wide.hip)
+int wide_tiles(const smc_problem& pb) {
+  if (pb.d <= kMaxNarrowD) return 1;
+  const WideShape w = wide_shape(pb.d, pb.precision == SMC_MIXED);
+  return (pb.precision == SMC_MIXED && pb.family == SMC_LOGISTIC && (w.G == 4 || w.G == 8)) ? 2 : 1;
+}
+
+// Every register-row count whose layout fits, smallest first, each FP32 one
+// with the x'delta product on the vector ALU and on the matrix cores.
+int resident_options(const smc_problem& pb, int max_lds, ResOption opt[kResMaxOptions]) {
   if (pb.d > kMaxNarrowD || (pb.family != SMC_LOGISTIC && pb.family != SMC_POISSON)) return 0;
   const bool fp32 = pb.precision == SMC_MIXED;
   const int dc = pad_dc(pb.d);
-  int cand[kResMaxOptions];
+  int cand[kResMaxRows];
   const int nc = res_candidates(fp32, dc, pb.family, cand);
   int n = 0;
   for (int q = 0; q < nc; ++q) {
@@ -258,22 +282,28 @@ int resident_options(const smc_problem& pb, int max_lds, int rpl[kResMaxOptions]
     // register rows are unpredicated in the kernel: every slot must hold a row
     const bool regs_full = pb.m >= kResLanes * cand[q];
     if (regs_full && l.total <= max_lds && (l.nlds + kResLanes - 1) / kResLanes <= kResMaxLdsGroups) {
-      rpl[n] = cand[q];
-      ly[n] = l;
-      ++n;
+      for (int mf = 0; mf <= (fp32 ? 1 : 0); ++mf) opt[n++] = ResOption{cand[q], mf, l, 0};
     }
   }
   return n;
 }
 
-// Smallest register-row count whose LDS part fits; -1 if the resident kernel
-// does not apply.
-int choose_resident(const smc_problem& pb, int max_lds, ResLayout& ly) {
-  int rpl[kResMaxOptions];
-  ResLayout l[kResMaxOptions];
-  if (resident_options(pb, max_lds, rpl, l) == 0) return -1;
-  ly = l[0];
-  return rpl[0];
+// Smallest register-row count whose LDS part fits, with the product in the
+// form the move path asks for (the default form on the automatic path);
+// false if the resident kernel does not apply.
+bool choose_resident(const smc_problem& pb, int max_lds, ResOption& o) {
+  ResOption opt[kResMaxOptions];
+  const int n = resident_options(pb, max_lds, opt);
+  const int want = pb.move_path == SMC_MOVE_RESIDENT_MFMA ? 1
+                   : pb.move_path == SMC_MOVE_RESIDENT    ? 0
+                                                           : kResMfmaDefault;
+  int best = -1;
+  for (int q = 0; q < n && best < 0; ++q)  // the options come by register rows, ascending
+    if (opt[q].mf == want) best = q;
+  if (best < 0 && pb.move_path == SMC_MOVE_AUTO && n > 0) best = 0;  // FP64 rows: the vector form only
+  if (best < 0) return false;
+  o = opt[best];
+  return true;
 }
 
 // The move kernel of a context (the estimator kernels use the narrow or wide
@@ -287,7 +317,9 @@ KernelShape move_shape(smc_ctx c) {
   s.lanes = w.G;
   s.ch = w.CH;
   s.rpl = c->res_rpl;
+  s.mf = c->res_rpl >= 0 ? c->res_mf : 0;
   s.kind = c->res_rpl >= 0 ? kMoveResident : (c->pb.d > kMaxNarrowD ? kMoveWide : kMoveNarrow);
+  s.tile = s.kind == kMoveWide ? c->wide_tile : 0;
   return s;
 }
 
@@ -650,6 +682,9 @@ MoveArgs move_args(smc_ctx c, double eps, int L) {
   a.grad_l = c->at<double>(c->lay.grad_l);
   a.grad_s = c->at<double>(c->lay.grad_s);
   a.accept = c->pb.accept;
+  a.ties = c->at<int32_t>(c->lay.ties);
+  a.tie_tol = c->pb.precision == SMC_MIXED ? 1e-5 : 1e-9;
+  a.diag = c->at<double>(c->lay.diag);
   return a;
 }
 
@@ -693,10 +728,15 @@ smc_status smc_init(const smc_problem* pb, void* stream, smc_ctx* out) {
   const int d = pb->d;
   if (pb->move_path != SMC_MOVE_STREAMING) {
     int dev = 0, max_lds = 0;
+    ResOption o;
     if (hipGetDevice(&dev) == hipSuccess &&
-        hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess)
-      c->res_rpl = choose_resident(*pb, max_lds, c->res_ly);
-    if (pb->move_path == SMC_MOVE_RESIDENT && c->res_rpl < 0) {
+        hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess &&
+        choose_resident(*pb, max_lds, o)) {
+      c->res_rpl = o.rpl;
+      c->res_mf = o.mf;
+      c->res_ly = o.ly;
+    }
+    if ((pb->move_path == SMC_MOVE_RESIDENT || pb->move_path == SMC_MOVE_RESIDENT_MFMA) && c->res_rpl < 0) {
       *out = c;
       return fail(c, SMC_ERR_UNSUPPORTED, "resident move kernel does not apply to this problem");
     }
@@ -920,6 +960,7 @@ smc_status smc_move(smc_ctx c, double eps, int32_t L, int32_t R) {
     hipEvent_t* ev = ring > 0 ? &c->mev[2 * (c->mev_next % ring)] : nullptr;
     if (ev) HIP_TRY(c, hipEventRecord(ev[0], c->stream));
     HIP_TRY(c, launch_move(c, move_args(c, eps, L)));
+    c->moved = 1;
     if (ev) {
       HIP_TRY(c, hipEventRecord(ev[1], c->stream));
       c->mev_next += 1;
@@ -940,23 +981,16 @@ smc_status smc_autotune_move(smc_ctx c, double eps, int32_t L, int32_t* rpl_out,
   const smc_problem& pb = c->pb;
   // the options: the streaming kernel and every resident layout that fits,
   // within the path the problem asked for
-  std::vector<int> rpl;
-  std::vector<ResLayout> lys;
-  if (pb.move_path != SMC_MOVE_RESIDENT) {
-    rpl.push_back(-1);
-    lys.push_back(ResLayout{});
-  }
+  std::vector<ResOption> opts;
+  if (pb.move_path == SMC_MOVE_AUTO || pb.move_path == SMC_MOVE_STREAMING)
+    for (int t = 0; t < wide_tiles(pb); ++t) opts.push_back(ResOption{-1, 0, ResLayout{}, t});
   if (pb.move_path != SMC_MOVE_STREAMING) {
     int dev = 0, max_lds = 0;
     HIP_TRY(c, hipGetDevice(&dev));
     HIP_TRY(c, hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
-    int r[kResMaxOptions];
-    ResLayout l[kResMaxOptions];
-    const int n = resident_options(pb, max_lds, r, l);
-    for (int q = 0; q < n; ++q) {
-      rpl.push_back(r[q]);
-      lys.push_back(l[q]);
-    }
+    ResOption o[kResMaxOptions];
+    const int n = resident_options(pb, max_lds, o);
+    for (int q = 0; q < n; ++q) opts.push_back(o[q]);
   }
   const size_t M = pb.M, d = pb.d, m = pb.m;
   struct Buf { void* live; void* saved; size_t bytes; };
@@ -977,14 +1011,16 @@ smc_status smc_autotune_move(smc_ctx c, double eps, int32_t L, int32_t* rpl_out,
     }
     return hipSuccess;
   };
-  const int move0 = c->move, rpl0 = c->res_rpl;
+  const int move0 = c->move, rpl0 = c->res_rpl, mf0 = c->res_mf, tile0 = c->wide_tile;
   const ResLayout ly0 = c->res_ly;
-  std::vector<hipEvent_t> ev(2 * rpl.size(), nullptr);
+  std::vector<hipEvent_t> ev(2 * opts.size(), nullptr);
   for (hipEvent_t& e : ev) HIP_TRY(c, hipEventCreate(&e));
   hipError_t err = hipSuccess;
-  for (size_t q = 0; q < rpl.size() && err == hipSuccess; ++q) {
-    c->res_rpl = rpl[q];
-    c->res_ly = lys[q];
+  for (size_t q = 0; q < opts.size() && err == hipSuccess; ++q) {
+    c->res_rpl = opts[q].rpl;
+    c->res_mf = opts[q].mf;
+    c->res_ly = opts[q].ly;
+    c->wide_tile = opts[q].rpl < 0 ? opts[q].tile : tile0;
     // a first launch absorbs one-time costs, the second is timed; both
     // start from the saved state
     for (int rep = 0; rep < 2 && err == hipSuccess; ++rep) {
@@ -1000,7 +1036,7 @@ smc_status smc_autotune_move(smc_ctx c, double eps, int32_t L, int32_t* rpl_out,
   c->move = move0;
   int best = -1;
   float best_ms = 0.f;
-  for (size_t q = 0; q < rpl.size() && err == hipSuccess; ++q) {
+  for (size_t q = 0; q < opts.size() && err == hipSuccess; ++q) {
     float t = 0.f;
     err = hipEventElapsedTime(&t, ev[2 * q], ev[2 * q + 1]);
     if (ms_out) ms_out[q] = t;
@@ -1013,14 +1049,49 @@ smc_status smc_autotune_move(smc_ctx c, double eps, int32_t L, int32_t* rpl_out,
     if (e) (void)hipEventDestroy(e);
   if (err != hipSuccess || best < 0) {
     c->res_rpl = rpl0;
+    c->res_mf = mf0;
     c->res_ly = ly0;
+    c->wide_tile = tile0;
     HIP_TRY(c, err);
     return fail(c, SMC_ERR_STATE, "no move kernel to tune");
   }
-  c->res_rpl = rpl[best];
-  c->res_ly = lys[best];
-  if (rpl_out) *rpl_out = rpl[best];
+  c->res_rpl = opts[best].rpl;
+  c->res_mf = opts[best].mf;
+  c->res_ly = opts[best].ly;
+  c->wide_tile = opts[best].rpl < 0 ? opts[best].tile : tile0;
+  if (rpl_out) *rpl_out = opts[best].rpl;
   return SMC_OK;
+}
+
+smc_status smc_set_move_option(smc_ctx c, int32_t res_rows, int32_t res_mfma, int32_t stream_tile) {
+  if (!c) return SMC_ERR_INVALID_ARG;
+  const smc_problem& pb = c->pb;
+  if (res_rows < 0) {
+    if (pb.move_path == SMC_MOVE_RESIDENT || pb.move_path == SMC_MOVE_RESIDENT_MFMA)
+      return fail(c, SMC_ERR_UNSUPPORTED, "the problem asks for the resident move");
+    if (stream_tile < 0 || stream_tile >= wide_tiles(pb))
+      return fail(c, SMC_ERR_UNSUPPORTED, "no tile form %d for this problem", stream_tile);
+    c->res_rpl = -1;
+    c->res_mf = 0;
+    c->wide_tile = stream_tile;
+    return SMC_OK;
+  }
+  if (pb.move_path == SMC_MOVE_STREAMING) return fail(c, SMC_ERR_UNSUPPORTED, "the problem asks for the streaming move");
+  int dev = 0, max_lds = 0;
+  HIP_TRY(c, hipGetDevice(&dev));
+  HIP_TRY(c, hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+  ResOption o[kResMaxOptions];
+  const int n = resident_options(pb, max_lds, o);
+  for (int q = 0; q < n; ++q) {
+    if (o[q].rpl == res_rows && o[q].mf == res_mfma) {
+      c->res_rpl = o[q].rpl;
+      c->res_mf = o[q].mf;
+      c->res_ly = o[q].ly;
+      return SMC_OK;
+    }
+  }
+  return fail(c, SMC_ERR_UNSUPPORTED, "no resident layout with %d register rows (matrix cores %d) fits", res_rows,
+              res_mfma);
 }
 
 smc_status smc_set_move_timing(smc_ctx c, int32_t n) {
@@ -1089,6 +1160,56 @@ smc_status smc_refresh(smc_ctx c) {
   return refresh(c);
 }
 
+smc_status loglik_lambda(smc_ctx c, int32_t count, const double* theta, const int32_t* u, double a, double* lam,
+                         double* lhat, double* sig2) {
+  if (!c || count < 0 || (count > 0 && (!theta || !u || !lam))) return SMC_ERR_INVALID_ARG;
+  if (!(a >= 0.0 && a <= 1.0)) return fail(c, SMC_ERR_INVALID_ARG, "exponent must be in [0, 1]");
+  EstArgs e;
+  std::memset(&e, 0, sizeof(e));
+  e.P = c->prob;
+  e.count = count;
+  e.theta = theta;
+  e.u = u;
+  e.lhat = lhat;
+  e.sig2 = sig2;
+  e.a = a;
+  e.lam = lam;
+  HIP_TRY(c, launch_estimator(c, count, e));
+  return SMC_OK;
+}
+
+smc_status smc_move_diag(smc_ctx c, double* diag) {
+  if (!c || !diag) return SMC_ERR_INVALID_ARG;
+  if (!c->moved) return fail(c, SMC_ERR_STATE, "no move has run on this context");
+  HIP_TRY(c, hipMemcpyAsync(diag, c->at<double>(c->lay.diag), (size_t)c->pb.M * 32, hipMemcpyDeviceToHost,
+                            c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return SMC_OK;
+}
+
+smc_status smc_move_stats(smc_ctx c, double* accept_u, double* accept_theta, int64_t* near_ties_u,
+                          int64_t* near_ties_theta) {
+  if (!c) return SMC_ERR_INVALID_ARG;
+  if (!c->moved) return fail(c, SMC_ERR_STATE, "no move has run on this context");
+  const size_t M = c->pb.M;
+  std::vector<int32_t> acc(M * 2), tie(M * 2);
+  HIP_TRY(c, hipMemcpyAsync(acc.data(), c->pb.accept, M * 8, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(tie.data(), c->at<int32_t>(c->lay.ties), M * 8, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  int64_t au = 0, at = 0, tu = 0, tt = 0;
+  for (size_t i = 0; i < M; ++i) {
+    au += acc[2 * i] != 0;
+    at += acc[2 * i + 1] != 0;
+    tu += tie[2 * i] != 0;
+    tt += tie[2 * i + 1] != 0;
+  }
+  if (accept_u) *accept_u = (double)au / (double)M;
+  if (accept_theta) *accept_theta = (double)at / (double)M;
+  if (near_ties_u) *near_ties_u = tu;
+  if (near_ties_theta) *near_ties_theta = tt;
+  return SMC_OK;
+}
+
 smc_status smc_recentre(smc_ctx c, const double* theta_bar_host) {
   if (!c) return SMC_ERR_INVALID_ARG;
   const int d = c->pb.d;
@@ -1122,6 +1243,9 @@ smc_status smc_get_info(smc_ctx c, smc_info* o) {
   o->have_mass = c->have_mass;
   o->newton_iters = c->newton_iters;
   o->move_path = c->res_rpl >= 0 ? SMC_MOVE_RESIDENT : SMC_MOVE_STREAMING;
+  o->res_rows = c->res_rpl;
+  o->res_mfma = c->res_rpl >= 0 ? c->res_mf : 0;
+  o->stream_tile = c->wide_tile;
   return SMC_OK;
 }
 
@@ -1132,6 +1256,177 @@ smc_status smc_set_stage(smc_ctx c, int32_t stage, int32_t move, double a, doubl
   c->move = move;
   c->a = a;
   c->logz = logz;
+  return SMC_OK;
+}
+
+// ------------------------------------------------------------------------
+// checkpoint and resume
+// ------------------------------------------------------------------------
+
+}  // extern "C"
+
+namespace {
+
+constexpr uint64_t kStateMagic = 0x5453434D53425553ull;  // "SUBSMCST"
+constexpr uint32_t kStateVersion = 3;
+
+struct StateHeader {
+  uint64_t magic;
+  uint32_t version;
+  int32_t family, precision, cv_order, d, M, m, G;
+  uint32_t dataset;
+  int64_t n;
+  uint64_t seed;
+  int32_t stage, move, have_mass, res_rpl, res_mf, wide_tile, newton_iters, moved;
+  double a, logz;
+  uint64_t bytes;
+};
+
+// the arrays of a state blob, in blob order: (device pointer, bytes)
+std::vector<std::pair<char*, size_t>> state_arrays(smc_ctx c) {
+  const size_t M = c->pb.M, d = c->pb.d, m = c->pb.m, dd = d * d * 8;
+  return {{const_cast<char*>(reinterpret_cast<const char*>(c->prob.theta_bar)), d * 8},
+          {c->at<char>(c->lay.Sigma), dd},
+          {c->at<char>(c->lay.Lchol), dd},
+          {c->at<char>(c->lay.Linv), dd},
+          {c->at<char>(c->lay.mean), d * 8},
+          {reinterpret_cast<char*>(c->pb.theta), M * d * 8},
+          {reinterpret_cast<char*>(c->pb.u), M * m * 4},
+          {reinterpret_cast<char*>(c->pb.logw), M * 8},
+          {reinterpret_cast<char*>(c->pb.lhat), M * 8},
+          {reinterpret_cast<char*>(c->pb.sig2), M * 8},
+          {c->at<char>(c->lay.grad_l), M * d * 8},
+          {c->at<char>(c->lay.grad_s), M * d * 8},
+          {reinterpret_cast<char*>(c->pb.accept), M * 8},
+          {c->at<char>(c->lay.ties), M * 8},
+          {c->at<char>(c->lay.diag), M * 32}};
+}
+
+size_t state_bytes(smc_ctx c) {
+  size_t total = sizeof(StateHeader);
+  for (const auto& a : state_arrays(c)) total += a.second;
+  return total;
+}
+
+StateHeader state_identity(smc_ctx c) {
+  StateHeader h;
+  std::memset(&h, 0, sizeof(h));
+  h.magic = kStateMagic;
+  h.version = kStateVersion;
+  h.family = c->pb.family;
+  h.precision = c->pb.precision;
+  h.cv_order = c->pb.cv_order;
+  h.d = c->pb.d;
+  h.M = c->pb.M;
+  h.m = c->pb.m;
+  h.G = c->pb.G;
+  h.dataset = c->pb.dataset;
+  h.n = c->pb.n;
+  h.seed = c->pb.seed;
+  h.bytes = state_bytes(c);
+  return h;
+}
+
+}  // namespace
+
+extern "C" {
+
+smc_status smc_get_state(smc_ctx c, void* blob, size_t* bytes) {
+  if (!c || !bytes) return SMC_ERR_INVALID_ARG;
+  const size_t need = state_bytes(c);
+  if (!blob) {
+    *bytes = need;
+    return SMC_OK;
+  }
+  if (*bytes < need) return fail(c, SMC_ERR_INVALID_ARG, "state blob needs %zu bytes", need);
+  (void)mass_ready(c);  // a failed factorisation is saved as no mass matrix
+  StateHeader h = state_identity(c);
+  h.stage = c->stage;
+  h.move = c->move;
+  h.have_mass = c->have_mass;
+  h.res_rpl = c->res_rpl;
+  h.res_mf = c->res_mf;
+  h.wide_tile = c->wide_tile;
+  h.newton_iters = c->newton_iters;
+  h.moved = c->moved;
+  h.a = c->a;
+  h.logz = c->logz;
+  char* out = static_cast<char*>(blob);
+  std::memcpy(out, &h, sizeof(h));
+  size_t off = sizeof(h);
+  for (const auto& a : state_arrays(c)) {
+    HIP_TRY(c, hipMemcpyAsync(out + off, a.first, a.second, hipMemcpyDeviceToHost, c->stream));
+    off += a.second;
+  }
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  *bytes = need;
+  return SMC_OK;
+}
+
+smc_status smc_set_state(smc_ctx c, const void* blob, size_t bytes) {
+  if (!c || !blob) return SMC_ERR_INVALID_ARG;
+  StateHeader h;
+  if (bytes < sizeof(h)) return fail(c, SMC_ERR_INVALID_ARG, "state blob too short");
+  std::memcpy(&h, blob, sizeof(h));
+  const StateHeader id = state_identity(c);
+  if (h.magic != id.magic || h.version != id.version)
+    return fail(c, SMC_ERR_INVALID_ARG, "not a state blob of this library version");
+  if (h.family != id.family || h.precision != id.precision || h.cv_order != id.cv_order || h.d != id.d ||
+      h.M != id.M || h.m != id.m || h.G != id.G || h.dataset != id.dataset || h.n != id.n || h.seed != id.seed)
+    return fail(c, SMC_ERR_INVALID_ARG, "state blob belongs to a different problem");
+  if (h.bytes != id.bytes || bytes < h.bytes) return fail(c, SMC_ERR_INVALID_ARG, "state blob size mismatch");
+  if (h.stage < 0 || h.move < 0 || !(h.a >= 0.0 && h.a <= 1.0) || h.have_mass < 0 || h.have_mass > 1)
+    return fail(c, SMC_ERR_INVALID_ARG, "state blob holds invalid counters");
+  if (h.wide_tile < 0 || h.wide_tile >= wide_tiles(c->pb))
+    return fail(c, SMC_ERR_INVALID_ARG, "state blob holds an unknown tile form");
+  // the move kernel: streaming, or a resident layout that fits this device
+  ResLayout ly{};
+  if (h.res_rpl >= 0) {
+    if (c->pb.move_path == SMC_MOVE_STREAMING) return fail(c, SMC_ERR_INVALID_ARG, "state uses the resident move");
+    int dev = 0, max_lds = 0;
+    HIP_TRY(c, hipGetDevice(&dev));
+    HIP_TRY(c, hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    ResOption o[kResMaxOptions];
+    const int n = resident_options(c->pb, max_lds, o);
+    int q = 0;
+    while (q < n && !(o[q].rpl == h.res_rpl && o[q].mf == h.res_mf)) ++q;
+    if (q == n) return fail(c, SMC_ERR_INVALID_ARG, "state's resident layout does not fit this device");
+    ly = o[q].ly;
+  } else if (c->pb.move_path == SMC_MOVE_RESIDENT || c->pb.move_path == SMC_MOVE_RESIDENT_MFMA) {
+    return fail(c, SMC_ERR_INVALID_ARG, "state uses the streaming move");
+  }
+  // settle anything in flight on the stream before overwriting its buffers
+  if (c->have_mass == 2) HIP_TRY(c, hipEventSynchronize(c->mass_ev));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  const int d = c->pb.d;
+  const char* in = static_cast<const char*>(blob) + sizeof(h);
+  // control-variate centre: rebuild A, B, C and the packed rows when it moved
+  std::vector<double> tb_now(d);
+  HIP_TRY(c, hipMemcpy(tb_now.data(), c->prob.theta_bar, (size_t)d * 8, hipMemcpyDeviceToHost));
+  const bool recentre = std::memcmp(tb_now.data(), in, (size_t)d * 8) != 0;
+  size_t off = 0;
+  for (const auto& a : state_arrays(c)) {
+    HIP_TRY(c, hipMemcpyAsync(a.first, in + off, a.second, hipMemcpyHostToDevice, c->stream));
+    off += a.second;
+  }
+  if (recentre) {
+    double* tb = const_cast<double*>(c->prob.theta_bar);
+    smc_status st = run_cv(c, tb, true, const_cast<double*>(c->prob.cvA), const_cast<double*>(c->prob.cvB),
+                           const_cast<double*>(c->prob.cvC));
+    if (st != SMC_OK) return st;
+  }
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  c->stage = h.stage;
+  c->move = h.move;
+  c->a = h.a;
+  c->logz = h.logz;
+  c->have_mass = h.have_mass;
+  c->res_rpl = h.res_rpl;
+  c->res_mf = h.res_rpl >= 0 ? h.res_mf : 0;
+  c->res_ly = ly;
+  c->wide_tile = h.wide_tile;
+  c->newton_iters = h.newton_iters;
+  c->moved = h.moved;
   return SMC_OK;
 }
 
@@ -1600,7 +1895,10 @@ smc_status smc_batch_move(smc_batch b, const double* eps, int32_t L, int32_t R) 
     } else {
       BATCH_TRY(b, issue_all(b->stream));
     }
-    for (int k : b->active) b->ctx[k]->move += 1;
+    for (int k : b->active) {
+      b->ctx[k]->move += 1;
+      b->ctx[k]->moved = 1;
+    }
     if (b->timing) b->timed_moves += 1;
   }
   return SMC_OK;

@@ -21,8 +21,16 @@ def test_several_gpus_are_refused():
 
 def test_peaks():
     # 256 CUs x 4 SIMDs x 16 lanes x 2 flops x 2.4 GHz, without and with packed FP32
-    assert abs(bench.PEAK_VALU_TFLOPS - 256 * 4 * 16 * 2 * 2.4e9 / 1e12) < 0.05
-    assert abs(bench.PEAK_VALU_PACKED_TFLOPS - 2 * bench.PEAK_VALU_TFLOPS) < 0.2
+    assert abs(bench.PEAK_VALU_NONPACKED_TFLOPS - 256 * 4 * 16 * 2 * 2.4e9 / 1e12) < 0.05
+    assert abs(bench.PEAK_FP32_TFLOPS - 2 * bench.PEAK_VALU_NONPACKED_TFLOPS) < 0.2
+
+
+def test_default_line_is_the_largest_configuration():
+    assert bench.HEADLINE == "config5"
+    assert set(bench.BESIDE) == {"config4", "config2"}
+    # bytes per eval of the d = 116 and d = 50 mixed-precision rows: x in FP32, y, the index
+    assert bench.algorithmic_bytes_per_eval(116, True) == 472
+    assert bench.algorithmic_bytes_per_eval(50, True) == 208
 
 
 class _W:
@@ -36,9 +44,11 @@ def test_roofline_resident_is_alu_bound():
     r = bench.roofline(w, True, 1.0, bench.MOVE_RESIDENT)
     evals = 2048 * 5000 * 21
     assert r["bound"] == "alu" and r["unit"] == "TFLOP/s"
-    assert r["flops_per_eval"] == 6 * 20 and r["evals_per_launch"] == evals
-    assert abs(r["achieved"] - 120 * evals / 1e-3 / 1e12) < 0.01
-    assert abs(r["frac"] - r["achieved"] / bench.PEAK_VALU_TFLOPS) < 1e-3
+    assert r["flops_per_eval"] == 8 * 20 and r["evals_per_launch"] == evals
+    assert abs(r["achieved"] - 160 * evals / 1e-3 / 1e12) < 0.01
+    assert r["peak"] == 157.3
+    assert abs(r["frac"] - r["achieved"] / bench.PEAK_FP32_TFLOPS) < 1e-3
+    assert abs(r["frac_of_nonpacked_fp32_peak"] - r["achieved"] / 78.6) < 1e-3
 
 
 def test_roofline_streaming_is_hbm_bound():

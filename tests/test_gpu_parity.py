@@ -47,6 +47,85 @@ def say(*a):
     print(*a, flush=True)
 
 
+def remainder_scales(P, th, u):
+    """Per particle, from the oracle's remainders d_j: S_d = (n/m) sum_j |d_j|, the absolute-sum
+    scale of d_hat = (n/m) sum_j d_j (a sum whose terms change sign), and
+    S_s = 2 (n/m)^2 sum_j |d_j - dbar| |d_j|, the first-order response of
+    sigma2_hat = (n/m)^2 sum_j (d_j - dbar)^2 to relative errors of its terms. The mixed path's
+    FP32 error is stated on these scales (as the gradients' on theirs)."""
+    X, y = P.Xy[:, :P.d], P.Xy[:, P.d]
+    eb = X @ P.theta_bar
+    sd, ss = np.zeros(len(th)), np.zeros(len(th))
+    nm = P.n / u.shape[1]
+    for i in range(len(th)):
+        De = X[u[i]] @ (th[i] - P.theta_bar)
+        dj = np.array([P.remainder(y[k], eb[k], De[j])[0] for j, k in enumerate(u[i])])
+        sd[i] = nm * np.abs(dj).sum()
+        ss[i] = 2 * nm * nm * (np.abs(dj - dj.mean()) * np.abs(dj)).sum()
+    return sd, ss
+
+
+def dhat_abs_scale(P, th, u):
+    return remainder_scales(P, th, u)[0]
+
+
+def oracle_move_diag(P, th0, u0, a, eps, L, seed, stage, mv, G, Sig, Lc, mixed):
+    """The oracle's log r of every decision of one move (diag), and again with each particle's
+    delta = theta - theta_bar scaled by 1 + rho, the factor of Sigma (so the momentum) by 1 + rho
+    and Sigma by 1 - rho, rho at the path's rounding level (1e-13 in FP64, 1e-6 for FP32 rows;
+    the GPU forms the momentum with its own inverse factor and transcendentals): how far the
+    oracle's own result moves under a perturbation of that size. Along some trajectories (here
+    the particle clouds with fewer particles than parameters, whose covariance is jittered) the
+    leapfrog amplifies such a change of the momentum by 1e8."""
+    out = oracle.move(P, th0, u0, a, eps, L, seed, stage, mv, G, Sig, Lc, diag=True)
+    rho = 1e-6 if mixed else 1e-13
+    thp = P.theta_bar + (th0 - P.theta_bar) * (1 + rho)
+    out2 = oracle.move(P, thp, u0, a, eps, L, seed, stage, mv, G, Sig * (1 - rho), Lc * (1 + rho), diag=True)
+    return out, out2
+
+
+def check_decisions(smc, acc, dg, mixed, a=None, scale=None, dg2=None):
+    """The GPU's accept decisions against the oracle's, through the move's record of log r and
+    log U: log U is the same draw on both sides (within a few ulps of the logarithm), every GPU
+    decision follows its own log r (log U < log r, log r finite), and the GPU's log r agrees with
+    the oracle's within the path's bound: tau (1 + |log r|), tau = 1e-9 in FP64 and 1e-5 in mixed
+    precision, plus in mixed precision 1e-5 of the scale of the FP32-computed part of the two
+    lambda_a values it differences (`scale`, per particle), plus ten times the oracle's own shift
+    of log r under a rounding-level perturbation of the particle (`dg2`, see oracle_move_diag).
+    So decisions can differ only where log U lies between the two log r values. Returns the
+    particles whose decisions are equal on both sides."""
+    gacc = smc.accept.cpu().numpy()
+    gd = smc.move_diag()
+    for k in (0, 1):
+        # the uniform is the same draw; its logarithm (device log vs the host's) within a few ulps
+        assert np.all(np.abs(gd[:, 2 * k + 1] - dg[:, 2 * k + 1]) <= 4e-16 * np.abs(dg[:, 2 * k + 1]) + 1e-300), k
+        own = np.isfinite(gd[:, 2 * k]) & (gd[:, 2 * k + 1] < gd[:, 2 * k])
+        assert np.array_equal(gacc[:, k] == 1, own), k
+        # a non-finite log r (an overflowing trajectory far from the data) rejects; where either
+        # side has one, both sides reject
+        fin = np.isfinite(dg[:, 2 * k]) & np.isfinite(gd[:, 2 * k])
+        assert np.all(gacc[~fin, k] == 0) and np.all(acc[~fin, k] == 0), k
+        if (~fin).any():
+            say("non-finite log r", "u" if k == 0 else "theta", "gpu", int((~np.isfinite(gd[:, 2 * k])).sum()),
+                "oracle", int((~np.isfinite(dg[:, 2 * k])).sum()))
+        err = np.abs(gd[fin, 2 * k] - dg[fin, 2 * k])
+        rel = err / (1 + np.abs(dg[fin, 2 * k]))
+        if mixed:
+            tol = 1e-5 * (1 + np.abs(dg[fin, 2 * k])) + (1e-5 * scale[fin] if scale is not None else 0.0)
+        else:
+            tol = 1e-9 * (1 + np.abs(dg[fin, 2 * k]))
+        if dg2 is not None:
+            sens = np.abs(dg2[fin, 2 * k] - dg[fin, 2 * k])
+            tol = tol + 10.0 * np.where(np.isfinite(sens), sens, np.inf)
+        say("log r", "u" if k == 0 else "theta", "max error / (1 + |log r|)", rel.max() if len(rel) else 0.0,
+            "max error / tol", (err / tol).max() if len(err) else 0.0)
+        assert np.all(err <= tol), (k, err.max(), (err / tol).max())
+        between = (np.abs(dg[:, 2 * k + 1] - dg[:, 2 * k])
+                   <= np.abs(gd[:, 2 * k] - dg[:, 2 * k]) + np.abs(gd[:, 2 * k + 1] - dg[:, 2 * k + 1]))
+        assert np.all((gacc[:, k] == acc[:, k]) | between | ~fin), k
+    return (gacc == acc).all(axis=1)
+
+
 CASES = [
     ("logistic", lambda: W.logistic_small(4000, 5, seed=1, M=64, m=500, G=4), 0.15),
     ("logistic_ragged", lambda: W.logistic_small(3000, 3, seed=2, M=33, m=101, G=3), 0.3),
@@ -160,17 +239,26 @@ def _check_estimator_mixed(name, w, scale, cv_order):
     grad, gl, gs = smc.loglik_grad(tht, ut, separate=True)
     torch.cuda.synchronize()
     ref = P.estimate(th, u, grad=True)
-    lh, s2, gl, gs = (x.cpu().numpy() for x in (lh, s2, gl, gs))
+    lh, s2, dh, gl, gs = (x.cpu().numpy() for x in (lh, s2, dh, gl, gs))
     # metric bound: relative log-likelihood error <= 1e-5
     assert np.max(np.abs(lh - ref["lhat"]) / np.abs(ref["lhat"])) <= 1e-5
+    # l_hat is dominated by the exact FP64 constant A; its FP32-computed part is
+    # d_hat, checked on its own against the absolute-sum scale of its terms
+    ds, ss = remainder_scales(P, th, u)
+    err_d = np.abs(dh - ref["dhat"])
+    say("dhat error / abs-sum scale", np.max(err_d / ds), "/ |dhat|", np.max(err_d / np.abs(ref["dhat"])))
+    assert np.all(err_d <= 1e-5 * ds + 1e-13 * np.abs(ref["lhat"]))
     # the absolute floor of the FP64 comparison (sigma2 exactly zero when all
     # remainders coincide)
     floor = (1e-12 * np.abs(ref["lhat"])) ** 2
-    assert np.all(np.abs(s2 - ref["sig2"]) <= 1e-4 * ref["sig2"] + floor)
+    err_s = np.abs(s2 - ref["sig2"])
+    say("sigma2 error / sigma2", np.max(err_s / (ref["sig2"] + floor)), "/ its scale", np.max(err_s / (ss + floor)))
+    assert np.all(err_s <= 1e-5 * ss + floor)
     sc = grad_scale(P, th, ref["grad_l"])
     assert np.max(np.abs(gl - ref["grad_l"]) / sc) <= 1e-5
     gsc = np.abs(ref["grad_s"]).max(axis=1, keepdims=True)
-    assert np.all(np.abs(gs - ref["grad_s"]) <= 1e-4 * gsc + floor[:, None])
+    say("grad sigma2 error / max component", np.max(np.abs(gs - ref["grad_s"]) / (gsc + floor[:, None])))
+    assert np.all(np.abs(gs - ref["grad_s"]) <= 1e-5 * gsc + floor[:, None])
     smc.close()
 
 
@@ -328,6 +416,17 @@ MOVE_CASES = [
     ("student", lambda: W.student_small(6000, 6, seed=64, M=48, m=300, G=10, L=8), 0.8, 0.1),
     ("student_mixed_d50", lambda: W.student_small(5000, 50, seed=65, precision=W.MIXED, M=16, m=200, G=8, L=5,
                                                   theta_scale=0.3), 0.8, 0.08),
+    # logistic rows of d = 12 with 3000 slots: too many for LDS alone, so 4 register rows per lane
+    ("logistic_mixed_m3000", lambda: W.logistic_small(20000, 12, seed=66, precision=W.MIXED, M=12, m=3000, G=30,
+                                                      L=4), 0.7, 0.05),
+    # the shapes of the logistic d = 50 and additive d = 116 benchmark configurations: 20,000 and
+    # 50,000 slots in 100 blocks (refreshed blocks of 200 and 500 indices), few particles
+    ("logistic_mixed_cfg4_shape", lambda: W.logistic_small(40000, 50, seed=67, precision=W.MIXED, M=6, m=20000,
+                                                           G=100, L=3, theta_scale=0.15), 0.9, 0.05),
+    ("logistic_cfg4_shape", lambda: W.logistic_small(40000, 50, seed=67, M=6, m=20000, G=100, L=3,
+                                                     theta_scale=0.15), 0.9, 0.05),
+    ("logistic_mixed_cfg5_shape", lambda: W.logistic_small(60000, 116, seed=68, precision=W.MIXED, M=4, m=50000,
+                                                           G=100, L=2, theta_scale=0.1), 0.9, 0.03),
 ]
 
 
@@ -340,6 +439,28 @@ def test_move_parity(name, mk, a, eps, spread, path):
     _check_move(name, mk(), a, eps, spread, path, 2)
 
 
+MFMA_CASES = ["logistic_mixed", "poisson_mixed_d20", "poisson_mixed_m5000", "logistic_mixed_m1500",
+              "logistic_mixed_m3000", "logistic_mixed_m4500", "poisson_mixed_m3000"]
+
+
+@pytest.mark.parametrize("spread", [0.02, 0.3], ids=["near", "far"])
+@pytest.mark.parametrize("name", MFMA_CASES)
+def test_move_parity_mfma(name, spread):
+    """The resident move with each row's x'delta on the matrix cores (v_mfma_f32_4x4x1f32):
+    every FP32 resident layout (all rows in LDS, 4 and 14 register rows per lane)."""
+    _, mk, a, eps = next(c for c in MOVE_CASES if c[0] == name)
+    _check_move(name, mk(), a, eps, spread, 3, 2)
+
+
+@pytest.mark.parametrize("name", ["logistic_mixed_d116", "logistic_mixed_cfg4_shape", "logistic_mixed_cfg5_shape"])
+def test_move_parity_stream_tiles(name):
+    """Both tile forms of the lane-group move's row loop for FP32 logistic rows: each row's
+    remainder evaluated in one lane of its group (form 0) or in every lane (form 1)."""
+    _, mk, a, eps = next(c for c in MOVE_CASES if c[0] == name)
+    for tile in (0, 1):
+        _check_move(name, mk(), a, eps, 0.02, 1, 2, tile=tile)
+
+
 @pytest.mark.parametrize("path", [1, 0], ids=["streaming", "auto"])
 @pytest.mark.parametrize("name", ["logistic", "poisson_mixed_d20", "logistic_d50", "logistic_mixed_d116",
                                   "poisson_mixed_m5000", "logistic_mixed_m1500", "student_mixed_d50"])
@@ -350,10 +471,12 @@ def test_move_first_order(name, path):
     _check_move(name, mk(), a, eps, 0.02, path, 1)
 
 
-def _check_move(name, w, a, eps, spread, path, cv_order):
-    say("move case", name, spread, path, "cv order", cv_order)
+def _check_move(name, w, a, eps, spread, path, cv_order, tile=None):
+    say("move case", name, spread, path, "cv order", cv_order, "tile", tile)
     P, smc = make_pair(w, move_path=path, cv_order=cv_order)
-    say("kernel", smc.info()["move_path"])
+    if tile is not None:
+        smc.set_move_option(-1, 0, tile)
+    say("kernel", smc.info())
     mixed = w.precision == W.MIXED
     # a particle cloud around theta_bar: the oracle's prior draws shrunk towards it
     thp, u0, _ = oracle.init_particles(w.M, w.d, w.m, w.n, w.seed, w.prior_mean, w.prior_prec)
@@ -367,28 +490,53 @@ def _check_move(name, w, a, eps, spread, path, cv_order):
     smc.set_stage(stage, mv, a)
     smc.move(eps, w.L, 1)
     torch.cuda.synchronize()
-    th1, u1, acc, lh1, sg1, dg = oracle.move(P, th0, u0, a, eps, w.L, w.seed, stage, mv, w.G, Sig, Lc, diag=True)
+    (th1, u1, acc, lh1, sg1, dg), out2 = oracle_move_diag(P, th0, u0, a, eps, w.L, w.seed, stage, mv, w.G, Sig, Lc,
+                                                         mixed)
+    th1b, dg2 = out2[0], out2[-1]
     gacc = smc.accept.cpu().numpy()
     tau = 1e-5 if mixed else 1e-9
     near_u = np.abs(dg[:, 1] - dg[:, 0]) <= tau * (1 + np.abs(dg[:, 0]))
     near_t = np.abs(dg[:, 3] - dg[:, 2]) <= tau * (1 + np.abs(dg[:, 2]))
-    ok_u = (gacc[:, 0] == acc[:, 0]) | near_u
-    ok_t = (gacc[:, 1] == acc[:, 1]) | near_t
     say("accept rates", acc.mean(0), "near ties", near_u.sum(), near_t.sum())
-    assert ok_u.all() and ok_t.all(), (np.where(~ok_u), np.where(~ok_t))
-    same = (gacc == acc).all(axis=1)
+    scale = None
+    if mixed:
+        # the FP32-computed part of the two lambda_a values each log r differences
+        sd, ss = remainder_scales(P, th0, u0)
+        scale = 2 * (a * sd + 0.5 * a * a * ss)
+    same = check_decisions(smc, acc, dg, mixed, a, scale, dg2)
     gu = smc.u.cpu().numpy()
     np.testing.assert_array_equal(gu[same], u1[same])
     rt = 1e-5 if mixed else 1e-9
     gth = smc.theta.cpu().numpy()
-    np.testing.assert_allclose(gth[same], th1[same], rtol=rt, atol=rt * np.abs(th1).max())
-    np.testing.assert_allclose(smc.lhat.cpu().numpy()[same], lh1[same], rtol=rt)
+    # theta within rt, plus ten times the oracle's own shift under the rounding-level perturbation
+    # (the same allowance as for log r; it matters only along ill-conditioned trajectories)
+    same2 = same & (out2[2] == acc).all(axis=1)
+    tol_th = rt * np.abs(th1[same2]) + rt * np.abs(th1).max() + 10 * np.abs(th1b[same2] - th1[same2])
+    assert np.all(np.abs(gth[same2] - th1[same2]) <= tol_th)
+    # the cached estimator at the particle's final state, against the oracle's estimator at that
+    # same state (the final states of the two sides differ within the trajectory tolerance, which
+    # sigma2_hat, of order Delta^6, would amplify)
+    gth_s, gu_s = gth[same], gu[same]
+    ref = P.estimate(gth_s, gu_s)
+    np.testing.assert_allclose(smc.lhat.cpu().numpy()[same], ref["lhat"], rtol=rt)
     if w.family != W.GAUSSIAN:
-        # with the absolute floor of the estimator checks (sigma2 = 0 when all remainders coincide)
+        fl = (1e-12 * np.abs(ref["lhat"])) ** 2
         gs2 = smc.sig2.cpu().numpy()[same]
-        fl = (1e-12 * np.abs(lh1[same])) ** 2
-        assert np.all(np.abs(gs2 - sg1[same]) <= (1e-4 if mixed else 1e-8) * np.abs(sg1[same]) + fl)
+        if mixed:
+            _, ss = remainder_scales(P, gth_s, gu_s)
+            assert np.all(np.abs(gs2 - ref["sig2"]) <= 1e-5 * ss + fl)
+        else:
+            assert np.all(np.abs(gs2 - ref["sig2"]) <= 1e-9 * np.abs(ref["sig2"]) + fl)
     assert 0 < acc[:, 1].mean() or spread > 0.1
+    # the library's own accounting of the move: accept rates, and near ties of its own log r
+    st = smc.move_stats()
+    gd = smc.move_diag()
+    assert st["accept_u"] == gacc[:, 0].mean() and st["accept_theta"] == gacc[:, 1].mean()
+    for k, key in ((0, "near_ties_u"), (1, "near_ties_theta")):
+        lr, lu = gd[:, 2 * k], gd[:, 2 * k + 1]
+        with np.errstate(invalid="ignore"):
+            own = np.isfinite(lr) & (np.abs(lu - lr) <= tau * (1 + np.abs(lr)))
+        assert st[key] == own.sum(), key
     smc.close()
 
 
@@ -416,8 +564,9 @@ def test_autotune_restores_state_and_keeps_parity():
         assert torch.equal(a, b)
     info1 = smc.info()
     assert info1["move"] == info0["move"] and info1["stage"] == info0["stage"]
-    # 0 or 4 register rows would leave too many of the 5000 rows for LDS: only streaming and 14 fit
-    assert rpl in (-1, 14) and (ms[:2] > 0).all() and (ms[2:] == 0).all()
+    # 0 or 4 register rows would leave too many of the 5000 rows for LDS: only streaming and 14 fit,
+    # the latter with x'delta on the vector ALU and on the matrix cores
+    assert rpl in (-1, 14) and (ms[:3] > 0).all() and (ms[3:] == 0).all()
     assert info1["move_path"] == (1 if rpl < 0 else 2)
     smc.move(0.1, w.L, 1)
     torch.cuda.synchronize()
@@ -433,17 +582,27 @@ def test_resident_path_is_selected():
     B = _binding()
     w = W.poisson_small(30000, 20, seed=59, precision=W.MIXED, M=8, m=5000, G=100)
     P, smc = make_pair(w, move_path=B.MOVE_RESIDENT)
-    assert smc.info()["move_path"] == B.MOVE_RESIDENT
+    assert smc.info()["move_path"] == B.MOVE_RESIDENT and smc.info()["res_rows"] == 14
     smc.close()
     # Poisson d = 12 with 3000 rows: too many for LDS alone, too few for 14 register rows; 4 fit
     w = W.poisson_small(20000, 12, seed=62, precision=W.MIXED, M=8, m=3000, G=30)
     P, smc = make_pair(w, move_path=B.MOVE_RESIDENT)
-    assert smc.info()["move_path"] == B.MOVE_RESIDENT
+    assert smc.info()["move_path"] == B.MOVE_RESIDENT and smc.info()["res_rows"] == 4
     smc.close()
     # logistic d = 12 with 4500 rows: only the layout with 14 register rows per lane fits
     w = W.logistic_small(20000, 12, seed=61, precision=W.MIXED, M=8, m=4500, G=50)
     P, smc = make_pair(w, move_path=B.MOVE_RESIDENT)
-    assert smc.info()["move_path"] == B.MOVE_RESIDENT
+    assert smc.info()["move_path"] == B.MOVE_RESIDENT and smc.info()["res_rows"] == 14
+    smc.close()
+    # logistic d = 12 with 3000 rows: 4 register rows per lane (the case of logistic_mixed_m3000)
+    w = W.logistic_small(20000, 12, seed=66, precision=W.MIXED, M=8, m=3000, G=30)
+    P, smc = make_pair(w)
+    assert smc.info()["move_path"] == B.MOVE_RESIDENT and smc.info()["res_rows"] == 4
+    smc.close()
+    # 500 rows fit in LDS alone
+    w = W.logistic_small(4000, 5, seed=51, precision=W.MIXED, M=8, m=500, G=4)
+    P, smc = make_pair(w)
+    assert smc.info()["move_path"] == B.MOVE_RESIDENT and smc.info()["res_rows"] == 0
     smc.close()
     w = W.logistic_small(4000, 50, seed=14, M=8, m=300, G=10, theta_scale=0.15)
     with pytest.raises(B.SMCError):
@@ -599,3 +758,121 @@ def test_unsupported_width_is_refused():
     with pytest.raises(B.SMCError):
         B.SubsampledSMC(Xy, w.d, w.family, W.FP64, w.M, w.m, w.G, w.prior_mean, w.prior_prec, w.seed,
                         theta_bar=w.theta_true)
+
+
+def _teacher_forced_stages(w, precision, path, tol, max_stages=60):
+    """Every stage of Algorithm 2 (steps b-f: exponent, reweighting, mass matrix,
+    resampling, one move) on the GPU, and the oracle's same stage restarted from
+    the GPU's state before it: exponent, evidence increment, mass matrix and
+    ancestors from identical inputs, then the move."""
+    P, smc = make_pair(w, precision=precision, move_path=path)
+    mixed = precision == W.MIXED
+    tau = 1e-5 if mixed else 1e-9
+    eps, L = 1.0 / w.L, w.L
+    stages = 0
+    ties = 0
+    while smc.info()["a"] < 1.0 and stages < max_stages:
+        torch.cuda.synchronize()
+        th0, u0 = smc.theta.cpu().numpy(), smc.u.cpu().numpy()
+        lw0, lh0, s20 = smc.logw.cpu().numpy(), smc.lhat.cpu().numpy(), smc.sig2.cpu().numpy()
+        a_prev = smc.info()["a"]
+        a, dz, ess = smc.stage(eps, L, 1)
+        torch.cuda.synchronize()
+        info = smc.info()
+        stages += 1
+        a_o, dz_o, ess_o, lw_o = oracle.temper(lh0, s20, lw0, a_prev, w.ess_frac)
+        assert abs(a - a_o) <= 1e-12 * a_o, (stages, a, a_o)
+        assert abs(dz - dz_o) <= 1e-9 * max(1.0, abs(dz_o)), (stages, dz, dz_o)
+        assert abs(ess - ess_o) <= 1e-9 * w.M
+        _, Sig, Lc = oracle.moments(th0, lw_o)
+        S_gpu = smc.get_mass()[0]
+        np.testing.assert_allclose(S_gpu, Sig, rtol=1e-10, atol=1e-12 * np.abs(Sig).max())
+        anc = oracle.resample_ancestors(lw_o, oracle.resample_offset(w.seed, info["stage"]))
+        (th1, u1, acc, lh1, sg1, dg), out2 = oracle_move_diag(P, th0[anc], u0[anc], a_o, eps, L, w.seed,
+                                                             info["stage"], 0, w.G, Sig, Lc, mixed)
+        th1b, dg2 = out2[0], out2[-1]
+        near_u = np.abs(dg[:, 1] - dg[:, 0]) <= tau * (1 + np.abs(dg[:, 0]))
+        near_t = np.abs(dg[:, 3] - dg[:, 2]) <= tau * (1 + np.abs(dg[:, 2]))
+        ties += int(near_u.sum() + near_t.sum())
+        scale = None
+        if mixed:
+            sd, ss = remainder_scales(P, th0[anc], u0[anc])
+            scale = 2 * (a_o * sd + 0.5 * a_o * a_o * ss)
+        same = check_decisions(smc, acc, dg, mixed, a_o, scale, dg2)
+        gu = smc.u.cpu().numpy()
+        np.testing.assert_array_equal(gu[same], u1[same])
+        gth = smc.theta.cpu().numpy()
+        same2 = same & (out2[2] == acc).all(axis=1)
+        tol_th = tol * np.abs(th1[same2]) + tol * np.abs(th1).max() + 10 * np.abs(th1b[same2] - th1[same2])
+        assert np.all(np.abs(gth[same2] - th1[same2]) <= tol_th), stages
+        # the GPU's cached estimator against the oracle's at the GPU's own state
+        ref = P.estimate(gth, gu)
+        fl = (1e-12 * np.abs(ref["lhat"])) ** 2
+        np.testing.assert_allclose(smc.lhat.cpu().numpy(), ref["lhat"], rtol=tol)
+        if mixed:
+            _, ss = remainder_scales(P, gth, gu)
+            assert np.all(np.abs(smc.sig2.cpu().numpy() - ref["sig2"]) <= 1e-5 * ss + fl), stages
+        else:
+            assert np.all(np.abs(smc.sig2.cpu().numpy() - ref["sig2"]) <= 1e-9 * ref["sig2"] + fl), stages
+        np.testing.assert_allclose(smc.logw.cpu().numpy(), -math.log(w.M), rtol=0, atol=1e-15)
+    say("teacher-forced stages", stages, "near ties", ties)
+    assert smc.info()["a"] == 1.0 and stages >= 3
+    smc.close()
+
+
+TF_CASES = [
+    ("logistic_fp64", lambda: W.logistic_small(3000, 3, seed=61, M=128, m=150, G=4, L=6), W.FP64),
+    ("poisson_fp64", lambda: W.poisson_small(8000, 6, seed=62, M=96, m=300, G=10, L=6), W.FP64),
+    ("logistic_d40_fp64", lambda: W.logistic_small(4000, 40, seed=63, M=64, m=200, G=10, L=4, theta_scale=0.2),
+     W.FP64),
+    ("logistic_mixed", lambda: W.logistic_small(3000, 3, seed=61, precision=W.MIXED, M=128, m=150, G=4, L=6),
+     W.MIXED),
+    ("poisson_mixed_d20", lambda: W.poisson_small(20000, 20, seed=64, precision=W.MIXED, M=64, m=1000, G=100,
+                                                  L=6), W.MIXED),
+]
+
+
+@pytest.mark.parametrize("path", [1, 0], ids=["streaming", "auto"])
+@pytest.mark.parametrize("name,mk,prec", TF_CASES, ids=[c[0] for c in TF_CASES])
+def test_teacher_forced_stages(name, mk, prec, path):
+    """Multi-stage parity with teacher forcing (the oracle restarts every stage
+    from the GPU's state): 1e-9 relative in FP64, 1e-5 in mixed precision."""
+    say("teacher forced", name, "path", path)
+    _teacher_forced_stages(mk(), prec, path, 1e-5 if prec == W.MIXED else 1e-9)
+
+
+def test_full_run_mixed_matches_oracle():
+    """A whole mixed-precision run to a = 1 against the oracle's FP64 run on the
+    same (FP32-rounded) data, free running: same number of stages, exponents
+    and log evidence within the mixed-precision bound."""
+    w = W.logistic_small(3000, 3, seed=61, precision=W.MIXED, M=128, m=150, G=4, L=6)
+    P, smc = make_pair(w)
+    eps_fn = lambda st, a, d: 1.0 / 6
+    logz, rec = smc.run(eps_fn, L=6, R=2)
+    ref = oracle.run_smc(P, M=w.M, m=w.m, G=w.G, seed=w.seed, eps_fn=eps_fn, L=6, R=2)
+    temps = np.array([r["a"] for r in rec])
+    say("mixed run stages", len(temps), len(ref["temps"]), "logz", logz, ref["logz"])
+    assert len(temps) == len(ref["temps"])
+    np.testing.assert_allclose(temps, ref["temps"], rtol=1e-5)
+    assert abs(logz - ref["logz"]) <= 1e-5 * abs(ref["logz"])
+    smc.close()
+
+
+@pytest.mark.parametrize("name", ["logistic", "poisson_d20", "logistic_d50", "student"])
+def test_loglik_lambda(name):
+    """lambda_a = a l_hat - a^2 sigma2_hat / 2 (the annealed estimator of the
+    extended target) against the oracle's estimator."""
+    _, mk, scale = next(c for c in CASES if c[0] == name)
+    w = mk()
+    P, smc = make_pair(w)
+    th, u = W.random_state(w, 16, 4 * scale, P.theta_bar, seed=13)
+    ref = P.estimate(th, u)
+    for a in (0.0, 0.37, 1.0):
+        lam, lh, s2 = smc.loglik_lambda(torch.tensor(th, device=DEV), torch.tensor(u, device=DEV), a)
+        want = a * ref["lhat"] - 0.5 * a * a * ref["sig2"]
+        np.testing.assert_allclose(lam.cpu().numpy(), want, rtol=1e-9, atol=1e-9 * np.abs(ref["lhat"]).max() * a)
+        np.testing.assert_allclose(lh.cpu().numpy(), ref["lhat"], rtol=1e-9)
+    B = _binding()
+    with pytest.raises(B.SMCError):
+        smc.loglik_lambda(torch.tensor(th, device=DEV), torch.tensor(u, device=DEV), 1.5)
+    smc.close()
