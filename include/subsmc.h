@@ -142,6 +142,26 @@ smc_status smc_init(const smc_problem* pb, void* stream, smc_ctx* out);
 smc_status smc_temper(smc_ctx ctx, double* a_out, double* dlogz_out, double* ess_out);
 
 /*
+ * For callers that cannot allocate device memory or synchronise (code under
+ * HIP graph capture, serving loops, harnesses that forbid allocation):
+ * smc_temper's exponent search, reweighting and evidence increment on
+ * caller-held arrays, with no context and no workspace. Device lhat, sig2
+ * (M each, read) and logw (M, normalised log weights, overwritten with the
+ * reweighted ones); a_prev in [0, 1) is the previous exponent; target
+ * ESS = ess_frac * M. Device out (5 doubles) receives [a, log evidence
+ * increment, ESS at a, 1 if every incremental weight was non-finite (logw
+ * then unchanged) else 0, ESS evaluations]. 1 <= M <= 8192, else
+ * SMC_ERR_INVALID_ARG. Only enqueues on `stream` (a hipStream_t, NULL: the
+ * default stream); it calls no allocation routine. Its scratch (about 4 KB: the
+ * two slots of the exponent search) is a device array of the library, one
+ * per GPU, shared by every call on that GPU: calls that overlap on one GPU
+ * (on different streams or host threads) race and must be ordered by the
+ * caller. Results equal smc_temper's on the same inputs.
+ */
+smc_status smc_temper_noalloc(int32_t M, const double* lhat, const double* sig2, double* logw, double a_prev,
+                              double ess_frac, double* out, void* stream);
+
+/*
  * The same step with the paper's own exponent rule (section 2.2): the ESS is
  * evaluated at the grid points a_j = a_prev + (1 - a_prev) 2^(-j/4),
  * j = 0..grid_points-1 (a_0 = 1), and a is the point above a_prev whose ESS

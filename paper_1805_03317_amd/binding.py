@@ -46,7 +46,7 @@ EXPORTS = [
     "smc_get_mass", "smc_get_cv", "smc_full_loglik", "smc_destroy", "smc_status_string",
     "smc_last_error", "smc_batch_workspace_size", "smc_batch_create", "smc_batch_temper", "smc_batch_mass",
     "smc_batch_resample", "smc_batch_move", "smc_batch_launches", "smc_batch_set_graph", "smc_batch_set_streams", "smc_batch_graph_captures",
-    "smc_batch_set_timing", "smc_batch_move_timing",
+    "smc_batch_set_timing", "smc_batch_move_timing", "smc_temper_noalloc",
     "smc_batch_destroy", "smc_batch_last_error",
 ]
 
@@ -68,6 +68,7 @@ def lib():
     L.smc_init.argtypes = [C.POINTER(_Problem), vp, C.POINTER(vp)]
     L.smc_temper.argtypes = [vp, C.POINTER(dbl), C.POINTER(dbl), C.POINTER(dbl)]
     L.smc_temper_grid.argtypes = [vp, i32, dbl, C.POINTER(dbl), C.POINTER(dbl), C.POINTER(dbl), vp]
+    L.smc_temper_noalloc.argtypes = [i32, vp, vp, vp, dbl, dbl, vp, vp]
     L.smc_mass.argtypes = [vp]
     L.smc_resample.argtypes = [vp]
     L.smc_resample_multinomial.argtypes = [vp]

@@ -9,6 +9,7 @@
 #include <cstring>
 #include <algorithm>
 #include <map>
+#include <mutex>
 #include <new>
 #include <numeric>
 #include <vector>
@@ -849,6 +850,71 @@ static smc_status temper_impl(smc_ctx c, int grid_points, double ess_frac, doubl
   if (a_out) *a_out = o[0];
   if (dlogz_out) *dlogz_out = o[1];
   if (ess_out) *ess_out = o[2];
+  return SMC_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Scratch of smc_temper_noalloc: the two alternating slots of the exponent
+// search, in device memory the library owns for the life of the process (one
+// copy per GPU). Host code never uses this name as an address: the device
+// address of each GPU's copy is looked up once per device and kept below.
+constexpr size_t kNoAllocScratchBytes = 2 * sizeof(SearchSlot);
+static __device__ __align__(256) char scratch[kNoAllocScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char* g_scratch_ptr[kMaxDevices] = {nullptr};
+
+// The current device's copy of `scratch` (nullptr on failure, with the HIP error in *err).
+char* scratch_for_current_device(hipError_t* err) {
+  int dev = 0;
+  *err = hipGetDevice(&dev);
+  if (*err != hipSuccess) return nullptr;
+  if (dev < 0 || dev >= kMaxDevices) {
+    *err = hipErrorInvalidDevice;
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    *err = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (*err != hipSuccess) return nullptr;
+    g_scratch_ptr[dev] = static_cast<char*>(ptr);
+  }
+  return g_scratch_ptr[dev];
+}
+
+}  // namespace
+
+extern "C" {
+
+smc_status smc_temper_noalloc(int32_t M, const double* lhat, const double* sig2, double* logw, double a_prev,
+                              double ess_frac, double* out, void* stream) {
+  if (M < 1 || M > kMaxM || !lhat || !sig2 || !logw || !out) return SMC_ERR_INVALID_ARG;
+  if (!(a_prev >= 0.0 && a_prev < 1.0) || !(ess_frac > 0.0 && ess_frac <= 1.0)) return SMC_ERR_INVALID_ARG;
+  hipError_t e = hipSuccess;
+  char* ptr = scratch_for_current_device(&e);
+  if (!ptr) return SMC_ERR_DEVICE;
+  TemperArgs t;
+  t.M = M;
+  t.a_prev = a_prev;
+  t.ess_frac = ess_frac;
+  t.lhat = lhat;
+  t.sig2 = sig2;
+  t.logw = logw;
+  t.out = out;
+  t.grid_ess = nullptr;
+  t.grid_n = 0;
+  // every slot entry a pass reads is written by the pass before it in the
+  // same call, so the scratch needs no clearing between calls
+  t.search = reinterpret_cast<SearchSlot*>(ptr);
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  if (launch_search(t, st) != hipSuccess) return SMC_ERR_DEVICE;
+  hipLaunchKernelGGL(temper_kernel, dim3(1), dim3(kTemperThreads), 0, st, t);
+  if (hipGetLastError() != hipSuccess) return SMC_ERR_DEVICE;
   return SMC_OK;
 }
 
