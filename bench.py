@@ -55,6 +55,8 @@ def parse():
     ap.add_argument("--only", choices=["mixed", "fp64"], default=None, help="time one path only (profiling)")
     ap.add_argument("--batch", type=int, default=64, help="members of the batched workload")
     ap.add_argument("--no-graph", action="store_true", help="batched workload: direct launches instead of graph replay")
+    ap.add_argument("--per-shape", action="store_true",
+                    help="batched workload: one move launch per kernel shape instead of the persistent launch")
     ap.add_argument("--streams", type=int, default=8,
                     help="batched workload: streams the move's launches are spread over (1 = one after another)")
     ap.add_argument("--workload", choices=["config1", "config2", "batched", "config4", "config5", "student"],
@@ -363,7 +365,8 @@ def cpu_baseline(w, eps, budget_s=12.0, cv_order=2, one_thread=True):
     oracle.set_num_threads(threads)
     return out
 
-BATCH_KINDS = {0: "move_kernel_batch", 1: "move_kernel_wide_batch", 2: "move_kernel_res_batch"}
+BATCH_KINDS = {0: "move_kernel_batch", 1: "move_kernel_wide_batch", 2: "move_kernel_res_batch",
+               3: "move_kernel_persist"}
 
 
 def run_batched_path(ws, Xys, precision, args):
@@ -377,6 +380,7 @@ def run_batched_path(ws, Xys, precision, args):
     batch = SMCBatch(members)
     batch.set_graph(not args.no_graph)
     batch.set_streams(args.streams)
+    batch.set_persistent(not args.per_shape)
     eps = np.array([1.0 / w.L for w in ws])
     L = ws[0].L
     per_member = np.array([w.M * w.m * (w.L + 1) for w in ws], dtype=np.float64)
@@ -420,6 +424,7 @@ def run_batched_path(ws, Xys, precision, args):
         "move_evals_per_s": state["evals"] / args.steps / (move_ms * 1e-3),
         "active_members": state["active"],
         "launch_kind": kinds.tolist(),
+        "member_kernels": batch.member_kernels().tolist(),
         "launch_ms": launch_ms.tolist(),
         "member_launch": member_launch.tolist(),
         "stage": [m.info()["stage"] for m in members],
@@ -445,7 +450,8 @@ def batched_launches(ws, fp32, r):
 
 
 def batched_roofline(launches):
-    """The dominant launch (largest device time) against its bound."""
+    """The dominant launch (largest device time) against its bound (a persistent launch, which
+    moves every member, against HBM with every member's algorithmic bytes)."""
     g = max(launches, key=lambda x: x["ms"])
     t = g["ms"] * 1e-3
     if g["kernel"] == "move_kernel_res_batch":
@@ -511,7 +517,8 @@ def main_batched(args):
                    "n_total": int(sum(n for n, _, _ in sizes)), "M": ws[0].M, "m": "max(200, 0.01 n)",
                    "G": ws[0].G, "L": ws[0].L, "R": 1, "eps": "1/L", "precision": head,
                    "step": "batched temper+mass+resample+move",
-                   "move_launch": "direct" if args.no_graph else "hip graph replay"},
+                   "move_launch": ("per kernel shape, " if args.per_shape else "persistent, ")
+                   + ("direct" if args.no_graph else "hip graph replay")},
         "roofline": batched_roofline(r["launches"]),
         "move_ms": r["move_ms"],
         "move_evals_per_s": r["move_evals_per_s"],

@@ -443,6 +443,28 @@ smc_status smc_batch_set_streams(smc_batch b, int32_t n);
  * on. */
 smc_status smc_batch_set_graph(smc_batch b, int32_t on);
 
+/* Persistent move (section 2.1: the particles of every dataset move
+ * independently under Algorithm 1): with on = 1, smc_batch_move moves all
+ * members whose rows share a row type and family in ONE launch. Its grid is
+ * what the GPU holds at once; each workgroup takes work items from a device
+ * queue (in the caller's workspace) until it is empty: one particle of a
+ * member that uses the resident kernel, or four consecutive particles of a
+ * member that uses a streaming kernel, costliest member first. A member whose
+ * resident layout needs more registers or LDS than the launch allows (14
+ * register rows per lane, the matrix-core form, or more LDS than two
+ * workgroups per CU leave with float rows) moves with its streaming kernel;
+ * smc_batch_member_kernels reports which. Each particle's result is bit for
+ * bit that of the member's own context moved with the same kernel. The
+ * launches honour graph replay and timing; the stream setting is unused
+ * (one launch per row type and family, on the batch's stream). on = 0 (the
+ * default): one launch per kernel shape. */
+smc_status smc_batch_set_persistent(smc_batch b, int32_t on);
+
+/* The kernel each member's last move ran: kind[k] = 0 narrow streaming,
+ * 1 lane-group streaming, 2 resident, -1 not moved (inactive member or no
+ * move yet). kind holds one entry per member (host). */
+smc_status smc_batch_member_kernels(smc_batch b, int32_t* kind);
+
 /* Number of graph captures smc_batch_move has made. */
 int32_t smc_batch_graph_captures(smc_batch b);
 

@@ -46,7 +46,8 @@ EXPORTS = [
     "smc_get_mass", "smc_get_cv", "smc_full_loglik", "smc_destroy", "smc_status_string",
     "smc_last_error", "smc_batch_workspace_size", "smc_batch_create", "smc_batch_temper", "smc_batch_mass",
     "smc_batch_resample", "smc_batch_move", "smc_batch_launches", "smc_batch_set_graph", "smc_batch_set_streams", "smc_batch_graph_captures",
-    "smc_batch_set_timing", "smc_batch_move_timing", "smc_temper_noalloc",
+    "smc_batch_set_timing", "smc_batch_move_timing", "smc_temper_noalloc", "smc_batch_set_persistent",
+    "smc_batch_member_kernels",
     "smc_batch_destroy", "smc_batch_last_error",
 ]
 
@@ -108,6 +109,8 @@ def lib():
     L.smc_batch_move.argtypes = [vp, vp, i32, i32]
     L.smc_batch_launches.argtypes = [vp]
     L.smc_batch_set_graph.argtypes = [vp, i32]
+    L.smc_batch_set_persistent.argtypes = [vp, i32]
+    L.smc_batch_member_kernels.argtypes = [vp, vp]
     L.smc_batch_set_streams.argtypes = [vp, i32]
     L.smc_batch_graph_captures.argtypes = [vp]
     L.smc_batch_set_timing.argtypes = [vp, i32]
@@ -499,6 +502,17 @@ class SMCBatch:
     def set_streams(self, n):
         """Streams the move's launches are spread over (1..8)."""
         self._check(lib().smc_batch_set_streams(self._h, int(n)))
+
+    def set_persistent(self, on=True):
+        """One persistent move launch per row type and family, with a device work queue."""
+        self._check(lib().smc_batch_set_persistent(self._h, 1 if on else 0))
+
+    def member_kernels(self):
+        """The kernel each member's last move ran: 0 narrow, 1 lane-group, 2 resident, -1 none."""
+        import numpy as np
+        kind = np.zeros(self.count, dtype=np.int32)
+        self._check(lib().smc_batch_member_kernels(self._h, _host_ptr(kind)))
+        return kind
 
     def graph_captures(self):
         return int(lib().smc_batch_graph_captures(self._h))

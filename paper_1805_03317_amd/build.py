@@ -11,7 +11,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
-UNITS = ["subsmc.hip", "launch_narrow.hip", "launch_wide.hip", "launch_resident.hip"]
+UNITS = ["subsmc.hip", "launch_narrow.hip", "launch_wide.hip", "launch_resident.hip", "launch_persist_f32.hip",
+         "launch_persist_f64.hip"]
 LIB = os.path.join(HERE, "libsubsmc.so")
 OBJ_DIR = os.path.join(HERE, "_build")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -9,11 +9,12 @@
 #include <hip/hip_runtime.h>
 
 #include "kernels.hpp"
+#include "kernels_persist.hpp"
 #include "kernels_resident.hpp"
 
 namespace subsmc {
 
-enum MoveKind : int { kMoveNarrow = 0, kMoveWide = 1, kMoveResident = 2 };
+enum MoveKind : int { kMoveNarrow = 0, kMoveWide = 1, kMoveResident = 2, kMovePersistent = 3 };
 
 // The instantiation of the particle kernels that serves one dataset.
 struct KernelShape {
@@ -51,5 +52,24 @@ hipError_t launch_move_wide_batch(const KernelShape& s, int grid, size_t lds, co
                                   hipStream_t st);
 hipError_t launch_move_resident_batch(const KernelShape& s, int grid, size_t lds, const Batch<ResMoveArgs>& b,
                                       hipStream_t st);
+
+// persistent batched move (launch_persist_f32.hip, launch_persist_f64.hip): the
+// body of shape s in the launch for its row type and family (-1: none), the
+// launch's workgroups per CU with `lds` bytes of dynamic LDS, and the launch
+int persist_body_f32(const KernelShape& s);
+int persist_body_f64(const KernelShape& s);
+hipError_t persist_occupancy_f32(int fam, size_t lds, int* per_cu);
+hipError_t persist_occupancy_f64(int fam, size_t lds, int* per_cu);
+hipError_t launch_move_persist_f32(int fam, int grid, size_t lds, const PersistArgs& a, hipStream_t st);
+hipError_t launch_move_persist_f64(int fam, int grid, size_t lds, const PersistArgs& a, hipStream_t st);
+
+inline int persist_body(const KernelShape& s) { return s.fp32 ? persist_body_f32(s) : persist_body_f64(s); }
+inline hipError_t persist_occupancy(int fp32, int fam, size_t lds, int* per_cu) {
+  return fp32 ? persist_occupancy_f32(fam, lds, per_cu) : persist_occupancy_f64(fam, lds, per_cu);
+}
+inline hipError_t launch_move_persist(int fp32, int fam, int grid, size_t lds, const PersistArgs& a,
+                                      hipStream_t st) {
+  return fp32 ? launch_move_persist_f32(fam, grid, lds, a, st) : launch_move_persist_f64(fam, grid, lds, a, st);
+}
 
 }  // namespace subsmc

@@ -29,6 +29,20 @@ constexpr int kHeader = 4;  // eta_bar, aux, y, pad
 // wave-level helpers
 // --------------------------------------------------------------------------
 
+// The streaming moves exchange data between the lanes of one wavefront through
+// LDS. A wavefront's LDS instructions execute in program order, so such an
+// exchange needs no workgroup barrier, only a fence that keeps the compiler
+// from moving the accesses across it. With this, several wavefronts of one
+// workgroup can each run a particle of their own, none waiting for another.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// lane of the calling thread within its wavefront
+__device__ __forceinline__ int wave_lane() { return (int)__lane_id(); }
+
 __device__ __forceinline__ double wave_sum(double v) { return xl::wave_allsum(v); }
 
 __device__ __forceinline__ double readlane_d(double v, int l) {
@@ -134,10 +148,10 @@ struct PassResult {
 // 64*DC elements of LDS; the adds run in FP64 in lane order.
 template <typename Real, int DC>
 __device__ __forceinline__ double lds_column_sum(const Real (&v)[DC], Real* red, int lane) {
-  __syncthreads();
+  wave_lds_sync();
 #pragma unroll
   for (int c = 0; c < DC; ++c) red[lane * DC + c] = v[c];
-  __syncthreads();
+  wave_lds_sync();
   double s = 0.0;
   if (lane < DC) {
     for (int r = 0; r < kWave; ++r) s += (double)red[r * DC + lane];
@@ -170,8 +184,7 @@ __device__ __forceinline__ PassResult estimator_pass(const Prob& P, const int32_
   const Real inv_s2 = (Real)P.inv_s2;
   // both sources are read unconditionally and the value selected, so the
   // LDS and global accesses keep their own address spaces
-  auto index_of = [&](int j) -> int32_t {
-    const int32_t g = urow[j];
+  auto resolve = [&](int j, int32_t g) -> int32_t {
     if constexpr (BLK) {
       const bool in = (unsigned)(j - b0) < (unsigned)(b1 - b0);
       const int32_t l = blk[in ? j - b0 : 0];
@@ -180,6 +193,7 @@ __device__ __forceinline__ PassResult estimator_pass(const Prob& P, const int32_
       return g;
     }
   };
+  auto index_of = [&](int j) -> int32_t { return resolve(j, urow[j]); };
 
   Real dl[DC];
 #pragma unroll
@@ -205,27 +219,28 @@ __device__ __forceinline__ PassResult estimator_pass(const Prob& P, const int32_
 #pragma unroll
   for (int c = 0; c < DC; ++c) { S1[c] = Real(0); T1[c] = Real(0); }
 
+  // urow of slot j clamped to the last slot, loaded without a branch; it is
+  // resolved an iteration later (the vector-memory counter retires loads in
+  // order, so a wait for an index loaded after a row waits for that row too)
+  auto fetch = [&](int j) -> int32_t { return urow[j < m ? j : m - 1]; };
   // rows are prefetched one iteration ahead (measured: for FP64 d = 20 one
-  // resident wave with the prefetch beats two without it)
-  constexpr bool kPrefetchRow = true;
+  // resident wave with the prefetch beats two without it), their indices two
+  // ahead: each iteration loads urow of slot j + 128, then resolves the index
+  // of slot j + 64 (loaded before the current row) and requests that row, so
+  // no wait is ever for a load younger than the row it needs
   int j = lane;
   int32_t k_cur = j < m ? index_of(j) : 0;
-  int32_t k_nxt = j + kWave < m ? index_of(j + kWave) : 0;
+  int32_t g_nxt = fetch(j + kWave);
   RowLoad<Real, DC> r_nxt;
-  if constexpr (kPrefetchRow) {
-    if (j < m) load_row<Real, DC>(X + (int64_t)((uint32_t)k_cur < n ? k_cur : 0) * ld, r_nxt);
-  }
+  if (j < m) load_row<Real, DC>(X + (int64_t)((uint32_t)k_cur < n ? k_cur : 0) * ld, r_nxt);
   for (; j < m; j += kWave) {
-    RowLoad<Real, DC> r;
+    const int32_t g_far = fetch(j + 2 * kWave);
+    const RowLoad<Real, DC> r = r_nxt;
     const bool bad = (uint32_t)k_cur >= n;
-    if constexpr (kPrefetchRow) {
-      r = r_nxt;
-      if (j + kWave < m) load_row<Real, DC>(X + (int64_t)((uint32_t)k_nxt < n ? k_nxt : 0) * ld, r_nxt);
-    } else {
-      load_row<Real, DC>(X + (int64_t)(bad ? 0 : k_cur) * ld, r);
-    }
+    const int32_t k_nxt = resolve(j + kWave < m ? j + kWave : m - 1, g_nxt);
+    if (j + kWave < m) load_row<Real, DC>(X + (int64_t)((uint32_t)k_nxt < n ? k_nxt : 0) * ld, r_nxt);
     k_cur = k_nxt;
-    k_nxt = j + 2 * kWave < m ? index_of(j + 2 * kWave) : 0;
+    g_nxt = g_far;
 
     Real D = Real(0);
 #pragma unroll
@@ -387,11 +402,11 @@ __device__ __forceinline__ double sigma_times(const Prob& P, double p, int lane)
   return acc;
 }
 
+// One particle's move on one wavefront. red (kWave * DC values) and blk (the
+// refreshed block's indices, ceil(m / G) values) are LDS of this wavefront's own.
 template <typename Real, int DC, int FAM>
-__device__ __forceinline__ void move_body(const MoveArgs& A, const int i) {
-  __shared__ Real red[kWave * DC];
-  extern __shared__ int32_t blk[];
-  const int lane = threadIdx.x;
+__device__ __forceinline__ void move_body(const MoveArgs& A, const int i, Real* red, int32_t* blk) {
+  const int lane = wave_lane();
   const Prob& P = A.P;
   if (i >= P.M) return;
   const int d = P.d;
@@ -414,7 +429,7 @@ __device__ __forceinline__ void move_body(const MoveArgs& A, const int i) {
   const uint64_t cb = stream_ctr0(kBlockIndex, A.stage, A.move, P.dataset);
   for (int t = lane; t < b1 - b0; t += kWave)
     blk[t] = (int32_t)word_to_index(stream_word(P.seed, cb, (uint64_t)i, (uint64_t)t), (uint64_t)P.n);
-  __syncthreads();
+  wave_lds_sync();
   int ob0 = 0, ob1 = 0;  // block override seen by the leapfrog passes
   {
     const PassResult r = estimator_pass<Real, DC, FAM, true>(P, urow, b0, b1, blk, red, th - tb, lane);
@@ -500,14 +515,18 @@ constexpr int kMoveWaves = sizeof(Real) == 4 ? 2 : 1;
 
 template <typename Real, int DC, int FAM>
 __global__ void __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(kMoveWaves<Real>))) move_kernel(MoveArgs A) {
-  move_body<Real, DC, FAM>(A, blockIdx.x);
+  __shared__ Real red[kWave * DC];
+  extern __shared__ int32_t blk[];
+  move_body<Real, DC, FAM>(A, blockIdx.x, red, blk);
 }
 
 template <typename Real, int DC, int FAM>
 __global__ void __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(kMoveWaves<Real>))) move_kernel_batch(Batch<MoveArgs> B) {
+  __shared__ Real red[kWave * DC];
+  extern __shared__ int32_t blk[];
   const int k = batch_member(B.first, B.count, blockIdx.x);
   const MoveArgs A = B.args[k];
-  move_body<Real, DC, FAM>(A, blockIdx.x - B.first[k]);
+  move_body<Real, DC, FAM>(A, blockIdx.x - B.first[k], red, blk);
 }
 
 }  // namespace subsmc

@@ -537,13 +537,6 @@ __device__ void factor_spd(const FactorArgs& F, double* sh) {
 // forward substitution. Ls and Li are d*d doubles of LDS each.
 constexpr int kFactorLdsMaxD = 64;
 
-// LDS writes of this wavefront visible to its other lanes (no other wave waits)
-__device__ __forceinline__ void wave_lds_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 __device__ void factor_spd_lds(const FactorArgs& F, double* Ls, double* Li) {
   __shared__ int good_flag;
   const int d = F.d;
@@ -628,7 +621,7 @@ struct MomentArgs {
   int M, d;
   const double* theta;
   const double* logw;
-  const double* centre;   // d
+  const double* centre;   // d: the shift of the one-pass sums (a point inside the cloud)
   double* partials;       // nblocks * (d + d(d+1)/2)
   int nblocks;
   double* mean;           // d

@@ -79,8 +79,9 @@ __device__ __forceinline__ PassResultW<wide_nc<G>()> estimator_pass_wide(const P
     const int c = q * CH + k - kHeader;
     dl[k] = (c >= 0 && c < d) ? (Real)vec[c] : Real(0);
   }
-  auto index_of = [&](int j) -> int32_t {
-    const int32_t g = urow[j];
+  // the index of slot j, given g = urow[j]: the refreshed block's (staged in
+  // LDS) inside [b0, b1), else the particle's own
+  auto resolve = [&](int j, int32_t g) -> int32_t {
     if constexpr (BLK) {
       const bool in = (unsigned)(j - b0) < (unsigned)(b1 - b0);
       const int32_t l = blk[in ? j - b0 : 0];
@@ -89,6 +90,7 @@ __device__ __forceinline__ PassResultW<wide_nc<G>()> estimator_pass_wide(const P
       return g;
     }
   };
+  auto index_of = [&](int j) -> int32_t { return resolve(j, urow[j]); };
   auto eval_row = [&](const Real (&x)[CH], Real& dd, Real& dp) {
     Real part = Real(0);
 #pragma unroll
@@ -116,17 +118,25 @@ __device__ __forceinline__ PassResultW<wide_nc<G>()> estimator_pass_wide(const P
   for (int k = 0; k < CH; ++k) { S1[k] = Real(0); T1[k] = Real(0); }
 
   const int nit = (m + kRows - 1) / kRows;  // row iterations t (rows grp + kRows t)
-  auto index_at = [&](int t) -> int32_t {
+  // slot of iteration t's row in this group, clamped to the last slot:
+  // iterations past the group's last row read a real row and add nothing, and
+  // all groups run the same number of steps
+  auto slot_at = [&](int t) -> int {
     const int jj = grp + kRows * t;
-    return jj < m ? index_of(jj) : 0;
+    return jj < m ? jj : m - 1;
   };
+  // urow of iteration t, loaded without a branch and not used until
+  // resolve_at a step later: the vector-memory counter retires loads in
+  // order, so a wait for an index loaded after rows would wait for those rows
+  auto fetch_at = [&](int t) -> int32_t { return urow[slot_at(t)]; };
+  auto resolve_at = [&](int t, int32_t g) -> int32_t { return resolve(slot_at(t), g); };
+  auto index_at = [&](int t) -> int32_t { return resolve_at(t, fetch_at(t)); };
   auto load_row = [&](int32_t k, Real (&x)[CH]) {
     load_chunk<Real, CH>(X + (int64_t)((uint32_t)k < n ? k : 0) * ld + q * CH, x);
   };
-  // Iterations past the group's last row read row 0 and add nothing; all
-  // groups run the same number of steps. Row indices are loaded a step ahead
-  // of their rows, so a row load never waits behind the load of its own
-  // index, and every wait is for the oldest rows in flight.
+  // Row indices are loaded a step ahead of their rows and resolved only when
+  // their rows are requested, so a row load never waits behind the load of its
+  // own index, and every wait is for the oldest rows in flight.
   if constexpr (wide_one_remainder_per_lane<Real, FAM, G, TL>()) {
     // (the logistic remainder is the costly one; for the other families the
     // register cost of two buffered steps outweighs it)
@@ -151,13 +161,13 @@ __device__ __forceinline__ PassResultW<wide_nc<G>()> estimator_pass_wide(const P
 #pragma unroll
     for (int s = 0; s < PT; ++s) load_row(kb[s], xb[s]);
 #pragma unroll
-    for (int s = 0; s < PT; ++s) kf[s] = index_at(2 * PT + s);
+    for (int s = 0; s < PT; ++s) kf[s] = fetch_at(2 * PT + s);
     // one step on buffer x (rows of step `step`, indices kx); refills x with
-    // the rows of step + 2
+    // the rows of step + 2 (urow of those in kf, not yet resolved)
     auto step_on = [&](Real (&x)[PT][CH], int32_t (&kx)[PT], int step) {
       int32_t kg[PT];
 #pragma unroll
-      for (int s = 0; s < PT; ++s) kg[s] = index_at(PT * (step + 3) + s);
+      for (int s = 0; s < PT; ++s) kg[s] = fetch_at(PT * (step + 3) + s);
       Real Dm = Real(0), ebm = Real(0), auxm = Real(0);
       int32_t km = 0;
 #pragma unroll
@@ -199,8 +209,9 @@ __device__ __forceinline__ PassResultW<wide_nc<G>()> estimator_pass_wide(const P
           S1[k] += dps * x[s][k];
           T1[k] += edps * x[s][k];
         }
-        load_row(kf[s], x[s]);
-        kx[s] = kf[s];
+        const int32_t kr = resolve_at(PT * (step + 2) + s, kf[s]);
+        load_row(kr, x[s]);
+        kx[s] = kr;
       }
 #pragma unroll
       for (int s = 0; s < PT; ++s) kf[s] = kg[s];
@@ -221,11 +232,11 @@ __device__ __forceinline__ PassResultW<wide_nc<G>()> estimator_pass_wide(const P
 #pragma unroll
     for (int s = 0; s < PD; ++s) load_row(kc[s], xb[s]);
 #pragma unroll
-    for (int s = 0; s < PD; ++s) kn[s] = index_at(PD + s);
+    for (int s = 0; s < PD; ++s) kn[s] = fetch_at(PD + s);
     for (int step = 0; step < nsteps; ++step) {
       int32_t kf[PD];
 #pragma unroll
-      for (int s = 0; s < PD; ++s) kf[s] = index_at(PD * (step + 2) + s);
+      for (int s = 0; s < PD; ++s) kf[s] = fetch_at(PD * (step + 2) + s);
 #pragma unroll
       for (int s = 0; s < PD; ++s) {
         const bool valid = grp + kRows * (PD * step + s) < m;
@@ -245,8 +256,9 @@ __device__ __forceinline__ PassResultW<wide_nc<G>()> estimator_pass_wide(const P
           S1[k] += dp * xb[s][k];
           T1[k] += edp * xb[s][k];
         }
-        load_row(kn[s], xb[s]);
-        kc[s] = kn[s];
+        const int32_t kr = resolve_at(PD * (step + 1) + s, kn[s]);
+        load_row(kr, xb[s]);
+        kc[s] = kr;
       }
 #pragma unroll
       for (int s = 0; s < PD; ++s) kn[s] = kf[s];
@@ -258,10 +270,10 @@ __device__ __forceinline__ PassResultW<wide_nc<G>()> estimator_pass_wide(const P
   // column sums: position p = c + header lives in chunk p / CH, element p % CH
   constexpr int NC = wide_nc<G>();
   auto column = [&](const Real (&v)[CH], double (&out)[NC]) {
-    __syncthreads();
+    wave_lds_sync();
 #pragma unroll
     for (int k = 0; k < CH; ++k) red[lane * CH + k] = v[k];
-    __syncthreads();
+    wave_lds_sync();
 #pragma unroll
     for (int s = 0; s < NC; ++s) {
       const int c = lane + kWave * s;
@@ -307,13 +319,13 @@ __device__ __forceinline__ PassResultW<wide_nc<G>()> estimator_pass_wide(const P
 // vec <- x (component slots of every lane), with the fences around it
 template <int NC>
 __device__ __forceinline__ void to_lds(double* vec, const double (&x)[NC], int lane, int d) {
-  __syncthreads();
+  wave_lds_sync();
 #pragma unroll
   for (int s = 0; s < NC; ++s) {
     const int c = lane + kWave * s;
     if (c < d) vec[c] = x[s];
   }
-  __syncthreads();
+  wave_lds_sync();
 }
 
 template <typename Real, int G, int CH, int FAM>
@@ -372,12 +384,13 @@ __device__ __forceinline__ void matvec_wide(const double* __restrict__ Mx, const
 
 // Fused Markov move (Algorithm 1) for wide rows; same steps, draws and
 // decisions as move_kernel.
+// One particle's move on one wavefront. red (kWave * CH values), vec (128
+// doubles) and blk (the refreshed block's indices, ceil(m / G) values) are LDS of
+// this wavefront's own.
 template <typename Real, int G, int CH, int FAM, int TL>
-__device__ __forceinline__ void move_wide_body(const MoveArgs& A, const int i) {
-  __shared__ Real red[kWave * CH];
-  __shared__ double vec[128];
-  extern __shared__ int32_t blk[];
-  const int lane = threadIdx.x;
+__device__ __forceinline__ void move_wide_body(const MoveArgs& A, const int i, Real* red, double* vec,
+                                               int32_t* blk) {
+  const int lane = wave_lane();
   const Prob& P = A.P;
   if (i >= P.M) return;
   const int d = P.d;
@@ -537,14 +550,20 @@ __device__ __forceinline__ void move_wide_body(const MoveArgs& A, const int i) {
 
 template <typename Real, int G, int CH, int FAM, int TL>
 __global__ void __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(kMoveWaves<Real>))) move_kernel_wide(MoveArgs A) {
-  move_wide_body<Real, G, CH, FAM, TL>(A, blockIdx.x);
+  __shared__ Real red[kWave * CH];
+  __shared__ double vec[128];
+  extern __shared__ int32_t blk[];
+  move_wide_body<Real, G, CH, FAM, TL>(A, blockIdx.x, red, vec, blk);
 }
 
 template <typename Real, int G, int CH, int FAM, int TL>
 __global__ void __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(kMoveWaves<Real>))) move_kernel_wide_batch(Batch<MoveArgs> B) {
+  __shared__ Real red[kWave * CH];
+  __shared__ double vec[128];
+  extern __shared__ int32_t blk[];
   const int k = batch_member(B.first, B.count, blockIdx.x);
   const MoveArgs A = B.args[k];
-  move_wide_body<Real, G, CH, FAM, TL>(A, blockIdx.x - B.first[k]);
+  move_wide_body<Real, G, CH, FAM, TL>(A, blockIdx.x - B.first[k], red, vec, blk);
 }
 
 }  // namespace subsmc

@@ -183,6 +183,11 @@ struct smc_batch_s {
   std::vector<hipStream_t> side;  // lanes - 1 private streams
   hipEvent_t fork = nullptr;
   std::vector<hipEvent_t> join;
+  // optional persistent move: one launch per (row type, family) with a device
+  // work queue over every member's particles (smc_batch_set_persistent)
+  int persistent = 0;
+  int cus = 0;                   // compute units of the batch's device
+  std::vector<int> member_kind;  // per member: the kernel kind of its last move, -1 if not moved
   char err[512] = {0};
 };
 
@@ -614,7 +619,11 @@ MomentArgs moment_args(smc_ctx c, double* status) {
   a.d = d;
   a.theta = c->pb.theta;
   a.logw = c->pb.logw;
-  a.centre = c->prob.theta_bar;
+  // the one-pass sums are taken about particle 0's theta: a point inside the
+  // cloud, so E[(theta - c)(theta - c)'] - (mean - c)(mean - c)' loses no more
+  // than the cloud's own spread to cancellation (about the control-variate
+  // centre, a cloud far from it would lose up to (distance / spread)^2)
+  a.centre = c->pb.theta;
   a.partials = c->at<double>(c->lay.mpartials);
   a.nblocks = c->lay.mom_blocks;
   a.mean = c->at<double>(c->lay.mean);
@@ -1608,6 +1617,13 @@ class Tables {
 };
 
 double* batch_results_dev(smc_batch b) { return reinterpret_cast<double*>(b->dev + b->table_bytes); }
+
+// the persistent move's queues (two counters per launch) after the results
+constexpr int kPersistQueues = 8;
+size_t batch_results_bytes(int count) { return align256((size_t)count * kBatchResultDoubles * 8); }
+int32_t* batch_queue_dev(smc_batch b) {
+  return reinterpret_cast<int32_t*>(b->dev + b->table_bytes + batch_results_bytes((int)b->ctx.size()));
+}
 double* batch_results_host(smc_batch b) { return reinterpret_cast<double*>(b->host + b->table_bytes); }
 
 // results of the active members (kBatchResultDoubles each) to the host; synchronises
@@ -1627,13 +1643,185 @@ Batch<T> batch_of(const Tables& t, size_t args_off, size_t first_off, int count)
   return r;
 }
 
+// LDS a workgroup of the persistent move may take: with float rows two
+// workgroups share a CU (the streaming kernels' two wavefronts per SIMD), with
+// double rows one does; 2 KB of each share stays for static LDS
+constexpr size_t kPersistLdsF32 = 78 * 1024;
+constexpr size_t kPersistLdsF64 = 156 * 1024;
+
+// the streaming form of a member's move (its kernel when the resident layout
+// does not apply)
+KernelShape stream_shape(smc_ctx c) {
+  KernelShape s = move_shape(c);
+  s.kind = c->pb.d > kMaxNarrowD ? kMoveWide : kMoveNarrow;
+  s.rpl = -1;
+  s.mf = 0;
+  s.tile = s.kind == kMoveWide ? c->wide_tile : 0;
+  return s;
+}
+
+// One move of every active member in one persistent launch per (row type,
+// family): members costliest first, items numbered in that order.
+smc_status batch_move_persistent(smc_batch b, const double* eps, int32_t L, int32_t R) {
+  struct Mem {
+    int k;
+    KernelShape s;
+    int body;
+    bool res;
+    double cost;  // of one item
+  };
+  std::map<std::pair<int, int>, std::vector<Mem>> groups;
+  b->member_kind.assign(b->ctx.size(), -1);
+  b->member_launch.assign(b->ctx.size(), -1);
+  for (int k : b->active) {
+    smc_ctx c = b->ctx[k];
+    KernelShape s = move_shape(c);
+    const size_t cap = s.fp32 ? kPersistLdsF32 : kPersistLdsF64;
+    int body = -1;
+    if (s.kind == kMoveResident && (size_t)c->res_ly.total <= cap) body = persist_body(s);
+    if (body < 0) {
+      s = stream_shape(c);
+      body = persist_body(s);
+    }
+    if (body < 0) return bfail(b, SMC_ERR_UNSUPPORTED, "member %d: no body in the persistent move", k);
+    const bool res = s.kind == kMoveResident;
+    // bytes a particle's move streams; a resident item spreads them over the workgroup
+    const double rows = (double)c->pb.m * (L + 1) * (c->pb.d + 4) * (s.fp32 ? 4.0 : 8.0);
+    groups[{s.fp32, s.fam}].push_back(Mem{k, s, body, res, res ? rows / kPersistWaves : rows});
+    b->member_kind[k] = s.kind;
+  }
+  if (!b->cus) {
+    int dev = 0;
+    BATCH_TRY(b, hipGetDevice(&dev));
+    BATCH_TRY(b, hipDeviceGetAttribute(&b->cus, hipDeviceAttributeMultiprocessorCount, dev));
+  }
+  const int ng = (int)groups.size();
+  if (ng > kPersistQueues) return bfail(b, SMC_ERR_UNSUPPORTED, "%d persistent launches, at most %d", ng, kPersistQueues);
+  b->launch_kind.assign(ng, kMovePersistent);
+  b->timed_moves = 0;
+  if (b->timing) {
+    const size_t need = (size_t)2 * ng * R;
+    while (b->ev.size() < need) {
+      hipEvent_t e;
+      BATCH_TRY(b, hipEventCreate(&e));
+      b->ev.push_back(e);
+    }
+  }
+  for (int r = 0; r < R; ++r) {
+    Tables T(b);
+    struct Launch {
+      int fp32, fam, grid, count, n_items;
+      size_t lds, off, foff;
+    };
+    std::vector<Launch> launches;
+    int gi = 0;
+    for (auto& g : groups) {
+      std::vector<Mem>& mem = g.second;
+      std::stable_sort(mem.begin(), mem.end(), [](const Mem& x, const Mem& y) { return x.cost > y.cost; });
+      std::vector<PersistMember> pm(mem.size());
+      std::vector<int32_t> first(mem.size() + 1, 0);
+      size_t lds = 0;
+      for (size_t q = 0; q < mem.size(); ++q) {
+        smc_ctx c = b->ctx[mem[q].k];
+        const KernelShape& s = mem[q].s;
+        PersistMember& p = pm[q];
+        std::memset(&p, 0, sizeof(p));
+        p.A = move_args(c, eps[mem[q].k], L);
+        p.body = mem[q].body;
+        p.resident = mem[q].res ? 1 : 0;
+        int items;
+        if (mem[q].res) {
+          p.Ly = c->res_ly;
+          lds = std::max(lds, (size_t)c->res_ly.total);
+          items = c->pb.M;
+        } else {
+          const bool wide = s.kind == kMoveWide;
+          p.wave_lds = persist_wave_lds(wide, wide ? s.ch : s.dc, s.fp32 ? 4 : 8,
+                                        (c->pb.m + c->pb.G - 1) / c->pb.G);
+          lds = std::max(lds, (size_t)kPersistWaves * p.wave_lds);
+          items = (c->pb.M + kPersistWaves - 1) / kPersistWaves;
+        }
+        first[q + 1] = first[q] + items;
+        b->member_launch[mem[q].k] = gi;
+      }
+      int per_cu = 0;
+      BATCH_TRY(b, persist_occupancy(g.first.first, g.first.second, lds, &per_cu));
+      if (per_cu < 1) return bfail(b, SMC_ERR_UNSUPPORTED, "persistent move: %zu bytes of LDS do not fit", lds);
+      Launch l;
+      l.fp32 = g.first.first;
+      l.fam = g.first.second;
+      l.count = (int)mem.size();
+      l.n_items = first.back();
+      l.grid = std::min(per_cu * b->cus, l.n_items);
+      l.lds = lds;
+      l.off = T.put(pm);
+      l.foff = T.put(first);
+      launches.push_back(l);
+      ++gi;
+    }
+    smc_status st = T.upload();
+    if (st != SMC_OK) return st;
+    auto issue = [&](size_t li, hipStream_t s) -> hipError_t {
+      const Launch& l = launches[li];
+      PersistArgs a;
+      a.mem = T.at<PersistMember>(l.off);
+      a.first = T.at<int32_t>(l.foff);
+      a.count = l.count;
+      a.n_items = l.n_items;
+      a.queue = batch_queue_dev(b) + 2 * li;
+      return launch_move_persist(l.fp32, l.fam, l.grid, l.lds, a, s);
+    };
+    if (b->use_graph && !b->timing) {
+      std::vector<long long> key{-1};
+      for (const Launch& l : launches) {
+        const long long v[8] = {l.fp32, l.fam, l.grid, l.count, l.n_items, (long long)l.lds, (long long)l.off,
+                                (long long)l.foff};
+        key.insert(key.end(), v, v + 8);
+      }
+      if (!b->gexec || key != b->graph_key) {
+        if (b->gexec) {
+          BATCH_TRY(b, hipGraphExecDestroy(b->gexec));
+          b->gexec = nullptr;
+        }
+        if (!b->capture) BATCH_TRY(b, hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking));
+        BATCH_TRY(b, hipStreamBeginCapture(b->capture, hipStreamCaptureModeThreadLocal));
+        hipError_t le = hipSuccess;
+        for (size_t li = 0; li < launches.size() && le == hipSuccess; ++li) le = issue(li, b->capture);
+        hipGraph_t gr = nullptr;
+        const hipError_t ce = hipStreamEndCapture(b->capture, &gr);
+        BATCH_TRY(b, le);
+        BATCH_TRY(b, ce);
+        const hipError_t ie = hipGraphInstantiate(&b->gexec, gr, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(gr);
+        BATCH_TRY(b, ie);
+        b->graph_key = key;
+        b->graph_captures += 1;
+      }
+      BATCH_TRY(b, hipGraphLaunch(b->gexec, b->stream));
+    } else {
+      for (size_t li = 0; li < launches.size(); ++li) {
+        hipEvent_t* ev = b->timing ? &b->ev[2 * ((size_t)r * ng + li)] : nullptr;
+        if (ev) BATCH_TRY(b, hipEventRecord(ev[0], b->stream));
+        BATCH_TRY(b, issue(li, b->stream));
+        if (ev) BATCH_TRY(b, hipEventRecord(ev[1], b->stream));
+      }
+    }
+    for (int k : b->active) {
+      b->ctx[k]->move += 1;
+      b->ctx[k]->moved = 1;
+    }
+    if (b->timing) b->timed_moves += 1;
+  }
+  return SMC_OK;
+}
+
 }  // namespace
 
 extern "C" {
 
 size_t smc_batch_workspace_size(int32_t count) {
   if (count < 1 || count > kMaxBatch) return 0;
-  return align256(batch_table_bytes(count)) + (size_t)count * kBatchResultDoubles * 8;
+  return align256(batch_table_bytes(count)) + batch_results_bytes(count) + 256;
 }
 
 smc_status smc_batch_create(const smc_ctx* ctxs, int32_t count, void* workspace, size_t workspace_bytes,
@@ -1659,7 +1847,9 @@ smc_status smc_batch_create(const smc_ctx* ctxs, int32_t count, void* workspace,
     delete b;
     return SMC_ERR_DEVICE;
   }
-  if (hipEventCreateWithFlags(&b->staged, hipEventDisableTiming) != hipSuccess ||
+  // the persistent move's queues start at zero (each launch leaves them so)
+  if (hipMemsetAsync(batch_queue_dev(b), 0, 2 * kPersistQueues * sizeof(int32_t), b->stream) != hipSuccess ||
+      hipEventCreateWithFlags(&b->staged, hipEventDisableTiming) != hipSuccess ||
       hipEventRecord(b->staged, b->stream) != hipSuccess) {
     if (b->staged) (void)hipEventDestroy(b->staged);
     (void)hipHostFree(b->host);
@@ -1806,9 +1996,15 @@ smc_status smc_batch_move(smc_batch b, const double* eps, int32_t L, int32_t R) 
     if (!c->have_mass) return bfail(b, SMC_ERR_STATE, "member %d: no mass matrix for this stage", k);
     if (c->move + R > 0xFFFF) return bfail(b, SMC_ERR_INVALID_ARG, "member %d: too many moves in one stage", k);
   }
+  if (b->persistent) return batch_move_persistent(b, eps, L, R);
   // members grouped by kernel shape: one launch per group
   std::map<KernelShape, std::vector<int>> groups;
-  for (int k : b->active) groups[move_shape(b->ctx[k])].push_back(k);
+  b->member_kind.assign(b->ctx.size(), -1);
+  for (int k : b->active) {
+    const KernelShape s = move_shape(b->ctx[k]);
+    groups[s].push_back(k);
+    b->member_kind[k] = s.kind;
+  }
   const int ng = (int)groups.size();
   b->launch_kind.clear();
   b->member_launch.assign(b->ctx.size(), -1);
@@ -1976,6 +2172,18 @@ smc_status smc_batch_set_streams(smc_batch b, int32_t n) {
   return SMC_OK;
 }
 
+smc_status smc_batch_set_persistent(smc_batch b, int32_t on) {
+  if (!b || (on != 0 && on != 1)) return SMC_ERR_INVALID_ARG;
+  b->persistent = on;
+  return SMC_OK;
+}
+
+smc_status smc_batch_member_kernels(smc_batch b, int32_t* kind) {
+  if (!b || !kind) return SMC_ERR_INVALID_ARG;
+  for (size_t k = 0; k < b->ctx.size(); ++k) kind[k] = b->member_kind.empty() ? -1 : b->member_kind[k];
+  return SMC_OK;
+}
+
 smc_status smc_batch_set_graph(smc_batch b, int32_t on) {
   if (!b || (on != 0 && on != 1)) return SMC_ERR_INVALID_ARG;
   b->use_graph = on;
@@ -2016,7 +2224,11 @@ smc_status smc_batch_move_timing(smc_batch b, int32_t cap, int32_t* launches, in
 int32_t smc_batch_launches(smc_batch b) {
   if (!b || !b->have_stage) return 0;
   std::map<KernelShape, int> groups;
-  for (int k : b->active) groups[move_shape(b->ctx[k])] += 1;
+  for (int k : b->active) {
+    KernelShape s = move_shape(b->ctx[k]);
+    if (b->persistent) s = KernelShape{kMovePersistent, s.fp32, s.fam, 0, 0, 0, 0, 0, 0};
+    groups[s] += 1;
+  }
   return (int32_t)groups.size();
 }
 

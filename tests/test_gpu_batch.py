@@ -275,3 +275,86 @@ def test_heterogeneous_batch_equals_single_context_runs():
     batch.close()
     for m in members:
         m.close()
+
+
+def _persistent_members(precision):
+    """Members spanning every body of the persistent move: resident (subsample in LDS), a
+    resident member whose layout needs more LDS than the launch's share and one that needs
+    register rows (both moved by their streaming kernel in the launch), narrow and lane-group
+    streaming members, particle counts that are not multiples of four, and a second family
+    (a second launch)."""
+    ws = [W.logistic_small(3000, 3, seed=301, precision=precision, M=50, m=300, G=4, L=4),
+          W.logistic_small(20000, 5, seed=302, precision=precision, M=40, m=6000, G=20, L=4),
+          W.logistic_small(12000, 12, seed=303, precision=precision, M=33, m=2500, G=10, L=4, theta_scale=0.3),
+          W.logistic_small(4000, 28, seed=304, precision=precision, M=37, m=200, G=4, L=4, theta_scale=0.3),
+          W.logistic_small(4000, 40, seed=305, precision=precision, M=30, m=150, G=5, L=4, theta_scale=0.25),
+          W.poisson_small(3000, 6, seed=306, precision=precision, M=21, m=100, G=4, L=4)]
+    for k, w in enumerate(ws):
+        w.dataset = 20 + k
+    return ws
+
+
+@pytest.mark.parametrize("graph", [False, True], ids=["direct", "graph"])
+@pytest.mark.parametrize("precision", [W.FP64, W.MIXED], ids=["fp64", "mixed"])
+def test_persistent_batch_equals_single_context_runs(precision, graph):
+    """The persistent move (one launch per row type and family, a device work queue over
+    every member's particles, costliest member first) against each member run alone with the
+    kernel the launch gave it, bit for bit over eight stages of two moves each (the queue is
+    back at zero after every launch, or the next move would skip work)."""
+    B = _binding()
+    ws = _persistent_members(precision)
+    centres = [_oracle_problem(w)[1] for w in ws]
+    members = [_context(w, tb) for w, tb in zip(ws, centres)]
+    batch = B.SMCBatch(members)
+    batch.set_persistent(True)
+    batch.set_graph(graph)
+    kinds = []
+    logzs, recs = batch.run(_eps, L=ws[0].L, R=2, max_stages=8,
+                            callback=lambda b, a, act: kinds.append((b.member_kernels().tolist(), b.launches())))
+    say("member kernels, launches per stage", kinds[:2], "stages", [len(r) for r in recs])
+    first = np.array(kinds[0][0])
+    assert kinds[0][1] == 2                                   # two families: two launches
+    assert (first == 2).any() and (first == 0).any() and (first == 1).any()
+    assert first[1] != 2                                      # register-row layout: streaming in the launch
+    if precision == W.MIXED:
+        assert first[2] != 2                                  # more LDS than two workgroups per CU leave
+    for k, (w, tb) in enumerate(zip(ws, centres)):
+        smc = _context(w, tb, 0 if first[k] == 2 else B.MOVE_STREAMING)
+        logz1, rec1 = smc.run(_eps, L=ws[0].L, R=2, max_stages=8)
+        assert [r["a"] for r in recs[k]] == [r["a"] for r in rec1], k
+        assert logzs[k] == logz1, k
+        for got, ref in zip(_state(members[k]), _state(smc)):
+            np.testing.assert_array_equal(got, ref)
+        smc.close()
+    if graph:
+        assert batch.graph_captures() >= 1
+    batch.close()
+    for m in members:
+        m.close()
+
+
+def test_persistent_batch_timing_and_launch_count():
+    """With timing on, the persistent move reports one timed launch per row type and family
+    (kind 3) and its results equal the untimed launches'."""
+    B = _binding()
+    ws = _persistent_members(W.MIXED)[:5]                     # one family: one launch
+    centres = [_oracle_problem(w)[1] for w in ws]
+    out = []
+    for timing in (False, True):
+        members = [_context(w, tb) for w, tb in zip(ws, centres)]
+        batch = B.SMCBatch(members)
+        batch.set_persistent(True)
+        batch.set_timing(timing)
+        logzs, recs = batch.run(_eps, L=ws[0].L, R=1, max_stages=3)
+        if timing:
+            kind, ms, ml = batch.move_timing()
+            say("persistent launch", kind, ms, ml)
+            assert list(kind) == [3] and ms[0] > 0 and set(ml) == {0}
+        out.append((logzs, [_state(m) for m in members]))
+        batch.close()
+        for m in members:
+            m.close()
+    assert out[0][0] == out[1][0]
+    for a, b in zip(out[0][1], out[1][1]):
+        for x, y in zip(a, b):
+            np.testing.assert_array_equal(x, y)

@@ -69,60 +69,114 @@ def dhat_abs_scale(P, th, u):
     return remainder_scales(P, th, u)[0]
 
 
+def laplace_mass(P, w, a):
+    """A well-conditioned mass matrix for one move from a given state: the covariance of the
+    Laplace approximation of the tempered posterior at the control-variate centre,
+    (prior precision - a C)^-1, C the Hessian of the log-likelihood there (the matrix the
+    particle covariance of a converged cloud approximates). Eigenvalues of the precision below
+    1e-3 of its largest are raised to that floor (a log-likelihood that is not concave there)."""
+    pp = np.asarray(w.prior_prec, dtype=np.float64)
+    pp = pp if pp.ndim == 2 else np.diag(np.broadcast_to(pp, (w.d,)))
+    H = pp - a * P.C
+    ev, V = np.linalg.eigh(0.5 * (H + H.T))
+    ev = np.maximum(ev, 1e-3 * ev.max())
+    Sig = (V / ev) @ V.T
+    Sig = 0.5 * (Sig + Sig.T)
+    return Sig, oracle.cholesky(Sig)
+
+
 def oracle_move_diag(P, th0, u0, a, eps, L, seed, stage, mv, G, Sig, Lc, mixed):
-    """The oracle's log r of every decision of one move (diag), and again with each particle's
-    delta = theta - theta_bar scaled by 1 + rho, the factor of Sigma (so the momentum) by 1 + rho
-    and Sigma by 1 - rho, rho at the path's rounding level (1e-13 in FP64, 1e-6 for FP32 rows;
-    the GPU forms the momentum with its own inverse factor and transcendentals): how far the
-    oracle's own result moves under a perturbation of that size. Along some trajectories (here
-    the particle clouds with fewer particles than parameters, whose covariance is jittered) the
-    leapfrog amplifies such a change of the momentum by 1e8."""
+    """The oracle's move with its log r of every decision (diag), and how far that result moves
+    under perturbations at the path's rounding level rho (1e-13 in FP64, 1e-6 for FP32 rows; the
+    GPU forms delta, the momentum and the energies with its own rounding): once with every
+    delta = theta - theta_bar scaled by 1 + rho, the factor of Sigma by 1 + rho and Sigma by
+    1 - rho, and twice with random changes of that size in every coordinate of delta and every
+    entry of the factor. A scaling alone can miss the unstable direction of an ill-conditioned
+    trajectory (a mass matrix that is singular but for its jitter amplifies a change of the
+    momentum by 1e8 or more); the random directions find it.
+    Returns the oracle's move and a summary: per particle and decision the largest shift of
+    log r (inf where a perturbed run's log r is non-finite and the unperturbed one's is not, or
+    the other way round), the largest shift of each coordinate of the final theta, and whether
+    any perturbed run decides differently."""
     out = oracle.move(P, th0, u0, a, eps, L, seed, stage, mv, G, Sig, Lc, diag=True)
     rho = 1e-6 if mixed else 1e-13
-    thp = P.theta_bar + (th0 - P.theta_bar) * (1 + rho)
-    out2 = oracle.move(P, thp, u0, a, eps, L, seed, stage, mv, G, Sig * (1 - rho), Lc * (1 + rho), diag=True)
-    return out, out2
+    runs = [(P.theta_bar + (th0 - P.theta_bar) * (1 + rho), Sig * (1 - rho), Lc * (1 + rho))]
+    g = np.random.default_rng(1000 * stage + mv)
+    for _ in range(2):
+        dmax = np.abs(th0 - P.theta_bar).max(axis=1, keepdims=True)
+        thr = th0 + rho * dmax * g.standard_normal(th0.shape)
+        runs.append((thr, Sig, Lc * (1 + rho * np.tril(g.standard_normal(Lc.shape)))))
+    dg = out[-1]
+    dlogr = np.zeros((len(th0), 2))
+    dtheta = np.zeros_like(th0)
+    flip = np.zeros(len(th0), dtype=bool)
+    for thp, Sp, Lp in runs:
+        o2 = oracle.move(P, thp, u0, a, eps, L, seed, stage, mv, G, Sp, Lp, diag=True)
+        for k in (0, 1):
+            f0, f1 = np.isfinite(dg[:, 2 * k]), np.isfinite(o2[-1][:, 2 * k])
+            with np.errstate(invalid="ignore"):
+                sh = np.where(f0 & f1, np.abs(o2[-1][:, 2 * k] - dg[:, 2 * k]), np.where(f0 == f1, 0.0, np.inf))
+            dlogr[:, k] = np.maximum(dlogr[:, k], sh)
+        with np.errstate(invalid="ignore"):
+            dtheta = np.maximum(dtheta, np.where(np.isfinite(o2[0]), np.abs(o2[0] - out[0]), np.inf))
+        flip |= (o2[2] != out[2]).any(axis=1)
+    return out, {"dlogr": dlogr, "dtheta": dtheta, "flip": flip}
 
 
-def check_decisions(smc, acc, dg, mixed, a=None, scale=None, dg2=None):
+# the smallest log U: the uniform in (0, 1] is (w >> 11) + 1 over 2^53, at least 2^-53
+LOG_U_MIN = -53 * math.log(2.0)
+
+
+def check_decisions(smc, acc, dg, mixed, a=None, scale=None, sens=None):
     """The GPU's accept decisions against the oracle's, through the move's record of log r and
     log U: log U is the same draw on both sides (within a few ulps of the logarithm), every GPU
     decision follows its own log r (log U < log r, log r finite), and the GPU's log r agrees with
     the oracle's within the path's bound: tau (1 + |log r|), tau = 1e-9 in FP64 and 1e-5 in mixed
     precision, plus in mixed precision 1e-5 of the scale of the FP32-computed part of the two
     lambda_a values it differences (`scale`, per particle), plus ten times the oracle's own shift
-    of log r under a rounding-level perturbation of the particle (`dg2`, see oracle_move_diag).
-    So decisions can differ only where log U lies between the two log r values. Returns the
-    particles whose decisions are equal on both sides."""
+    of log r under rounding-level perturbations (`sens`, the summary of oracle_move_diag). A log r
+    that is non-finite on one side only is allowed only where the oracle's own perturbed runs
+    change its finiteness. So decisions can differ only where log U lies between the two log r
+    values. Returns the particles whose decisions are equal on both sides."""
     gacc = smc.accept.cpu().numpy()
     gd = smc.move_diag()
+    dl = sens["dlogr"] if sens is not None else np.zeros((len(dg), 2))
     for k in (0, 1):
         # the uniform is the same draw; its logarithm (device log vs the host's) within a few ulps
         assert np.all(np.abs(gd[:, 2 * k + 1] - dg[:, 2 * k + 1]) <= 4e-16 * np.abs(dg[:, 2 * k + 1]) + 1e-300), k
         own = np.isfinite(gd[:, 2 * k]) & (gd[:, 2 * k + 1] < gd[:, 2 * k])
         assert np.array_equal(gacc[:, k] == 1, own), k
-        # a non-finite log r (an overflowing trajectory far from the data) rejects; where either
-        # side has one, both sides reject
-        fin = np.isfinite(dg[:, 2 * k]) & np.isfinite(gd[:, 2 * k])
-        assert np.all(gacc[~fin, k] == 0) and np.all(acc[~fin, k] == 0), k
+        # a non-finite log r (an overflowing trajectory far from the data), or one below the
+        # smallest log U the uniform in (0, 1] can take, rejects whatever its value; where both
+        # sides are such certain rejects only the decision is compared, and a log r non-finite on
+        # one side only is allowed where the other side's is a certain reject too or the oracle's
+        # own finiteness is unstable (the FP32 rows of the mixed path overflow before the oracle)
+        f_o, f_g = np.isfinite(dg[:, 2 * k]), np.isfinite(gd[:, 2 * k])
+        with np.errstate(invalid="ignore"):
+            low_o = ~f_o | (dg[:, 2 * k] < LOG_U_MIN)
+            low_g = ~f_g | (gd[:, 2 * k] < LOG_U_MIN)
+        assert np.all(acc[low_o, k] == 0) and np.all(gacc[low_g, k] == 0), k
+        assert np.all((f_o == f_g) | (low_o & low_g) | np.isinf(dl[:, k])), k
+        fin = f_o & f_g & ~(low_o & low_g)
         if (~fin).any():
-            say("non-finite log r", "u" if k == 0 else "theta", "gpu", int((~np.isfinite(gd[:, 2 * k])).sum()),
-                "oracle", int((~np.isfinite(dg[:, 2 * k])).sum()))
+            say("log r not compared", "u" if k == 0 else "theta", "non-finite gpu", int((~f_g).sum()),
+                "oracle", int((~f_o).sum()), "certain rejects", int((low_o & low_g).sum()),
+                "unstable", int(np.isinf(dl[:, k]).sum()))
         err = np.abs(gd[fin, 2 * k] - dg[fin, 2 * k])
         rel = err / (1 + np.abs(dg[fin, 2 * k]))
         if mixed:
             tol = 1e-5 * (1 + np.abs(dg[fin, 2 * k])) + (1e-5 * scale[fin] if scale is not None else 0.0)
         else:
             tol = 1e-9 * (1 + np.abs(dg[fin, 2 * k]))
-        if dg2 is not None:
-            sens = np.abs(dg2[fin, 2 * k] - dg[fin, 2 * k])
-            tol = tol + 10.0 * np.where(np.isfinite(sens), sens, np.inf)
+        tol = tol + 10.0 * dl[fin, k]
         say("log r", "u" if k == 0 else "theta", "max error / (1 + |log r|)", rel.max() if len(rel) else 0.0,
             "max error / tol", (err / tol).max() if len(err) else 0.0)
         assert np.all(err <= tol), (k, err.max(), (err / tol).max())
-        between = (np.abs(dg[:, 2 * k + 1] - dg[:, 2 * k])
-                   <= np.abs(gd[:, 2 * k] - dg[:, 2 * k]) + np.abs(gd[:, 2 * k + 1] - dg[:, 2 * k + 1]))
-        assert np.all((gacc[:, k] == acc[:, k]) | between | ~fin), k
+        with np.errstate(invalid="ignore"):
+            between = (np.abs(dg[:, 2 * k + 1] - dg[:, 2 * k])
+                       <= np.abs(gd[:, 2 * k] - dg[:, 2 * k]) + np.abs(gd[:, 2 * k + 1] - dg[:, 2 * k + 1])
+                       + 10.0 * dl[:, k])
+        assert np.all((gacc[:, k] == acc[:, k]) | between | ~fin | np.isinf(dl[:, k])), k
     return (gacc == acc).all(axis=1)
 
 
@@ -471,8 +525,32 @@ def test_move_first_order(name, path):
     _check_move(name, mk(), a, eps, 0.02, path, 1)
 
 
-def _check_move(name, w, a, eps, spread, path, cv_order, tile=None):
-    say("move case", name, spread, path, "cv order", cv_order, "tile", tile)
+@pytest.mark.parametrize("path", [1, 0], ids=["streaming", "auto"])
+@pytest.mark.parametrize("name", ["logistic_d50", "poisson_d70", "logistic_mixed_m3000"])
+def test_move_degenerate_mass(name, path):
+    """Clouds of no more particles than parameters, moved with their own weighted covariance as
+    the mass matrix (singular but for its jitter, condition numbers 1e11 to 1e17): along such
+    trajectories a change of the momentum at the rounding level moves the oracle's own log r by
+    many orders more, so log r is compared where the oracle's perturbed runs show it stable,
+    and everywhere each GPU decision follows its own log r from the same uniform."""
+    _, mk, a, eps = next(c for c in MOVE_CASES if c[0] == name)
+    _check_move(name, mk(), a, eps, 0.02, path, 2, mass="particles")
+
+
+_ORACLE_MOVES = {}
+
+
+def _oracle_move_cached(key, *args):
+    """oracle_move_diag of one case, kept for the next call with the same key (the case on
+    the other kernel path runs the same oracle move)."""
+    if key not in _ORACLE_MOVES:
+        _ORACLE_MOVES.clear()
+        _ORACLE_MOVES[key] = oracle_move_diag(*args)
+    return _ORACLE_MOVES[key]
+
+
+def _check_move(name, w, a, eps, spread, path, cv_order, tile=None, mass="laplace"):
+    say("move case", name, spread, path, "cv order", cv_order, "tile", tile, "mass", mass)
     P, smc = make_pair(w, move_path=path, cv_order=cv_order)
     if tile is not None:
         smc.set_move_option(-1, 0, tile)
@@ -481,18 +559,25 @@ def _check_move(name, w, a, eps, spread, path, cv_order, tile=None):
     # a particle cloud around theta_bar: the oracle's prior draws shrunk towards it
     thp, u0, _ = oracle.init_particles(w.M, w.d, w.m, w.n, w.seed, w.prior_mean, w.prior_prec)
     th0 = P.theta_bar + spread * (thp - w.prior_mean)
-    _, Sig, Lc = oracle.moments(th0, np.full(w.M, -math.log(w.M)))
+    if mass == "laplace":
+        Sig, Lc = laplace_mass(P, w, a)
+    else:
+        # the weighted covariance of the cloud itself (jittered where it is singular)
+        _, Sig, Lc = oracle.moments(th0, np.full(w.M, -math.log(w.M)))
     smc.theta.copy_(torch.tensor(th0))
     smc.u.copy_(torch.tensor(u0))
     smc.refresh()
     smc.set_mass(Sig)
+    # both sides move with the same factor of Sigma: the library's own (it agrees with the oracle's
+    # to 1e-10, test_mass_parity; a nearly singular Sigma would otherwise give the two sides
+    # momenta that differ by its condition number times the rounding)
+    Lc = smc.get_mass()[1]
     stage, mv = 3, 1
     smc.set_stage(stage, mv, a)
     smc.move(eps, w.L, 1)
     torch.cuda.synchronize()
-    (th1, u1, acc, lh1, sg1, dg), out2 = oracle_move_diag(P, th0, u0, a, eps, w.L, w.seed, stage, mv, w.G, Sig, Lc,
-                                                         mixed)
-    th1b, dg2 = out2[0], out2[-1]
+    (th1, u1, acc, lh1, sg1, dg), sens = _oracle_move_cached(
+        (name, spread, cv_order, mass), P, th0, u0, a, eps, w.L, w.seed, stage, mv, w.G, Sig, Lc, mixed)
     gacc = smc.accept.cpu().numpy()
     tau = 1e-5 if mixed else 1e-9
     near_u = np.abs(dg[:, 1] - dg[:, 0]) <= tau * (1 + np.abs(dg[:, 0]))
@@ -503,27 +588,33 @@ def _check_move(name, w, a, eps, spread, path, cv_order, tile=None):
         # the FP32-computed part of the two lambda_a values each log r differences
         sd, ss = remainder_scales(P, th0, u0)
         scale = 2 * (a * sd + 0.5 * a * a * ss)
-    same = check_decisions(smc, acc, dg, mixed, a, scale, dg2)
+    same = check_decisions(smc, acc, dg, mixed, a, scale, sens)
     gu = smc.u.cpu().numpy()
     np.testing.assert_array_equal(gu[same], u1[same])
     rt = 1e-5 if mixed else 1e-9
     gth = smc.theta.cpu().numpy()
-    # theta within rt, plus ten times the oracle's own shift under the rounding-level perturbation
+    # theta within rt, plus ten times the oracle's own shift under the rounding-level perturbations
     # (the same allowance as for log r; it matters only along ill-conditioned trajectories)
-    same2 = same & (out2[2] == acc).all(axis=1)
-    tol_th = rt * np.abs(th1[same2]) + rt * np.abs(th1).max() + 10 * np.abs(th1b[same2] - th1[same2])
+    same2 = same & ~sens["flip"]
+    tol_th = rt * np.abs(th1[same2]) + rt * np.abs(th1).max() + 10 * sens["dtheta"][same2]
     assert np.all(np.abs(gth[same2] - th1[same2]) <= tol_th)
     # the cached estimator at the particle's final state, against the oracle's estimator at that
     # same state (the final states of the two sides differ within the trajectory tolerance, which
     # sigma2_hat, of order Delta^6, would amplify)
     gth_s, gu_s = gth[same], gu[same]
     ref = P.estimate(gth_s, gu_s)
-    np.testing.assert_allclose(smc.lhat.cpu().numpy()[same], ref["lhat"], rtol=rt)
+    glh = smc.lhat.cpu().numpy()[same]
+    if mixed:
+        # 1e-5 of |l_hat| plus 1e-5 of the absolute-sum scale of its FP32-computed part d_hat
+        # (l_hat itself can be far smaller than its terms: one observation, n = 1)
+        sd, ss = remainder_scales(P, gth_s, gu_s)
+        assert np.all(np.abs(glh - ref["lhat"]) <= 1e-5 * (np.abs(ref["lhat"]) + sd))
+    else:
+        np.testing.assert_allclose(glh, ref["lhat"], rtol=rt)
     if w.family != W.GAUSSIAN:
         fl = (1e-12 * np.abs(ref["lhat"])) ** 2
         gs2 = smc.sig2.cpu().numpy()[same]
         if mixed:
-            _, ss = remainder_scales(P, gth_s, gu_s)
             assert np.all(np.abs(gs2 - ref["sig2"]) <= 1e-5 * ss + fl)
         else:
             assert np.all(np.abs(gs2 - ref["sig2"]) <= 1e-9 * np.abs(ref["sig2"]) + fl)
@@ -776,21 +867,38 @@ def _teacher_forced_stages(w, precision, path, tol, max_stages=60):
         th0, u0 = smc.theta.cpu().numpy(), smc.u.cpu().numpy()
         lw0, lh0, s20 = smc.logw.cpu().numpy(), smc.lhat.cpu().numpy(), smc.sig2.cpu().numpy()
         a_prev = smc.info()["a"]
-        a, dz, ess = smc.stage(eps, L, 1)
+        # the stage's steps one call each, so that every step starts from the GPU's own result
+        # of the step before (smc_stage queues the same calls: test_stage_equals_its_steps)
+        a, dz, ess = smc.temper()
         torch.cuda.synchronize()
+        lw_g = smc.logw.cpu().numpy()
         info = smc.info()
         stages += 1
         a_o, dz_o, ess_o, lw_o = oracle.temper(lh0, s20, lw0, a_prev, w.ess_frac)
         assert abs(a - a_o) <= 1e-12 * a_o, (stages, a, a_o)
         assert abs(dz - dz_o) <= 1e-9 * max(1.0, abs(dz_o)), (stages, dz, dz_o)
         assert abs(ess - ess_o) <= 1e-9 * w.M
-        _, Sig, Lc = oracle.moments(th0, lw_o)
-        S_gpu = smc.get_mass()[0]
+        # reweighted log weights: 1e-9, plus the first-order effect of the two exponents'
+        # difference (d log W_i / da = g_i - sum_j W_j g_j, g = l_hat - a sigma2_hat), doubled
+        fin = np.isfinite(lw_o)
+        assert np.array_equal(fin, np.isfinite(lw_g)), stages
+        gi = lh0 - a_o * s20
+        Wn = np.exp(lw_o[fin] - lw_o[fin].max())
+        Wn /= Wn.sum()
+        dlw = 2.0 * abs(a - a_o) * np.abs(gi[fin] - (Wn * gi[fin]).sum())
+        assert np.all(np.abs(lw_g[fin] - lw_o[fin]) <= 1e-9 * (1 + np.abs(lw_o[fin])) + dlw), stages
+        smc.mass()
+        _, Sig, Lc = oracle.moments(th0, lw_g)
+        S_gpu, L_gpu, _ = smc.get_mass()
         np.testing.assert_allclose(S_gpu, Sig, rtol=1e-10, atol=1e-12 * np.abs(Sig).max())
-        anc = oracle.resample_ancestors(lw_o, oracle.resample_offset(w.seed, info["stage"]))
-        (th1, u1, acc, lh1, sg1, dg), out2 = oracle_move_diag(P, th0[anc], u0[anc], a_o, eps, L, w.seed,
-                                                             info["stage"], 0, w.G, Sig, Lc, mixed)
-        th1b, dg2 = out2[0], out2[-1]
+        smc.resample()
+        smc.move(eps, L, 1)
+        torch.cuda.synchronize()
+        anc = oracle.resample_ancestors(lw_g, oracle.resample_offset(w.seed, info["stage"]))
+        # the move from the GPU's state, mass matrix and its factor included (they agree with the
+        # oracle's to 1e-10; the move is compared from identical inputs)
+        (th1, u1, acc, lh1, sg1, dg), sens = oracle_move_diag(P, th0[anc], u0[anc], a_o, eps, L, w.seed,
+                                                             info["stage"], 0, w.G, S_gpu, L_gpu, mixed)
         near_u = np.abs(dg[:, 1] - dg[:, 0]) <= tau * (1 + np.abs(dg[:, 0]))
         near_t = np.abs(dg[:, 3] - dg[:, 2]) <= tau * (1 + np.abs(dg[:, 2]))
         ties += int(near_u.sum() + near_t.sum())
@@ -798,12 +906,12 @@ def _teacher_forced_stages(w, precision, path, tol, max_stages=60):
         if mixed:
             sd, ss = remainder_scales(P, th0[anc], u0[anc])
             scale = 2 * (a_o * sd + 0.5 * a_o * a_o * ss)
-        same = check_decisions(smc, acc, dg, mixed, a_o, scale, dg2)
+        same = check_decisions(smc, acc, dg, mixed, a_o, scale, sens)
         gu = smc.u.cpu().numpy()
         np.testing.assert_array_equal(gu[same], u1[same])
         gth = smc.theta.cpu().numpy()
-        same2 = same & (out2[2] == acc).all(axis=1)
-        tol_th = tol * np.abs(th1[same2]) + tol * np.abs(th1).max() + 10 * np.abs(th1b[same2] - th1[same2])
+        same2 = same & ~sens["flip"]
+        tol_th = tol * np.abs(th1[same2]) + tol * np.abs(th1).max() + 10 * sens["dtheta"][same2]
         assert np.all(np.abs(gth[same2] - th1[same2]) <= tol_th), stages
         # the GPU's cached estimator against the oracle's at the GPU's own state
         ref = P.estimate(gth, gu)
@@ -823,7 +931,10 @@ def _teacher_forced_stages(w, precision, path, tol, max_stages=60):
 TF_CASES = [
     ("logistic_fp64", lambda: W.logistic_small(3000, 3, seed=61, M=128, m=150, G=4, L=6), W.FP64),
     ("poisson_fp64", lambda: W.poisson_small(8000, 6, seed=62, M=96, m=300, G=10, L=6), W.FP64),
-    ("logistic_d40_fp64", lambda: W.logistic_small(4000, 40, seed=63, M=64, m=200, G=10, L=4, theta_scale=0.2),
+    # 128 particles in 40 dimensions: the particle covariance stays well conditioned (condition
+    # numbers 30-90 over the run); with 64 the cloud collapses onto a subspace (1e17 by a = 1) and
+    # the trajectories amplify rounding without bound
+    ("logistic_d40_fp64", lambda: W.logistic_small(4000, 40, seed=63, M=128, m=200, G=10, L=4, theta_scale=0.2),
      W.FP64),
     ("logistic_mixed", lambda: W.logistic_small(3000, 3, seed=61, precision=W.MIXED, M=128, m=150, G=4, L=6),
      W.MIXED),
@@ -839,6 +950,30 @@ def test_teacher_forced_stages(name, mk, prec, path):
     from the GPU's state): 1e-9 relative in FP64, 1e-5 in mixed precision."""
     say("teacher forced", name, "path", path)
     _teacher_forced_stages(mk(), prec, path, 1e-5 if prec == W.MIXED else 1e-9)
+
+
+@pytest.mark.parametrize("path", [1, 0], ids=["streaming", "auto"])
+def test_stage_equals_its_steps(path):
+    """smc_stage (one call per stage) and its four steps called one by one (smc_temper,
+    smc_mass, smc_resample, smc_move) leave the same state, bit for bit, stage after stage."""
+    w = W.logistic_small(4000, 12, seed=69, precision=W.MIXED, M=128, m=400, G=10, L=5, theta_scale=0.2)
+    _, one = make_pair(w, move_path=path)
+    _, steps = make_pair(w, move_path=path)
+    eps, L = 1.0 / w.L, w.L
+    for k in range(4):
+        out1 = one.stage(eps, L, 1)
+        out2 = steps.temper()
+        steps.mass()
+        steps.resample()
+        steps.move(eps, L, 1)
+        torch.cuda.synchronize()
+        assert out1 == out2, k
+        for t1, t2 in ((one.theta, steps.theta), (one.u, steps.u), (one.logw, steps.logw), (one.lhat, steps.lhat),
+                       (one.sig2, steps.sig2), (one.accept, steps.accept)):
+            assert torch.equal(t1, t2), k
+        assert one.info() == steps.info(), k
+    one.close()
+    steps.close()
 
 
 def test_full_run_mixed_matches_oracle():
