@@ -224,13 +224,22 @@ def laplace_state_move(smc, w, eps, reps=10, warm=3, seed=77):
             "state": "a = 1, theta ~ Laplace approximation at the centre, u uniform, Sigma = (-C - Q0)^-1"}
 
 
-DEVICE_SOURCES = ["kernels.hpp", "kernels_wide.hpp", "kernels_resident.hpp", "xlane.hpp", "glm.hpp", "rng.hpp"]
+# the device sources each move kernel is compiled from: a committed PMC summary
+# counts only while these are unchanged
+_COMMON_SOURCES = ["kernels.hpp", "xlane.hpp", "glm.hpp", "rng.hpp"]
+DEVICE_SOURCES = {
+    "move_kernel": _COMMON_SOURCES,
+    "move_kernel_wide": _COMMON_SOURCES + ["kernels_wide.hpp"],
+    "move_kernel_res": _COMMON_SOURCES + ["kernels_resident.hpp"],
+    "move_kernel_persist": _COMMON_SOURCES + ["kernels_wide.hpp", "kernels_resident.hpp", "kernels_persist.hpp",
+                                              "launch_persist.hpp"],
+}
 
 
-def device_source_hash():
+def device_source_hash(kernel):
     import hashlib
     h = hashlib.sha256()
-    for f in DEVICE_SOURCES:
+    for f in DEVICE_SOURCES[kernel]:
         with open(os.path.join(ROOT, "paper_1805_03317_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -254,7 +263,7 @@ def measured_traffic(w, precision, kernel):
             if ln.strip() and not ln.startswith("#") and len(ln.split()) == 2:
                 k, v = ln.split()
                 kv[k] = v
-    if kv.get("device_source_sha256") != device_source_hash():
+    if kv.get("device_source_sha256") != device_source_hash(kernel):
         return None
     return float(kv["traffic_bytes_per_launch"])
 

@@ -67,9 +67,12 @@ def test_traffic_only_for_current_sources(tmp_path, monkeypatch):
     prof.mkdir()
     f = prof / "move_kernel_res_poisson_n1e6_d20_fp32data_mixed_traffic.txt"
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
-    monkeypatch.setattr(bench, "device_source_hash", lambda: "abc")
+    monkeypatch.setattr(bench, "device_source_hash", lambda kernel: "abc")
     f.write_text("# header\ndevice_source_sha256 abc\ntraffic_bytes_per_launch 1234\n")
     assert bench.measured_traffic(w, "mixed", "move_kernel_res") == 1234.0
     f.write_text("# header\ndevice_source_sha256 old\ntraffic_bytes_per_launch 1234\n")
     assert bench.measured_traffic(w, "mixed", "move_kernel_res") is None
     assert bench.measured_traffic(w, "fp64", "move_kernel") is None
+    # each kernel's summary follows its own sources
+    assert set(bench.DEVICE_SOURCES) >= {"move_kernel", "move_kernel_wide", "move_kernel_res"}
+    assert "kernels_resident.hpp" not in bench.DEVICE_SOURCES["move_kernel_wide"]
