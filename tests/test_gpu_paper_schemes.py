@@ -98,6 +98,8 @@ def test_full_run_paper_schemes_matches_oracle():
     temps = np.array([r["a"] for r in rec])
     assert len(temps) == len(ref["temps"])
     np.testing.assert_array_equal(temps, ref["temps"])
+    # free running over the whole run (the per-stage 1e-9 comparison is the teacher-forced test of
+    # test_gpu_parity): rounding differences compound over the stages' moves
     assert abs(logz - ref["logz"]) <= 1e-7 * abs(ref["logz"])
     np.testing.assert_allclose(smc.theta.cpu().numpy(), ref["theta"], rtol=1e-6, atol=1e-8)
     np.testing.assert_array_equal(smc.u.cpu().numpy(), ref["u"])
@@ -139,7 +141,14 @@ def test_recentre_parity(precision):
     ref = P.estimate(th, u)
     rt = 1e-5 if precision == W.MIXED else 1e-9
     np.testing.assert_allclose(smc.lhat.cpu().numpy(), ref["lhat"], rtol=rt)
-    np.testing.assert_allclose(smc.sig2.cpu().numpy(), ref["sig2"], rtol=1e-4 if precision == W.MIXED else 1e-8)
+    if precision == W.MIXED:
+        # 1e-5 of the first-order scale of sigma2_hat's FP32-computed terms (as in test_gpu_parity)
+        from test_gpu_parity import remainder_scales
+        _, ss = remainder_scales(P, th, u)
+        floor = (1e-12 * np.abs(ref["lhat"])) ** 2
+        assert np.all(np.abs(smc.sig2.cpu().numpy() - ref["sig2"]) <= 1e-5 * ss + floor)
+    else:
+        np.testing.assert_allclose(smc.sig2.cpu().numpy(), ref["sig2"], rtol=1e-8)
     # an explicit centre
     c2 = mean + 0.01
     smc.recentre(c2)
@@ -169,6 +178,8 @@ def test_full_run_recentre_matches_oracle():
     temps = np.array([r["a"] for r in rec])
     assert len(temps) == len(ref["temps"])
     np.testing.assert_allclose(temps, ref["temps"], rtol=1e-8, atol=1e-10)
+    # free running over the whole run (the per-stage 1e-9 comparison is the teacher-forced test of
+    # test_gpu_parity): rounding differences compound over the stages' moves
     assert abs(logz - ref["logz"]) <= 1e-7 * abs(ref["logz"])
     np.testing.assert_allclose(smc.theta.cpu().numpy(), ref["theta"], rtol=1e-6, atol=1e-8)
     np.testing.assert_array_equal(smc.u.cpu().numpy(), ref["u"])
