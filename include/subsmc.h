@@ -44,7 +44,7 @@ typedef enum {
   SMC_ERR_DEVICE = 3,      /* a HIP call failed; see smc_last_error */
   SMC_ERR_NOT_PD = 4,      /* covariance not positive definite even after jitter */
   SMC_ERR_NONFINITE = 5,   /* every incremental weight is non-finite */
-  SMC_ERR_UNSUPPORTED = 6  /* valid request this build does not implement (e.g. d > 128) */
+  SMC_ERR_UNSUPPORTED = 6  /* valid request the library does not implement (e.g. d > 128) */
 } smc_status;
 
 typedef enum {

@@ -358,3 +358,49 @@ def test_persistent_batch_timing_and_launch_count():
     for a, b in zip(out[0][1], out[1][1]):
         for x, y in zip(a, b):
             np.testing.assert_array_equal(x, y)
+
+
+@pytest.mark.parametrize("precision", [W.FP64, W.MIXED], ids=["fp64", "mixed"])
+def test_persistent_batch_edge_members(precision):
+    """The persistent move at the edges of its items and bodies: a resident member of three
+    particles, streaming members whose last item leaves one to three wavefronts idle (9, 7 and 6
+    particles), the widest rows (d = 128), and the Gaussian and Student-t families beside
+    logistic rows (three launches); each member equals its own run bit for bit."""
+    B = _binding()
+    ws = [W.logistic_small(2000, 5, seed=311, precision=precision, M=3, m=120, G=4, L=4),
+          W.logistic_small(3000, 128, seed=312, precision=precision, M=7, m=90, G=3, L=4, theta_scale=0.1),
+          W.gaussian_small(800, 3, seed=313, precision=precision, M=5, m=40, G=4, L=4),
+          W.student_small(2500, 40, seed=314, precision=precision, M=9, m=110, G=5, L=4, theta_scale=0.3),
+          W.logistic_small(2500, 20, seed=315, precision=precision, M=6, m=100, G=4, L=4, theta_scale=0.3)]
+    for k, w in enumerate(ws):
+        w.dataset = 40 + k
+    P = [oracle.Problem(w.Xy(np.float64), w.d, w.family, w.prior_mean, w.prior_prec, gauss_s2=w.gauss_s2)
+         for w in ws]
+    centres = [p.newton_mode()[0] for p in P]
+    dt = np.float32 if precision == W.MIXED else np.float64
+
+    def ctx(w, tb, path):
+        return B.SubsampledSMC(torch.tensor(w.Xy(dt), device=DEV), w.d, w.family, w.precision, w.M, w.m, w.G,
+                               w.prior_mean, w.prior_prec, w.seed, theta_bar=tb, move_path=path,
+                               dataset=w.dataset, gauss_s2=w.gauss_s2)
+
+    members = [ctx(w, tb, 0) for w, tb in zip(ws, centres)]
+    batch = B.SMCBatch(members)
+    batch.set_persistent(True)
+    kinds = []
+    logzs, recs = batch.run(_eps, L=ws[0].L, R=2, max_stages=5,
+                            callback=lambda b, a, act: kinds.append((b.member_kernels().tolist(), b.launches())))
+    say("member kernels, launches", kinds[0])
+    first = np.array(kinds[0][0])
+    assert kinds[0][1] == 3
+    for k, (w, tb) in enumerate(zip(ws, centres)):
+        smc = ctx(w, tb, 0 if first[k] == 2 else B.MOVE_STREAMING)
+        logz1, rec1 = smc.run(_eps, L=ws[0].L, R=2, max_stages=5)
+        assert [r["a"] for r in recs[k]] == [r["a"] for r in rec1], k
+        assert logzs[k] == logz1, k
+        for got, ref in zip(_state(members[k]), _state(smc)):
+            np.testing.assert_array_equal(got, ref)
+        smc.close()
+    batch.close()
+    for m in members:
+        m.close()
