@@ -12,6 +12,8 @@ the oracle cannot redo a stage, so each test
 * compares the sampled particles' decisions, u, theta and the cached estimator to the bounds of
   the move-parity tests (decisions exact outside the near-tie band; u bit-exact where the
   decisions agree; theta, l_hat and sigma2_hat within 1e-5 of their scales);
+* checks the stage's other steps (exponent search, mass matrix, resampling) on the whole
+  population against the oracle from the library's state before each;
 * checks the whole population through properties that hold at any size: the refreshed indices
   lie in [0, n) and differ from the old u only inside one of the G blocks (section 3.3); a
   rejected u-refresh leaves u unchanged and a rejected HMC step leaves theta unchanged; theta
@@ -123,6 +125,39 @@ def _compare(w, smc, P, i0, out, sens, scale, a):
     assert np.all(e_l <= 1e-5) and np.all(e_s <= 1e-5)
 
 
+def _check_stage_steps(w, smc):
+    """The stage's steps before its move, each against the oracle from the library's state
+    before the step: the exponent search (section 2.1, exponent to 1e-12, log-weights and the
+    log-evidence increment to 1e-9), the mass matrix (particle covariance to 1e-10 of its
+    largest entry, and its factor) and systematic resampling (ancestors, hence theta, u and the
+    caches, bit for bit; weights reset to 1/M)."""
+    lh, s2, lw = (x.cpu().numpy() for x in (smc.lhat, smc.sig2, smc.logw))
+    a_prev = smc.info()["a"]
+    a, dz, ess = smc.temper()
+    a_o, dz_o, ess_o, lw_o = oracle.temper(lh, s2, lw, a_prev, w.ess_frac)
+    say("temper", a_prev, "->", a, "oracle", a_o, "ess", ess, ess_o)
+    assert abs(a - a_o) <= 1e-12 * max(1.0, a_o)
+    assert abs(dz - dz_o) <= 1e-9 * max(1.0, abs(dz_o))
+    assert abs(ess - ess_o) <= 1e-9 * w.M
+    lw1 = smc.logw.cpu().numpy()
+    np.testing.assert_allclose(lw1, lw_o, rtol=1e-9, atol=1e-9)
+    th = smc.theta.cpu().numpy()
+    smc.mass()
+    S, Lc, _ = smc.get_mass()
+    _, S_o, L_o = oracle.moments(th, lw1)
+    np.testing.assert_allclose(S, S_o, rtol=1e-10, atol=1e-10 * np.abs(S_o).max())
+    np.testing.assert_allclose(Lc, L_o, rtol=1e-9, atol=1e-9 * np.abs(L_o).max())
+    u = smc.u.cpu().numpy()
+    lh = smc.lhat.cpu().numpy()
+    smc.resample()
+    anc = oracle.resample_ancestors(lw1, oracle.resample_offset(w.seed, smc.info()["stage"]))
+    np.testing.assert_array_equal(smc.theta.cpu().numpy(), th[anc])
+    np.testing.assert_array_equal(smc.u.cpu().numpy(), u[anc])
+    np.testing.assert_array_equal(smc.lhat.cpu().numpy(), lh[anc])
+    np.testing.assert_allclose(smc.logw.cpu().numpy(), -math.log(w.M), rtol=0, atol=1e-15)
+    say("resample: distinct ancestors", len(np.unique(anc)))
+
+
 def _oracle_problem(w, smc):
     tb, A, B, Cm = smc.get_cv()
     P = oracle.Problem(w.Xy(np.float64), w.d, w.family, w.prior_mean, w.prior_prec)
@@ -167,16 +202,15 @@ LIVE = [("config5", 8, 1365), ("config4", 16, 2730), ("config2", 32, 1000)]
 @pytest.mark.parametrize("name,k,i0", LIVE, ids=[c[0] for c in LIVE])
 def test_live_stage_move_at_benchmark_size(name, k, i0):
     """The third stage of a run from the prior, as the benchmark's steps run it: two whole
-    stages, then the third stage's exponent search, mass matrix and resampling, and its move."""
+    stages, then the third stage's exponent search, mass matrix and resampling (each checked),
+    and its move."""
     w = _workload(name)
     smc = _context(w)
     say("kernel", smc.info())
     eps = 1.0 / w.L
     smc.stage(eps, w.L, 1)
     smc.stage(eps, w.L, 1)
-    smc.temper()
-    smc.mass()
-    smc.resample()
+    _check_stage_steps(w, smc)
     info = smc.info()
     a, stage, mv = info["a"], info["stage"], info["move"]
     th0_all = smc.theta.cpu().numpy()
