@@ -43,7 +43,8 @@ def _workload(name):
 def _context(w):
     from paper_1805_03317_amd.binding import SubsampledSMC
     Xy = torch.tensor(w.Xy(np.float32), device=DEV)
-    smc = SubsampledSMC(Xy, w.d, w.family, W.MIXED, w.M, w.m, w.G, w.prior_mean, w.prior_prec, w.seed)
+    smc = SubsampledSMC(Xy, w.d, w.family, W.MIXED, w.M, w.m, w.G, w.prior_mean, w.prior_prec, w.seed,
+                        dataset=w.dataset)
     return smc
 
 
@@ -86,7 +87,8 @@ def _check_sampled(w, smc, P, i0, th0, u0, a, eps, stage, mv, Sig, Lc):
     k = len(th0)
     # the oracle's move first alone; its sensitivity to rounding-level perturbations (three more
     # runs) only if a comparison needs it (an ill-conditioned trajectory)
-    out = oracle.move(P, th0, u0, a, eps, w.L, w.seed, stage, mv, w.G, Sig, Lc, i0=i0, diag=True)
+    out = oracle.move(P, th0, u0, a, eps, w.L, w.seed, stage, mv, w.G, Sig, Lc, i0=i0, diag=True,
+                      dataset=w.dataset)
     sd, ss = remainder_scales(P, th0, u0)
     scale = 2 * (a * sd + 0.5 * a * a * ss)
     zero = {"dlogr": np.zeros((k, 2)), "dtheta": np.zeros_like(th0), "flip": np.zeros(k, dtype=bool)}
@@ -94,7 +96,8 @@ def _check_sampled(w, smc, P, i0, th0, u0, a, eps, stage, mv, Sig, Lc):
         _compare(w, smc, P, i0, out, zero, scale, a)
     except AssertionError as e:
         say("comparison needs the oracle's sensitivity:", repr(e)[:200])
-        out, sens = oracle_move_diag(P, th0, u0, a, eps, w.L, w.seed, stage, mv, w.G, Sig, Lc, True, i0=i0)
+        out, sens = oracle_move_diag(P, th0, u0, a, eps, w.L, w.seed, stage, mv, w.G, Sig, Lc, True, i0=i0,
+                                     dataset=w.dataset)
         _compare(w, smc, P, i0, out, sens, scale, a)
 
 
@@ -150,7 +153,7 @@ def _check_stage_steps(w, smc):
     u = smc.u.cpu().numpy()
     lh = smc.lhat.cpu().numpy()
     smc.resample()
-    anc = oracle.resample_ancestors(lw1, oracle.resample_offset(w.seed, smc.info()["stage"]))
+    anc = oracle.resample_ancestors(lw1, oracle.resample_offset(w.seed, smc.info()["stage"], w.dataset))
     np.testing.assert_array_equal(smc.theta.cpu().numpy(), th[anc])
     np.testing.assert_array_equal(smc.u.cpu().numpy(), u[anc])
     np.testing.assert_array_equal(smc.lhat.cpu().numpy(), lh[anc])
@@ -224,3 +227,80 @@ def test_live_stage_move_at_benchmark_size(name, k, i0):
     P = _oracle_problem(w, smc)
     _check_sampled(w, smc, P, i0, th0_all[i0:i0 + k], u0_all[i0:i0 + k], a, eps, stage, mv, Sig, Lc)
     smc.close()
+
+
+def test_batched_persistent_move_at_full_size():
+    """The 64-dataset batch as the benchmark runs it (mixed path, one persistent move launch for
+    every member's particles, replayed from a HIP graph, eight streams for the per-member
+    steps): two whole stages, then the third stage's exponent search, mass matrix and resampling
+    checked on every member, and its move checked on every member through the population
+    properties and on sampled particles of the largest member of each kernel body (narrow,
+    lane-group, resident) against the oracle."""
+    from paper_1805_03317_amd.binding import SMCBatch
+    count = 64
+    ws, members = [], []
+    for b in range(count):
+        w = W.config3_member(b, count)
+        members.append(_context(w))
+        ws.append(w)
+    batch = SMCBatch(members)
+    batch.set_graph(True)
+    batch.set_streams(8)
+    batch.set_persistent(True)
+    eps = np.array([1.0 / w.L for w in ws])
+    L = ws[0].L
+    for _ in range(2):
+        batch.temper()
+        batch.mass()
+        batch.resample()
+        batch.move(eps, L, 1)
+    torch.cuda.synchronize()
+    # the third stage's steps, each against the oracle on every member
+    pre = [(c.lhat.cpu().numpy(), c.sig2.cpu().numpy(), c.logw.cpu().numpy(), c.info()["a"]) for c in members]
+    a, dz, ess, act = batch.temper()
+    torch.cuda.synchronize()
+    for b, (w, c) in enumerate(zip(ws, members)):
+        lh, s2, lw, a_prev = pre[b]
+        a_o, dz_o, ess_o, lw_o = oracle.temper(lh, s2, lw, a_prev, w.ess_frac)
+        assert abs(a[b] - a_o) <= 1e-12 * max(1.0, a_o), b
+        assert abs(dz[b] - dz_o) <= 1e-9 * max(1.0, abs(dz_o)), b
+        np.testing.assert_allclose(c.logw.cpu().numpy(), lw_o, rtol=1e-9, atol=1e-9)
+    lw1 = [c.logw.cpu().numpy() for c in members]
+    th = [c.theta.cpu().numpy() for c in members]
+    batch.mass()
+    torch.cuda.synchronize()
+    for b, c in enumerate(members):
+        S, Lc, _ = c.get_mass()
+        _, S_o, L_o = oracle.moments(th[b], lw1[b])
+        np.testing.assert_allclose(S, S_o, rtol=1e-10, atol=1e-10 * np.abs(S_o).max())
+    u = [c.u.cpu().numpy() for c in members]
+    batch.resample()
+    torch.cuda.synchronize()
+    for b, (w, c) in enumerate(zip(ws, members)):
+        anc = oracle.resample_ancestors(lw1[b], oracle.resample_offset(w.seed, c.info()["stage"], w.dataset))
+        np.testing.assert_array_equal(c.theta.cpu().numpy(), th[b][anc])
+        np.testing.assert_array_equal(c.u.cpu().numpy(), u[b][anc])
+    # the move
+    kinds = batch.member_kernels()
+    say("member kernel bodies", np.bincount(kinds, minlength=3))
+    state = []
+    for w, c in zip(ws, members):
+        i = c.info()
+        Sig, Lc, _ = c.get_mass()
+        state.append((c.theta.cpu().numpy(), c.u.cpu().numpy(), i["a"], i["stage"], i["move"], Sig, Lc))
+    batch.move(eps, L, 1)
+    torch.cuda.synchronize()
+    for b, (w, c) in enumerate(zip(ws, members)):
+        th0, u0 = state[b][:2]
+        _check_population(w, th0, u0, c.theta.cpu().numpy(), c.u.cpu().numpy(), c.accept.cpu().numpy())
+    for kind in np.unique(kinds):
+        b = max(np.flatnonzero(kinds == kind), key=lambda j: ws[j].m)
+        w, c = ws[b], members[b]
+        th0, u0, a_b, stage, mv, Sig, Lc = state[b]
+        say("member", b, "body", int(kind), "n", w.n, "d", w.d, "m", w.m, "a", a_b)
+        P = _oracle_problem(w, c)
+        i0, k = 500, 8
+        _check_sampled(w, c, P, i0, th0[i0:i0 + k], u0[i0:i0 + k], a_b, eps[b], stage, mv, Sig, Lc)
+    batch.close()
+    for c in members:
+        c.close()

@@ -85,7 +85,7 @@ def laplace_mass(P, w, a):
     return Sig, oracle.cholesky(Sig)
 
 
-def oracle_move_diag(P, th0, u0, a, eps, L, seed, stage, mv, G, Sig, Lc, mixed, i0=0):
+def oracle_move_diag(P, th0, u0, a, eps, L, seed, stage, mv, G, Sig, Lc, mixed, i0=0, dataset=0):
     """The oracle's move with its log r of every decision (diag), and how far that result moves
     under perturbations at the path's rounding level rho (1e-13 in FP64, 1e-6 for FP32 rows; the
     GPU forms delta, the momentum and the energies with its own rounding): once with every
@@ -98,8 +98,8 @@ def oracle_move_diag(P, th0, u0, a, eps, L, seed, stage, mv, G, Sig, Lc, mixed, 
     log r (inf where a perturbed run's log r is non-finite and the unperturbed one's is not, or
     the other way round), the largest shift of each coordinate of the final theta, and whether
     any perturbed run decides differently. The particles are i0, i0 + 1, ... of the run (their
-    random-number streams)."""
-    out = oracle.move(P, th0, u0, a, eps, L, seed, stage, mv, G, Sig, Lc, i0=i0, diag=True)
+    random-number streams; `dataset` is the streams' dataset field)."""
+    out = oracle.move(P, th0, u0, a, eps, L, seed, stage, mv, G, Sig, Lc, i0=i0, diag=True, dataset=dataset)
     rho = 1e-6 if mixed else 1e-13
     runs = [(P.theta_bar + (th0 - P.theta_bar) * (1 + rho), Sig * (1 - rho), Lc * (1 + rho))]
     g = np.random.default_rng(1000 * stage + mv)
@@ -112,7 +112,8 @@ def oracle_move_diag(P, th0, u0, a, eps, L, seed, stage, mv, G, Sig, Lc, mixed, 
     dtheta = np.zeros_like(th0)
     flip = np.zeros(len(th0), dtype=bool)
     for thp, Sp, Lp in runs:
-        o2 = oracle.move(P, thp, u0, a, eps, L, seed, stage, mv, G, Sp, Lp, i0=i0, diag=True)
+        o2 = oracle.move(P, thp, u0, a, eps, L, seed, stage, mv, G, Sp, Lp, i0=i0, diag=True,
+                         dataset=dataset)
         for k in (0, 1):
             f0, f1 = np.isfinite(dg[:, 2 * k]), np.isfinite(o2[-1][:, 2 * k])
             with np.errstate(invalid="ignore"):
