@@ -95,6 +95,19 @@ struct Batch {
   int count;
 };
 
+// Workgroups are dispatched to the chip's 8 XCDs in turn (workgroup b to XCD b mod 8), each XCD
+// with its own L2. The moves run particle xcd_particle(b, count) in workgroup b, which gives
+// every XCD a contiguous range of particles: systematic resampling leaves the copies of a
+// particle at adjacent indices with the same subsample u, so the copies run behind one L2 at
+// about the same time and share their row fetches there. (A bijection of [0, count); for a
+// batch member, b and count are local to the member, whose workgroups with equal b mod 8 also
+// share an XCD.)
+constexpr int kXcds = 8;
+__device__ __forceinline__ int xcd_particle(int b, int count) {
+  const int x = b % kXcds, k = b / kXcds, q = count / kXcds, r = count % kXcds;
+  return x * q + (x < r ? x : r) + k;
+}
+
 // the member owning workgroup b: the largest k with first[k] <= b
 __device__ __forceinline__ int batch_member(const int* __restrict__ first, int count, int b) {
   int lo = 0, hi = count - 1;
@@ -517,7 +530,7 @@ template <typename Real, int DC, int FAM>
 __global__ void __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(kMoveWaves<Real>))) move_kernel(MoveArgs A) {
   __shared__ Real red[kWave * DC];
   extern __shared__ int32_t blk[];
-  move_body<Real, DC, FAM>(A, blockIdx.x, red, blk);
+  move_body<Real, DC, FAM>(A, xcd_particle((int)blockIdx.x, (int)gridDim.x), red, blk);
 }
 
 template <typename Real, int DC, int FAM>
@@ -526,7 +539,7 @@ __global__ void __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(kMov
   extern __shared__ int32_t blk[];
   const int k = batch_member(B.first, B.count, blockIdx.x);
   const MoveArgs A = B.args[k];
-  move_body<Real, DC, FAM>(A, blockIdx.x - B.first[k], red, blk);
+  move_body<Real, DC, FAM>(A, xcd_particle((int)blockIdx.x - B.first[k], B.first[k + 1] - B.first[k]), red, blk);
 }
 
 }  // namespace subsmc

@@ -702,7 +702,7 @@ __device__ __forceinline__ void move_res_body(const MoveArgs& A, const ResLayout
 
 template <typename Real, int DC, int FAM, int RPL, int MF>
 __global__ void __launch_bounds__(kResLanes) move_kernel_res(MoveArgs A, ResLayout Ly) {
-  move_res_body<Real, DC, FAM, RPL, MF>(A, Ly, blockIdx.x);
+  move_res_body<Real, DC, FAM, RPL, MF>(A, Ly, xcd_particle((int)blockIdx.x, (int)gridDim.x));
 }
 
 // a batch member of the resident move: its arguments and its on-chip layout
@@ -716,7 +716,7 @@ template <typename Real, int DC, int FAM, int RPL, int MF>
 __global__ void __launch_bounds__(kResLanes) move_kernel_res_batch(Batch<ResMoveArgs> B) {
   const int k = batch_member(B.first, B.count, blockIdx.x);
   const ResMoveArgs R = B.args[k];
-  move_res_body<Real, DC, FAM, RPL, MF>(R.A, R.Ly, blockIdx.x - B.first[k]);
+  move_res_body<Real, DC, FAM, RPL, MF>(R.A, R.Ly, xcd_particle((int)blockIdx.x - B.first[k], B.first[k + 1] - B.first[k]));
 }
 
 }  // namespace subsmc

@@ -553,7 +553,7 @@ __global__ void __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(kMov
   __shared__ Real red[kWave * CH];
   __shared__ double vec[128];
   extern __shared__ int32_t blk[];
-  move_wide_body<Real, G, CH, FAM, TL>(A, blockIdx.x, red, vec, blk);
+  move_wide_body<Real, G, CH, FAM, TL>(A, xcd_particle((int)blockIdx.x, (int)gridDim.x), red, vec, blk);
 }
 
 template <typename Real, int G, int CH, int FAM, int TL>
@@ -563,7 +563,8 @@ __global__ void __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(kMov
   extern __shared__ int32_t blk[];
   const int k = batch_member(B.first, B.count, blockIdx.x);
   const MoveArgs A = B.args[k];
-  move_wide_body<Real, G, CH, FAM, TL>(A, blockIdx.x - B.first[k], red, vec, blk);
+  move_wide_body<Real, G, CH, FAM, TL>(A, xcd_particle((int)blockIdx.x - B.first[k], B.first[k + 1] - B.first[k]),
+                                       red, vec, blk);
 }
 
 }  // namespace subsmc
