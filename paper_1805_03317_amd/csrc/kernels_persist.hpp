@@ -40,7 +40,10 @@ struct PersistArgs {
 };
 
 // Body kinds of the launch's list: narrow (padded d), lane-group (lanes, chunk,
-// tile form) and resident (padded d, register rows per lane).
+// tile form) and resident (padded d, register rows per lane). Each body is a
+// function of its own (not inlined into the kernel), so that its registers are
+// allocated as in its own kernel: inlined together, the bodies' live ranges
+// made the allocator spill some 1,800 values per lane.
 template <int DC>
 struct NarrowBody {};
 template <int G, int CH, int TL>
@@ -51,7 +54,7 @@ template <typename... B>
 struct BodyList {};
 
 template <typename Real, int FAM, int DC>
-__device__ __forceinline__ void run_body(NarrowBody<DC>, const PersistMember& Mb, int j, char* smem) {
+__device__ __noinline__ void run_body(NarrowBody<DC>, const PersistMember& Mb, int j, char* smem) {
   const int wave = (int)threadIdx.x / kWave;
   const MoveArgs A = Mb.A;
   char* base = smem + wave * Mb.wave_lds;
@@ -61,7 +64,7 @@ __device__ __forceinline__ void run_body(NarrowBody<DC>, const PersistMember& Mb
 }
 
 template <typename Real, int FAM, int G, int CH, int TL>
-__device__ __forceinline__ void run_body(WideBody<G, CH, TL>, const PersistMember& Mb, int j, char* smem) {
+__device__ __noinline__ void run_body(WideBody<G, CH, TL>, const PersistMember& Mb, int j, char* smem) {
   const int wave = (int)threadIdx.x / kWave;
   const MoveArgs A = Mb.A;
   char* base = smem + wave * Mb.wave_lds;
@@ -72,7 +75,7 @@ __device__ __forceinline__ void run_body(WideBody<G, CH, TL>, const PersistMembe
 }
 
 template <typename Real, int FAM, int DC, int RPL>
-__device__ __forceinline__ void run_body(ResBody<DC, RPL>, const PersistMember& Mb, int j, char*) {
+__device__ __noinline__ void run_body(ResBody<DC, RPL>, const PersistMember& Mb, int j, char*) {
   const MoveArgs A = Mb.A;
   const ResLayout Ly = Mb.Ly;
   move_res_body<Real, DC, FAM, RPL, 0>(A, Ly, j);
