@@ -289,7 +289,6 @@ __device__ __forceinline__ void resident_accumulate_mfma(const Prob& P, const Re
                                                          char* lrows, int nlds, const float* row0, const float* dsh,
                                                          int tid, double& se, double& se2, float (&S1)[DC],
                                                          float (&T1)[DC], double& shift) {
-  const int m = P.m;
   const float inv_s2 = (float)P.inv_s2;
   float dl[DC];
 #pragma unroll
