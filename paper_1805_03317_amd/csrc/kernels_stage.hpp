@@ -530,12 +530,14 @@ __device__ void factor_spd(const FactorArgs& F, double* sh) {
   (void)sh;
 }
 
-// The same factorisation with the matrices in LDS (d <= kFactorLdsMaxD):
+// The same factorisation with the factor in LDS (d <= kFactorLdsLMaxD):
 // left-looking by columns, L[r][j] = (S[r][j] - sum_{k<j} L[r][k] L[j][k]) /
 // L[j][j] with the subtractions in the order of the right-looking update
 // above, so the factor is the same; then the inverse by the same column-wise
-// forward substitution. Ls and Li are d*d doubles of LDS each.
-constexpr int kFactorLdsMaxD = 64;
+// forward substitution. Ls is d*d doubles of LDS; Li is d*d doubles of LDS
+// (d <= kFactorLdsMaxD) or F.Linv itself (the inverse written in place).
+constexpr int kFactorLdsMaxD = 64;    // factor and inverse in LDS
+constexpr int kFactorLdsLMaxD = 128;  // the factor in LDS, the inverse in global memory
 
 __device__ void factor_spd_lds(const FactorArgs& F, double* Ls, double* Li) {
   __shared__ int good_flag;
@@ -552,28 +554,36 @@ __device__ void factor_spd_lds(const FactorArgs& F, double* Ls, double* Li) {
       Ls[e] = F.S[e] + (r == c ? jit : 0.0);
     }
     __syncthreads();
-    // the columns by wavefront 0 alone (row t in lane t, d <= 64), so the
-    // steps of a column synchronise one wavefront only
+    // the columns by wavefront 0 alone (rows t and t + 64 in lane t, d <=
+    // 128), so the steps of a column synchronise one wavefront only
     if (t < kWave) {
       bool good = true;
       for (int j = 0; j < d; ++j) {
-        double sj = 0.0;
+        double sj0 = 0.0, sj1 = 0.0;
+        const int r1 = t + kWave;
         if (t >= j && t < d) {
-          sj = Ls[t * d + j];
+          sj0 = Ls[t * d + j];
 #pragma unroll 8
-          for (int k = 0; k < j; ++k) sj -= Ls[t * d + k] * Ls[j * d + k];
+          for (int k = 0; k < j; ++k) sj0 -= Ls[t * d + k] * Ls[j * d + k];
+        }
+        if (r1 >= j && r1 < d) {
+          sj1 = Ls[r1 * d + j];
+#pragma unroll 8
+          for (int k = 0; k < j; ++k) sj1 -= Ls[r1 * d + k] * Ls[j * d + k];
         }
         // row j's entries left of the diagonal are final; nobody reads (j, j) now
-        if (t == j) Ls[j * d + j] = sj;
+        if (t == j) Ls[j * d + j] = sj0;
+        if (r1 == j) Ls[j * d + j] = sj1;
         wave_lds_sync();
         const double p = Ls[j * d + j];
         good = p > 0.0;
         if (!good) break;  // the same value in every lane
         const double ljj = sqrt(p);
-        if (t > j && t < d) Ls[t * d + j] = sj / ljj;
+        if (t > j && t < d) Ls[t * d + j] = sj0 / ljj;
+        if (r1 > j && r1 < d) Ls[r1 * d + j] = sj1 / ljj;
         wave_lds_sync();
         // (j, j) is read again only after the loop
-        if (t == j) Ls[j * d + j] = ljj;
+        if (t == j || r1 == j) Ls[j * d + j] = ljj;
       }
       if (t == 0) good_flag = good ? 1 : 0;
     }
@@ -598,15 +608,21 @@ __device__ void factor_spd_lds(const FactorArgs& F, double* Ls, double* Li) {
   for (int e = t; e < d * d; e += kMomThreads) {
     const int r = e / d, c = e % d;
     F.L[e] = c > r ? 0.0 : Ls[e];
-    F.Linv[e] = Li[e];
+    if (Li != F.Linv) F.Linv[e] = Li[e];
   }
   if (t == 0) F.status[0] = ok ? 0.0 : 1.0;
 }
 
+// dynamic LDS bytes of factor_kernel for dimension d (host side too)
+__host__ __device__ inline size_t factor_lds_bytes(int d) {
+  return d <= kFactorLdsMaxD ? (size_t)2 * d * d * 8 : (d <= kFactorLdsLMaxD ? (size_t)d * d * 8 : 0);
+}
+
 __global__ void __launch_bounds__(kMomThreads) factor_kernel(FactorArgs F) {
   __shared__ double sh[kMomThreads / kWave];
-  extern __shared__ double fl[];  // 2 d*d when d <= kFactorLdsMaxD
+  extern __shared__ double fl[];  // factor_lds_bytes(d)
   if (F.d <= kFactorLdsMaxD) factor_spd_lds(F, fl, fl + F.d * F.d);
+  else if (F.d <= kFactorLdsLMaxD) factor_spd_lds(F, fl, F.Linv);
   else factor_spd(F, sh);
 }
 
@@ -673,7 +689,7 @@ __device__ __forceinline__ void moments_partial_body(const MomentArgs& A, const 
 
 __device__ __forceinline__ void moments_final_body(const MomentArgs& A) {
   __shared__ double sh[kMomThreads / kWave];
-  extern __shared__ double tot[];  // d + d(d+1)/2, then 2 d*d when d <= kFactorLdsMaxD
+  extern __shared__ double tot[];  // d + d(d+1)/2 (moments_final_lds), then the factor's LDS
   const int t = threadIdx.x;
   const int d = A.d;
   const int ne = d + d * (d + 1) / 2;
@@ -695,6 +711,9 @@ __device__ __forceinline__ void moments_final_body(const MomentArgs& A) {
   if (d <= kFactorLdsMaxD) {
     double* Ls = tot + ne;
     factor_spd_lds(A.F, Ls, Ls + d * d);
+  } else if (d <= kFactorLdsLMaxD) {
+    // the moments are in A.F.S now: the factor takes their LDS
+    factor_spd_lds(A.F, tot, A.F.Linv);
   } else {
     factor_spd(A.F, sh);
   }

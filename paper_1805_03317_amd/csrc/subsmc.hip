@@ -532,7 +532,7 @@ smc_status factor_device(smc_ctx c, double* S, double* L, double* Linv) {
   f.L = L;
   f.Linv = Linv;
   f.status = c->at<double>(c->lay.status);
-  const size_t flds = (c->pb.d <= kFactorLdsMaxD) ? (size_t)2 * c->pb.d * c->pb.d * 8 : 0;
+  const size_t flds = factor_lds_bytes(c->pb.d);
   HIP_TRY(c, hipFuncSetAttribute(reinterpret_cast<const void*>(factor_kernel),
                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)flds));
   hipLaunchKernelGGL(factor_kernel, dim3(1), dim3(kMomThreads), flds, c->stream, f);
@@ -637,7 +637,9 @@ MomentArgs moment_args(smc_ctx c, double* status) {
 
 size_t moments_partial_lds(int d) { return (size_t)kMomTile * d * 8; }
 size_t moments_final_lds(int d) {
-  return (size_t)(d + d * (d + 1) / 2) * 8 + (d <= kFactorLdsMaxD ? (size_t)2 * d * d * 8 : 0);
+  const size_t mom = (size_t)(d + d * (d + 1) / 2) * 8;
+  // d <= kFactorLdsMaxD: the factor after the moments; up to kFactorLdsLMaxD: over them
+  return d <= kFactorLdsMaxD ? mom + factor_lds_bytes(d) : std::max(mom, factor_lds_bytes(d));
 }
 
 ResampleArgs resample_args(smc_ctx c, int multinomial) {
