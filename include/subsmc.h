@@ -278,7 +278,7 @@ smc_status loglik_lambda(smc_ctx ctx, int32_t count, const double* theta, const 
 /*
  * Picks the move kernel by measurement: times one move (after an untimed
  * one) of every option the problem's move_path allows — the streaming kernel
- * (for FP32 logistic rows with d > 32 in both tile forms of its row loop,
+ * (for FP32 logistic rows with d > 32 in each tile form of its row loop,
  * smc_info.stream_tile) and each resident layout that fits (register rows per
  * lane; for FP32 rows each with x'delta on the vector ALU and on the matrix
  * cores) — from the
@@ -288,7 +288,7 @@ smc_status loglik_lambda(smc_ctx ctx, int32_t count, const double* theta, const 
  * choice: -1 streaming, else the register rows per lane of the resident
  * kernel (smc_info.res_mfma tells the form of the product); ms_out (nullable,
  * up to 8 entries) the timed durations in the order streaming (when allowed,
- * tile forms 0 then 1), then the resident layouts by register rows, the
+ * tile forms 0, 1, 2), then the resident layouts by register rows, the
  * vector form before the matrix-core form. Needs a mass matrix.
  * Uses the resampling buffers of the workspace. Synchronises.
  */
@@ -297,7 +297,7 @@ smc_status smc_autotune_move(smc_ctx ctx, double eps, int32_t L, int32_t* rpl_ou
 /*
  * Sets the move kernel directly (a choice smc_autotune_move made on an
  * earlier run, or a test): res_rows = -1 selects the streaming move with tile
- * form stream_tile (0 or 1, where smc_info documents both), else the resident
+ * form stream_tile (0, 1 or 2, where smc_info documents them), else the resident
  * move with res_rows register rows per lane and x'delta on the matrix cores
  * when res_mfma = 1. SMC_ERR_UNSUPPORTED when the option does not exist or
  * does not fit this problem and device, or the problem's move_path excludes it.
@@ -331,8 +331,12 @@ typedef struct smc_info {
   int32_t res_mfma;   /* resident move: 1 when x'delta is formed on the matrix cores
                          (v_mfma_f32_4x4x1f32), 0 on the vector ALU */
   int32_t stream_tile; /* lane-group streaming move (d > 32): the tile form of its row loop,
-                          0 (default: FP32 logistic rows evaluate each row's remainder once,
-                          in one lane of the row's group) or 1 (in every lane of the group) */
+                          0 (FP32 logistic rows evaluate each row's remainder once, in one
+                          lane of the row's group), 1 (in every lane of the group) or 2
+                          (form 0 with 4 consecutive particles per workgroup whose row steps
+                          meet at a barrier, so that resampled copies, which share their
+                          subsample, read each row at the same time; offered when 4 divides
+                          M). Default: 2 for FP32 logistic rows with d > 60, else 0 */
 } smc_info;
 smc_status smc_get_info(smc_ctx ctx, smc_info* out);
 

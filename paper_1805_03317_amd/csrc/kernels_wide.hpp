@@ -58,7 +58,12 @@ constexpr bool wide_one_remainder_per_lane() {
   return sizeof(Real) == 4 && FAM == kLogistic && (G == 4 || G == 8) && TL == 0;
 }
 
-template <typename Real, int G, int CH, int FAM, bool BLK, int TL = 0>
+// SYNC: the caller runs several particles in one workgroup (one per wavefront)
+// and the wavefronts meet at a workgroup barrier before every row step (every
+// wavefront of the workgroup takes the same number of steps: same m), so that
+// the copies of a resampled particle, which read the same rows, read them at
+// the same time (the second read then hits the L2 or merges with the first).
+template <typename Real, int G, int CH, int FAM, bool BLK, int TL = 0, bool SYNC = false>
 __device__ __forceinline__ PassResultW<wide_nc<G>()> estimator_pass_wide(const Prob& P, const int32_t* __restrict__ urow,
                                                            int b0, int b1, const int32_t* blk, Real* red,
                                                            const double* vec /* LDS: delta, d values */,
@@ -217,10 +222,15 @@ __device__ __forceinline__ PassResultW<wide_nc<G>()> estimator_pass_wide(const P
       for (int s = 0; s < PT; ++s) kf[s] = kg[s];
     };
     for (int step = 0; step < nsteps; step += 2) {
+      if constexpr (SYNC) __builtin_amdgcn_s_barrier();
       step_on(xa, ka, step);
-      if (step + 1 < nsteps) step_on(xb, kb, step + 1);
+      if (step + 1 < nsteps) {
+        if constexpr (SYNC) __builtin_amdgcn_s_barrier();
+        step_on(xb, kb, step + 1);
+      }
     }
   } else {
+    static_assert(!SYNC, "the row steps are synchronised in the one-remainder-per-lane form only");
     // PD iterations per step, their chunks in xb, each refilled with the next
     // step's row as soon as it has been used.
     constexpr int PD = 2;
@@ -387,7 +397,7 @@ __device__ __forceinline__ void matvec_wide(const double* __restrict__ Mx, const
 // One particle's move on one wavefront. red (kWave * CH values), vec (128
 // doubles) and blk (the refreshed block's indices, ceil(m / G) values) are LDS of
 // this wavefront's own.
-template <typename Real, int G, int CH, int FAM, int TL>
+template <typename Real, int G, int CH, int FAM, int TL, bool SYNC = false>
 __device__ __forceinline__ void move_wide_body(const MoveArgs& A, const int i, Real* red, double* vec,
                                                int32_t* blk) {
   const int lane = wave_lane();
@@ -425,7 +435,7 @@ __device__ __forceinline__ void move_wide_body(const MoveArgs& A, const int i, R
 #pragma unroll
     for (int s = 0; s < NC; ++s) dl[s] = th[s] - tb[s];
     to_lds(vec, dl, lane, d);  // also fences the block indices
-    const auto r = estimator_pass_wide<Real, G, CH, FAM, true, TL>(P, urow, b0, b1, blk, red, vec, lane);
+    const auto r = estimator_pass_wide<Real, G, CH, FAM, true, TL, SYNC>(P, urow, b0, b1, blk, red, vec, lane);
     const double lam0 = a * lh0 - 0.5 * a * a * sg0;
     const double lam1 = a * r.lhat - 0.5 * a * a * r.sig2;
     const double logr = lam1 - lam0;
@@ -508,7 +518,7 @@ __device__ __forceinline__ void move_wide_body(const MoveArgs& A, const int i, R
       dl[s] = th1[s] - tb[s];
     }
     to_lds(vec, dl, lane, d);
-    const auto r = estimator_pass_wide<Real, G, CH, FAM, true, TL>(P, urow, ob0, ob1, blk, red, vec, lane);
+    const auto r = estimator_pass_wide<Real, G, CH, FAM, true, TL, SYNC>(P, urow, ob0, ob1, blk, red, vec, lane);
     lh1 = r.lhat;
     sg1 = r.sig2;
     lp1 = prior(th1, rq);
@@ -554,6 +564,30 @@ __global__ void __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(kMov
   __shared__ double vec[128];
   extern __shared__ int32_t blk[];
   move_wide_body<Real, G, CH, FAM, TL>(A, xcd_particle((int)blockIdx.x, (int)gridDim.x), red, vec, blk);
+}
+
+// The lane-group move of FP32 logistic rows (the one-remainder-per-lane form)
+// with kWideGroup consecutive particles per workgroup, one per wavefront, each
+// with an LDS slice of its own of wide_group_wave_lds bytes, their row steps
+// held together by a barrier (estimator_pass_wide, SYNC). The launch covers
+// the particles exactly (gridDim.x * kWideGroup == M), so every wavefront has a
+// particle and takes the same number of barriers.
+constexpr int kWideGroup = 4;
+
+__host__ __device__ inline int wide_group_wave_lds(int ch, int real_bytes, int block_bytes) {
+  return ((kWave * ch * real_bytes + 15) & ~15) + 128 * 8 + ((block_bytes + 15) & ~15);
+}
+
+template <typename Real, int G, int CH, int FAM, int TL>
+__global__ void __launch_bounds__(kWave * kWideGroup) __attribute__((amdgpu_waves_per_eu(kMoveWaves<Real>)))
+move_kernel_wide_group(MoveArgs A, int wave_lds) {
+  extern __shared__ __attribute__((aligned(16))) char gsm[];
+  const int wave = (int)threadIdx.x / kWave;
+  char* base = gsm + wave * wave_lds;
+  constexpr int kRed = (kWave * CH * (int)sizeof(Real) + 15) & ~15;
+  const int i = kWideGroup * xcd_particle((int)blockIdx.x, (int)gridDim.x) + wave;
+  move_wide_body<Real, G, CH, FAM, TL, true>(A, i, reinterpret_cast<Real*>(base), reinterpret_cast<double*>(base + kRed),
+                                             reinterpret_cast<int32_t*>(base + kRed + 128 * 8));
 }
 
 template <typename Real, int G, int CH, int FAM, int TL>

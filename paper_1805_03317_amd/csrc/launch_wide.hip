@@ -27,7 +27,8 @@ hipError_t by_wide(const KernelShape& s, F&& f) {
   return hipErrorInvalidValue;
 }
 
-// f(real, family, lanes, ch, tile) for an instantiated shape; `tiles` allows tile form 1
+// f(real, family, lanes, ch, tile) for an instantiated shape; `tiles` allows
+// tile forms 1 and 2 (2: form 0 with kWideGroup particles per workgroup)
 template <typename F>
 hipError_t wide_dispatch(const KernelShape& s, bool tiles, F&& f) {
   auto go = [&](auto real) -> hipError_t {
@@ -38,6 +39,7 @@ hipError_t wide_dispatch(const KernelShape& s, bool tiles, F&& f) {
         if (s.tile == 0) return f(real, fam, g, ch, IntC<0>{});
         if constexpr (two) {
           if (tiles && s.tile == 1) return f(real, fam, g, ch, IntC<1>{});
+          if (tiles && s.tile == 2) return f(real, fam, g, ch, IntC<2>{});
         }
         return hipErrorInvalidValue;
       });
@@ -68,9 +70,18 @@ hipError_t launch_estimator_wide(const KernelShape& s, int grid, const EstArgs& 
 hipError_t launch_move_wide(const KernelShape& s, int grid, size_t lds, const MoveArgs& a, hipStream_t st) {
   return wide_dispatch(s, true, [&](auto real, auto fam, auto g, auto ch, auto tl) {
     using Real = decltype(real);
-    hipLaunchKernelGGL((move_kernel_wide<Real, decltype(g)::value, decltype(ch)::value, decltype(fam)::value,
-                                         decltype(tl)::value>),
-                       dim3(grid), dim3(kWave), lds, st, a);
+    constexpr int G = decltype(g)::value, CH = decltype(ch)::value, FAM = decltype(fam)::value;
+    if constexpr (decltype(tl)::value == 2) {
+      // grid particles, kWideGroup to a workgroup (the host offers form 2 only
+      // when they divide the particle count)
+      if (grid % kWideGroup != 0) return hipErrorInvalidValue;
+      const int wave_lds = wide_group_wave_lds(CH, (int)sizeof(Real), (int)lds);
+      hipLaunchKernelGGL((move_kernel_wide_group<Real, G, CH, FAM, 0>), dim3(grid / kWideGroup),
+                         dim3(kWave * kWideGroup), (size_t)wave_lds * kWideGroup, st, a, wave_lds);
+    } else {
+      hipLaunchKernelGGL((move_kernel_wide<Real, G, CH, FAM, decltype(tl)::value>), dim3(grid), dim3(kWave), lds, st,
+                         a);
+    }
     return hipGetLastError();
   });
 }
@@ -79,9 +90,10 @@ hipError_t launch_move_wide_batch(const KernelShape& s, int grid, size_t lds, co
                                   hipStream_t st) {
   return wide_dispatch(s, true, [&](auto real, auto fam, auto g, auto ch, auto tl) {
     using Real = decltype(real);
+    // (form 2 is form 0 with grouped particles; batch launches take form 0)
+    constexpr int TL = decltype(tl)::value == 2 ? 0 : decltype(tl)::value;
     hipLaunchKernelGGL(
-        (move_kernel_wide_batch<Real, decltype(g)::value, decltype(ch)::value, decltype(fam)::value,
-                                decltype(tl)::value>),
+        (move_kernel_wide_batch<Real, decltype(g)::value, decltype(ch)::value, decltype(fam)::value, TL>),
         dim3(grid), dim3(kWave), lds, st, b);
     return hipGetLastError();
   });

@@ -268,10 +268,23 @@ struct ResOption {
 };
 
 // tile forms of the lane-group streaming move for a problem (see launch_wide.hip)
+// Tile forms of the lane-group move for this problem: 0 always; for FP32
+// logistic rows also 1 (the remainder in every lane) and, when kWideGroup
+// divides the particle count, 2 (form 0 with kWideGroup particles per
+// workgroup, their row steps held together).
 int wide_tiles(const smc_problem& pb) {
   if (pb.d <= kMaxNarrowD) return 1;
   const WideShape w = wide_shape(pb.d, pb.precision == SMC_MIXED);
-  return (pb.precision == SMC_MIXED && pb.family == SMC_LOGISTIC && (w.G == 4 || w.G == 8)) ? 2 : 1;
+  if (!(pb.precision == SMC_MIXED && pb.family == SMC_LOGISTIC && (w.G == 4 || w.G == 8))) return 1;
+  return pb.M % kWideGroup == 0 ? 3 : 2;
+}
+
+// The default tile form: 2 for rows of 8-lane groups (d > 60; measured on the
+// d = 116 configuration's live stages 288 -> 228 ms, where resampled copies
+// share their rows), else 0 (d = 50: 34.8 ms against 36.9 with form 2).
+int default_wide_tile(const smc_problem& pb) {
+  const WideShape w = wide_shape(pb.d, pb.precision == SMC_MIXED);
+  return (wide_tiles(pb) == 3 && w.G == 8) ? 2 : 0;
 }
 
 // Every register-row count whose layout fits, smallest first, each FP32 one
@@ -326,6 +339,13 @@ KernelShape move_shape(smc_ctx c) {
   s.mf = c->res_rpl >= 0 ? c->res_mf : 0;
   s.kind = c->res_rpl >= 0 ? kMoveResident : (c->pb.d > kMaxNarrowD ? kMoveWide : kMoveNarrow);
   s.tile = s.kind == kMoveWide ? c->wide_tile : 0;
+  return s;
+}
+
+// A batch member's shape: tile form 2 (grouped particles) is form 0 in batch launches
+KernelShape member_shape(smc_ctx c) {
+  KernelShape s = move_shape(c);
+  if (s.tile == 2) s.tile = 0;
   return s;
 }
 
@@ -753,6 +773,7 @@ smc_status smc_init(const smc_problem* pb, void* stream, smc_ctx* out) {
       return fail(c, SMC_ERR_UNSUPPORTED, "resident move kernel does not apply to this problem");
     }
   }
+  c->wide_tile = default_wide_tile(*pb);
   c->mu0.assign(pb->prior_mean, pb->prior_mean + d);
   c->Q0.assign(pb->prior_prec, pb->prior_prec + (size_t)d * d);
   c->pb.theta_bar = nullptr;  // host pointer not kept
@@ -1654,11 +1675,11 @@ constexpr size_t kPersistLdsF64 = 156 * 1024;
 // the streaming form of a member's move (its kernel when the resident layout
 // does not apply)
 KernelShape stream_shape(smc_ctx c) {
-  KernelShape s = move_shape(c);
+  KernelShape s = member_shape(c);
   s.kind = c->pb.d > kMaxNarrowD ? kMoveWide : kMoveNarrow;
   s.rpl = -1;
   s.mf = 0;
-  s.tile = s.kind == kMoveWide ? c->wide_tile : 0;
+  s.tile = s.kind == kMoveWide && c->wide_tile != 2 ? c->wide_tile : 0;
   return s;
 }
 
@@ -1677,7 +1698,7 @@ smc_status batch_move_persistent(smc_batch b, const double* eps, int32_t L, int3
   b->member_launch.assign(b->ctx.size(), -1);
   for (int k : b->active) {
     smc_ctx c = b->ctx[k];
-    KernelShape s = move_shape(c);
+    KernelShape s = member_shape(c);
     const size_t cap = s.fp32 ? kPersistLdsF32 : kPersistLdsF64;
     int body = -1;
     if (s.kind == kMoveResident && (size_t)c->res_ly.total <= cap) body = persist_body(s);
@@ -2003,7 +2024,7 @@ smc_status smc_batch_move(smc_batch b, const double* eps, int32_t L, int32_t R) 
   std::map<KernelShape, std::vector<int>> groups;
   b->member_kind.assign(b->ctx.size(), -1);
   for (int k : b->active) {
-    const KernelShape s = move_shape(b->ctx[k]);
+    const KernelShape s = member_shape(b->ctx[k]);
     groups[s].push_back(k);
     b->member_kind[k] = s.kind;
   }
@@ -2227,7 +2248,7 @@ int32_t smc_batch_launches(smc_batch b) {
   if (!b || !b->have_stage) return 0;
   std::map<KernelShape, int> groups;
   for (int k : b->active) {
-    KernelShape s = move_shape(b->ctx[k]);
+    KernelShape s = member_shape(b->ctx[k]);
     if (b->persistent) s = KernelShape{kMovePersistent, s.fp32, s.fam, 0, 0, 0, 0, 0, 0};
     groups[s] += 1;
   }

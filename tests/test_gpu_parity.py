@@ -510,11 +510,63 @@ def test_move_parity_mfma(name, spread):
 
 @pytest.mark.parametrize("name", ["logistic_mixed_d116", "logistic_mixed_cfg4_shape", "logistic_mixed_cfg5_shape"])
 def test_move_parity_stream_tiles(name):
-    """Both tile forms of the lane-group move's row loop for FP32 logistic rows: each row's
-    remainder evaluated in one lane of its group (form 0) or in every lane (form 1)."""
+    """Every tile form of the lane-group move's row loop for FP32 logistic rows: each row's
+    remainder evaluated in one lane of its group (form 0), in every lane (form 1), and form 0
+    with four consecutive particles per workgroup held to the same row step (form 2, offered when
+    four divides M)."""
     _, mk, a, eps = next(c for c in MOVE_CASES if c[0] == name)
-    for tile in (0, 1):
-        _check_move(name, mk(), a, eps, 0.02, 1, 2, tile=tile)
+    w = mk()
+    for tile in (0, 1) + ((2,) if w.M % 4 == 0 else ()):
+        _check_move(name, w, a, eps, 0.02, 1, 2, tile=tile)
+
+
+@pytest.mark.parametrize("name", ["logistic_mixed_d116", "logistic_mixed_cfg5_shape"])
+def test_grouped_tile_form_equals_form_0(name):
+    """Tile form 2 runs form 0's arithmetic for each particle (only the workgroup a particle
+    runs in and the barriers between row steps differ): one move from the same state gives the
+    same theta, u, accept flags, decision record and caches, bit for bit, with copies among the
+    particles (duplicated rows of theta and u, as after resampling)."""
+    _, mk, a, eps = next(c for c in MOVE_CASES if c[0] == name)
+    w = mk()
+    assert w.M % 4 == 0
+    P, smc = make_pair(w, move_path=1)
+    say("default tile form", smc.info()["stream_tile"])
+    assert smc.info()["stream_tile"] == 2          # d > 60, 4 divides M: the grouped form
+    thp, u0, _ = oracle.init_particles(w.M, w.d, w.m, w.n, w.seed, w.prior_mean, w.prior_prec)
+    th0 = P.theta_bar + 0.02 * (thp - w.prior_mean)
+    anc = np.repeat(np.arange(w.M), 2)[: w.M]      # every particle copied once
+    th0, u0 = th0[anc], u0[anc]
+    Sig, _ = laplace_mass(P, w, a)
+    out = []
+    for tile in (0, 2):
+        smc.set_move_option(-1, 0, tile)
+        smc.theta.copy_(torch.tensor(th0))
+        smc.u.copy_(torch.tensor(u0))
+        smc.refresh()
+        smc.set_mass(Sig)
+        smc.set_stage(3, 1, a)
+        smc.move(eps, w.L, 1)
+        torch.cuda.synchronize()
+        out.append([x.cpu().numpy().copy() for x in (smc.theta, smc.u, smc.accept, smc.lhat, smc.sig2)]
+                   + [smc.move_diag().copy()])
+    for x0, x2 in zip(*out):
+        np.testing.assert_array_equal(x0, x2)
+    smc.close()
+
+
+def test_default_tile_forms():
+    """The default tile form: 2 for FP32 logistic rows with d > 60 when four divides M, else 0."""
+    B = _binding()
+    for d, M, want in ((116, 16, 2), (116, 6, 0), (50, 16, 0)):
+        w = W.logistic_small(3000, d, seed=3, precision=W.MIXED, M=M, m=64, G=4)
+        Xy = torch.tensor(w.Xy(np.float32), device=DEV)
+        smc = B.SubsampledSMC(Xy, w.d, w.family, W.MIXED, w.M, w.m, w.G, w.prior_mean, w.prior_prec, w.seed,
+                              theta_bar=np.zeros(w.d), move_path=1)
+        assert smc.info()["stream_tile"] == want, (d, M)
+        if want == 0 and d == 116:
+            with pytest.raises(B.SMCError):
+                smc.set_move_option(-1, 0, 2)
+        smc.close()
 
 
 @pytest.mark.parametrize("path", [1, 0], ids=["streaming", "auto"])
