@@ -230,6 +230,7 @@ _COMMON_SOURCES = ["kernels.hpp", "xlane.hpp", "glm.hpp", "rng.hpp"]
 DEVICE_SOURCES = {
     "move_kernel": _COMMON_SOURCES,
     "move_kernel_wide": _COMMON_SOURCES + ["kernels_wide.hpp"],
+    "move_kernel_wide_group": _COMMON_SOURCES + ["kernels_wide.hpp"],
     "move_kernel_res": _COMMON_SOURCES + ["kernels_resident.hpp"],
     "move_kernel_persist": _COMMON_SOURCES + ["kernels_wide.hpp", "kernels_resident.hpp", "kernels_persist.hpp",
                                               "launch_persist.hpp"],
@@ -245,10 +246,13 @@ def device_source_hash(kernel):
     return h.hexdigest()[:16]
 
 
-def move_kernel_name(w, move_path):
+def move_kernel_name(w, move_path, stream_tile=0):
     if move_path == MOVE_RESIDENT:
         return "move_kernel_res"
-    return "move_kernel_wide" if w.d > 32 else "move_kernel"
+    if w.d <= 32:
+        return "move_kernel"
+    # tile form 2: the lane-group move with four particles per workgroup
+    return "move_kernel_wide_group" if stream_tile == 2 else "move_kernel_wide"
 
 
 def measured_traffic(w, precision, kernel):
@@ -268,13 +272,13 @@ def measured_traffic(w, precision, kernel):
     return float(kv["traffic_bytes_per_launch"])
 
 
-def roofline(w, fp32, move_ms, move_path):
+def roofline(w, fp32, move_ms, move_path, stream_tile=0):
     """The move kernel against its bound. The streaming kernels re-read every
     row on every pass and are bounded by memory bandwidth; the resident kernel
     gathers the rows once per move and keeps them on chip, so its passes are
     bounded by the vector ALU."""
     evals = w.M * w.m * (w.L + 1)
-    kernel = move_kernel_name(w, move_path)
+    kernel = move_kernel_name(w, move_path, stream_tile)
     traffic = measured_traffic(w, "mixed" if fp32 else "fp64", kernel)
     if move_path == MOVE_RESIDENT:
         fpe = algorithmic_flops_per_eval(w.d)
@@ -611,7 +615,7 @@ def bench_workload(name, args, cpu, e2e):
         "config": {"workload": w.name, "n": w.n, "d": w.d, "M": w.M, "m": w.m, "G": w.G, "L": w.L,
                    "R": 1, "eps": eps, "precision": head, "step": "temper+mass+resample+move",
                    "schemes": args.schemes, "recentre": bool(args.recentre), "cv_order": args.cv_order},
-        "roofline": roofline(w, head == "mixed", r["move_ms"], r["move_path"]),
+        "roofline": roofline(w, head == "mixed", r["move_ms"], r["move_path"], r.get("stream_tile", 0)),
         "move_ms": r["move_ms"],
         "move_evals_per_s": r["move_evals_per_s"],
         "run": {k: r[k] for k in ("a", "stage", "stages_tempered", "accept_u", "accept_theta", "newton_iters",
@@ -621,7 +625,7 @@ def bench_workload(name, args, cpu, e2e):
     if "fp64" in results and head == "mixed":
         f = results["fp64"]
         out["fp64"] = {"value": f["evals_per_s"], "ms_per_step": f["ms_per_step"], "move_ms": f["move_ms"],
-                       "roofline": roofline(w, False, f["move_ms"], f["move_path"]),
+                       "roofline": roofline(w, False, f["move_ms"], f["move_path"], f.get("stream_tile", 0)),
                        "mixed_over_fp64": r["evals_per_s"] / f["evals_per_s"]}
         # error of the mixed path against the FP64 path on the same particles: l_hat (dominated by
         # the exact FP64 constant A), and its FP32-computed part d_hat = (n/m) sum_j d_j on its own
@@ -640,7 +644,7 @@ def bench_workload(name, args, cpu, e2e):
     # the move on the fixed benchmark state (a = 1, Laplace approximation) for the dominant path
     out["laplace_a1"] = laplace_state_move(ctxs[head], w, eps)
     out["laplace_a1"]["roofline"] = roofline(w, head == "mixed", out["laplace_a1"]["move_ms_median"],
-                                             r["move_path"])
+                                             r["move_path"], r.get("stream_tile", 0))
     if name in ("config1", "config2") and e2e:
         out["run_to_end"] = run_to_end(w, W.MIXED if head == "mixed" else W.FP64, Xy, eps, args.cv_order)
     for c in ctxs.values():
