@@ -335,8 +335,9 @@ typedef struct smc_info {
                           lane of the row's group), 1 (in every lane of the group) or 2
                           (form 0 with 4 consecutive particles per workgroup whose row steps
                           meet at a barrier, so that resampled copies, which share their
-                          subsample, read each row at the same time; offered when 4 divides
-                          M). Default: 2 for FP32 logistic rows with d > 60, else 0 */
+                          subsample, read each row at the same time; offered for every
+                          lane-group shape when 4 divides M). Form 1 exists for FP32 logistic
+                          rows only. Default: 2 for FP32 logistic rows with d > 60, else 0 */
 } smc_info;
 smc_status smc_get_info(smc_ctx ctx, smc_info* out);
 

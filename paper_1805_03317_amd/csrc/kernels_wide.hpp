@@ -230,7 +230,6 @@ __device__ __forceinline__ PassResultW<wide_nc<G>()> estimator_pass_wide(const P
       }
     }
   } else {
-    static_assert(!SYNC, "the row steps are synchronised in the one-remainder-per-lane form only");
     // PD iterations per step, their chunks in xb, each refilled with the next
     // step's row as soon as it has been used.
     constexpr int PD = 2;
@@ -244,6 +243,7 @@ __device__ __forceinline__ PassResultW<wide_nc<G>()> estimator_pass_wide(const P
 #pragma unroll
     for (int s = 0; s < PD; ++s) kn[s] = fetch_at(PD + s);
     for (int step = 0; step < nsteps; ++step) {
+      if constexpr (SYNC) __builtin_amdgcn_s_barrier();
       int32_t kf[PD];
 #pragma unroll
       for (int s = 0; s < PD; ++s) kf[s] = fetch_at(PD * (step + 2) + s);
@@ -566,8 +566,8 @@ __global__ void __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(kMov
   move_wide_body<Real, G, CH, FAM, TL>(A, xcd_particle((int)blockIdx.x, (int)gridDim.x), red, vec, blk);
 }
 
-// The lane-group move of FP32 logistic rows (the one-remainder-per-lane form)
-// with kWideGroup consecutive particles per workgroup, one per wavefront, each
+// The lane-group move (tile form 2: form 0's row loop) with kWideGroup
+// consecutive particles per workgroup, one per wavefront, each
 // with an LDS slice of its own of wide_group_wave_lds bytes, their row steps
 // held together by a barrier (estimator_pass_wide, SYNC). The launch covers
 // the particles exactly (gridDim.x * kWideGroup == M), so every wavefront has a

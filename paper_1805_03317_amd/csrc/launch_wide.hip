@@ -28,7 +28,8 @@ hipError_t by_wide(const KernelShape& s, F&& f) {
 }
 
 // f(real, family, lanes, ch, tile) for an instantiated shape; `tiles` allows
-// tile forms 1 and 2 (2: form 0 with kWideGroup particles per workgroup)
+// tile forms 1 (FP32 logistic rows) and 2 (form 0 with kWideGroup particles
+// per workgroup, every shape)
 template <typename F>
 hipError_t wide_dispatch(const KernelShape& s, bool tiles, F&& f) {
   auto go = [&](auto real) -> hipError_t {
@@ -37,9 +38,9 @@ hipError_t wide_dispatch(const KernelShape& s, bool tiles, F&& f) {
       return by_wide<Real>(s, [&](auto g, auto ch) -> hipError_t {
         constexpr bool two = wide_one_remainder_per_lane<Real, decltype(fam)::value, decltype(g)::value, 0>();
         if (s.tile == 0) return f(real, fam, g, ch, IntC<0>{});
+        if (tiles && s.tile == 2) return f(real, fam, g, ch, IntC<2>{});
         if constexpr (two) {
           if (tiles && s.tile == 1) return f(real, fam, g, ch, IntC<1>{});
-          if (tiles && s.tile == 2) return f(real, fam, g, ch, IntC<2>{});
         }
         return hipErrorInvalidValue;
       });

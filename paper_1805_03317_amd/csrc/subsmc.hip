@@ -268,23 +268,27 @@ struct ResOption {
 };
 
 // tile forms of the lane-group streaming move for a problem (see launch_wide.hip)
-// Tile forms of the lane-group move for this problem: 0 always; for FP32
-// logistic rows also 1 (the remainder in every lane) and, when kWideGroup
-// divides the particle count, 2 (form 0 with kWideGroup particles per
-// workgroup, their row steps held together).
-int wide_tiles(const smc_problem& pb) {
+// Tile forms of the lane-group move for this problem, as bits: form 0 always;
+// form 1 (the remainder in every lane) for FP32 logistic rows; form 2 (form 0
+// with kWideGroup particles per workgroup, their row steps held together) when
+// kWideGroup divides the particle count. The narrow move has form 0 only.
+int wide_forms(const smc_problem& pb) {
   if (pb.d <= kMaxNarrowD) return 1;
   const WideShape w = wide_shape(pb.d, pb.precision == SMC_MIXED);
-  if (!(pb.precision == SMC_MIXED && pb.family == SMC_LOGISTIC && (w.G == 4 || w.G == 8))) return 1;
-  return pb.M % kWideGroup == 0 ? 3 : 2;
+  int f = 1;
+  if (pb.precision == SMC_MIXED && pb.family == SMC_LOGISTIC && (w.G == 4 || w.G == 8)) f |= 2;
+  if (pb.M % kWideGroup == 0) f |= 4;
+  return f;
 }
 
-// The default tile form: 2 for rows of 8-lane groups (d > 60; measured on the
-// d = 116 configuration's live stages 288 -> 228 ms, where resampled copies
+bool wide_form_ok(const smc_problem& pb, int t) { return t >= 0 && t <= 2 && ((wide_forms(pb) >> t) & 1); }
+
+// The default tile form: 2 for FP32 logistic rows of 8-lane groups (d > 60; measured on
+// the d = 116 configuration's live stages 288 -> 228 ms, where resampled copies
 // share their rows), else 0 (d = 50: 34.8 ms against 36.9 with form 2).
 int default_wide_tile(const smc_problem& pb) {
   const WideShape w = wide_shape(pb.d, pb.precision == SMC_MIXED);
-  return (wide_tiles(pb) == 3 && w.G == 8) ? 2 : 0;
+  return (wide_form_ok(pb, 2) && w.G == 8 && pb.precision == SMC_MIXED && pb.family == SMC_LOGISTIC) ? 2 : 0;
 }
 
 // Every register-row count whose layout fits, smallest first, each FP32 one
@@ -1081,7 +1085,8 @@ smc_status smc_autotune_move(smc_ctx c, double eps, int32_t L, int32_t* rpl_out,
   // within the path the problem asked for
   std::vector<ResOption> opts;
   if (pb.move_path == SMC_MOVE_AUTO || pb.move_path == SMC_MOVE_STREAMING)
-    for (int t = 0; t < wide_tiles(pb); ++t) opts.push_back(ResOption{-1, 0, ResLayout{}, t});
+    for (int t = 0; t <= 2; ++t)
+      if (wide_form_ok(pb, t)) opts.push_back(ResOption{-1, 0, ResLayout{}, t});
   if (pb.move_path != SMC_MOVE_STREAMING) {
     int dev = 0, max_lds = 0;
     HIP_TRY(c, hipGetDevice(&dev));
@@ -1167,7 +1172,7 @@ smc_status smc_set_move_option(smc_ctx c, int32_t res_rows, int32_t res_mfma, in
   if (res_rows < 0) {
     if (pb.move_path == SMC_MOVE_RESIDENT || pb.move_path == SMC_MOVE_RESIDENT_MFMA)
       return fail(c, SMC_ERR_UNSUPPORTED, "the problem asks for the resident move");
-    if (stream_tile < 0 || stream_tile >= wide_tiles(pb))
+    if (!wide_form_ok(pb, stream_tile))
       return fail(c, SMC_ERR_UNSUPPORTED, "no tile form %d for this problem", stream_tile);
     c->res_rpl = -1;
     c->res_mf = 0;
@@ -1475,7 +1480,7 @@ smc_status smc_set_state(smc_ctx c, const void* blob, size_t bytes) {
   if (h.bytes != id.bytes || bytes < h.bytes) return fail(c, SMC_ERR_INVALID_ARG, "state blob size mismatch");
   if (h.stage < 0 || h.move < 0 || !(h.a >= 0.0 && h.a <= 1.0) || h.have_mass < 0 || h.have_mass > 1)
     return fail(c, SMC_ERR_INVALID_ARG, "state blob holds invalid counters");
-  if (h.wide_tile < 0 || h.wide_tile >= wide_tiles(c->pb))
+  if (!wide_form_ok(c->pb, h.wide_tile))
     return fail(c, SMC_ERR_INVALID_ARG, "state blob holds an unknown tile form");
   // the move kernel: streaming, or a resident layout that fits this device
   ResLayout ly{};

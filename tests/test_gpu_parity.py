@@ -520,18 +520,31 @@ def test_move_parity_stream_tiles(name):
         _check_move(name, w, a, eps, 0.02, 1, 2, tile=tile)
 
 
-@pytest.mark.parametrize("name", ["logistic_mixed_d116", "logistic_mixed_cfg5_shape"])
-def test_grouped_tile_form_equals_form_0(name):
+GROUPED_CASES = [
+    ("logistic_mixed_d116", None),
+    ("logistic_mixed_cfg5_shape", None),
+    ("logistic_fp64_d116", lambda: W.logistic_small(5000, 116, seed=16, M=16, m=211, G=4, L=6)),
+    ("poisson_mixed_d65", lambda: W.poisson_small(6000, 65, seed=23, precision=W.MIXED, M=12, m=180, G=6, L=5)),
+    ("student_mixed_d50", lambda: W.student_small(4000, 50, seed=24, precision=W.MIXED, M=8, m=150, G=5, L=5)),
+]
+
+
+@pytest.mark.parametrize("name,mk", GROUPED_CASES, ids=[c[0] for c in GROUPED_CASES])
+def test_grouped_tile_form_equals_form_0(name, mk):
     """Tile form 2 runs form 0's arithmetic for each particle (only the workgroup a particle
     runs in and the barriers between row steps differ): one move from the same state gives the
     same theta, u, accept flags, decision record and caches, bit for bit, with copies among the
-    particles (duplicated rows of theta and u, as after resampling)."""
-    _, mk, a, eps = next(c for c in MOVE_CASES if c[0] == name)
+    particles (duplicated rows of theta and u, as after resampling); FP32 logistic rows (form 0:
+    one remainder per lane) and the other lane-group shapes (FP64 rows, Poisson, Student-t: the
+    two-row loop)."""
+    if mk is None:
+        _, mk, a, eps = next(c for c in MOVE_CASES if c[0] == name)
+    else:
+        a, eps = 0.3, 0.1
     w = mk()
     assert w.M % 4 == 0
     P, smc = make_pair(w, move_path=1)
     say("default tile form", smc.info()["stream_tile"])
-    assert smc.info()["stream_tile"] == 2          # d > 60, 4 divides M: the grouped form
     thp, u0, _ = oracle.init_particles(w.M, w.d, w.m, w.n, w.seed, w.prior_mean, w.prior_prec)
     th0 = P.theta_bar + 0.02 * (thp - w.prior_mean)
     anc = np.repeat(np.arange(w.M), 2)[: w.M]      # every particle copied once
@@ -555,17 +568,25 @@ def test_grouped_tile_form_equals_form_0(name):
 
 
 def test_default_tile_forms():
-    """The default tile form: 2 for FP32 logistic rows with d > 60 when four divides M, else 0."""
+    """The default tile form: 2 for FP32 logistic rows with d > 60 when four divides M, else 0;
+    form 2 is offered for every lane-group shape when four divides M, form 1 for FP32 logistic
+    rows only."""
     B = _binding()
-    for d, M, want in ((116, 16, 2), (116, 6, 0), (50, 16, 0)):
-        w = W.logistic_small(3000, d, seed=3, precision=W.MIXED, M=M, m=64, G=4)
-        Xy = torch.tensor(w.Xy(np.float32), device=DEV)
-        smc = B.SubsampledSMC(Xy, w.d, w.family, W.MIXED, w.M, w.m, w.G, w.prior_mean, w.prior_prec, w.seed,
+    for d, M, prec, want, offered in ((116, 16, W.MIXED, 2, (0, 1, 2)), (116, 6, W.MIXED, 0, (0, 1)),
+                                      (50, 16, W.MIXED, 0, (0, 1, 2)), (116, 16, W.FP64, 0, (0, 2)),
+                                      (20, 16, W.MIXED, 0, (0,))):
+        w = W.logistic_small(3000, d, seed=3, precision=prec, M=M, m=64, G=4)
+        Xy = torch.tensor(w.Xy(np.float32 if prec == W.MIXED else np.float64), device=DEV)
+        smc = B.SubsampledSMC(Xy, w.d, w.family, prec, w.M, w.m, w.G, w.prior_mean, w.prior_prec, w.seed,
                               theta_bar=np.zeros(w.d), move_path=1)
-        assert smc.info()["stream_tile"] == want, (d, M)
-        if want == 0 and d == 116:
-            with pytest.raises(B.SMCError):
-                smc.set_move_option(-1, 0, 2)
+        assert smc.info()["stream_tile"] == want, (d, M, prec)
+        for tile in (0, 1, 2):
+            if tile in offered:
+                smc.set_move_option(-1, 0, tile)
+                assert smc.info()["stream_tile"] == tile
+            else:
+                with pytest.raises(B.SMCError):
+                    smc.set_move_option(-1, 0, tile)
         smc.close()
 
 
