@@ -59,8 +59,9 @@ constexpr bool wide_one_remainder_per_lane() {
 }
 
 // SYNC: the caller runs several particles in one workgroup (one per wavefront)
-// and the wavefronts meet at a workgroup barrier before every row step (every
-// wavefront of the workgroup takes the same number of steps: same m), so that
+// and the wavefronts meet at a workgroup barrier before every row step, or
+// every pair of steps where the loop takes them in pairs (every wavefront of
+// the workgroup takes the same number of steps: same m), so that
 // the copies of a resampled particle, which read the same rows, read them at
 // the same time (the second read then hits the L2 or merges with the first).
 template <typename Real, int G, int CH, int FAM, bool BLK, int TL = 0, bool SYNC = false>
@@ -224,10 +225,7 @@ __device__ __forceinline__ PassResultW<wide_nc<G>()> estimator_pass_wide(const P
     for (int step = 0; step < nsteps; step += 2) {
       if constexpr (SYNC) __builtin_amdgcn_s_barrier();
       step_on(xa, ka, step);
-      if (step + 1 < nsteps) {
-        if constexpr (SYNC) __builtin_amdgcn_s_barrier();
-        step_on(xb, kb, step + 1);
-      }
+      if (step + 1 < nsteps) step_on(xb, kb, step + 1);
     }
   } else {
     // PD iterations per step, their chunks in xb, each refilled with the next
