@@ -59,11 +59,13 @@ constexpr bool wide_one_remainder_per_lane() {
 }
 
 // SYNC: the caller runs several particles in one workgroup (one per wavefront)
-// and the wavefronts meet at a workgroup barrier before every row step, or
-// every pair of steps where the loop takes them in pairs (every wavefront of
-// the workgroup takes the same number of steps: same m), so that
-// the copies of a resampled particle, which read the same rows, read them at
-// the same time (the second read then hits the L2 or merges with the first).
+// and the wavefronts meet at a workgroup barrier once every kSyncIters
+// iterations of the row loop (every wavefront of the workgroup takes the same
+// number of steps: same m), so that the copies of a resampled particle, which
+// read the same rows, read them at nearly the same time (the second read then
+// hits the L2 or merges with the first). A barrier at every step holds each
+// wavefront to the slowest one's remainders; with none the copies drift apart.
+constexpr int kSyncIters = 32;
 template <typename Real, int G, int CH, int FAM, bool BLK, int TL = 0, bool SYNC = false>
 __device__ __forceinline__ PassResultW<wide_nc<G>()> estimator_pass_wide(const Prob& P, const int32_t* __restrict__ urow,
                                                            int b0, int b1, const int32_t* blk, Real* red,
@@ -223,7 +225,9 @@ __device__ __forceinline__ PassResultW<wide_nc<G>()> estimator_pass_wide(const P
       for (int s = 0; s < PT; ++s) kf[s] = kg[s];
     };
     for (int step = 0; step < nsteps; step += 2) {
-      if constexpr (SYNC) __builtin_amdgcn_s_barrier();
+      if constexpr (SYNC) {
+        if (step % (kSyncIters / PT) == 0) __builtin_amdgcn_s_barrier();
+      }
       step_on(xa, ka, step);
       if (step + 1 < nsteps) step_on(xb, kb, step + 1);
     }
@@ -241,7 +245,9 @@ __device__ __forceinline__ PassResultW<wide_nc<G>()> estimator_pass_wide(const P
 #pragma unroll
     for (int s = 0; s < PD; ++s) kn[s] = fetch_at(PD + s);
     for (int step = 0; step < nsteps; ++step) {
-      if constexpr (SYNC) __builtin_amdgcn_s_barrier();
+      if constexpr (SYNC) {
+        if (step % (kSyncIters / PD) == 0) __builtin_amdgcn_s_barrier();
+      }
       int32_t kf[PD];
 #pragma unroll
       for (int s = 0; s < PD; ++s) kf[s] = fetch_at(PD * (step + 2) + s);
@@ -567,7 +573,8 @@ __global__ void __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(kMov
 // The lane-group move (tile form 2: form 0's row loop) with kWideGroup
 // consecutive particles per workgroup, one per wavefront, each
 // with an LDS slice of its own of wide_group_wave_lds bytes, their row steps
-// held together by a barrier (estimator_pass_wide, SYNC). The launch covers
+// held close together by a barrier every kSyncIters row iterations
+// (estimator_pass_wide, SYNC). The launch covers
 // the particles exactly (gridDim.x * kWideGroup == M), so every wavefront has a
 // particle and takes the same number of barriers.
 constexpr int kWideGroup = 4;
