@@ -333,9 +333,10 @@ typedef struct smc_info {
   int32_t stream_tile; /* lane-group streaming move (d > 32): the tile form of its row loop,
                           0 (FP32 logistic rows evaluate each row's remainder once, in one
                           lane of the row's group), 1 (in every lane of the group) or 2
-                          (form 0 with 4 consecutive particles per workgroup whose row steps
-                          meet at a barrier, so that resampled copies, which share their
-                          subsample, read each row at the same time; offered for every
+                          (form 0 with 4 consecutive particles per workgroup whose row loops
+                          meet at a barrier every 32 iterations, so that resampled copies,
+                          which share their subsample, read each row at nearly the same
+                          time; offered for every
                           lane-group shape when 4 divides M). Form 1 exists for FP32 logistic
                           rows only. Default: 2 for FP32 logistic rows with d > 60, else 0 */
 } smc_info;
