@@ -255,9 +255,10 @@ def move_kernel_name(w, move_path, stream_tile=0):
     return "move_kernel_wide_group" if stream_tile == 2 else "move_kernel_wide"
 
 
-def measured_traffic(w, precision, kernel):
+def measured_traffic(w, precision, kernel, state="live"):
     """HBM bytes per move launch from the committed PMC summary, if it was
-    taken on the current device sources (else None)."""
+    taken on the current device sources (else None): the live stages' mean, or
+    with state="a1" the mean over the moves of the fixed a = 1 state."""
     path = os.path.join(ROOT, "profiles", f"{kernel}_{w.name}_{precision}_traffic.txt")
     if not os.path.exists(path):
         return None
@@ -269,17 +270,18 @@ def measured_traffic(w, precision, kernel):
                 kv[k] = v
     if kv.get("device_source_sha256") != device_source_hash(kernel):
         return None
-    return float(kv["traffic_bytes_per_launch"])
+    key = "traffic_bytes_per_launch" + ("_a1" if state == "a1" else "")
+    return float(kv[key]) if key in kv else None
 
 
-def roofline(w, fp32, move_ms, move_path, stream_tile=0):
+def roofline(w, fp32, move_ms, move_path, stream_tile=0, state="live"):
     """The move kernel against its bound. The streaming kernels re-read every
     row on every pass and are bounded by memory bandwidth; the resident kernel
     gathers the rows once per move and keeps them on chip, so its passes are
     bounded by the vector ALU."""
     evals = w.M * w.m * (w.L + 1)
     kernel = move_kernel_name(w, move_path, stream_tile)
-    traffic = measured_traffic(w, "mixed" if fp32 else "fp64", kernel)
+    traffic = measured_traffic(w, "mixed" if fp32 else "fp64", kernel, state)
     if move_path == MOVE_RESIDENT:
         fpe = algorithmic_flops_per_eval(w.d)
         achieved = fpe * evals / (move_ms * 1e-3) / 1e12
@@ -644,7 +646,7 @@ def bench_workload(name, args, cpu, e2e):
     # the move on the fixed benchmark state (a = 1, Laplace approximation) for the dominant path
     out["laplace_a1"] = laplace_state_move(ctxs[head], w, eps)
     out["laplace_a1"]["roofline"] = roofline(w, head == "mixed", out["laplace_a1"]["move_ms_median"],
-                                             r["move_path"], r.get("stream_tile", 0))
+                                             r["move_path"], r.get("stream_tile", 0), state="a1")
     if name in ("config1", "config2") and e2e:
         out["run_to_end"] = run_to_end(w, W.MIXED if head == "mixed" else W.FP64, Xy, eps, args.cv_order)
     for c in ctxs.values():

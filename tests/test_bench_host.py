@@ -70,6 +70,12 @@ def test_traffic_only_for_current_sources(tmp_path, monkeypatch):
     monkeypatch.setattr(bench, "device_source_hash", lambda kernel: "abc")
     f.write_text("# header\ndevice_source_sha256 abc\ntraffic_bytes_per_launch 1234\n")
     assert bench.measured_traffic(w, "mixed", "move_kernel_res") == 1234.0
+    # the a = 1 state's moves have a figure of their own, or none
+    assert bench.measured_traffic(w, "mixed", "move_kernel_res", "a1") is None
+    f.write_text("# header\ndevice_source_sha256 abc\ntraffic_bytes_per_launch 1234\n"
+                 "traffic_bytes_per_launch_a1 5678\n")
+    assert bench.measured_traffic(w, "mixed", "move_kernel_res") == 1234.0
+    assert bench.measured_traffic(w, "mixed", "move_kernel_res", "a1") == 5678.0
     f.write_text("# header\ndevice_source_sha256 old\ntraffic_bytes_per_launch 1234\n")
     assert bench.measured_traffic(w, "mixed", "move_kernel_res") is None
     assert bench.measured_traffic(w, "fp64", "move_kernel") is None
