@@ -270,7 +270,8 @@ struct ResOption {
 // tile forms of the lane-group streaming move for a problem (see launch_wide.hip)
 // Tile forms of the lane-group move for this problem, as bits: form 0 always;
 // form 1 (the remainder in every lane) for FP32 logistic rows; form 2 (form 0
-// with kWideGroup particles per workgroup, their row steps held together) when
+// with kWideGroup particles per workgroup whose row loops meet at a barrier
+// every kSyncIters iterations) when
 // kWideGroup divides the particle count. The narrow move has form 0 only.
 int wide_forms(const smc_problem& pb) {
   if (pb.d <= kMaxNarrowD) return 1;
